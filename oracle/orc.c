@@ -1,0 +1,968 @@
+/*
+ * Serial FP64 CPU oracle for the batched BDF-Newton hot path.
+ * TEST INFRASTRUCTURE ONLY: loaded by tests, the smoke check and the CPU
+ * baseline of the benchmark; never by the product library.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fPIC -shared
+ *
+ * What each part follows
+ *  - Vector operations: the streaming / reduction split of Section 2 and
+ *    the reduction semantics of Section 4.1 (reductions produce one scalar).
+ *    The fused operations (linear combination, scale-add-multi, multiple
+ *    dot products, WRMS norm) are not defined in the paper; their plain
+ *    definitions are written out here.  Reductions add in index order with
+ *    Neumaier's compensated summation.
+ *  - Dense LU: the batched block-diagonal direct solve of Section 5 (one
+ *    shared pattern, one dense block per cell) as LAPACK getrf semantics:
+ *    right-looking partial pivoting, first maximal pivot, whole-row swaps,
+ *    division by the pivot.
+ *  - The Newton iteration over all cells at once with a block-diagonal
+ *    solve and whole-step retry on any failure: Section 7 (task-local
+ *    nonlinear solver and ensemble failure rule).
+ *  - The BDF integrator itself is not given by the paper (it only names
+ *    CVODE); this is a fixed-coefficient Nordsieck BDF of orders 1..5 with
+ *    CVODE-style weights, Newton and local error test.  Its constants are
+ *    the readings listed in the design notes (parity unpinned for the
+ *    step-control constants themselves).
+ */
+#include "orc.h"
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Neumaier compensated summation (A. Neumaier, 1974)                       */
+/* ------------------------------------------------------------------------ */
+typedef struct { double s, c; } nsum;
+
+static void ns_add(nsum* a, double v) {
+  double t = a->s + v;
+  if (fabs(a->s) >= fabs(v))
+    a->c += (a->s - t) + v;
+  else
+    a->c += (v - t) + a->s;
+  a->s = t;
+}
+static double ns_val(const nsum* a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------------ */
+/* N_Vector operations                                                      */
+/* ------------------------------------------------------------------------ */
+void orc_nv_linear_sum(long n, double a, const double* x, double b,
+                       const double* y, double* z) {
+  for (long i = 0; i < n; ++i) {
+    double xi = x[i], yi = y[i];
+    z[i] = a * xi + b * yi;
+  }
+}
+
+void orc_nv_linear_combination(int nv, const double* c,
+                               const double* const* X, double* z, long n) {
+  for (long i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < nv; ++j) s = s + c[j] * X[j][i];
+    z[i] = s;
+  }
+}
+
+void orc_nv_scale_add_multi(int nv, const double* a, const double* x,
+                            const double* const* Y, double* const* Z, long n) {
+  for (long i = 0; i < n; ++i) {
+    double xi = x[i];
+    for (int j = 0; j < nv; ++j) Z[j][i] = a[j] * xi + Y[j][i];
+  }
+}
+
+void orc_nv_dot_prod_multi(int nv, const double* x, const double* const* Y,
+                           double* d, long n) {
+  for (int j = 0; j < nv; ++j) {
+    nsum s = {0.0, 0.0};
+    for (long i = 0; i < n; ++i) ns_add(&s, x[i] * Y[j][i]);
+    d[j] = ns_val(&s);
+  }
+}
+
+double orc_nv_wrms_norm(long n, const double* x, const double* w) {
+  if (n <= 0) return 0.0;
+  nsum s = {0.0, 0.0};
+  for (long i = 0; i < n; ++i) {
+    double v = x[i] * w[i];
+    ns_add(&s, v * v);
+  }
+  return sqrt(ns_val(&s) / (double)n);
+}
+
+double orc_nv_max_norm(long n, const double* x) {
+  double m = 0.0;
+  for (long i = 0; i < n; ++i)
+    if (fabs(x[i]) > m) m = fabs(x[i]);
+  return m;
+}
+
+void orc_nv_ewt(long n, double rtol, double atol, const double* y, double* w) {
+  for (long i = 0; i < n; ++i) w[i] = 1.0 / (rtol * fabs(y[i]) + atol);
+}
+
+void orc_nv_scale(long n, double c, const double* x, double* z) {
+  for (long i = 0; i < n; ++i) z[i] = c * x[i];
+}
+
+void orc_nv_const(long n, double c, double* z) {
+  for (long i = 0; i < n; ++i) z[i] = c;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense LU, one block                                                      */
+/* ------------------------------------------------------------------------ */
+#define AT(A, i, j, n) (A)[(i) + (long)(j) * (n)]
+
+int orc_lu_factor(int n, double* A, int* piv) {
+  int info = 0;
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double amax = fabs(AT(A, k, k, n));
+    for (int i = k + 1; i < n; ++i) {
+      double v = fabs(AT(A, i, k, n));
+      if (v > amax) { amax = v; p = i; }
+    }
+    piv[k] = p;
+    if (p != k)
+      for (int j = 0; j < n; ++j) {
+        double t = AT(A, k, j, n);
+        AT(A, k, j, n) = AT(A, p, j, n);
+        AT(A, p, j, n) = t;
+      }
+    if (AT(A, k, k, n) == 0.0) {
+      if (!info) info = k + 1;
+      continue;
+    }
+    for (int i = k + 1; i < n; ++i) AT(A, i, k, n) = AT(A, i, k, n) / AT(A, k, k, n);
+    for (int j = k + 1; j < n; ++j)
+      for (int i = k + 1; i < n; ++i)
+        AT(A, i, j, n) = AT(A, i, j, n) - AT(A, i, k, n) * AT(A, k, j, n);
+  }
+  return info;
+}
+
+void orc_lu_solve(int n, const double* LU, const int* piv, double* b) {
+  for (int k = 0; k < n; ++k) {
+    int p = piv[k];
+    if (p != k) { double t = b[k]; b[k] = b[p]; b[p] = t; }
+  }
+  for (int i = 0; i < n; ++i) {
+    double s = b[i];
+    for (int j = 0; j < i; ++j) s = s - AT(LU, i, j, n) * b[j];
+    b[i] = s;
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (int j = i + 1; j < n; ++j) s = s - AT(LU, i, j, n) * b[j];
+    b[i] = s / AT(LU, i, i, n);
+  }
+}
+
+int orc_lu_factor_f32(int n, float* A, int* piv) {
+  int info = 0;
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    float amax = fabsf(AT(A, k, k, n));
+    for (int i = k + 1; i < n; ++i) {
+      float v = fabsf(AT(A, i, k, n));
+      if (v > amax) { amax = v; p = i; }
+    }
+    piv[k] = p;
+    if (p != k)
+      for (int j = 0; j < n; ++j) {
+        float t = AT(A, k, j, n);
+        AT(A, k, j, n) = AT(A, p, j, n);
+        AT(A, p, j, n) = t;
+      }
+    if (AT(A, k, k, n) == 0.0f) {
+      if (!info) info = k + 1;
+      continue;
+    }
+    for (int i = k + 1; i < n; ++i) AT(A, i, k, n) = AT(A, i, k, n) / AT(A, k, k, n);
+    for (int j = k + 1; j < n; ++j)
+      for (int i = k + 1; i < n; ++i)
+        AT(A, i, j, n) = AT(A, i, j, n) - AT(A, i, k, n) * AT(A, k, j, n);
+  }
+  return info;
+}
+
+void orc_lu_solve_f32(int n, const float* LU, const int* piv, float* b) {
+  for (int k = 0; k < n; ++k) {
+    int p = piv[k];
+    if (p != k) { float t = b[k]; b[k] = b[p]; b[p] = t; }
+  }
+  for (int i = 0; i < n; ++i) {
+    float s = b[i];
+    for (int j = 0; j < i; ++j) s = s - AT(LU, i, j, n) * b[j];
+    b[i] = s;
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    float s = b[i];
+    for (int j = i + 1; j < n; ++j) s = s - AT(LU, i, j, n) * b[j];
+    b[i] = s / AT(LU, i, i, n);
+  }
+}
+
+/* Mixed-precision refinement for one block.
+ * x0 = FP32 solve of b; then up to max_it corrections d = FP32 solve of the
+ * FP64 residual r = b - M x.  Converged when the residual is at FP64
+ * working accuracy, |r|_inf <= sqrt(n) * eps64 * |M|_inf * |x|_inf (the
+ * residual test of LAPACK's mixed-precision dsgesv).  Not converged after
+ * max_it corrections, or a correction that fails to halve (|d_k| >
+ * 0.5 |d_{k-1}|, the sign that cond(M) * eps32 is near 1), means the block
+ * must be solved in FP64 instead: returns 1 and leaves x undefined. */
+int orc_lu_refine_solve(int n, const double* M, const float* LU32,
+                        const int* piv32, const double* b, double* x,
+                        int max_it, int* sweeps) {
+  float* v = (float*)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+  double* r = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double mnorm = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s = s + fabs(AT(M, i, j, n));
+    if (s > mnorm) mnorm = s;
+  }
+  for (int i = 0; i < n; ++i) v[i] = (float)b[i];
+  orc_lu_solve_f32(n, LU32, piv32, v);
+  for (int i = 0; i < n; ++i) x[i] = (double)v[i];
+  const double eps64 = 2.220446049250313e-16;
+  double dprev = 0.0;
+  int it, status = 1;
+  *sweeps = 0;
+  for (it = 0; it <= max_it; ++it) {
+    double rn = 0.0, xn = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double s = b[i];
+      for (int j = 0; j < n; ++j) s = s - AT(M, i, j, n) * x[j];
+      r[i] = s;
+      if (fabs(s) > rn) rn = fabs(s);
+      if (fabs(x[i]) > xn) xn = fabs(x[i]);
+    }
+    if (!(rn == rn) || !(xn == xn)) break;           /* NaN */
+    if (rn <= sqrt((double)n) * eps64 * mnorm * xn) { status = 0; break; }
+    if (it == max_it) break;
+    for (int i = 0; i < n; ++i) v[i] = (float)r[i];
+    orc_lu_solve_f32(n, LU32, piv32, v);
+    double dn = 0.0;
+    for (int i = 0; i < n; ++i) {
+      x[i] = x[i] + (double)v[i];
+      if (fabs((double)v[i]) > dn) dn = fabs((double)v[i]);
+    }
+    *sweeps = it + 1;
+    if (it >= 1 && dn > 0.5 * dprev) break;          /* stagnation */
+    dprev = dn;
+  }
+  free(v);
+  free(r);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mass-action kinetics: r_k = kappa_k prod_s y_s^nu_ks,                     */
+/* f_s = sum_k (mu_ks - nu_ks) r_k, J_sj = df_s/dy_j (analytic).             */
+/* ------------------------------------------------------------------------ */
+static double ipow(double y, int e) {
+  double r = 1.0;
+  for (int i = 0; i < e; ++i) r = r * y;
+  return r;
+}
+
+void orc_ma_rhs(int n, int R, const int* nu, const int* mu,
+                const double* kappa, const double* y, double* f) {
+  for (int s = 0; s < n; ++s) f[s] = 0.0;
+  for (int k = 0; k < R; ++k) {
+    double r = kappa[k];
+    for (int s = 0; s < n; ++s) r = r * ipow(y[s], nu[k * n + s]);
+    for (int s = 0; s < n; ++s) {
+      int c = mu[k * n + s] - nu[k * n + s];
+      if (c) f[s] = f[s] + (double)c * r;
+    }
+  }
+}
+
+void orc_ma_jac(int n, int R, const int* nu, const int* mu,
+                const double* kappa, const double* y, double* J) {
+  for (long i = 0; i < (long)n * n; ++i) J[i] = 0.0;
+  for (int k = 0; k < R; ++k) {
+    for (int j = 0; j < n; ++j) {
+      int e = nu[k * n + j];
+      if (!e) continue;
+      double d = kappa[k] * (double)e * ipow(y[j], e - 1);
+      for (int s = 0; s < n; ++s)
+        if (s != j) d = d * ipow(y[s], nu[k * n + s]);
+      for (int s = 0; s < n; ++s) {
+        int c = mu[k * n + s] - nu[k * n + s];
+        if (c) AT(J, s, j, n) = AT(J, s, j, n) + (double)c * d;
+      }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Small MLP with BF16 operands at every matrix product                     */
+/* ------------------------------------------------------------------------ */
+float orc_bf16_round(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) {
+    if (u & 0x007fffffu) u |= 0x00400000u;
+    u &= 0xffff0000u;
+  } else {
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    u &= 0xffff0000u;
+  }
+  float r;
+  memcpy(&r, &u, 4);
+  return r;
+}
+
+/* Rounding points can be switched off so that finite differences can check
+ * the backward pass (rounding is passed straight through in the gradient). */
+static int g_bf16_on = 1;
+void orc_set_bf16(int on) { g_bf16_on = on; }
+
+static double bf(double v) {
+  return g_bf16_on ? (double)orc_bf16_round((float)v) : v;
+}
+
+typedef struct {
+  double* xs;  /* nin  : standardised, BF16-rounded input */
+  double* a1;  /* hid  : pre-activation 1 */
+  double* h1;  /* hid  : BF16-rounded ReLU(a1) */
+  double* a2;
+  double* h2;
+  double* out; /* nout */
+} mlp_trace;
+
+static void mlp_fwd(const orc_mlp* m, const double* x_raw, mlp_trace* t) {
+  const int ni = m->nin, nh = m->hid, no = m->nout;
+  for (int i = 0; i < ni; ++i) t->xs[i] = bf((x_raw[i] - m->in_mean[i]) / m->in_std[i]);
+  for (int o = 0; o < nh; ++o) {
+    double s = 0.0;
+    for (int i = 0; i < ni; ++i) s = s + bf(m->W1[(long)o * ni + i]) * t->xs[i];
+    s = s + (double)m->b1[o];
+    t->a1[o] = s;
+    t->h1[o] = bf(s > 0.0 ? s : 0.0);
+  }
+  for (int o = 0; o < nh; ++o) {
+    double s = 0.0;
+    for (int i = 0; i < nh; ++i) s = s + bf(m->W2[(long)o * nh + i]) * t->h1[i];
+    s = s + (double)m->b2[o];
+    t->a2[o] = s;
+    t->h2[o] = bf(s > 0.0 ? s : 0.0);
+  }
+  for (int o = 0; o < no; ++o) {
+    double s = 0.0;
+    for (int i = 0; i < nh; ++i) s = s + bf(m->W3[(long)o * nh + i]) * t->h2[i];
+    t->out[o] = s + (double)m->b3[o];
+  }
+}
+
+static mlp_trace trace_alloc(const orc_mlp* m) {
+  mlp_trace t;
+  t.xs = (double*)calloc((size_t)m->nin, sizeof(double));
+  t.a1 = (double*)calloc((size_t)m->hid, sizeof(double));
+  t.h1 = (double*)calloc((size_t)m->hid, sizeof(double));
+  t.a2 = (double*)calloc((size_t)m->hid, sizeof(double));
+  t.h2 = (double*)calloc((size_t)m->hid, sizeof(double));
+  t.out = (double*)calloc((size_t)m->nout, sizeof(double));
+  return t;
+}
+static void trace_free(mlp_trace* t) {
+  free(t->xs); free(t->a1); free(t->h1); free(t->a2); free(t->h2); free(t->out);
+}
+
+void orc_mlp_forward(const orc_mlp* m, const double* x_raw, double* out) {
+  mlp_trace t = trace_alloc(m);
+  mlp_fwd(m, x_raw, &t);
+  memcpy(out, t.out, sizeof(double) * (size_t)m->nout);
+  trace_free(&t);
+}
+
+/* Loss L = mean_b |X_b M_b - I|_F^2 / n^2 with X = I + reshape(out)
+ * (row-major: X[i][j] = out[i*n + j]).  The rounding to BF16 of each matrix
+ * product's inputs is passed straight through in the backward pass; the
+ * backward products use the same BF16-rounded weights as the forward. */
+double orc_mlp_loss_grad(const orc_mlp* m, int B, const double* X_raw,
+                         const double* Mb, double* gW1, double* gb1,
+                         double* gW2, double* gb2, double* gW3, double* gb3) {
+  const int ni = m->nin, nh = m->hid, no = m->nout;
+  int n = 0;
+  while ((n + 1) * (n + 1) <= no) ++n;
+  memset(gW1, 0, sizeof(double) * (size_t)nh * ni);
+  memset(gb1, 0, sizeof(double) * (size_t)nh);
+  memset(gW2, 0, sizeof(double) * (size_t)nh * nh);
+  memset(gb2, 0, sizeof(double) * (size_t)nh);
+  memset(gW3, 0, sizeof(double) * (size_t)no * nh);
+  memset(gb3, 0, sizeof(double) * (size_t)no);
+  mlp_trace t = trace_alloc(m);
+  double* X = (double*)malloc(sizeof(double) * (size_t)no);
+  double* E = (double*)malloc(sizeof(double) * (size_t)no);
+  double* dout = (double*)malloc(sizeof(double) * (size_t)no);
+  double* dh2 = (double*)malloc(sizeof(double) * (size_t)nh);
+  double* dh1 = (double*)malloc(sizeof(double) * (size_t)nh);
+  const double scale = 1.0 / ((double)no * (double)B);
+  double L = 0.0;
+  for (int b = 0; b < B; ++b) {
+    const double* M = Mb + (long)b * no;
+    mlp_fwd(m, X_raw + (long)b * ni, &t);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        X[i * n + j] = t.out[i * n + j] + (i == j ? 1.0 : 0.0);
+    /* E = X M - I   (M column-major) */
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s = s + X[i * n + k] * AT(M, k, j, n);
+        E[i * n + j] = s - (i == j ? 1.0 : 0.0);
+        L = L + E[i * n + j] * E[i * n + j] * scale;
+      }
+    /* dL/dX = 2 E M^T * scale */
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s = s + E[i * n + j] * AT(M, k, j, n);
+        dout[i * n + k] = 2.0 * s * scale;
+      }
+    for (int o = 0; o < no; ++o) {
+      gb3[o] += dout[o];
+      for (int i = 0; i < nh; ++i) gW3[(long)o * nh + i] += dout[o] * t.h2[i];
+    }
+    for (int i = 0; i < nh; ++i) {
+      double s = 0.0;
+      for (int o = 0; o < no; ++o) s = s + bf(m->W3[(long)o * nh + i]) * dout[o];
+      dh2[i] = t.a2[i] > 0.0 ? s : 0.0;
+    }
+    for (int o = 0; o < nh; ++o) {
+      gb2[o] += dh2[o];
+      for (int i = 0; i < nh; ++i) gW2[(long)o * nh + i] += dh2[o] * t.h1[i];
+    }
+    for (int i = 0; i < nh; ++i) {
+      double s = 0.0;
+      for (int o = 0; o < nh; ++o) s = s + bf(m->W2[(long)o * nh + i]) * dh2[o];
+      dh1[i] = t.a1[i] > 0.0 ? s : 0.0;
+    }
+    for (int o = 0; o < nh; ++o) {
+      gb1[o] += dh1[o];
+      for (int i = 0; i < ni; ++i) gW1[(long)o * ni + i] += dh1[o] * t.xs[i];
+    }
+  }
+  free(X); free(E); free(dout); free(dh2); free(dh1);
+  trace_free(&t);
+  return L;
+}
+
+/* Adam (Kingma & Ba, 2015) on FP32 master weights, moments in FP64. */
+void orc_adam_step(long np, float* p, const double* g, double* m1, double* m2,
+                   long t, double lr, double b1, double b2, double eps) {
+  double c1 = 1.0 - pow(b1, (double)t);
+  double c2 = 1.0 - pow(b2, (double)t);
+  for (long i = 0; i < np; ++i) {
+    m1[i] = b1 * m1[i] + (1.0 - b1) * g[i];
+    m2[i] = b2 * m2[i] + (1.0 - b2) * g[i] * g[i];
+    double mh = m1[i] / c1, vh = m2[i] / c2;
+    p[i] = (float)((double)p[i] - lr * mh / (sqrt(vh) + eps));
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grouped fixed-coefficient Nordsieck BDF                                  */
+/* ------------------------------------------------------------------------ */
+#define QMAX_ALL 5
+#define MXNCF 10      /* Newton failures per step before giving up */
+#define MXNEF 7       /* error-test failures per step before giving up */
+#define CRDOWN 0.3    /* memory factor of the convergence-rate estimate */
+#define RDIV 2.0      /* divergence factor */
+#define NLS_COEF 0.1  /* Newton tolerance in WRMS units of the correction */
+#define ETA_MAX 10.0  /* largest step growth */
+#define ETA_MIN_EF 0.2
+#define ETA_CF 0.25
+#define ETA_RESTART 0.1
+#define THRESH 1.5    /* hysteresis: smaller proposed growth keeps h, q */
+#define BIAS_QM1 1.3
+#define BIAS_Q 1.2
+#define BIAS_QP1 1.4
+#define ADDON 1e-6
+#define LP_CELL_RATIO 0.9
+
+struct orc_bdf {
+  orc_problem p;
+  orc_options o;
+  long N, nmat;
+  long *yoff, *roff, *moff;
+  int *cn, *cR;
+  const int **cnu, **cmu;
+  double* z[QMAX_ALL + 1];
+  double* zp[QMAX_ALL + 1];
+  double *dprev, *acor, *y, *w, *f, *r, *del, *tmp;
+  double *M, *LU;
+  float* LU32;
+  int *piv, *piv32, *cellmode, *cellinfo;
+  double *X, *dcell_prev;
+  double t, h, err_last, hu;
+  int q, qwait, qu, initialized;
+  orc_stats st;
+};
+
+static double harmonic(int q) {
+  double s = 0.0;
+  for (int i = 1; i <= q; ++i) s += 1.0 / (double)i;
+  return s;
+}
+
+static double factorial(int q) {
+  double s = 1.0;
+  for (int i = 2; i <= q; ++i) s *= (double)i;
+  return s;
+}
+
+void orc_bdf_coeffs(int q, double* l, double* tq) {
+  /* coefficients of prod_{i=1..q} (1 + x/i), divided by H_q */
+  double c[QMAX_ALL + 2];
+  for (int j = 0; j <= QMAX_ALL + 1; ++j) c[j] = 0.0;
+  c[0] = 1.0;
+  for (int i = 1; i <= q; ++i)
+    for (int j = i; j >= 1; --j) c[j] = c[j] + c[j - 1] / (double)i;
+  double H = harmonic(q);
+  for (int j = 0; j <= q; ++j) l[j] = c[j] / H;
+  /* local error of order q from the correction: with an interpolating
+   * history the correction is H_{q+1} times the (q+1)-th backward difference
+   * and the truncation error is that difference over (q+1) H_q */
+  if (tq) *tq = 1.0 / ((double)(q + 1) * H * harmonic(q + 1));
+}
+
+orc_bdf* orc_bdf_create(const orc_problem* p, const orc_options* o) {
+  orc_bdf* b = (orc_bdf*)calloc(1, sizeof(orc_bdf));
+  b->p = *p;
+  b->o = *o;
+  long nc = p->ncells;
+  b->yoff = (long*)calloc((size_t)nc + 1, sizeof(long));
+  b->roff = (long*)calloc((size_t)nc + 1, sizeof(long));
+  b->moff = (long*)calloc((size_t)nc + 1, sizeof(long));
+  b->cn = (int*)calloc((size_t)nc + 1, sizeof(int));
+  b->cR = (int*)calloc((size_t)nc + 1, sizeof(int));
+  b->cnu = (const int**)calloc((size_t)nc + 1, sizeof(int*));
+  b->cmu = (const int**)calloc((size_t)nc + 1, sizeof(int*));
+  for (long c = 0; c < nc; ++c) {
+    int t = p->cell_topo[c];
+    b->cn[c] = p->topo_n[t];
+    b->cR[c] = p->topo_R[t];
+    b->cnu[c] = p->nu_all + p->topo_off[t];
+    b->cmu[c] = p->mu_all + p->topo_off[t];
+    b->yoff[c + 1] = b->yoff[c] + b->cn[c];
+    b->roff[c + 1] = b->roff[c] + b->cR[c];
+    b->moff[c + 1] = b->moff[c] + (long)b->cn[c] * b->cn[c];
+  }
+  b->N = b->yoff[nc];
+  b->nmat = b->moff[nc];
+  size_t N = (size_t)(b->N > 0 ? b->N : 1);
+  for (int j = 0; j <= QMAX_ALL; ++j) {
+    b->z[j] = (double*)calloc(N, sizeof(double));
+    b->zp[j] = (double*)calloc(N, sizeof(double));
+  }
+  b->dprev = (double*)calloc(N, sizeof(double));
+  b->acor = (double*)calloc(N, sizeof(double));
+  b->y = (double*)calloc(N, sizeof(double));
+  b->w = (double*)calloc(N, sizeof(double));
+  b->f = (double*)calloc(N, sizeof(double));
+  b->r = (double*)calloc(N, sizeof(double));
+  b->del = (double*)calloc(N, sizeof(double));
+  b->tmp = (double*)calloc(N, sizeof(double));
+  size_t NM = (size_t)(b->nmat > 0 ? b->nmat : 1);
+  b->M = (double*)calloc(NM, sizeof(double));
+  b->LU = (double*)calloc(NM, sizeof(double));
+  b->LU32 = (float*)calloc(NM, sizeof(float));
+  b->piv = (int*)calloc(N, sizeof(int));
+  b->piv32 = (int*)calloc(N, sizeof(int));
+  b->cellmode = (int*)calloc((size_t)nc + 1, sizeof(int));
+  b->cellinfo = (int*)calloc((size_t)nc + 1, sizeof(int));
+  b->dcell_prev = (double*)calloc((size_t)nc + 1, sizeof(double));
+  if (o->linsol == ORC_LS_LEARNED) b->X = (double*)calloc(NM, sizeof(double));
+  b->t = p->t0;
+  memcpy(b->z[0], p->y0, sizeof(double) * (size_t)b->N);
+  return b;
+}
+
+void orc_bdf_destroy(orc_bdf* b) {
+  if (!b) return;
+  free(b->yoff); free(b->roff); free(b->moff); free(b->cn); free(b->cR);
+  free(b->cnu); free(b->cmu);
+  for (int j = 0; j <= QMAX_ALL; ++j) { free(b->z[j]); free(b->zp[j]); }
+  free(b->dprev); free(b->acor); free(b->y); free(b->w); free(b->f);
+  free(b->r); free(b->del); free(b->tmp); free(b->M); free(b->LU);
+  free(b->LU32); free(b->piv); free(b->piv32); free(b->cellmode);
+  free(b->cellinfo); free(b->dcell_prev); free(b->X);
+  free(b);
+}
+
+long orc_bdf_N(const orc_bdf* b) { return b->N; }
+
+static void rhs_all(orc_bdf* b, const double* y, double* f) {
+  for (long c = 0; c < b->p.ncells; ++c)
+    orc_ma_rhs(b->cn[c], b->cR[c], b->cnu[c], b->cmu[c], b->p.rates + b->roff[c],
+               y + b->yoff[c], f + b->yoff[c]);
+  b->st.nfevals++;
+}
+
+static double wrms(const orc_bdf* b, const double* x) {
+  return orc_nv_wrms_norm(b->N, x, b->w);
+}
+
+static void rescale(orc_bdf* b, double eta) {
+  double fac = 1.0;
+  for (int j = 1; j <= b->q; ++j) {
+    fac = fac * eta;
+    for (long i = 0; i < b->N; ++i) b->z[j][i] = b->z[j][i] * fac;
+  }
+}
+
+/* Starting step: Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4,
+ * with WRMS norms and p = 1. */
+static double hnw_h0(orc_bdf* b, double t_end) {
+  long N = b->N;
+  orc_nv_ewt(N, b->o.rtol, b->o.atol, b->z[0], b->w);
+  rhs_all(b, b->z[0], b->f);
+  double d0 = wrms(b, b->z[0]);
+  double d1 = wrms(b, b->f);
+  double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * (d0 / d1);
+  if (h0 > t_end - b->t) h0 = t_end - b->t;
+  for (long i = 0; i < N; ++i) b->tmp[i] = b->z[0][i] + h0 * b->f[i];
+  rhs_all(b, b->tmp, b->r);
+  for (long i = 0; i < N; ++i) b->r[i] = b->r[i] - b->f[i];
+  double d2 = wrms(b, b->r) / h0;
+  double dm = d1 > d2 ? d1 : d2;
+  double h1 = dm <= 1e-15 ? (h0 * 1e-3 > 1e-6 ? h0 * 1e-3 : 1e-6)
+                          : pow(0.01 / dm, 1.0 / 2.0);
+  double h = 100.0 * h0 < h1 ? 100.0 * h0 : h1;
+  return h;
+}
+
+static void initialize(orc_bdf* b, double t_end) {
+  long N = b->N;
+  double h = b->o.h0 > 0.0 ? b->o.h0 : hnw_h0(b, t_end);
+  if (h > t_end - b->t) h = t_end - b->t;
+  rhs_all(b, b->z[0], b->f);
+  for (long i = 0; i < N; ++i) b->z[1][i] = h * b->f[i];
+  for (int j = 2; j <= QMAX_ALL; ++j) memset(b->z[j], 0, sizeof(double) * (size_t)N);
+  memset(b->dprev, 0, sizeof(double) * (size_t)N);
+  b->h = h;
+  b->q = 1;
+  b->qwait = 2;
+  b->initialized = 1;
+}
+
+/* Fresh Jacobian at the predicted state and M = I - gamma J, per cell. */
+static void build_M(orc_bdf* b, long c, double gamma) {
+  int n = b->cn[c];
+  double* M = b->M + b->moff[c];
+  orc_ma_jac(n, b->cR[c], b->cnu[c], b->cmu[c], b->p.rates + b->roff[c],
+             b->zp[0] + b->yoff[c], M);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i)
+      AT(M, i, j, n) = (i == j ? 1.0 : 0.0) - gamma * AT(M, i, j, n);
+}
+
+static int factor64(orc_bdf* b, long c) {
+  int n = b->cn[c];
+  memcpy(b->LU + b->moff[c], b->M + b->moff[c], sizeof(double) * (size_t)n * n);
+  return orc_lu_factor(n, b->LU + b->moff[c], b->piv + b->yoff[c]);
+}
+
+/* Solve M del_c = r_c for one cell according to cellmode:
+ * 0 FP64 LU, 1 FP32 LU + refinement, 2 learned X, 3 FP64 LU after fallback. */
+static int cell_solve(orc_bdf* b, long c) {
+  int n = b->cn[c];
+  long off = b->yoff[c];
+  double* d = b->del + off;
+  const double* r = b->r + off;
+  int mode = b->cellmode[c];
+  if (mode == 1) {
+    int sw = 0;
+    int st = orc_lu_refine_solve(n, b->M + b->moff[c], b->LU32 + b->moff[c],
+                                 b->piv32 + off, r, d, b->o.refine_max_it, &sw);
+    b->st.refine_sweeps += sw;
+    if (st == 0) return 0;
+    b->st.refine_fallbacks++;
+    b->cellmode[c] = 3;
+    if (factor64(b, c)) return 1;
+    mode = 3;
+  }
+  if (mode == 2) {
+    const double* X = b->X + b->moff[c];
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) s = s + X[i * n + j] * r[j];
+      d[i] = s;
+    }
+    b->st.lp_cell_solves++;
+    return 0;
+  }
+  memcpy(d, r, sizeof(double) * (size_t)n);
+  orc_lu_solve(n, b->LU + b->moff[c], b->piv + off, d);
+  return 0;
+}
+
+static double cell_wrms(const orc_bdf* b, long c, const double* x) {
+  return orc_nv_wrms_norm(b->cn[c], x + b->yoff[c], b->w + b->yoff[c]);
+}
+
+static int finite_cell(const orc_bdf* b, long c, const double* x) {
+  for (int i = 0; i < b->cn[c]; ++i)
+    if (!isfinite(x[b->yoff[c] + i])) return 0;
+  return 1;
+}
+
+/* Newton iteration on all cells at once (grouped; one global norm).
+ * Returns 0 converged, 1 failed (caller retries the step). */
+static int newton(orc_bdf* b, double gamma, double l0, int force_lu) {
+  long N = b->N, nc = b->p.ncells;
+  int ls = b->o.linsol;
+  int setup_fail = 0;
+  b->st.nsetups++;
+  if (ls == ORC_LS_LEARNED && !force_lu) {
+    double xin[64];
+    double lg = log(gamma);
+    for (long c = 0; c < nc; ++c) {
+      int n = b->cn[c];
+      for (int i = 0; i < n; ++i) xin[i] = b->zp[0][b->yoff[c] + i];
+      xin[n] = lg;
+      double* X = b->X + b->moff[c];
+      orc_mlp_forward(b->o.mlp, xin, X);
+      for (int i = 0; i < n; ++i) X[i * n + i] += 1.0;
+      b->cellmode[c] = 2;
+      b->cellinfo[c] = 0;   /* M not built yet */
+    }
+  } else {
+    for (long c = 0; c < nc; ++c) {
+      build_M(b, c, gamma);
+      b->cellinfo[c] = 1;
+      if (ls == ORC_LS_LU32REF) {
+        int n = b->cn[c];
+        for (long i = 0; i < (long)n * n; ++i)
+          b->LU32[b->moff[c] + i] = (float)b->M[b->moff[c] + i];
+        int info = orc_lu_factor_f32(n, b->LU32 + b->moff[c], b->piv32 + b->yoff[c]);
+        b->cellmode[c] = 1;
+        if (info) {
+          b->st.refine_fallbacks++;
+          b->cellmode[c] = 3;
+          if (factor64(b, c)) setup_fail = 1;
+        }
+      } else {
+        b->cellmode[c] = 0;
+        if (factor64(b, c)) setup_fail = 1;
+      }
+    }
+  }
+  if (setup_fail) return 1;
+  memcpy(b->y, b->zp[0], sizeof(double) * (size_t)N);
+  double crate = 1.0, dold = 0.0;
+  for (int m = 0; m < b->o.maxcor; ++m) {
+    rhs_all(b, b->y, b->f);
+    for (long i = 0; i < N; ++i)
+      b->r[i] = gamma * b->f[i] - l0 * b->zp[1][i] - (b->y[i] - b->zp[0][i]);
+    for (long c = 0; c < nc; ++c) {
+      if (b->cellmode[c] == 2) {
+        cell_solve(b, c);
+        if (!finite_cell(b, c, b->del)) b->cellmode[c] = 4;  /* switch now */
+      }
+      if (b->cellmode[c] == 4) {   /* learned cell moved to exact LU */
+        if (b->cellinfo[c] == 0) {
+          build_M(b, c, gamma);
+          b->cellinfo[c] = 1;
+          b->st.lp_fallback_cells++;
+          if (factor64(b, c)) return 1;
+        }
+        int n = b->cn[c];
+        memcpy(b->del + b->yoff[c], b->r + b->yoff[c], sizeof(double) * (size_t)n);
+        orc_lu_solve(n, b->LU + b->moff[c], b->piv + b->yoff[c], b->del + b->yoff[c]);
+      } else if (b->cellmode[c] != 2) {
+        if (cell_solve(b, c)) return 1;
+      }
+    }
+    b->st.nlinsolves++;
+    if (ls == ORC_LS_LEARNED && !force_lu) {
+      for (long c = 0; c < nc; ++c) {
+        double dc = cell_wrms(b, c, b->del);
+        if (b->cellmode[c] == 2 && m >= 1 && dc > LP_CELL_RATIO * b->dcell_prev[c])
+          b->cellmode[c] = 4;     /* exact LU from the next iteration on */
+        b->dcell_prev[c] = dc;
+      }
+    }
+    for (long i = 0; i < N; ++i) b->y[i] = b->y[i] + b->del[i];
+    double d = wrms(b, b->del);
+    b->st.nniters++;
+    if (!isfinite(d)) return 1;
+    if (m > 0) {
+      double ratio = d / dold;
+      crate = CRDOWN * crate > ratio ? CRDOWN * crate : ratio;
+    }
+    double dcon = d * (crate < 1.0 ? crate : 1.0);
+    if (dcon <= NLS_COEF) return 0;
+    if (m + 1 == b->o.maxcor) return 1;
+    if (m >= 1 && d > RDIV * dold) return 1;
+    dold = d;
+  }
+  return 1;
+}
+
+int orc_bdf_step(orc_bdf* b, double t_end) {
+  long N = b->N;
+  if (!b->initialized) initialize(b, t_end);
+  if (b->t >= t_end) return 1;
+  int ncf = 0, netf = 0, force_lu = 0;
+  for (;;) {
+    int q = b->q;
+    if (b->t + b->h > t_end) {
+      double eta = (t_end - b->t) / b->h;
+      rescale(b, eta);
+      b->h = t_end - b->t;
+      b->qwait = q + 1;
+    }
+    int last = (b->t + b->h >= t_end);
+    double l[QMAX_ALL + 1], tq;
+    orc_bdf_coeffs(q, l, &tq);
+    orc_nv_ewt(N, b->o.rtol, b->o.atol, b->z[0], b->w);
+    for (int j = 0; j <= q; ++j) memcpy(b->zp[j], b->z[j], sizeof(double) * (size_t)N);
+    for (int k = 1; k <= q; ++k)
+      for (int j = q; j >= k; --j)
+        for (long i = 0; i < N; ++i) b->zp[j - 1][i] = b->zp[j - 1][i] + b->zp[j][i];
+    double gamma = b->h * l[0];
+    b->st.nattempts++;
+    int nst = newton(b, gamma, l[0], force_lu);
+    if (nst) {
+      if (b->o.linsol == ORC_LS_LEARNED && !force_lu) {
+        force_lu = 1;
+        b->st.lp_step_fallbacks++;
+        continue;
+      }
+      force_lu = 0;
+      ncf++;
+      b->st.nncfails++;
+      if (ncf >= MXNCF) return -4;
+      if (b->h * ETA_CF < b->o.hmin) return -5;
+      rescale(b, ETA_CF);
+      b->h = b->h * ETA_CF;
+      b->qwait = q + 1;
+      continue;
+    }
+    for (long i = 0; i < N; ++i) b->acor[i] = (b->y[i] - b->zp[0][i]) / l[0];
+    double err = wrms(b, b->acor) * tq;
+    b->err_last = err;
+    if (err > 1.0) {
+      force_lu = 0;
+      netf++;
+      b->st.netfails++;
+      if (netf >= MXNEF) return -3;
+      if (netf >= 3) {
+        double hn = b->h * ETA_RESTART;
+        if (hn < b->o.hmin) return -5;
+        b->h = hn;
+        b->q = 1;
+        rhs_all(b, b->z[0], b->f);
+        for (long i = 0; i < N; ++i) b->z[1][i] = b->h * b->f[i];
+        b->qwait = 2;
+      } else {
+        double eta = 0.9 * pow(err, -1.0 / (double)(q + 1));
+        if (eta < ETA_MIN_EF) eta = ETA_MIN_EF;
+        if (b->h * eta < b->o.hmin) return -5;
+        rescale(b, eta);
+        b->h = b->h * eta;
+        b->qwait = q + 1;
+      }
+      continue;
+    }
+    /* accept: z[j] = z(0)[j] + l_j * acor */
+    for (int j = 0; j <= q; ++j)
+      for (long i = 0; i < N; ++i) b->z[j][i] = b->zp[j][i] + l[j] * b->acor[i];
+    b->t = last ? t_end : b->t + b->h;
+    b->hu = b->h;
+    b->qu = q;
+    b->st.nsteps++;
+    b->st.order_hist[q]++;
+    b->qwait--;
+    /* step size and order for the next step */
+    double etaq = 1.0 / (pow(BIAS_Q * err, 1.0 / (double)(q + 1)) + ADDON);
+    double eta = etaq;
+    int qnew = q;
+    if (b->qwait == 0) {
+      b->qwait = 2;
+      double etaqm1 = 0.0, etaqp1 = 0.0;
+      if (q > 1) {
+        double e = wrms(b, b->z[q]) * factorial(q - 1) / harmonic(q - 1);
+        etaqm1 = 1.0 / (pow(BIAS_QM1 * e, 1.0 / (double)q) + ADDON);
+      }
+      if (q < b->o.qmax) {
+        for (long i = 0; i < N; ++i) b->tmp[i] = b->acor[i] - b->dprev[i];
+        double e = wrms(b, b->tmp) / ((double)(q + 2) * harmonic(q + 1) * harmonic(q + 1));
+        etaqp1 = 1.0 / (pow(BIAS_QP1 * e, 1.0 / (double)(q + 2)) + ADDON);
+      }
+      if (etaq >= etaqm1 && etaq >= etaqp1) {
+        eta = etaq; qnew = q;
+      } else if (etaqm1 >= etaqp1) {
+        eta = etaqm1; qnew = q - 1;
+      } else {
+        eta = etaqp1; qnew = q + 1;
+      }
+    }
+    if (eta >= THRESH) {
+      if (eta > ETA_MAX) eta = ETA_MAX;
+      if (qnew == q + 1) {
+        double c = 1.0 / (factorial(q + 1) * harmonic(q + 1));
+        for (long i = 0; i < N; ++i) b->z[q + 1][i] = c * b->acor[i];
+      }
+      b->q = qnew;
+      rescale(b, eta);
+      b->h = b->h * eta;
+      b->qwait = b->q + 1;
+    }
+    memcpy(b->dprev, b->acor, sizeof(double) * (size_t)N);
+    return 0;
+  }
+}
+
+int orc_bdf_integrate(orc_bdf* b, double t_end) {
+  long ns = 0;
+  if (!b->initialized) initialize(b, t_end);
+  while (b->t < t_end) {
+    int s = orc_bdf_step(b, t_end);
+    if (s < 0) return s;
+    if (b->o.max_steps > 0 && ++ns >= b->o.max_steps && b->t < t_end) return -6;
+  }
+  return 0;
+}
+
+void orc_bdf_get_y(const orc_bdf* b, double* y) {
+  memcpy(y, b->z[0], sizeof(double) * (size_t)b->N);
+}
+
+void orc_bdf_get_stats(const orc_bdf* b, orc_stats* s) { *s = b->st; }
+
+void orc_bdf_get_scalars(const orc_bdf* b, orc_scalars* s) {
+  s->t = b->t; s->h = b->h; s->err_last = b->err_last;
+  s->q = b->q; s->qwait = b->qwait; s->qprime_pending = 0;
+  s->initialized = b->initialized; s->hu = b->hu; s->qu = b->qu;
+}
+
+void orc_bdf_set_scalars(orc_bdf* b, const orc_scalars* s) {
+  b->t = s->t; b->h = s->h; b->err_last = s->err_last;
+  b->q = s->q; b->qwait = s->qwait; b->initialized = s->initialized;
+  b->hu = s->hu; b->qu = s->qu;
+}
+
+void orc_bdf_get_history(const orc_bdf* b, double* z6, double* dprev) {
+  for (int j = 0; j <= QMAX_ALL; ++j)
+    memcpy(z6 + (long)j * b->N, b->z[j], sizeof(double) * (size_t)b->N);
+  memcpy(dprev, b->dprev, sizeof(double) * (size_t)b->N);
+}
+
+void orc_bdf_set_history(orc_bdf* b, const double* z6, const double* dprev) {
+  for (int j = 0; j <= QMAX_ALL; ++j)
+    memcpy(b->z[j], z6 + (long)j * b->N, sizeof(double) * (size_t)b->N);
+  memcpy(b->dprev, dprev, sizeof(double) * (size_t)b->N);
+}
