@@ -1,0 +1,231 @@
+/*
+ * bdfgpu: batched stiff-ODE BDF-Newton on AMD MI355X (gfx950).
+ *
+ * C ABI of the library.  Every argument is a plain pointer or size.
+ *
+ * Conventions (all entry points)
+ *  - Memory.  Vector and matrix arguments are caller-owned DEVICE pointers
+ *    unless stated "host".  The library never frees memory it did not
+ *    allocate; memory it allocates (handle state, reduction scratch) it
+ *    frees in the matching destroy call or at process exit.  This follows
+ *    the ownership flag of the paper's SUNMemory structure (Section 3).
+ *  - Layout.  Vectors are contiguous FP64.  When a vector holds many small
+ *    systems it is cell-major: cell c owns entries [off_c, off_c + n_c)
+ *    (grouping of independent systems, Section 2, Fig. blockdiag_jacobian).
+ *    Dense blocks are contiguous column-major n x n blocks, block b at
+ *    offset b*n*n.  Pivots are int32, 0-based: piv[b*n + k] is the row
+ *    exchanged with row k at step k.
+ *  - Streams.  Every call takes `stream`, a hipStream_t (NULL = the legacy
+ *    default stream), and enqueues its work only there; vector, matrix and
+ *    solver calls that work on the same data must share a stream
+ *    (Sections 4.1 and 5).  Streaming operations return without waiting
+ *    (Section 4.1, Listing lst:synchronize: the caller synchronises before
+ *    touching results).  Reductions return their scalar through a HOST
+ *    pointer and then have synchronised the stream (Section 4.1: reductions
+ *    end with a transfer to the host), or, with flags &
+ *    BDFGPU_RESULT_DEVICE, write a DEVICE pointer asynchronously.
+ *  - Status.  0 success; > 0 recoverable (the caller may retry with a
+ *    smaller step: singular pivot, Newton or error-test failure); < 0
+ *    unrecoverable (codes below).  n == 0 is a no-op returning 0 (norms
+ *    return 0).  bdfgpu_last_error() describes the last failure.
+ *  - Concurrency.  Calls that use the library's internal reduction
+ *    scratch (the nvec reductions) must not run concurrently on two streams
+ *    of the same device.
+ */
+#ifndef BDFGPU_H
+#define BDFGPU_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BDFGPU_SUCCESS 0
+#define BDFGPU_RECOVERABLE 1
+#define BDFGPU_ERR_ARG (-1)       /* bad argument */
+#define BDFGPU_ERR_HIP (-2)       /* HIP runtime error */
+#define BDFGPU_ERR_CONV (-4)      /* too many Newton failures in one step */
+#define BDFGPU_ERR_TEST (-5)      /* too many error-test failures in one step */
+#define BDFGPU_ERR_HMIN (-6)      /* step size fell below hmin */
+#define BDFGPU_ERR_MAXSTEPS (-7)  /* max_steps reached before t_end */
+
+#define BDFGPU_RESULT_DEVICE 1
+
+/* Text of the last error recorded by any call on this thread's process. */
+const char* bdfgpu_last_error(void);
+/* Library version string. */
+const char* bdfgpu_version(void);
+
+/* ========================================================================
+ * N_Vector operations (Section 2: streaming operations and reductions;
+ * Section 4.1: reductions run fully on the GPU and end with one scalar
+ * transfer; streaming operations are asynchronous).  The fused operations
+ * below are defined by their plain formulas; arrays of coefficients and of
+ * vector pointers are HOST arrays of length nv, the vectors themselves are
+ * device arrays of length n.
+ * ======================================================================== */
+
+/* z = a x + b y.  z may alias x or y. */
+int nvec_linear_sum(long n, double a, const double* x, double b,
+                    const double* y, double* z, void* stream);
+/* z = sum_j c[j] X[j], 1 <= nv <= 16.  z may alias X[0]. */
+int nvec_linear_combination(int nv, const double* c, const double* const* X,
+                            double* z, long n, void* stream);
+/* Z[j] = a[j] x + Y[j], 1 <= nv <= 8.  Z[j] may alias Y[j]. */
+int nvec_scale_add_multi(int nv, const double* a, const double* x,
+                         const double* const* Y, double* const* Z, long n,
+                         void* stream);
+/* d[j] = sum_i x_i Y[j]_i, 1 <= nv <= 8.  d: host (sync) or device. */
+int nvec_dot_prod_multi(int nv, const double* x, const double* const* Y,
+                        double* d, long n, int flags, void* stream);
+/* out = sqrt(sum_i (x_i w_i)^2 / n).  out: host (sync) or device. */
+int nvec_wrms_norm(long n, const double* x, const double* w, double* out,
+                   int flags, void* stream);
+/* out = max_i |x_i|.  out: host (sync) or device. */
+int nvec_max_norm(long n, const double* x, double* out, int flags, void* stream);
+/* w_i = 1 / (rtol |y_i| + atol)  (error weights of the WRMS norm). */
+int nvec_ewt(long n, double rtol, double atol, const double* y, double* w,
+             void* stream);
+/* z = c x. */
+int nvec_scale(long n, double c, const double* x, double* z, void* stream);
+/* z = c. */
+int nvec_const(long n, double c, double* z, void* stream);
+
+/* ========================================================================
+ * Batched dense LU of block-diagonal matrices (Section 5: a direct solver
+ * for block-diagonal systems whose blocks share one pattern; here every
+ * block is dense, n <= 64).  getrf semantics: right-looking partial
+ * pivoting, first maximal pivot, whole-row exchanges, division by the
+ * pivot.  info[b] = k (1-based) if U(k,k) is exactly zero (first such k);
+ * factoring continues; a singular block is not an error of the call.
+ * ======================================================================== */
+
+/* In place: A (nb blocks, n x n column-major) becomes L\U. */
+int batched_lu_factor_f64(int nb, int n, double* A, int* piv, int* info,
+                          void* stream);
+/* In place: B (nb x n, block b at B + b*n) becomes the solution. */
+int batched_lu_solve_f64(int nb, int n, const double* LU, const int* piv,
+                         double* B, void* stream);
+int batched_lu_factor_f32(int nb, int n, float* A, int* piv, int* info,
+                          void* stream);
+int batched_lu_solve_f32(int nb, int n, const float* LU, const int* piv,
+                         float* B, void* stream);
+/* FP32 LU (LU32/piv32, from batched_lu_factor_f32 of M rounded to FP32)
+ * plus FP64 iterative refinement: x0 = FP32 solve of b; then corrections
+ * from the FP64 residual b - M x until |r|_inf <= sqrt(n) eps64 |M|_inf
+ * |x|_inf, at most max_it corrections; a block that does not converge, or
+ * whose corrections stop halving, is solved with FP64 LU of M instead.
+ * status[b] = 0 refined, 1 fell back to FP64, 2 FP64 fallback singular.
+ * sweeps[b] = corrections applied.  M, B unchanged; X receives x. */
+int batched_lu_solve_refine(int nb, int n, const double* M, const float* LU32,
+                            const int* piv32, const double* B, double* X,
+                            int max_it, int* sweeps, int* status,
+                            void* stream);
+
+/* ========================================================================
+ * Grouped BDF integrator over many independent mass-action systems.
+ *
+ * The systems ("cells") are grouped into one ODE with a block-diagonal
+ * Jacobian (Section 2) and advanced with one step size and order; every
+ * Newton iteration solves all cells' blocks at once and one failing cell
+ * makes the whole step retry with a smaller step (Section 7, task-local
+ * Newton and ensemble failure rule).  The method is a fixed-coefficient
+ * Nordsieck BDF of orders 1..qmax (the paper names CVODE for this role but
+ * does not state the method).  Integrator control lives on the device; the
+ * host only enqueues attempts and reads the status every few attempts.
+ *
+ * Kinetics: r_k = kappa_k prod_s y_s^nu_ks, f_s = sum_k (mu_ks - nu_ks) r_k;
+ * each reaction may have at most two reactant molecules.
+ * ======================================================================== */
+
+#define BDFGPU_LS_LU64 0     /* FP64 LU per block */
+#define BDFGPU_LS_LU32REF 1  /* FP32 LU + FP64 refinement, per-block fallback */
+
+#define BDFGPU_MODE_STREAM 0 /* kernels enqueued on the stream */
+#define BDFGPU_MODE_GRAPH 1  /* one attempt captured in a hipGraph */
+
+typedef struct {
+  int ntopo;              /* number of network topologies */
+  const int* topo_n;      /* host [ntopo]: species per topology (1..64) */
+  const int* topo_R;      /* host [ntopo]: reactions per topology */
+  const int* topo_off;    /* host [ntopo]: offset of topology t in nu/mu */
+  const int* nu_all;      /* host: R_t x n_t row-major reactant counts */
+  const int* mu_all;      /* host: R_t x n_t row-major product counts */
+  long ncells;
+  const int* cell_topo;   /* host [ncells]: topology of each cell */
+  const double* rates;    /* device: R_c rate constants per cell, concatenated */
+  const double* y0;       /* device: n_c initial values per cell, concatenated */
+  double t0;
+} bdf_problem;
+
+typedef struct {
+  double rtol, atol;      /* error weights 1/(rtol |y| + atol) */
+  int qmax;               /* 1..5 */
+  int maxcor;             /* Newton iterations per attempt (<= 4; 3 usual) */
+  double h0;              /* first step; 0 = Hairer-Norsett-Wanner estimate */
+  double hmin;
+  int linsol;             /* BDFGPU_LS_* */
+  int refine_max_it;      /* FP32 refinement corrections before FP64 */
+  long max_steps;         /* per integrate call; 0 = unlimited */
+  int mode;               /* BDFGPU_MODE_* */
+  int attempts_per_sync;  /* attempts enqueued between status reads (>= 1) */
+  int block;              /* threads per workgroup for per-cell kernels (0 = 256) */
+  int nonneg;             /* 1: each corrected solution is projected onto y >= 0
+                             before the error test (the constraint-mask
+                             operation of the N_Vector interface, Section 4.2);
+                             initial values must then be >= 0 */
+} bdf_options;
+
+typedef struct {
+  long nsteps, nattempts, nfevals, nsetups, nniters, nncfails, netfails;
+  long nlinsolves, refine_sweeps, refine_fallbacks, nprojections;
+  long hist_reads;        /* sum over attempts of q + 1 */
+  long order_hist[6];
+  double t, h, hu, err_last;
+  int q, qu, qwait, status;
+} bdf_stats;
+
+typedef struct bdf_handle bdf_handle;
+
+/* Copies the problem into library-owned device memory (internal layouts),
+ * computes the first step, and returns a handle.  `stream` is used by
+ * every later call on the handle. */
+int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream,
+               bdf_handle** out);
+int bdf_destroy(bdf_handle* h);
+/* One accepted internal step that does not pass t_end (the last step lands
+ * on t_end exactly).  *tret = t after the step (host). */
+int bdf_step(bdf_handle* h, double t_end, double* tret);
+/* Steps until t == t_end exactly.  *tret = t (host). */
+int bdf_integrate(bdf_handle* h, double t_end, double* tret);
+/* At most nsteps accepted steps towards t_end (stops early at t_end).
+ * *tret = t (host); *taken = steps accepted by this call. */
+int bdf_advance(bdf_handle* h, double t_end, long nsteps, double* tret, long* taken);
+/* Kernel timing with HIP events on the handle's stream (stream mode only):
+ * on != 0 starts (and resets) timing of the three kernel groups of an
+ * attempt: 0 predictor + first Newton iteration, 1 further Newton
+ * iterations, 2 history update.  ms[3] receives the summed durations in
+ * milliseconds, counts[3] the number of timed launches (host arrays). */
+int bdf_set_profiling(bdf_handle* h, int on);
+int bdf_get_kernel_times(bdf_handle* h, double* ms, long* counts);
+/* Current solution z[0], cell-major, into the device array y (length N). */
+int bdf_get_y(bdf_handle* h, double* y);
+/* Counters and scalars (host struct). */
+int bdf_get_stats(bdf_handle* h, bdf_stats* s);
+/* Total unknowns N and number of cells. */
+long bdf_get_N(bdf_handle* h);
+/* Integrator state for exact single-step comparisons: scalars (host
+ * arrays: dvals = {t, h}, ivals = {q, qwait}) and history z[0..5] plus the
+ * previous correction, each a device array of N values, cell-major. */
+int bdf_get_state(bdf_handle* h, double* dvals, int* ivals, double* z6,
+                  double* dprev);
+int bdf_set_state(bdf_handle* h, const double* dvals, const int* ivals,
+                  const double* z6, const double* dprev);
+/* Mass-action right-hand side f(y) and Jacobian of every cell of the
+ * handle's problem at the device state y (cell-major); J receives
+ * column-major blocks.  Either output may be NULL. */
+int bdf_eval_rhs_jac(bdf_handle* h, const double* y, double* f, double* J);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDFGPU_H */

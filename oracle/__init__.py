@@ -69,7 +69,7 @@ class OrcOptions(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("qmax", C.c_int),
                 ("maxcor", C.c_int), ("h0", C.c_double), ("linsol", C.c_int),
                 ("refine_max_it", C.c_int), ("max_steps", C.c_long),
-                ("hmin", C.c_double), ("mlp", C.POINTER(OrcMLP))]
+                ("hmin", C.c_double), ("mlp", C.POINTER(OrcMLP)), ("nonneg", C.c_int)]
 
 
 class OrcStats(C.Structure):
@@ -77,7 +77,7 @@ class OrcStats(C.Structure):
         "nsteps", "nattempts", "nfevals", "nsetups", "nniters", "nncfails",
         "netfails", "nlinsolves", "refine_sweeps", "refine_fallbacks",
         "lp_cell_solves", "lp_fallback_cells", "lp_step_fallbacks")] + [
-        ("order_hist", C.c_long * 6)]
+        ("order_hist", C.c_long * 6), ("nprojections", C.c_long)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "order_hist"}
@@ -418,7 +418,7 @@ class Bdf:
 
     def __init__(self, prob, rtol=None, atol=None, qmax=None, maxcor=3, h0=0.0,
                  linsol=LS_LU64, refine_max_it=5, max_steps=0, hmin=0.0,
-                 mlp: MLP | None = None):
+                 mlp: MLP | None = None, nonneg=None):
         self._keep = []
         topo_n = np.array([nu.shape[1] for nu, _ in prob.topologies], np.int32)
         topo_R = np.array([nu.shape[0] for nu, _ in prob.topologies], np.int32)
@@ -440,7 +440,8 @@ class Bdf:
                                prob.atol if atol is None else atol,
                                prob.qmax if qmax is None else qmax, maxcor, h0,
                                linsol, refine_max_it, max_steps, hmin,
-                               C.pointer(mlp.s) if mlp is not None else None)
+                               C.pointer(mlp.s) if mlp is not None else None,
+                               int(prob.get("nonneg", False) if nonneg is None else nonneg))
         self.h = lib().orc_bdf_create(C.byref(self.prob), C.byref(self.opts))
         self.N = lib().orc_bdf_N(self.h)
 

@@ -824,6 +824,7 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
       b->h = t_end - b->t;
       b->qwait = q + 1;
     }
+    if (b->h <= 4.0 * 2.220446049250313e-16 * fabs(b->t)) return -5;  /* t + h == t */
     int last = (b->t + b->h >= t_end);
     double l[QMAX_ALL + 1], tq;
     orc_bdf_coeffs(q, l, &tq);
@@ -851,6 +852,19 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
       b->qwait = q + 1;
       continue;
     }
+    if (b->o.nonneg) {
+      /* inequality constraints y >= 0 (the constraint-mask vector operation
+       * of the N_Vector interface): the corrected solution is projected onto
+       * the constraint before the error test; the projection enters the
+       * correction, so the whole history stays consistent with it */
+      int any = 0;
+      for (long i = 0; i < N; ++i)
+        if (b->y[i] < 0.0) {
+          b->y[i] = 0.0;
+          any = 1;
+        }
+      if (any) b->st.nprojections++;
+    }
     for (long i = 0; i < N; ++i) b->acor[i] = (b->y[i] - b->zp[0][i]) / l[0];
     double err = wrms(b, b->acor) * tq;
     b->err_last = err;
@@ -877,9 +891,11 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
       }
       continue;
     }
-    /* accept: z[j] = z(0)[j] + l_j * acor */
-    for (int j = 0; j <= q; ++j)
+    /* accept: z[j] = z(0)[j] + l_j * acor; for j = 0 that is the corrected
+     * solution y itself, which is stored as is */
+    for (int j = 1; j <= q; ++j)
       for (long i = 0; i < N; ++i) b->z[j][i] = b->zp[j][i] + l[j] * b->acor[i];
+    memcpy(b->z[0], b->y, sizeof(double) * (size_t)N);
     b->t = last ? t_end : b->t + b->h;
     b->hu = b->h;
     b->qu = q;

@@ -114,6 +114,7 @@ typedef struct {
   long max_steps;    /* per integrate call */
   double hmin;
   const orc_mlp* mlp;  /* learned mode */
+  int nonneg;        /* 1: corrected solutions projected onto y >= 0 */
 } orc_options;
 
 typedef struct {
@@ -121,6 +122,7 @@ typedef struct {
   long nlinsolves, refine_sweeps, refine_fallbacks;
   long lp_cell_solves, lp_fallback_cells, lp_step_fallbacks;
   long order_hist[6];
+  long nprojections;
 } orc_stats;
 
 typedef struct orc_bdf orc_bdf;

@@ -1,0 +1,320 @@
+"""Batched stiff-ODE BDF-Newton on AMD MI355X (gfx950).
+
+Python binding of the C ABI declared in include/bdfgpu.h.  Every function
+keeps the C name and only marshals arguments: torch tensors provide device
+memory and the current HIP stream.  Dense blocks are passed as contiguous
+tensors of shape (nb, n, n) holding column-major blocks, i.e. element (i, j)
+of block b is ``A[b, j, i]``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from ._lib import BdfGpuError, BdfOptions, BdfProblem, BdfStats, check, dp, ip, lib, vp
+
+__all__ = [
+    "nvec_linear_sum", "nvec_linear_combination", "nvec_scale_add_multi",
+    "nvec_dot_prod_multi", "nvec_wrms_norm", "nvec_max_norm", "nvec_ewt", "nvec_scale",
+    "nvec_const", "batched_lu_factor_f64", "batched_lu_solve_f64", "batched_lu_factor_f32",
+    "batched_lu_solve_f32", "batched_lu_solve_refine", "Bdf", "BdfGpuError", "lib",
+    "LS_LU64", "LS_LU32REF", "MODE_STREAM", "MODE_GRAPH", "RESULT_DEVICE",
+]
+
+LS_LU64, LS_LU32REF = 0, 1
+MODE_STREAM, MODE_GRAPH = 0, 1
+RESULT_DEVICE = 1
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype):
+    torch = _torch()
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} device tensor")
+    return t
+
+
+def _ptr_array(ts):
+    arr = (vp * len(ts))()
+    for j, t in enumerate(ts):
+        arr[j] = t.data_ptr()
+    return arr
+
+
+def _dbl_array(vals):
+    vals = [float(v) for v in vals]
+    return (C.c_double * len(vals))(*vals)
+
+
+# ---------------------------------------------------------------------------
+# vector operations
+# ---------------------------------------------------------------------------
+
+def nvec_linear_sum(a, x, b, y, z):
+    torch = _torch()
+    for t in (x, y, z):
+        _dev(t, torch.float64)
+    check("nvec_linear_sum", lib().nvec_linear_sum(x.numel(), a, _p(x), b, _p(y), _p(z), _stream()))
+    return z
+
+
+def nvec_linear_combination(c, X, z):
+    torch = _torch()
+    for t in list(X) + [z]:
+        _dev(t, torch.float64)
+    cc = _dbl_array(c)
+    check("nvec_linear_combination",
+          lib().nvec_linear_combination(len(X), C.cast(cc, dp), _ptr_array(X), _p(z), z.numel(),
+                                        _stream()))
+    return z
+
+
+def nvec_scale_add_multi(a, x, Y, Z):
+    torch = _torch()
+    for t in [x] + list(Y) + list(Z):
+        _dev(t, torch.float64)
+    aa = _dbl_array(a)
+    check("nvec_scale_add_multi",
+          lib().nvec_scale_add_multi(len(Y), C.cast(aa, dp), _p(x), _ptr_array(Y), _ptr_array(Z),
+                                     x.numel(), _stream()))
+    return Z
+
+
+def nvec_dot_prod_multi(x, Y, out=None):
+    """Host list of dots (synchronising), or into device tensor `out`."""
+    torch = _torch()
+    for t in [x] + list(Y):
+        _dev(t, torch.float64)
+    if out is None:
+        d = (C.c_double * len(Y))()
+        check("nvec_dot_prod_multi",
+              lib().nvec_dot_prod_multi(len(Y), _p(x), _ptr_array(Y), C.cast(d, vp), x.numel(), 0,
+                                        _stream()))
+        return list(d)
+    check("nvec_dot_prod_multi",
+          lib().nvec_dot_prod_multi(len(Y), _p(x), _ptr_array(Y), _p(out), x.numel(), RESULT_DEVICE,
+                                    _stream()))
+    return out
+
+
+def nvec_wrms_norm(x, w, out=None):
+    torch = _torch()
+    _dev(x, torch.float64)
+    _dev(w, torch.float64)
+    if out is None:
+        r = C.c_double(0.0)
+        check("nvec_wrms_norm", lib().nvec_wrms_norm(x.numel(), _p(x), _p(w), C.cast(C.pointer(r), vp),
+                                                     0, _stream()))
+        return r.value
+    check("nvec_wrms_norm", lib().nvec_wrms_norm(x.numel(), _p(x), _p(w), _p(out), RESULT_DEVICE,
+                                                 _stream()))
+    return out
+
+
+def nvec_max_norm(x, out=None):
+    torch = _torch()
+    _dev(x, torch.float64)
+    if out is None:
+        r = C.c_double(0.0)
+        check("nvec_max_norm", lib().nvec_max_norm(x.numel(), _p(x), C.cast(C.pointer(r), vp), 0,
+                                                   _stream()))
+        return r.value
+    check("nvec_max_norm", lib().nvec_max_norm(x.numel(), _p(x), _p(out), RESULT_DEVICE, _stream()))
+    return out
+
+
+def nvec_ewt(y, rtol, atol, w):
+    check("nvec_ewt", lib().nvec_ewt(y.numel(), rtol, atol, _p(y), _p(w), _stream()))
+    return w
+
+
+def nvec_scale(c, x, z):
+    check("nvec_scale", lib().nvec_scale(x.numel(), c, _p(x), _p(z), _stream()))
+    return z
+
+
+def nvec_const(c, z):
+    check("nvec_const", lib().nvec_const(z.numel(), c, _p(z), _stream()))
+    return z
+
+
+# ---------------------------------------------------------------------------
+# batched LU
+# ---------------------------------------------------------------------------
+
+def _blocks(A, dtype):
+    torch = _torch()
+    _dev(A, dtype)
+    if A.dim() != 3 or A.shape[1] != A.shape[2]:
+        raise ValueError("expected (nb, n, n) blocks")
+    return A.shape[0], A.shape[1]
+
+
+def batched_lu_factor_f64(A, piv, info):
+    nb, n = _blocks(A, _torch().float64)
+    check("batched_lu_factor_f64",
+          lib().batched_lu_factor_f64(nb, n, _p(A), _p(piv), _p(info), _stream()))
+    return A, piv, info
+
+
+def batched_lu_solve_f64(LU, piv, B):
+    nb, n = _blocks(LU, _torch().float64)
+    check("batched_lu_solve_f64", lib().batched_lu_solve_f64(nb, n, _p(LU), _p(piv), _p(B), _stream()))
+    return B
+
+
+def batched_lu_factor_f32(A, piv, info):
+    nb, n = _blocks(A, _torch().float32)
+    check("batched_lu_factor_f32",
+          lib().batched_lu_factor_f32(nb, n, _p(A), _p(piv), _p(info), _stream()))
+    return A, piv, info
+
+
+def batched_lu_solve_f32(LU, piv, B):
+    nb, n = _blocks(LU, _torch().float32)
+    check("batched_lu_solve_f32", lib().batched_lu_solve_f32(nb, n, _p(LU), _p(piv), _p(B), _stream()))
+    return B
+
+
+def batched_lu_solve_refine(M, LU32, piv32, B, X, max_it, sweeps, status):
+    nb, n = _blocks(M, _torch().float64)
+    check("batched_lu_solve_refine",
+          lib().batched_lu_solve_refine(nb, n, _p(M), _p(LU32), _p(piv32), _p(B), _p(X), max_it,
+                                        _p(sweeps), _p(status), _stream()))
+    return X
+
+
+# ---------------------------------------------------------------------------
+# BDF integrator
+# ---------------------------------------------------------------------------
+
+class Bdf:
+    """Handle on a grouped BDF integrator (bdf_create ... bdf_destroy).
+
+    topologies: list of (nu, mu) integer arrays of shape (R, n);
+    cell_topo: int array (ncells,); rates, y0: float64 device tensors
+    (concatenated per cell)."""
+
+    def __init__(self, topologies, cell_topo, rates, y0, t0=0.0, rtol=1e-6, atol=1e-10,
+                 qmax=5, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64, refine_max_it=5,
+                 max_steps=0, mode=MODE_STREAM, attempts_per_sync=8, nonneg=False):
+        torch = _torch()
+        _dev(rates, torch.float64)
+        _dev(y0, torch.float64)
+        self._keep = []
+        topo_n = np.array([nu.shape[1] for nu, _ in topologies], np.int32)
+        topo_R = np.array([nu.shape[0] for nu, _ in topologies], np.int32)
+        off = np.concatenate([[0], np.cumsum(topo_n * topo_R)[:-1]]).astype(np.int32)
+        nu_all = np.concatenate([np.ascontiguousarray(nu, np.int32).ravel() for nu, _ in topologies]).astype(np.int32)
+        mu_all = np.concatenate([np.ascontiguousarray(mu, np.int32).ravel() for _, mu in topologies]).astype(np.int32)
+        ct = np.ascontiguousarray(cell_topo, np.int32)
+        self._keep += [topo_n, topo_R, off, nu_all, mu_all, ct, rates, y0]
+        ipt = lambda a: a.ctypes.data_as(ip)
+        prob = BdfProblem(len(topo_n), ipt(topo_n), ipt(topo_R), ipt(off), ipt(nu_all),
+                          ipt(mu_all), len(ct), ipt(ct), _p(rates), _p(y0), float(t0))
+        opts = BdfOptions(rtol, atol, qmax, maxcor, h0, hmin, linsol, refine_max_it, max_steps,
+                          mode, attempts_per_sync, 0, int(bool(nonneg)))
+        h = vp()
+        check("bdf_create", lib().bdf_create(C.byref(prob), C.byref(opts), _stream(), C.byref(h)))
+        self.h = h
+        self.N = lib().bdf_get_N(h)
+        self.device = y0.device
+
+    @classmethod
+    def from_problem(cls, prob, device="cuda", **kw):
+        torch = _torch()
+        rates = torch.tensor(np.asarray(prob["rates"], np.float64), device=device)
+        y0 = torch.tensor(np.asarray(prob["y0"], np.float64), device=device)
+        kw.setdefault("rtol", prob["rtol"])
+        kw.setdefault("atol", prob["atol"])
+        kw.setdefault("qmax", prob["qmax"])
+        kw.setdefault("nonneg", bool(prob.get("nonneg", False)))
+        return cls(prob["topologies"], prob["cell_topo"], rates, y0, t0=prob["t0"], **kw)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().bdf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, t_end):
+        t = C.c_double(0.0)
+        check("bdf_step", lib().bdf_step(self.h, t_end, C.byref(t)))
+        return t.value
+
+    def integrate(self, t_end):
+        t = C.c_double(0.0)
+        code = lib().bdf_integrate(self.h, t_end, C.byref(t))
+        check("bdf_integrate", code)
+        return t.value
+
+    def advance(self, t_end, nsteps):
+        """At most nsteps accepted steps towards t_end; returns (t, taken)."""
+        t = C.c_double(0.0)
+        taken = C.c_long(0)
+        check("bdf_advance", lib().bdf_advance(self.h, t_end, nsteps, C.byref(t), C.byref(taken)))
+        return t.value, taken.value
+
+    def set_profiling(self, on=True):
+        check("bdf_set_profiling", lib().bdf_set_profiling(self.h, 1 if on else 0))
+
+    def kernel_times(self):
+        """{group: (total_ms, launches)} for predictor, newton, accept."""
+        ms = (C.c_double * 3)()
+        cnt = (C.c_long * 3)()
+        check("bdf_get_kernel_times", lib().bdf_get_kernel_times(self.h, C.cast(ms, dp),
+                                                                 C.cast(cnt, C.POINTER(C.c_long))))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(("predict", "newton", "accept"))}
+
+    def y(self):
+        torch = _torch()
+        y = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        check("bdf_get_y", lib().bdf_get_y(self.h, _p(y)))
+        torch.cuda.current_stream().synchronize()
+        return y
+
+    def stats(self):
+        s = BdfStats()
+        check("bdf_get_stats", lib().bdf_get_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def get_state(self):
+        torch = _torch()
+        dv = (C.c_double * 2)()
+        iv = (C.c_int * 2)()
+        z6 = torch.empty(6 * self.N, dtype=torch.float64, device=self.device)
+        dpv = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        check("bdf_get_state", lib().bdf_get_state(self.h, C.cast(dv, dp), C.cast(iv, ip), _p(z6), _p(dpv)))
+        return dict(t=dv[0], h=dv[1], q=iv[0], qwait=iv[1], z=z6.view(6, self.N), dprev=dpv)
+
+    def set_state(self, t, h, q, qwait, z6, dprev):
+        dv = (C.c_double * 2)(t, h)
+        iv = (C.c_int * 2)(q, qwait)
+        z6 = z6.contiguous().view(-1)
+        check("bdf_set_state", lib().bdf_set_state(self.h, C.cast(dv, dp), C.cast(iv, ip), _p(z6),
+                                                   _p(dprev.contiguous())))
+
+    def eval_rhs_jac(self, y, jac_entries):
+        torch = _torch()
+        f = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        J = torch.empty(jac_entries, dtype=torch.float64, device=self.device)
+        check("bdf_eval_rhs_jac", lib().bdf_eval_rhs_jac(self.h, _p(y.contiguous()), _p(f), _p(J)))
+        return f, J

@@ -1,0 +1,698 @@
+// Host side of the grouped BDF integrator: problem setup, internal layouts,
+// attempt sequencing and hipGraph capture.
+//
+// Cells are grouped by network topology into classes; every class gets its
+// own storage in the layout of its cell-to-lane mapping (tiled for thread
+// per cell, cell-major for segment per cell).  One step attempt is the fixed
+// launch sequence predictor, Newton 1..maxcor-1, accept over all classes;
+// kernels whose phase is not current return at once, so the same sequence
+// serves every outcome and can be captured once into a hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "bdf_dev.hpp"
+#include "common.hpp"
+
+namespace bdfgpu {
+
+int tpc_padded(int n);
+int spc_seg(int n);
+void launch_tpc(int np, int ls, int which, const BdfDev& D, int mslot, unsigned int grid,
+                hipStream_t s);
+void launch_spc(int seg, int ls, int which, const BdfDev& D, int mslot, unsigned int grid,
+                hipStream_t s);
+
+enum { MAP_TPC = 0, MAP_SPC = 1 };
+
+struct ClassHost {
+  int topo, n, R, map, np;      // np: TPC padded size or SPC segment
+  long ncells;
+  unsigned int grid;
+  long blk0;
+  long* d_yoff = nullptr;       // user-layout offset of each class cell's y
+  long* d_roff = nullptr;       // user-layout offset of each class cell's rates
+  ClassDev dev;
+};
+
+__global__ void k_resume(Ctrl* C, double tend, long inc) {
+  C->tend = tend;
+  const long lim = C->nsteps + inc;
+  C->step_limit = lim < C->nsteps ? LONG_MAX : lim;
+  if (C->phase == PH_PAUSE || C->phase == PH_DONE) {
+    if (C->t < tend)
+      prepare_attempt(C);
+    else
+      C->phase = PH_DONE;
+  }
+}
+
+// user layout <-> class layout.  tiled: element i of class cell c at
+// (c/64)*64*w + i*64 + c%64, else c*w + i.
+__global__ void k_to_class(long ncells, int w, int tiled, const long* off, const double* src,
+                           double* dst, double scale) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncells * w) return;
+  const long c = t / w;
+  const int i = (int)(t - c * w);
+  const long d = tiled ? (c >> 6) * 64L * w + (long)i * 64 + (c & 63) : c * w + i;
+  dst[d] = src[off[c] + i] * scale;
+}
+
+__global__ void k_from_class(long ncells, int w, int tiled, const long* off, const double* src,
+                             double* dst, double scale) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncells * w) return;
+  const long c = t / w;
+  const int i = (int)(t - c * w);
+  const long d = tiled ? (c >> 6) * 64L * w + (long)i * 64 + (c & 63) : c * w + i;
+  dst[off[c] + i] = src[d] * scale;
+}
+
+// f and J of every class cell at a user-layout state (test and inspection
+// path, one thread per cell, plain loops).
+__global__ void k_eval_rhs_jac(long ncells, NetDev nd, const long* yoff, const long* roff,
+                               const long* joff, const double* rates, const double* y,
+                               double* f, double* J) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  const double* yc = y + yoff[c];
+  const double* kc = rates + roff[c];
+  const int n = nd.n;
+  if (f)
+    for (int i = 0; i < n; ++i) f[yoff[c] + i] = 0.0;
+  if (J)
+    for (int i = 0; i < n * n; ++i) J[joff[c] + i] = 0.0;
+  for (int k = 0; k < nd.R; ++k) {
+    const int a = nd.ra[k], b = nd.rb[k];
+    double r = kc[k];
+    if (a >= 0) r *= yc[a];
+    if (b >= 0) r *= yc[b];
+    if (f)
+      for (int i = 0; i < n; ++i) f[yoff[c] + i] += nd.S[(long)k * nd.np + i] * r;
+  }
+  if (J)
+    for (int a = 0; a < n; ++a)
+      for (int e = nd.jst[a]; e < nd.jst[a + 1]; ++e) {
+        const int k = nd.jk[e], p = nd.jp[e];
+        double g = kc[k] * nd.jm[e];
+        if (p >= 0) g *= yc[p];
+        for (int i = 0; i < n; ++i) J[joff[c] + i + (long)a * n] += nd.S[(long)k * nd.np + i] * g;
+      }
+}
+
+}  // namespace bdfgpu
+
+using namespace bdfgpu;
+
+struct bdf_handle {
+  hipStream_t s = nullptr;
+  hipStream_t cap = nullptr;     // capture stream for graph mode
+  bdf_options o;
+  long N = 0, ncells = 0;
+  std::vector<ClassHost> cls;
+  Ctrl* dC = nullptr;
+  Ctrl* hC = nullptr;            // pinned mirror
+  double* partials = nullptr;
+  unsigned int* counter = nullptr;
+  unsigned int nblocks_total = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<void*> allocs;
+  std::vector<long> h_joff;      // per class: user offsets of J blocks (for eval)
+  std::vector<long*> d_joff;
+  // kernel timing (stream mode): event pairs around each kernel group
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_key;       // group of each pending pair
+  size_t ev_used = 0;            // pairs recorded since the last fold
+  double prof_ms[3] = {0, 0, 0};
+  long prof_cnt[3] = {0, 0, 0};
+};
+
+static int dalloc(bdf_handle* h, void** p, size_t bytes) {
+  BDF_HIP_TRY(hipMalloc(p, bytes < 16 ? 16 : bytes));
+  h->allocs.push_back(*p);
+  return 0;
+}
+
+template <typename T>
+static int upload(bdf_handle* h, T** d, const std::vector<T>& v) {
+  int st = dalloc(h, reinterpret_cast<void**>(d), sizeof(T) * std::max<size_t>(1, v.size()));
+  if (st) return st;
+  if (!v.empty()) BDF_HIP_TRY(hipMemcpy(*d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  return 0;
+}
+
+static BdfDev make_dev(bdf_handle* h, const ClassHost& c) {
+  BdfDev D;
+  D.C = h->dC;
+  D.partials = h->partials;
+  D.counter = h->counter;
+  D.nblocks_total = h->nblocks_total;
+  D.rtol = h->o.rtol;
+  D.atol = h->o.atol;
+  D.nonneg = h->o.nonneg ? 1 : 0;
+  D.k = c.dev;
+  D.k.blk0 = c.blk0;
+  return D;
+}
+
+static void launch_phase(bdf_handle* h, int which, int mslot, hipStream_t s) {
+  for (const ClassHost& c : h->cls) {
+    const BdfDev D = make_dev(h, c);
+    if (c.map == MAP_TPC)
+      launch_tpc(c.np, h->o.linsol, which, D, mslot, c.grid, s);
+    else
+      launch_spc(c.np, h->o.linsol, which, D, mslot, c.grid, s);
+  }
+}
+
+static void prof_mark(bdf_handle* h, int key, bool begin, hipStream_t s) {
+  if (!h->prof) return;
+  if (begin) {
+    if (2 * (h->ev_used + 1) > h->ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+      h->ev.push_back(a);
+      h->ev.push_back(b);
+      h->ev_key.push_back(key);
+    }
+    h->ev_key[h->ev_used] = key;
+    (void)hipEventRecord(h->ev[2 * h->ev_used], s);
+  } else {
+    (void)hipEventRecord(h->ev[2 * h->ev_used + 1], s);
+    h->ev_used++;
+  }
+}
+
+// after a stream synchronisation: add up the recorded pairs
+static void prof_fold(bdf_handle* h) {
+  for (size_t i = 0; i < h->ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) == hipSuccess) {
+      h->prof_ms[h->ev_key[i]] += ms;
+      h->prof_cnt[h->ev_key[i]]++;
+    }
+  }
+  h->ev_used = 0;
+}
+
+static void enqueue_attempt(bdf_handle* h, hipStream_t s) {
+  prof_mark(h, 0, true, s);
+  launch_phase(h, 2, 0, s);
+  prof_mark(h, 0, false, s);
+  for (int m = 1; m < h->o.maxcor; ++m) {
+    prof_mark(h, 1, true, s);
+    launch_phase(h, 2, m, s);
+    prof_mark(h, 1, false, s);
+  }
+  prof_mark(h, 2, true, s);
+  launch_phase(h, 3, 0, s);
+  prof_mark(h, 2, false, s);
+}
+
+static int read_ctrl(bdf_handle* h) {
+  BDF_HIP_TRY(hipMemcpyAsync(h->hC, h->dC, sizeof(Ctrl), hipMemcpyDeviceToHost, h->s));
+  BDF_HIP_TRY(hipStreamSynchronize(h->s));
+  return 0;
+}
+
+static int build_graph(bdf_handle* h) {
+  BDF_HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  BDF_HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
+  enqueue_attempt(h, h->cap);
+  BDF_HIP_TRY(hipStreamEndCapture(h->cap, &h->graph));
+  BDF_HIP_TRY(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+  return 0;
+}
+
+// Run attempts until the controller leaves the active phases.
+static int drive(bdf_handle* h, double tend, long inc, double* tret) {
+  hipLaunchKernelGGL(k_resume, dim3(1), dim3(1), 0, h->s, h->dC, tend, inc);
+  BDF_HIP_TRY(hipGetLastError());
+  launch_phase(h, 0, 0, h->s);   // starting-step estimate (no-ops once done)
+  launch_phase(h, 1, 0, h->s);
+  BDF_HIP_TRY(hipGetLastError());
+  const int per = std::max(1, h->o.attempts_per_sync);
+  long last_progress = -1;
+  for (;;) {
+    for (int a = 0; a < per; ++a) {
+      if (h->gexec) {
+        BDF_HIP_TRY(hipGraphLaunch(h->gexec, h->s));
+      } else {
+        enqueue_attempt(h, h->s);
+      }
+    }
+    BDF_HIP_TRY(hipGetLastError());
+    int st = read_ctrl(h);
+    if (st) return st;
+    prof_fold(h);
+    const int ph = h->hC->phase;
+    if (ph == PH_ERROR) {
+      if (tret) *tret = h->hC->t;
+      set_last_error("integrator failure (see status code)", __FILE__, __LINE__);
+      return h->hC->status;
+    }
+    if (ph == PH_DONE || ph == PH_PAUSE) break;
+    const long progress = h->hC->nattempts + h->hC->nsteps;
+    if (progress == last_progress) {
+      set_last_error("integrator made no progress (phase stuck)", __FILE__, __LINE__);
+      return BDFGPU_ERR_HIP;
+    }
+    last_progress = progress;
+  }
+  if (tret) *tret = h->hC->t;
+  return 0;
+}
+
+extern "C" {
+
+int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_handle** out) {
+  if (!p || !o || !out) return arg_error("bdf_create: null argument");
+  if (p->ncells < 0 || p->ntopo < 1 || !p->topo_n || !p->topo_R || !p->topo_off ||
+      !p->nu_all || !p->mu_all || (p->ncells > 0 && (!p->cell_topo || !p->rates || !p->y0)))
+    return arg_error("bdf_create: bad problem description");
+  if (o->qmax < 1 || o->qmax > kQmaxAll || o->maxcor < 1 || o->maxcor > 4 ||
+      !(o->rtol >= 0.0) || !(o->atol > 0.0) ||
+      (o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_LU32REF))
+    return arg_error("bdf_create: bad options (qmax 1..5, maxcor 1..4, atol > 0, linsol)");
+  *out = nullptr;
+  bdf_handle* h = new bdf_handle();
+  h->s = as_stream(stream);
+  h->o = *o;
+  if (h->o.refine_max_it <= 0) h->o.refine_max_it = 5;
+  h->ncells = p->ncells;
+  // per-cell user offsets
+  std::vector<long> yoff(p->ncells + 1, 0), roff(p->ncells + 1, 0);
+  for (long c = 0; c < p->ncells; ++c) {
+    const int t = p->cell_topo[c];
+    if (t < 0 || t >= p->ntopo) {
+      delete h;
+      return arg_error("bdf_create: cell_topo out of range");
+    }
+    yoff[c + 1] = yoff[c] + p->topo_n[t];
+    roff[c + 1] = roff[c] + p->topo_R[t];
+  }
+  h->N = yoff[p->ncells];
+  // classes: one per topology that has cells
+  std::map<int, std::vector<long>> members;
+  for (long c = 0; c < p->ncells; ++c) members[p->cell_topo[c]].push_back(c);
+  long blk = 0;
+  int st = 0;
+  for (auto& kv : members) {
+    const int t = kv.first;
+    const int n = p->topo_n[t], R = p->topo_R[t];
+    if (n < 1 || n > 64 || R < 0) {
+      bdf_destroy(h);
+      return arg_error("bdf_create: species per cell must be 1..64");
+    }
+    const int* nu = p->nu_all + p->topo_off[t];
+    const int* mu = p->mu_all + p->topo_off[t];
+    ClassHost ch;
+    ch.topo = t;
+    ch.n = n;
+    ch.R = R;
+    ch.ncells = (long)kv.second.size();
+    ch.map = n <= 12 ? MAP_TPC : MAP_SPC;
+    ch.np = ch.map == MAP_TPC ? tpc_padded(n) : spc_seg(n);
+    const int cpb = ch.map == MAP_TPC ? kCellThreads : kCellThreads / ch.np;
+    ch.grid = (unsigned int)std::max<long>(1, (ch.ncells + cpb - 1) / cpb);
+    ch.blk0 = blk;
+    blk += ch.grid;
+    // network tables
+    const int np = ch.np;
+    std::vector<double> S((size_t)R * np, 0.0);
+    std::vector<int> ra(R, -1), rb(R, -1);
+    std::vector<std::vector<std::pair<int, std::pair<int, double>>>> cols(np);
+    for (int k = 0; k < R; ++k) {
+      int order = 0;
+      std::vector<int> reac;
+      for (int s2 = 0; s2 < n; ++s2) {
+        const int e = nu[k * n + s2];
+        if (e < 0 || mu[k * n + s2] < 0) {
+          bdf_destroy(h);
+          return arg_error("bdf_create: negative stoichiometry");
+        }
+        for (int r = 0; r < e; ++r) reac.push_back(s2);
+        order += e;
+        S[(size_t)k * np + s2] = (double)(mu[k * n + s2] - nu[k * n + s2]);
+      }
+      if (order > 2) {
+        bdf_destroy(h);
+        return arg_error("bdf_create: reactions may have at most two reactant molecules");
+      }
+      if (order >= 1) ra[k] = reac[0];
+      if (order == 2) rb[k] = reac[1];
+      if (order == 1) cols[reac[0]].push_back({k, {-1, 1.0}});
+      if (order == 2) {
+        if (reac[0] == reac[1]) {
+          cols[reac[0]].push_back({k, {reac[0], 2.0}});
+        } else {
+          cols[reac[0]].push_back({k, {reac[1], 1.0}});
+          cols[reac[1]].push_back({k, {reac[0], 1.0}});
+        }
+      }
+    }
+    std::vector<int> jst(np + 1, 0), jk, jp;
+    std::vector<double> jm;
+    for (int a = 0; a < np; ++a) {
+      jst[a] = (int)jk.size();
+      for (auto& e : cols[a]) {
+        jk.push_back(e.first);
+        jp.push_back(e.second.first);
+        jm.push_back(e.second.second);
+      }
+    }
+    jst[np] = (int)jk.size();
+    NetDev nd;
+    nd.n = n;
+    nd.R = R;
+    nd.np = np;
+    if ((st = upload(h, const_cast<double**>(&nd.S), S)) || (st = upload(h, const_cast<int**>(&nd.ra), ra)) ||
+        (st = upload(h, const_cast<int**>(&nd.rb), rb)) || (st = upload(h, const_cast<int**>(&nd.jst), jst)) ||
+        (st = upload(h, const_cast<int**>(&nd.jk), jk)) || (st = upload(h, const_cast<int**>(&nd.jp), jp)) ||
+        (st = upload(h, const_cast<double**>(&nd.jm), jm))) {
+      bdf_destroy(h);
+      return st;
+    }
+    // vectors
+    const bool tiled = ch.map == MAP_TPC;
+    const long cap_cells = tiled ? ((ch.ncells + 63) / 64) * 64 : ch.ncells;
+    const size_t vbytes = sizeof(double) * (size_t)std::max<long>(1, cap_cells * n);
+    ClassDev& K = ch.dev;
+    memset(&K, 0, sizeof(K));
+    K.ncells = ch.ncells;
+    K.n = n;
+    K.R = R;
+    K.net = nd;
+    K.refine_max_it = h->o.refine_max_it;
+    for (int j = 0; j <= kQmaxAll; ++j) {
+      if ((st = dalloc(h, (void**)&K.z[j], vbytes))) { bdf_destroy(h); return st; }
+      BDF_HIP_TRY(hipMemset(K.z[j], 0, vbytes));
+    }
+    if ((st = dalloc(h, (void**)&K.dprev, vbytes)) || (st = dalloc(h, (void**)&K.zp0, vbytes)) ||
+        (st = dalloc(h, (void**)&K.cv, vbytes)) || (st = dalloc(h, (void**)&K.y, vbytes))) {
+      bdf_destroy(h);
+      return st;
+    }
+    BDF_HIP_TRY(hipMemset(K.dprev, 0, vbytes));
+    double* rates = nullptr;
+    if ((st = dalloc(h, (void**)&rates, sizeof(double) * (size_t)std::max<long>(1, cap_cells * R)))) {
+      bdf_destroy(h);
+      return st;
+    }
+    BDF_HIP_TRY(hipMemset(rates, 0, sizeof(double) * (size_t)std::max<long>(1, cap_cells * R)));
+    K.rates = rates;
+    std::vector<long> cy(ch.ncells), cr(ch.ncells);
+    for (long i = 0; i < ch.ncells; ++i) {
+      cy[i] = yoff[kv.second[i]];
+      cr[i] = roff[kv.second[i]];
+    }
+    if ((st = upload(h, &ch.d_yoff, cy)) || (st = upload(h, &ch.d_roff, cr))) {
+      bdf_destroy(h);
+      return st;
+    }
+    if (ch.ncells > 0) {
+      const unsigned int gy = ceil_div(ch.ncells * n, 256), gr = ceil_div(ch.ncells * (long)R, 256);
+      hipLaunchKernelGGL(k_to_class, dim3(gy), dim3(256), 0, h->s, ch.ncells, n, (int)tiled,
+                         ch.d_yoff, p->y0, K.z[0], 1.0);
+      if (R > 0)
+        hipLaunchKernelGGL(k_to_class, dim3(gr), dim3(256), 0, h->s, ch.ncells, R, (int)tiled,
+                           ch.d_roff, p->rates, rates, 1.0);
+      BDF_HIP_TRY(hipGetLastError());
+    }
+    h->cls.push_back(ch);
+  }
+  h->nblocks_total = (unsigned int)blk;
+  if ((st = dalloc(h, (void**)&h->partials, sizeof(double) * kRedVals * std::max<long>(1, blk))) ||
+      (st = dalloc(h, (void**)&h->counter, 256)) || (st = dalloc(h, (void**)&h->dC, sizeof(Ctrl)))) {
+    bdf_destroy(h);
+    return st;
+  }
+  BDF_HIP_TRY(hipMemset(h->counter, 0, 256));
+  BDF_HIP_TRY(hipHostMalloc((void**)&h->hC, sizeof(Ctrl), hipHostMallocDefault));
+  Ctrl C;
+  memset(&C, 0, sizeof(C));
+  C.t = p->t0;
+  C.tend = p->t0;
+  C.hmin = o->hmin;
+  C.h0user = o->h0;
+  for (int j = 0; j < kQmaxAll + 2; ++j) C.hs[j] = 1.0;
+  C.N = (double)h->N;
+  C.q = 1;
+  C.qmax = o->qmax;
+  C.qwait = 2;
+  C.maxcor = o->maxcor;
+  C.phase = h->N > 0 ? PH_INIT1 : PH_DONE;
+  C.step_limit = LONG_MAX;
+  BDF_HIP_TRY(hipMemcpyAsync(h->dC, &C, sizeof(Ctrl), hipMemcpyHostToDevice, h->s));
+  BDF_HIP_TRY(hipStreamSynchronize(h->s));
+  if (o->mode == BDFGPU_MODE_GRAPH && h->N > 0) {
+    st = build_graph(h);
+    if (st) {
+      bdf_destroy(h);
+      return st;
+    }
+  }
+  *out = h;
+  return 0;
+}
+
+int bdf_destroy(bdf_handle* h) {
+  if (!h) return 0;
+  if (h->s) (void)hipStreamSynchronize(h->s);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->hC) (void)hipHostFree(h->hC);
+  delete h;
+  return 0;
+}
+
+long bdf_get_N(bdf_handle* h) { return h ? h->N : -1; }
+
+int bdf_step(bdf_handle* h, double t_end, double* tret) {
+  if (!h) return arg_error("bdf_step: null handle");
+  if (h->N == 0) {
+    if (tret) *tret = t_end;
+    return 0;
+  }
+  return drive(h, t_end, 1, tret);
+}
+
+int bdf_advance(bdf_handle* h, double t_end, long nsteps, double* tret, long* taken) {
+  if (!h || nsteps < 0) return arg_error("bdf_advance: bad argument");
+  if (taken) *taken = 0;
+  if (h->N == 0 || nsteps == 0) {
+    if (tret) *tret = h->N == 0 ? t_end : h->hC->t;
+    return 0;
+  }
+  int st = read_ctrl(h);
+  if (st) return st;
+  const long before = h->hC->nsteps;
+  st = drive(h, t_end, nsteps, tret);
+  if (taken) *taken = h->hC->nsteps - before;
+  return st;
+}
+
+int bdf_set_profiling(bdf_handle* h, int on) {
+  if (!h) return arg_error("bdf_set_profiling: null handle");
+  if (on && h->gexec) return arg_error("bdf_set_profiling: not available in graph mode");
+  h->prof = on != 0;
+  h->ev_used = 0;
+  for (int k = 0; k < 3; ++k) {
+    h->prof_ms[k] = 0.0;
+    h->prof_cnt[k] = 0;
+  }
+  return 0;
+}
+
+int bdf_get_kernel_times(bdf_handle* h, double* ms, long* counts) {
+  if (!h || !ms || !counts) return arg_error("bdf_get_kernel_times: bad argument");
+  for (int k = 0; k < 3; ++k) {
+    ms[k] = h->prof_ms[k];
+    counts[k] = h->prof_cnt[k];
+  }
+  return 0;
+}
+
+int bdf_integrate(bdf_handle* h, double t_end, double* tret) {
+  if (!h) return arg_error("bdf_integrate: null handle");
+  if (h->N == 0) {
+    if (tret) *tret = t_end;
+    return 0;
+  }
+  const long inc = h->o.max_steps > 0 ? h->o.max_steps : LONG_MAX / 4;
+  int st = drive(h, t_end, inc, tret);
+  if (st) return st;
+  if (h->hC->phase == PH_PAUSE && h->hC->t < t_end) {
+    set_last_error("max_steps reached before t_end", __FILE__, __LINE__);
+    return BDFGPU_ERR_MAXSTEPS;
+  }
+  return 0;
+}
+
+int bdf_get_y(bdf_handle* h, double* y) {
+  if (!h || (!y && h->N > 0)) return arg_error("bdf_get_y: bad argument");
+  for (const ClassHost& c : h->cls) {
+    if (c.ncells == 0) continue;
+    hipLaunchKernelGGL(k_from_class, dim3(ceil_div(c.ncells * c.n, 256)), dim3(256), 0, h->s,
+                       c.ncells, c.n, (int)(c.map == MAP_TPC), c.d_yoff, c.dev.z[0], y, 1.0);
+  }
+  BDF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int bdf_get_stats(bdf_handle* h, bdf_stats* s) {
+  if (!h || !s) return arg_error("bdf_get_stats: bad argument");
+  int st = read_ctrl(h);
+  if (st) return st;
+  const Ctrl& C = *h->hC;
+  memset(s, 0, sizeof(*s));
+  s->nsteps = C.nsteps;
+  s->nattempts = C.nattempts;
+  s->nfevals = C.nfevals;
+  s->nsetups = C.nsetups;
+  s->nniters = C.nniters;
+  s->nncfails = C.nncfails;
+  s->netfails = C.netfails;
+  s->nlinsolves = C.nlinsolves;
+  s->refine_sweeps = C.refine_sweeps;
+  s->refine_fallbacks = C.refine_fallbacks;
+  s->nprojections = C.nprojections;
+  s->hist_reads = C.hist_reads;
+  for (int j = 0; j < 6; ++j) s->order_hist[j] = C.order_hist[j];
+  s->t = C.t;
+  s->h = C.h;
+  s->hu = C.hu;
+  s->err_last = C.err;
+  s->q = C.q;
+  s->qu = C.qu;
+  s->qwait = C.qwait;
+  s->status = C.status;
+  return 0;
+}
+
+int bdf_get_state(bdf_handle* h, double* dvals, int* ivals, double* z6, double* dprev) {
+  if (!h || !dvals || !ivals || (h->N > 0 && (!z6 || !dprev)))
+    return arg_error("bdf_get_state: bad argument");
+  int st = read_ctrl(h);
+  if (st) return st;
+  const Ctrl C = *h->hC;
+  dvals[0] = C.t;
+  dvals[1] = C.h;
+  ivals[0] = C.q;
+  ivals[1] = C.qwait;
+  BDF_HIP_TRY(hipMemsetAsync(z6, 0, sizeof(double) * 6 * h->N, h->s));
+  for (const ClassHost& c : h->cls) {
+    if (c.ncells == 0) continue;
+    const dim3 g(ceil_div(c.ncells * c.n, 256));
+    const int tiled = c.map == MAP_TPC;
+    for (int j = 0; j <= C.q && j <= kQmaxAll; ++j)
+      hipLaunchKernelGGL(k_from_class, g, dim3(256), 0, h->s, c.ncells, c.n, tiled, c.d_yoff,
+                         c.dev.z[j], z6 + (long)j * h->N, C.hs[j]);
+    hipLaunchKernelGGL(k_from_class, g, dim3(256), 0, h->s, c.ncells, c.n, tiled, c.d_yoff,
+                       c.dev.dprev, dprev, 1.0);
+  }
+  BDF_HIP_TRY(hipGetLastError());
+  BDF_HIP_TRY(hipStreamSynchronize(h->s));
+  return 0;
+}
+
+int bdf_set_state(bdf_handle* h, const double* dvals, const int* ivals, const double* z6,
+                  const double* dprev) {
+  if (!h || !dvals || !ivals || (h->N > 0 && (!z6 || !dprev)))
+    return arg_error("bdf_set_state: bad argument");
+  if (ivals[0] < 1 || ivals[0] > h->o.qmax) return arg_error("bdf_set_state: q out of range");
+  int st = read_ctrl(h);
+  if (st) return st;
+  Ctrl C = *h->hC;
+  C.t = dvals[0];
+  C.h = dvals[1];
+  C.q = ivals[0];
+  C.qwait = ivals[1];
+  for (int j = 0; j < kQmaxAll + 2; ++j) C.hs[j] = 1.0;
+  C.restart = 0;
+  C.ncf = 0;
+  C.netf = 0;
+  C.phase = PH_PAUSE;
+  for (const ClassHost& c : h->cls) {
+    if (c.ncells == 0) continue;
+    const dim3 g(ceil_div(c.ncells * c.n, 256));
+    const int tiled = c.map == MAP_TPC;
+    for (int j = 0; j <= kQmaxAll; ++j)
+      hipLaunchKernelGGL(k_to_class, g, dim3(256), 0, h->s, c.ncells, c.n, tiled, c.d_yoff,
+                         z6 + (long)j * h->N, c.dev.z[j], 1.0);
+    hipLaunchKernelGGL(k_to_class, g, dim3(256), 0, h->s, c.ncells, c.n, tiled, c.d_yoff, dprev,
+                       c.dev.dprev, 1.0);
+  }
+  BDF_HIP_TRY(hipGetLastError());
+  BDF_HIP_TRY(hipMemcpyAsync(h->dC, &C, sizeof(Ctrl), hipMemcpyHostToDevice, h->s));
+  BDF_HIP_TRY(hipStreamSynchronize(h->s));
+  return 0;
+}
+
+int bdf_eval_rhs_jac(bdf_handle* h, const double* y, double* f, double* J) {
+  if (!h || (h->N > 0 && !y)) return arg_error("bdf_eval_rhs_jac: bad argument");
+  // J offsets per class cell (user order of cells, blocks n_c^2)
+  if (h->d_joff.empty()) {
+    // recover the global cell order from the per-class y offsets
+    std::vector<std::pair<long, std::pair<int, long>>> order;   // (yoff, (class, idx))
+    std::vector<std::vector<long>> cy(h->cls.size());
+    for (size_t k = 0; k < h->cls.size(); ++k) {
+      const ClassHost& c = h->cls[k];
+      cy[k].resize(c.ncells);
+      if (c.ncells)
+        BDF_HIP_TRY(hipMemcpy(cy[k].data(), c.d_yoff, sizeof(long) * c.ncells, hipMemcpyDeviceToHost));
+      for (long i = 0; i < c.ncells; ++i) order.push_back({cy[k][i], {(int)k, i}});
+    }
+    std::sort(order.begin(), order.end());
+    std::vector<std::vector<long>> jo(h->cls.size());
+    for (size_t k = 0; k < h->cls.size(); ++k) jo[k].resize(h->cls[k].ncells);
+    long acc = 0;
+    for (auto& e : order) {
+      const int k = e.second.first;
+      jo[k][e.second.second] = acc;
+      acc += (long)h->cls[k].n * h->cls[k].n;
+    }
+    for (size_t k = 0; k < h->cls.size(); ++k) {
+      long* d = nullptr;
+      int st = upload(h, &d, jo[k]);
+      if (st) return st;
+      h->d_joff.push_back(d);
+    }
+  }
+  for (size_t k = 0; k < h->cls.size(); ++k) {
+    const ClassHost& c = h->cls[k];
+    if (c.ncells == 0) continue;
+    // rates back to user layout are not kept; evaluate from the class copy
+    // through a temporary cell-major copy of the rates
+    double* rtmp = nullptr;
+    BDF_HIP_TRY(hipMalloc(&rtmp, sizeof(double) * std::max<long>(1, c.ncells * c.R)));
+    std::vector<long> ro(c.ncells);
+    for (long i = 0; i < c.ncells; ++i) ro[i] = i * c.R;
+    long* dro = nullptr;
+    BDF_HIP_TRY(hipMalloc(&dro, sizeof(long) * std::max<long>(1, c.ncells)));
+    BDF_HIP_TRY(hipMemcpy(dro, ro.data(), sizeof(long) * c.ncells, hipMemcpyHostToDevice));
+    if (c.R > 0)
+      hipLaunchKernelGGL(k_from_class, dim3(ceil_div(c.ncells * (long)c.R, 256)), dim3(256), 0,
+                         h->s, c.ncells, c.R, (int)(c.map == MAP_TPC), dro, c.dev.rates, rtmp,
+                         1.0);
+    hipLaunchKernelGGL(k_eval_rhs_jac, dim3(ceil_div(c.ncells, 128)), dim3(128), 0, h->s,
+                       c.ncells, c.dev.net, c.d_yoff, dro, h->d_joff[k], rtmp, y, f, J);
+    BDF_HIP_TRY(hipGetLastError());
+    BDF_HIP_TRY(hipStreamSynchronize(h->s));
+    (void)hipFree(rtmp);
+    (void)hipFree(dro);
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,42 @@
+// Segment-per-cell instantiations of the BDF step kernels (blocks of 13 to
+// 64 species in segments of 16, 32 or 64 lanes).
+#include "bdf_dev.hpp"
+
+namespace bdfgpu {
+
+template <int SEG>
+static void spc_go(int ls, int which, const BdfDev& D, int mslot, unsigned int grid,
+                   hipStream_t s) {
+  const dim3 g(grid), b(kCellThreads);
+  switch (which) {
+    case 0: hipLaunchKernelGGL(k_spc_init1<SEG>, g, b, 0, s, D); break;
+    case 1: hipLaunchKernelGGL(k_spc_init2<SEG>, g, b, 0, s, D); break;
+    case 2:
+      if (mslot == 0) {
+        if (ls == 1)
+          hipLaunchKernelGGL((k_spc_newton<SEG, 1, 1>), g, b, 0, s, D, mslot);
+        else
+          hipLaunchKernelGGL((k_spc_newton<SEG, 0, 1>), g, b, 0, s, D, mslot);
+      } else {
+        if (ls == 1)
+          hipLaunchKernelGGL((k_spc_newton<SEG, 1, 0>), g, b, 0, s, D, mslot);
+        else
+          hipLaunchKernelGGL((k_spc_newton<SEG, 0, 0>), g, b, 0, s, D, mslot);
+      }
+      break;
+    default: hipLaunchKernelGGL(k_spc_accept<SEG>, g, b, 0, s, D); break;
+  }
+}
+
+int spc_seg(int n) { return n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 0; }
+
+void launch_spc(int seg, int ls, int which, const BdfDev& D, int mslot, unsigned int grid,
+                hipStream_t s) {
+  switch (seg) {
+    case 16: spc_go<16>(ls, which, D, mslot, grid, s); break;
+    case 32: spc_go<32>(ls, which, D, mslot, grid, s); break;
+    default: spc_go<64>(ls, which, D, mslot, grid, s); break;
+  }
+}
+
+}  // namespace bdfgpu

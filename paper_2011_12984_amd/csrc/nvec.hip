@@ -1,0 +1,583 @@
+// N_Vector operations for gfx950: streaming kernels and two-level
+// (wavefront shuffle, then LDS, then one last-block pass over per-block
+// partials) reductions.
+//
+// The paper groups vector operations into streaming operations and
+// reductions (Section 2); reductions are completed on the GPU and the scalar
+// returned by one transfer (Section 4.1).  The fused operations (linear
+// combination, scale-add-multi, multiple dot products, WRMS norm) are
+// memory-bound: each reads every input once and writes every output once,
+// with 16-byte loads and stores, so their speed is set by HBM bandwidth.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "common.hpp"
+
+namespace bdfgpu {
+
+static thread_local std::string g_last_error;
+static std::mutex g_err_mu;
+static std::string g_last_error_global;
+
+void set_last_error(const char* msg, const char* file, int line) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s (%s:%d)", msg, file, line);
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  g_last_error_global = buf;
+}
+
+int arg_error(const char* msg) {
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  g_last_error_global = msg;
+  return BDFGPU_ERR_ARG;
+}
+
+// ---------------------------------------------------------------------------
+// Per-device reduction scratch: per-block partials, a ticket counter, a
+// device result slot and a pinned host result buffer.
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 2048;   // upper bound on blocks of a reduction
+constexpr int kRedK = 8;           // values per block
+constexpr int kMaxDev = 64;
+
+struct RedScratch {
+  double* partials = nullptr;
+  unsigned int* counter = nullptr;
+  double* dres = nullptr;
+  double* hres = nullptr;
+};
+static RedScratch g_red[kMaxDev];
+static std::mutex g_red_mu;
+
+static int get_red_scratch(RedScratch** out) {
+  int dev = 0;
+  BDF_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDev) return arg_error("device index out of range");
+  std::lock_guard<std::mutex> lk(g_red_mu);
+  RedScratch& r = g_red[dev];
+  if (!r.partials) {
+    BDF_HIP_TRY(hipMalloc(&r.partials, sizeof(double) * kRedBlocks * kRedK));
+    BDF_HIP_TRY(hipMalloc(&r.counter, 256));
+    BDF_HIP_TRY(hipMemset(r.counter, 0, 256));
+    BDF_HIP_TRY(hipMalloc(&r.dres, sizeof(double) * kRedK));
+    BDF_HIP_TRY(hipHostMalloc(&r.hres, sizeof(double) * kRedK, hipHostMallocDefault));
+    BDF_HIP_TRY(hipDeviceSynchronize());
+  }
+  *out = &r;
+  return 0;
+}
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ dbl2 ntload(const double* p, long i) {
+  return __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(p) + i);
+}
+__device__ __forceinline__ void ntstore(double* p, long i, dbl2 v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(p) + i);
+}
+
+static inline bool aligned16(const void* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
+// Launch shape for memory-bound kernels: enough 256-thread blocks to keep
+// every CU busy with a grid-stride loop, never more than the data needs.
+constexpr int kStreamThreads = 256;
+static unsigned int stream_blocks(long nunits) {
+  long want = (nunits + kStreamThreads - 1) / kStreamThreads;
+  long cap = 256L * 16L;   // 256 CUs, 16 blocks each
+  return (unsigned int)std::max(1L, std::min(want, cap));
+}
+
+// ---------------------------------------------------------------------------
+// Streaming kernels
+// ---------------------------------------------------------------------------
+__global__ void k_linear_sum2(long n2, double a, const double2* __restrict__ x,
+                              double b, const double2* __restrict__ y,
+                              double2* __restrict__ z) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+    double2 xv = x[i], yv = y[i];
+    z[i] = make_double2(a * xv.x + b * yv.x, a * xv.y + b * yv.y);
+  }
+}
+
+__global__ void k_linear_sum1(long n, long start, double a, const double* x,
+                              double b, const double* y, double* z) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = start + (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    z[i] = a * x[i] + b * y[i];
+}
+
+struct LcArgs {
+  const double* X[16];
+  double c[16];
+};
+
+template <int NV>
+__global__ void k_linear_combination2(long n2, LcArgs A, double2* __restrict__ z) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+    dbl2 v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = ntload(A.X[j], i);
+    double sx = A.c[0] * v[0].x, sy = A.c[0] * v[0].y;
+#pragma unroll
+    for (int j = 1; j < NV; ++j) {
+      sx = fma(A.c[j], v[j].x, sx);
+      sy = fma(A.c[j], v[j].y, sy);
+    }
+    dbl2 o;
+    o.x = sx;
+    o.y = sy;
+    ntstore(reinterpret_cast<double*>(z), i, o);
+  }
+}
+
+__global__ void k_linear_combination1(int nv, long n, long start, LcArgs A, double* z) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = start + (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double s = A.c[0] * A.X[0][i];
+    for (int j = 1; j < nv; ++j) s = fma(A.c[j], A.X[j][i], s);
+    z[i] = s;
+  }
+}
+
+struct SamArgs {
+  const double* Y[8];
+  double* Z[8];
+  double a[8];
+};
+
+template <int NV>
+__global__ void k_scale_add_multi2(long n2, const double2* __restrict__ x, SamArgs A) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+    double2 xv = x[i];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      double2 yv = reinterpret_cast<const double2*>(A.Y[j])[i];
+      reinterpret_cast<double2*>(A.Z[j])[i] =
+          make_double2(fma(A.a[j], xv.x, yv.x), fma(A.a[j], xv.y, yv.y));
+    }
+  }
+}
+
+__global__ void k_scale_add_multi1(int nv, long n, long start, const double* x, SamArgs A) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = start + (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double xv = x[i];
+    for (int j = 0; j < nv; ++j) A.Z[j][i] = fma(A.a[j], xv, A.Y[j][i]);
+  }
+}
+
+__global__ void k_ewt(long n, double rtol, double atol, const double* y, double* w) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    w[i] = 1.0 / (rtol * fabs(y[i]) + atol);
+}
+
+__global__ void k_scale(long n, double c, const double* x, double* z) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    z[i] = c * x[i];
+}
+
+__global__ void k_const(long n, double c, double* z) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) z[i] = c;
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.  Per-thread FP64 partials -> wave shuffle -> LDS -> per-block
+// partial in HBM -> the last block to finish sums the block partials in
+// block order.  One launch, no float atomics, deterministic for a given
+// launch shape.
+// ---------------------------------------------------------------------------
+struct DotArgs {
+  const double* Y[8];
+};
+
+template <int NV>
+__global__ void __launch_bounds__(256) k_dot_prod_multi(long n, const double* __restrict__ x,
+                                                        DotArgs A, double* partials,
+                                                        unsigned int* counter, double* out) {
+  __shared__ double sh[4 * 8];
+  double acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  const long n2 = n >> 1;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+    dbl2 xv = ntload(x, i);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      dbl2 yv = ntload(A.Y[j], i);
+      acc[j] = fma(xv.x, yv.x, acc[j]);
+      acc[j] = fma(xv.y, yv.y, acc[j]);
+    }
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = fma(x[n - 1], A.Y[j][n - 1], acc[j]);
+  }
+  block_sum<8>(acc, sh);
+  double tot[8];
+  if (last_block_reduce<8>(acc, partials, counter, gridDim.x, tot, sh)) {
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) out[j] = tot[j];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_wrms(long n, const double* __restrict__ x,
+                                              const double* __restrict__ w, double* partials,
+                                              unsigned int* counter, double* out) {
+  __shared__ double sh[4];
+  double acc[1] = {0.0};
+  const long stride = (long)gridDim.x * blockDim.x;
+  const long n2 = n >> 1;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+    dbl2 xv = ntload(x, i);
+    dbl2 wv = ntload(w, i);
+    double a = xv.x * wv.x, b = xv.y * wv.y;
+    acc[0] = fma(a, a, acc[0]);
+    acc[0] = fma(b, b, acc[0]);
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double a = x[n - 1] * w[n - 1];
+    acc[0] = fma(a, a, acc[0]);
+  }
+  block_sum<1>(acc, sh);
+  double tot[1];
+  if (last_block_reduce<1>(acc, partials, counter, gridDim.x, tot, sh)) {
+    if (threadIdx.x == 0) out[0] = sqrt(tot[0] / (double)n);
+  }
+}
+
+// scalar-load variants for vectors that are not 16-byte aligned
+template <int NV>
+__global__ void __launch_bounds__(256) k_dot_prod_multi_u(long n, const double* x, DotArgs A,
+                                                          double* partials,
+                                                          unsigned int* counter, double* out) {
+  __shared__ double sh[4 * 8];
+  double acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double xv = x[i];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = fma(xv, A.Y[j][i], acc[j]);
+  }
+  block_sum<8>(acc, sh);
+  double tot[8];
+  if (last_block_reduce<8>(acc, partials, counter, gridDim.x, tot, sh)) {
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) out[j] = tot[j];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_wrms_u(long n, const double* x, const double* w,
+                                                double* partials, unsigned int* counter,
+                                                double* out) {
+  __shared__ double sh[4];
+  double acc[1] = {0.0};
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double a = x[i] * w[i];
+    acc[0] = fma(a, a, acc[0]);
+  }
+  block_sum<1>(acc, sh);
+  double tot[1];
+  if (last_block_reduce<1>(acc, partials, counter, gridDim.x, tot, sh)) {
+    if (threadIdx.x == 0) out[0] = sqrt(tot[0] / (double)n);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_maxnorm(long n, const double* x, double* partials,
+                                                 unsigned int* counter, double* out) {
+  __shared__ double sh[4];
+  double m = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    m = fmax(m, fabs(x[i]));
+  m = wave_max(m);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = m;
+  __syncthreads();
+  double acc[1] = {0.0};
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) v = fmax(v, sh[k]);
+    acc[0] = v;
+  }
+  __syncthreads();
+  // the max of non-negative values is order independent; reuse the
+  // block-partial protocol with a max in the final pass
+  __shared__ int am_last;
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = acc[0];
+    __threadfence();
+    unsigned int t = atomicAdd(counter, 1u);
+    am_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!am_last) return;
+  __threadfence();
+  double v = 0.0;
+  for (unsigned int b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+    v = fmax(v, __hip_atomic_load(&partials[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  v = wave_max(v);
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r = fmax(r, sh[k]);
+    out[0] = r;
+    *counter = 0u;
+  }
+}
+
+static unsigned int red_blocks(long nunits) {
+  long want = (nunits + kStreamThreads - 1) / kStreamThreads;
+  long cap = 256L * 4L;   // one wave of blocks on every CU keeps HBM busy
+  return (unsigned int)std::max(1L, std::min(want, std::min(cap, (long)kRedBlocks)));
+}
+
+// Finish a reduction: copy nv results to the host and wait, or leave them in
+// the caller's device array.
+static int finish_reduction(RedScratch* r, int nv, double* out, int flags, hipStream_t s) {
+  if (flags & BDFGPU_RESULT_DEVICE) {
+    BDF_HIP_TRY(hipMemcpyAsync(out, r->dres, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
+    return 0;
+  }
+  BDF_HIP_TRY(hipMemcpyAsync(r->hres, r->dres, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+  BDF_HIP_TRY(hipStreamSynchronize(s));
+  memcpy(out, r->hres, sizeof(double) * nv);
+  return 0;
+}
+
+}  // namespace bdfgpu
+
+using namespace bdfgpu;
+
+extern "C" {
+
+const char* bdfgpu_last_error(void) {
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  static thread_local std::string copy;
+  copy = g_last_error_global;
+  return copy.c_str();
+}
+
+const char* bdfgpu_version(void) { return "bdfgpu 0.1 gfx950"; }
+
+int nvec_linear_sum(long n, double a, const double* x, double b, const double* y, double* z,
+                    void* stream) {
+  if (n < 0 || (n > 0 && (!x || !y || !z))) return arg_error("nvec_linear_sum: bad argument");
+  if (n == 0) return 0;
+  hipStream_t s = as_stream(stream);
+  long n2 = 0;
+  if (aligned16(x) && aligned16(y) && aligned16(z)) {
+    n2 = n >> 1;
+    if (n2)
+      hipLaunchKernelGGL(k_linear_sum2, dim3(stream_blocks(n2)), dim3(kStreamThreads), 0, s, n2, a,
+                         reinterpret_cast<const double2*>(x), b,
+                         reinterpret_cast<const double2*>(y), reinterpret_cast<double2*>(z));
+  }
+  if (2 * n2 < n)
+    hipLaunchKernelGGL(k_linear_sum1, dim3(stream_blocks(n - 2 * n2)), dim3(kStreamThreads), 0, s,
+                       n, 2 * n2, a, x, b, y, z);
+  BDF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int nvec_linear_combination(int nv, const double* c, const double* const* X, double* z, long n,
+                            void* stream) {
+  if (nv < 1 || nv > 16 || n < 0 || !c || !X) return arg_error("nvec_linear_combination: bad nv/args");
+  if (n == 0) return 0;
+  LcArgs A;
+  memset(&A, 0, sizeof(A));
+  bool al = aligned16(z);
+  for (int j = 0; j < nv; ++j) {
+    if (!X[j]) return arg_error("nvec_linear_combination: null vector");
+    A.X[j] = X[j];
+    A.c[j] = c[j];
+    al = al && aligned16(X[j]);
+  }
+  hipStream_t s = as_stream(stream);
+  long n2 = 0;
+  if (al) {
+    n2 = n >> 1;
+    dim3 g(stream_blocks(n2)), b(kStreamThreads);
+    double2* z2 = reinterpret_cast<double2*>(z);
+    if (n2) switch (nv) {
+#define LC_CASE(K) case K: hipLaunchKernelGGL(k_linear_combination2<K>, g, b, 0, s, n2, A, z2); break;
+      LC_CASE(1) LC_CASE(2) LC_CASE(3) LC_CASE(4) LC_CASE(5) LC_CASE(6) LC_CASE(7) LC_CASE(8)
+      LC_CASE(9) LC_CASE(10) LC_CASE(11) LC_CASE(12) LC_CASE(13) LC_CASE(14) LC_CASE(15) LC_CASE(16)
+#undef LC_CASE
+    }
+  }
+  if (2 * n2 < n)
+    hipLaunchKernelGGL(k_linear_combination1, dim3(stream_blocks(n - 2 * n2)), dim3(kStreamThreads),
+                       0, s, nv, n, 2 * n2, A, z);
+  BDF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int nvec_scale_add_multi(int nv, const double* a, const double* x, const double* const* Y,
+                         double* const* Z, long n, void* stream) {
+  if (nv < 1 || nv > 8 || n < 0 || !a || !Y || !Z || (n > 0 && !x))
+    return arg_error("nvec_scale_add_multi: bad nv/args");
+  if (n == 0) return 0;
+  SamArgs A;
+  memset(&A, 0, sizeof(A));
+  bool al = aligned16(x);
+  for (int j = 0; j < nv; ++j) {
+    if (!Y[j] || !Z[j]) return arg_error("nvec_scale_add_multi: null vector");
+    A.Y[j] = Y[j];
+    A.Z[j] = Z[j];
+    A.a[j] = a[j];
+    al = al && aligned16(Y[j]) && aligned16(Z[j]);
+  }
+  hipStream_t s = as_stream(stream);
+  long n2 = 0;
+  if (al) {
+    n2 = n >> 1;
+    dim3 g(stream_blocks(n2)), b(kStreamThreads);
+    const double2* x2 = reinterpret_cast<const double2*>(x);
+    if (n2) switch (nv) {
+#define SAM_CASE(K) case K: hipLaunchKernelGGL(k_scale_add_multi2<K>, g, b, 0, s, n2, x2, A); break;
+      SAM_CASE(1) SAM_CASE(2) SAM_CASE(3) SAM_CASE(4) SAM_CASE(5) SAM_CASE(6) SAM_CASE(7) SAM_CASE(8)
+#undef SAM_CASE
+    }
+  }
+  if (2 * n2 < n)
+    hipLaunchKernelGGL(k_scale_add_multi1, dim3(stream_blocks(n - 2 * n2)), dim3(kStreamThreads), 0,
+                       s, nv, n, 2 * n2, x, A);
+  BDF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int nvec_dot_prod_multi(int nv, const double* x, const double* const* Y, double* d, long n,
+                        int flags, void* stream) {
+  if (nv < 1 || nv > 8 || n < 0 || !Y || !d || (n > 0 && !x))
+    return arg_error("nvec_dot_prod_multi: bad nv/args");
+  hipStream_t s = as_stream(stream);
+  if (n == 0) {
+    if (flags & BDFGPU_RESULT_DEVICE) {
+      BDF_HIP_TRY(hipMemsetAsync(d, 0, sizeof(double) * nv, s));
+    } else {
+      for (int j = 0; j < nv; ++j) d[j] = 0.0;
+    }
+    return 0;
+  }
+  RedScratch* r = nullptr;
+  int st = get_red_scratch(&r);
+  if (st) return st;
+  DotArgs A;
+  memset(&A, 0, sizeof(A));
+  bool al = aligned16(x);
+  for (int j = 0; j < nv; ++j) {
+    if (!Y[j]) return arg_error("nvec_dot_prod_multi: null vector");
+    A.Y[j] = Y[j];
+    al = al && aligned16(Y[j]);
+  }
+  dim3 g(red_blocks(al ? (n >> 1) + 1 : n)), b(256);
+  if (al) {
+    switch (nv) {
+#define DP_CASE(K) case K: hipLaunchKernelGGL(k_dot_prod_multi<K>, g, b, 0, s, n, x, A, r->partials, r->counter, r->dres); break;
+      DP_CASE(1) DP_CASE(2) DP_CASE(3) DP_CASE(4) DP_CASE(5) DP_CASE(6) DP_CASE(7) DP_CASE(8)
+#undef DP_CASE
+    }
+  } else {
+    switch (nv) {
+#define DP_CASE(K) case K: hipLaunchKernelGGL(k_dot_prod_multi_u<K>, g, b, 0, s, n, x, A, r->partials, r->counter, r->dres); break;
+      DP_CASE(1) DP_CASE(2) DP_CASE(3) DP_CASE(4) DP_CASE(5) DP_CASE(6) DP_CASE(7) DP_CASE(8)
+#undef DP_CASE
+    }
+  }
+  BDF_HIP_TRY(hipGetLastError());
+  return finish_reduction(r, nv, d, flags, s);
+}
+
+int nvec_wrms_norm(long n, const double* x, const double* w, double* out, int flags,
+                   void* stream) {
+  if (n < 0 || !out || (n > 0 && (!x || !w))) return arg_error("nvec_wrms_norm: bad argument");
+  hipStream_t s = as_stream(stream);
+  if (n == 0) {
+    if (flags & BDFGPU_RESULT_DEVICE) {
+      BDF_HIP_TRY(hipMemsetAsync(out, 0, sizeof(double), s));
+    } else {
+      *out = 0.0;
+    }
+    return 0;
+  }
+  RedScratch* r = nullptr;
+  int st = get_red_scratch(&r);
+  if (st) return st;
+  bool al = aligned16(x) && aligned16(w);
+  dim3 g(red_blocks(al ? (n >> 1) + 1 : n)), b(256);
+  if (al)
+    hipLaunchKernelGGL(k_wrms, g, b, 0, s, n, x, w, r->partials, r->counter, r->dres);
+  else
+    hipLaunchKernelGGL(k_wrms_u, g, b, 0, s, n, x, w, r->partials, r->counter, r->dres);
+  BDF_HIP_TRY(hipGetLastError());
+  return finish_reduction(r, 1, out, flags, s);
+}
+
+int nvec_max_norm(long n, const double* x, double* out, int flags, void* stream) {
+  if (n < 0 || !out || (n > 0 && !x)) return arg_error("nvec_max_norm: bad argument");
+  hipStream_t s = as_stream(stream);
+  if (n == 0) {
+    if (flags & BDFGPU_RESULT_DEVICE) {
+      BDF_HIP_TRY(hipMemsetAsync(out, 0, sizeof(double), s));
+    } else {
+      *out = 0.0;
+    }
+    return 0;
+  }
+  RedScratch* r = nullptr;
+  int st = get_red_scratch(&r);
+  if (st) return st;
+  hipLaunchKernelGGL(k_maxnorm, dim3(red_blocks(n)), dim3(256), 0, s, n, x, r->partials,
+                     r->counter, r->dres);
+  BDF_HIP_TRY(hipGetLastError());
+  return finish_reduction(r, 1, out, flags, s);
+}
+
+int nvec_ewt(long n, double rtol, double atol, const double* y, double* w, void* stream) {
+  if (n < 0 || (n > 0 && (!y || !w))) return arg_error("nvec_ewt: bad argument");
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_ewt, dim3(stream_blocks(n)), dim3(kStreamThreads), 0, as_stream(stream), n,
+                     rtol, atol, y, w);
+  BDF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int nvec_scale(long n, double c, const double* x, double* z, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !z))) return arg_error("nvec_scale: bad argument");
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_scale, dim3(stream_blocks(n)), dim3(kStreamThreads), 0, as_stream(stream), n,
+                     c, x, z);
+  BDF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int nvec_const(long n, double c, double* z, void* stream) {
+  if (n < 0 || (n > 0 && !z)) return arg_error("nvec_const: bad argument");
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_const, dim3(stream_blocks(n)), dim3(kStreamThreads), 0, as_stream(stream), n,
+                     c, z);
+  BDF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+// Segment-per-cell dense LU: one small block per SEG-lane segment of a
+// wavefront, lane r of the segment owns row r of the block in registers.
+//
+// Right-looking partial pivoting with LAPACK getrf semantics (first maximal
+// pivot, whole-row exchange, division by the pivot).  Rows never move
+// between lanes: every lane tracks the position its row holds in the
+// permuted matrix, so an exchange of rows k and p swaps two position labels.
+// The pivot search is a segmented arg-max over shuffles (ties go to the
+// smaller current position, i.e. LAPACK's first maximum); the pivot row is
+// published once through LDS and read back by the segment.
+//
+// Register indexing stays static without unrolling the whole elimination:
+// the k loop runs in chunks of CH columns, and after every chunk each lane
+// rotates its row left by CH, so inside a chunk the current column is always
+// row[kk] for a compile-time kk.  After SEG/CH rotations the row is back in
+// column order.  Blocks smaller than SEG are padded with identity rows and
+// columns, which leaves the leading factors, pivots and solution exactly
+// those of the unpadded block.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bdfgpu {
+
+template <int NP>
+struct SegOf {
+  static constexpr int value = NP <= 2 ? 2 : NP <= 4 ? 4 : NP <= 8 ? 8 : NP <= 16 ? 16 : NP <= 32 ? 32 : 64;
+};
+
+template <typename T>
+__device__ __forceinline__ T sabs(T v) { return v < T(0) ? -v : v; }
+
+template <int SEG, typename T>
+__device__ __forceinline__ T seg_max(T v) {
+#pragma unroll
+  for (int off = SEG / 2; off >= 1; off >>= 1) {
+    T o = __shfl_xor(v, off, SEG);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+template <int SEG, typename T>
+__device__ __forceinline__ T seg_sum(T v) {
+#pragma unroll
+  for (int off = SEG / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, SEG);
+  return v;
+}
+
+template <int SEG, typename T>
+struct SpcLU {
+  static constexpr int CH = SEG < 8 ? SEG : 8;
+  static constexpr int NCH = SEG / CH;
+
+  __device__ static __forceinline__ void rotl(T (&row)[SEG]) {
+    if (NCH == 1) return;
+    T tmp[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) tmp[c] = row[c];
+#pragma unroll
+    for (int j = 0; j < SEG - CH; ++j) row[j] = row[j + CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) row[SEG - CH + c] = tmp[c];
+  }
+
+  __device__ static __forceinline__ void rotr(T (&row)[SEG]) {
+    if (NCH == 1) return;
+    T tmp[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) tmp[c] = row[SEG - CH + c];
+#pragma unroll
+    for (int j = SEG - 1; j >= CH; --j) row[j] = row[j - CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) row[c] = tmp[c];
+  }
+
+  // Factor the lane-held rows in place (n <= SEG real rows, the rest are
+  // identity).  prow: SEG values of LDS for this segment; wl: SEG ints of LDS
+  // for this segment, receives the lane holding each position.  On return
+  // row[] holds this lane's row of L\U in column order, pos its position in
+  // the permuted matrix, piv the LAPACK pivot of step k == r.  Returns info
+  // (1-based first exactly-zero pivot, 0 if none).
+  __device__ static int factor(T (&row)[SEG], int r, int n, int& pos, int& piv, T* prow,
+                               int* wl) {
+    pos = r;
+    piv = r;
+    bool done = false;
+    int info = 0;
+    const int nch = (n + CH - 1) / CH;
+    for (int c = 0; c < NCH; ++c) {
+      if (c < nch) {
+        const int lim = SEG - c * CH;   // rotated columns >= lim hold L of earlier chunks
+#pragma unroll
+        for (int kk = 0; kk < CH; ++kk) {
+          const int k = c * CH + kk;
+          // NaN ranks above every number so that all lanes of the segment
+          // agree on one winner (the comparison below is then a total order)
+          T v = done ? T(-1) : sabs(row[kk]);
+          if (!(v == v)) v = T(__builtin_inf());
+          int key = done ? 0x7fffffff : pos;
+          int bl = r;
+#pragma unroll
+          for (int off = SEG / 2; off >= 1; off >>= 1) {
+            const T ov = __shfl_xor(v, off, SEG);
+            const int ok = __shfl_xor(key, off, SEG);
+            const int ol = __shfl_xor(bl, off, SEG);
+            const bool take = (ov > v) || (ov == v && ok < key);
+            v = take ? ov : v;
+            key = take ? ok : key;
+            bl = take ? ol : bl;
+          }
+          if (r == k) piv = key;
+          if (r == bl) {
+            prow[kk] = row[kk];
+#pragma unroll
+            for (int j = kk + 1; j < SEG; ++j) prow[j] = j < lim ? row[j] : T(0);
+            wl[k] = bl;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const T d = prow[kk];
+          if (pos == k) pos = key;
+          if (r == bl) {
+            pos = k;
+            done = true;
+          }
+          if (d == T(0)) {
+            if (!info) info = k + 1;
+          } else if (!done) {
+            const T l = row[kk] / d;
+            row[kk] = l;
+#pragma unroll
+            for (int j = kk + 1; j < SEG; ++j) row[j] = fma(-l, prow[j], row[j]);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      }
+      rotl(row);
+    }
+    return info;
+  }
+
+  // Solve with factors from factor() (pos, wl) or, with wl == nullptr, with
+  // factors already in position order (lane r holds position r).  `val` is
+  // this lane's right-hand-side entry, already permuted in the second case.
+  // Returns component r of the solution.  row[] is left unchanged.
+  __device__ static T solve(T (&row)[SEG], int r, int seg_base, int n, int pos, const int* wl,
+                            T val) {
+    const int nch = (n + CH - 1) / CH;
+    for (int c = 0; c < NCH; ++c) {
+      if (c < nch) {
+#pragma unroll
+        for (int kk = 0; kk < CH; ++kk) {
+          const int k = c * CH + kk;
+          const int src = wl ? wl[k] : k;
+          const T yk = __shfl(val, seg_base + src, 64);
+          if (pos > k) val = fma(-row[kk], yk, val);
+        }
+      }
+      rotl(row);
+    }
+    T x = T(0);
+    for (int c = NCH - 1; c >= 0; --c) {
+      rotr(row);
+      if (c < nch) {
+#pragma unroll
+        for (int kk = CH - 1; kk >= 0; --kk) {
+          const int k = c * CH + kk;
+          if (pos == k) val = val / row[kk];
+          const int src = wl ? wl[k] : k;
+          const T xk = __shfl(val, seg_base + src, 64);
+          if (pos < k) val = fma(-row[kk], xk, val);
+          if (r == k) x = xk;
+        }
+      }
+    }
+    return x;
+  }
+
+  // Solve with factors stored in LAPACK layout (lane r holds the row at
+  // position r) and LAPACK pivots piv[0..n-1] in global memory.
+  __device__ static T solve_stored(T (&row)[SEG], int r, int seg_base, const int* piv, int n,
+                                   T val) {
+    for (int k = 0; k < n; ++k) {
+      const int p = piv[k];
+      const T vk = __shfl(val, seg_base + k, 64);
+      const T vp = __shfl(val, seg_base + p, 64);
+      if (r == k)
+        val = vp;
+      else if (r == p)
+        val = vk;
+    }
+    return solve(row, r, seg_base, n, r, nullptr, val);
+  }
+};
+
+}  // namespace bdfgpu

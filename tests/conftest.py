@@ -18,3 +18,20 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2011_12984_amd as G
+    G.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="session")
+def G():
+    import paper_2011_12984_amd as G
+    G.lib()
+    return G

@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every entry point include/*.h
+declares (no compute: this runs without a GPU)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2011_12984_amd", "libbdfgpu.so")
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z][A-Za-z0-9_]*)\s*\(",
+                             txt, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("nvec_linear_sum", "nvec_linear_combination", "nvec_scale_add_multi",
+                     "nvec_dot_prod_multi", "nvec_wrms_norm", "batched_lu_factor_f64",
+                     "batched_lu_solve_f64", "batched_lu_solve_refine", "bdf_create", "bdf_step",
+                     "bdf_integrate", "bdf_destroy"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_names_match_header():
+    from paper_2011_12984_amd import _lib
+    assert set(_lib.SIGNATURES) == set(declared_functions())
+
+
+def test_no_oracle_in_product_sources():
+    """The product path never links, includes or imports the oracle."""
+    pkg = os.path.join(ROOT, "paper_2011_12984_amd")
+    for path in glob.glob(os.path.join(pkg, "**", "*"), recursive=True):
+        if os.path.isdir(path) or path.endswith((".so", ".o", ".pyc")):
+            continue
+        txt = open(path, errors="ignore").read()
+        assert "orc_" not in txt and "import oracle" not in txt and "liborc" not in txt, path

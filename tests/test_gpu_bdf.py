@@ -1,0 +1,201 @@
+"""GPU parity of the grouped BDF integrator against the CPU oracle.
+
+Grouped Newton with block-diagonal solves and whole-step retry (Section 7);
+the BDF method itself is the fixed-coefficient Nordsieck reading.  Bars:
+mass-action f and J within 1e-13 of the oracle (relative to the term
+scale); one step from an identical state makes the same decisions and
+lands within 1e-6 in WRMS units; whole trajectories take the same number
+of steps and end within 1e-3 WRMS (if a decision flips near a threshold the
+step counts may differ and the bar becomes 1 WRMS, the tolerance itself);
+graph capture reproduces stream execution bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def wrms_diff(a, b, rtol, atol):
+    w = 1.0 / (rtol * np.abs(b) + atol)
+    return float(np.sqrt(np.mean(((a - b) * w) ** 2)))
+
+
+def gpu_bdf(G, prob, dev, **kw):
+    return G.Bdf.from_problem(prob, device=dev, **kw)
+
+
+def jac_entries(prob):
+    return int((prob.sizes.astype(np.int64) ** 2).sum())
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.robertson_batch(37),
+    lambda: W.random_network_batch(300, n=10, seed=5),
+    lambda: W.learned_batch(70),
+    lambda: W.uneven_batch(1 << 12, seed=9),
+])
+def test_rhs_jac_parity(orc, dev, G, maker):
+    p = maker()
+    b = gpu_bdf(G, p, dev)
+    rng = W.rng_for(3)
+    y = rng.uniform(0.0, 1.0, p.N)
+    f, J = b.eval_rhs_jac(torch.tensor(y, device=dev), jac_entries(p))
+    f, J = f.cpu().numpy(), J.cpu().numpy()
+    sizes, R = p.sizes, p.nreact
+    yo = ro = jo = 0
+    for c in range(p.ncells):
+        n, r = int(sizes[c]), int(R[c])
+        nu, mu = p.topologies[p.cell_topo[c]]
+        k = p.rates[ro:ro + r]
+        fr = orc.ma_rhs(nu, mu, k, y[yo:yo + n])
+        Jr = orc.ma_jac(nu, mu, k, y[yo:yo + n])
+        scale = np.abs(k).sum() * 4
+        assert np.abs(f[yo:yo + n] - fr).max() <= 1e-13 * scale
+        Jg = J[jo:jo + n * n].reshape(n, n).T
+        assert np.abs(Jg - Jr).max() <= 1e-13 * scale
+        yo, ro, jo = yo + n, ro + r, jo + n * n
+
+
+def test_single_step_from_identical_state(orc, dev, G):
+    p = W.random_network_batch(512, n=10, seed=21)
+    ob = orc.Bdf(p)
+    for _ in range(30):
+        assert ob.step(p.t_end) == 0
+    sc = ob.scalars()
+    z, dprev = ob.history()
+    gb = gpu_bdf(G, p, dev)
+    gb.set_state(sc["t"], sc["h"], sc["q"], sc["qwait"], torch.tensor(z, device=dev),
+                 torch.tensor(dprev, device=dev))
+    s0 = ob.stats()
+    assert ob.step(p.t_end) == 0
+    s1 = ob.stats()
+    gb.step(p.t_end)
+    gs = gb.stats()
+    st = gb.get_state()
+    sc1 = ob.scalars()
+    assert gs["nattempts"] == s1["nattempts"] - s0["nattempts"]
+    assert gs["nniters"] == s1["nniters"] - s0["nniters"]
+    assert st["q"] == sc1["q"]
+    assert st["t"] == pytest.approx(sc1["t"], rel=1e-14)
+    assert st["h"] == pytest.approx(sc1["h"], rel=1e-12)
+    z1, _ = ob.history()
+    assert wrms_diff(st["z"][0].cpu().numpy(), z1[0], p.rtol, p.atol) <= 1e-6
+
+
+def compare_trajectory(orc, dev, G, p, **kw):
+    """Whole-trajectory parity.  Step-size and order decisions are
+    discontinuous in the rounding of the norms, so:
+    * identical decision sequences (steps, attempts, orders): the end states
+      agree within 0.1 WRMS, the Newton tolerance that defines each step's
+      result (rounding of near-zero components, weighted by 1/atol, is what
+      remains);
+    * a flipped decision: both runs must be equally accurate against a
+      tight-tolerance oracle run, and take a comparable number of steps."""
+    lin = kw.pop("linsol", 0)
+    ob = orc.Bdf(p, linsol=lin)
+    assert ob.integrate(p.t_end) == 0
+    gb = gpu_bdf(G, p, dev, linsol=lin, **kw)
+    t = gb.integrate(p.t_end)
+    assert t == p.t_end
+    so, sg = ob.stats(), gb.stats()
+    yg, yo = gb.y().cpu().numpy(), ob.y()
+    d = wrms_diff(yg, yo, p.rtol, p.atol)
+    print(f"{p.label}: steps oracle {so['nsteps']} gpu {sg['nsteps']}, attempts "
+          f"{so['nattempts']}/{sg['nattempts']}, wrms diff {d:.3e}")
+    if so["nsteps"] == sg["nsteps"] and so["nattempts"] == sg["nattempts"]:
+        assert so["order_hist"] == sg["order_hist"]
+        assert d <= 0.1
+    else:
+        ref = orc.Bdf(p, rtol=p.rtol * 1e-3, atol=p.atol * 1e-3)
+        assert ref.integrate(p.t_end) == 0
+        yr = ref.y()
+        eg, eo = wrms_diff(yg, yr, p.rtol, p.atol), wrms_diff(yo, yr, p.rtol, p.atol)
+        print(f"  decisions differ: error vs reference gpu {eg:.3e} oracle {eo:.3e}")
+        assert eg <= max(3.0 * eo, 1.0)
+        assert abs(so["nsteps"] - sg["nsteps"]) <= 0.15 * so["nsteps"]
+    return ob, gb
+
+
+def test_trajectory_robertson_bdf2(orc, dev, G):
+    compare_trajectory(orc, dev, G, W.robertson_batch(1000))
+
+
+def test_trajectory_network10(orc, dev, G):
+    compare_trajectory(orc, dev, G, W.random_network_batch(256, n=10, seed=31))
+
+
+def test_trajectory_network10_fp32_refined(orc, dev, G):
+    ob, gb = compare_trajectory(orc, dev, G, W.random_network_batch(256, n=10, seed=31), linsol=1)
+    assert gb.stats()["refine_sweeps"] > 0
+
+
+def test_trajectory_uneven(orc, dev, G):
+    compare_trajectory(orc, dev, G, W.uneven_batch(1 << 12, seed=9))
+
+
+def test_trajectory_n21(orc, dev, G):
+    compare_trajectory(orc, dev, G, W.learned_batch(64, seed=12))
+
+
+def test_small_odd_sizes(orc, dev, G):
+    # n = 1 (padded thread-per-cell), n = 5, and a ragged last tile
+    for n, cells in ((1, 65), (5, 130), (2, 3)):
+        p = W.linear_chain_batch(cells, n, seed=n)
+        compare_trajectory(orc, dev, G, p)
+
+
+def test_graph_mode_bitwise_equal_to_stream(dev, G):
+    p = W.random_network_batch(1000, n=10, seed=41)
+    a = gpu_bdf(G, p, dev, mode=G.MODE_STREAM)
+    b = gpu_bdf(G, p, dev, mode=G.MODE_GRAPH, attempts_per_sync=3)
+    a.integrate(1.0)
+    b.integrate(1.0)
+    b.integrate(p.t_end)     # graph replays across several host checks
+    a.integrate(p.t_end)
+    assert a.stats()["nsteps"] == b.stats()["nsteps"]
+    assert torch.equal(a.y(), b.y())
+
+
+def test_step_by_step_equals_integrate(dev, G):
+    p = W.robertson_batch(100)
+    a = gpu_bdf(G, p, dev)
+    b = gpu_bdf(G, p, dev)
+    a.integrate(1e-2)
+    t = 0.0
+    n = 0
+    while t < 1e-2:
+        t = b.step(1e-2)
+        n += 1
+    assert n == a.stats()["nsteps"] == b.stats()["nsteps"]
+    assert torch.equal(a.y(), b.y())
+
+
+def test_max_steps_error(dev, G):
+    p = W.robertson_batch(10)
+    b = gpu_bdf(G, p, dev, max_steps=4)
+    with pytest.raises(G.BdfGpuError) as e:
+        b.integrate(10.0)
+    assert e.value.code == -7
+
+
+def test_conservation_without_projection(dev, G):
+    # the method keeps sum(y) to rounding; a short horizon keeps every cell
+    # away from the negative-concentration regime
+    p = W.random_network_batch(4096, n=10, seed=8, t_end=1e-3)
+    b = gpu_bdf(G, p, dev, nonneg=False)
+    b.integrate(p.t_end)
+    y = b.y().cpu().numpy().reshape(-1, 10)
+    assert np.abs(y.sum(1) - p.y0.reshape(-1, 10).sum(1)).max() <= 1e-12
+
+
+def test_projection_large_batch(dev, G):
+    p = W.random_network_batch(4096, n=10, seed=8)
+    b = gpu_bdf(G, p, dev)
+    assert b.integrate(p.t_end) == p.t_end
+    y = b.y().cpu().numpy().reshape(-1, 10)
+    assert y.min() >= 0.0
+    assert np.abs(y.sum(1) - p.y0.reshape(-1, 10).sum(1)).max() <= 1e3 * p.atol
+    assert b.stats()["nprojections"] > 0

@@ -1,0 +1,144 @@
+"""GPU parity of the N_Vector operations against the CPU oracle.
+
+Streaming and reduction operations of Section 2 / Section 4.1.  Bar:
+componentwise |z - z_ref| <= 1e-12 * sum_j |c_j x_ji| for streaming
+operations, |d - d_ref| <= 1e-12 * sum_i |x_i y_i| for dot products,
+1e-12 relative for the WRMS norm; exact for max norm, ewt-free ops on
+integers.  Sizes span several launch tiles, a ragged tail, length 0 and 1,
+and misaligned (odd-offset) vectors.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 17, 4099, 1 << 18 | 3]
+
+
+def T(a, dev):
+    return torch.tensor(np.asarray(a, np.float64), device=dev)
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("nv", [1, 2, 7, 16])
+def test_linear_combination(orc, dev, G, n, nv):
+    X = W.uniform_vectors(nv, n, seed=11 + n)
+    c = W.uniform_coefficients(nv, seed=3 + nv)
+    Xd = [T(x, dev) for x in X]
+    z = torch.empty(n, dtype=torch.float64, device=dev)
+    G.nvec_linear_combination(c, Xd, z)
+    if n == 0:
+        return
+    ref = orc.linear_combination(c, list(X))
+    bound = 1e-12 * (np.abs(c[:, None] * X).sum(0)) + 1e-300
+    assert np.all(np.abs(z.cpu().numpy() - ref) <= bound)
+
+
+def test_linear_combination_misaligned_and_aliased(orc, dev, G):
+    n = 10001
+    X = W.uniform_vectors(3, n + 1, seed=5)
+    base = [T(x, dev) for x in X]
+    Xd = [b[1:] for b in base]               # 8-byte offset: scalar path
+    c = [0.5, -1.25, 2.0]
+    out = Xd[0]                              # z aliases X[0]
+    ref = orc.linear_combination(c, [x[1:] for x in X])
+    G.nvec_linear_combination(c, Xd, out)
+    bound = 1e-12 * np.abs(np.array(c)[:, None] * X[:, 1:]).sum(0)
+    assert np.all(np.abs(out.cpu().numpy() - ref) <= bound)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_linear_sum_scale_const_ewt(orc, dev, G, n):
+    rng = W.rng_for(40 + n)
+    x, y = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    xd, yd = T(x, dev), T(y, dev)
+    z = torch.empty(n, dtype=torch.float64, device=dev)
+    G.nvec_linear_sum(0.3, xd, -1.7, yd, z)
+    ref = orc.linear_sum(0.3, x, -1.7, y)
+    assert np.all(np.abs(z.cpu().numpy() - ref) <= 1e-12 * (0.3 * np.abs(x) + 1.7 * np.abs(y)) + 1e-300)
+    G.nvec_scale(2.5, xd, z)
+    assert np.array_equal(z.cpu().numpy(), orc.scale(2.5, x))
+    G.nvec_const(-3.0, z)
+    assert np.array_equal(z.cpu().numpy(), orc.const(-3.0, n))
+    G.nvec_ewt(xd, 1e-6, 1e-10, z)
+    assert np.allclose(z.cpu().numpy(), orc.ewt(x, 1e-6, 1e-10), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("nv", [1, 3, 6])
+def test_scale_add_multi(orc, dev, G, n, nv):
+    rng = W.rng_for(60 + n + nv)
+    x = rng.uniform(-1, 1, n)
+    Y = [rng.uniform(-1, 1, n) for _ in range(nv)]
+    a = rng.uniform(-1, 1, nv)
+    Zd = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(nv)]
+    G.nvec_scale_add_multi(a, T(x, dev), [T(v, dev) for v in Y], Zd)
+    ref = orc.scale_add_multi(a, x, Y)
+    for j in range(nv):
+        b = 1e-12 * (np.abs(a[j] * x) + np.abs(Y[j])) + 1e-300
+        assert np.all(np.abs(Zd[j].cpu().numpy() - ref[j]) <= b)
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("nv", [1, 8])
+def test_dot_prod_multi(orc, dev, G, n, nv):
+    rng = W.rng_for(80 + n)
+    x = rng.uniform(-1, 1, n)
+    Y = [rng.uniform(-1, 1, n) for _ in range(nv)]
+    d = G.nvec_dot_prod_multi(T(x, dev), [T(v, dev) for v in Y])
+    if n == 0:
+        assert d == [0.0] * nv
+        return
+    ref = orc.dot_prod_multi(x, Y)
+    for j in range(nv):
+        assert abs(d[j] - ref[j]) <= 1e-12 * np.abs(x * Y[j]).sum()
+    # device-result variant is asynchronous and gives the same numbers
+    out = torch.empty(nv, dtype=torch.float64, device=dev)
+    G.nvec_dot_prod_multi(T(x, dev), [T(v, dev) for v in Y], out=out)
+    assert np.array_equal(out.cpu().numpy(), np.array(d))
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_wrms_and_max(orc, dev, G, n):
+    x = W.uniform_vectors(1, n, seed=90 + n)[0]
+    w = W.weight_vector(n, seed=91 + n)
+    v = G.nvec_wrms_norm(T(x, dev), T(w, dev))
+    ref = orc.wrms_norm(x, w)
+    assert v == pytest.approx(ref, rel=1e-12, abs=0)
+    assert G.nvec_max_norm(T(x, dev)) == orc.max_norm(x)
+
+
+def test_wrms_constant_closed_form(dev, G):
+    n = 1 << 20
+    v = G.nvec_wrms_norm(torch.full((n,), -3.0, dtype=torch.float64, device=dev),
+                         torch.full((n,), 0.25, dtype=torch.float64, device=dev))
+    assert v == pytest.approx(0.75, rel=1e-15)
+
+
+def test_full_size_microbench_parity(orc, dev, G):
+    """The 2^26-element workload in the launch configuration the benchmark
+    times: sampled elements of the 16-vector combination against the oracle
+    element by element; the 8 dot products and the WRMS norm against the
+    oracle over the whole vectors."""
+    n = 1 << 26
+    X = [W.torch_uniform_device(n, seed=1000 + j, device=dev) for j in range(16)]
+    c = W.uniform_coefficients(16, seed=20242)
+    z = torch.empty(n, dtype=torch.float64, device=dev)
+    G.nvec_linear_combination(c, X, z)
+    idx = torch.tensor(np.sort(W.rng_for(7).choice(n, 4096, replace=False)), device=dev)
+    xs = torch.stack([x[idx] for x in X]).cpu().numpy()
+    ref = orc.linear_combination(c, list(xs))
+    bound = 1e-12 * np.abs(c[:, None] * xs).sum(0)
+    assert np.all(np.abs(z[idx].cpu().numpy() - ref) <= bound)
+    d = G.nvec_dot_prod_multi(X[0], X[1:9])
+    x0 = X[0].cpu().numpy()
+    for j in range(8):
+        yj = X[1 + j].cpu().numpy()
+        r = orc.dot_prod_multi(x0, [yj])[0]
+        assert abs(d[j] - r) <= 1e-12 * np.abs(x0 * yj).sum()
+    w = W.torch_uniform_device(n, seed=77, device=dev, lo=1e2, hi=1e8)
+    v = G.nvec_wrms_norm(X[2], w)
+    assert v == pytest.approx(orc.wrms_norm(X[2].cpu().numpy(), w.cpu().numpy()), rel=1e-12)

@@ -146,8 +146,9 @@ def test_robertson_against_radau(orc):
 
 
 def test_conservation_and_exact_end_time(orc):
+    # the method itself (no projection) keeps sum(y) to rounding
     p = W.random_network_batch(16, n=10, seed=77)
-    b = orc.Bdf(p)
+    b = orc.Bdf(p, nonneg=False)
     assert b.integrate(p.t_end) == 0
     y = b.y().reshape(16, 10)
     y0 = p.y0.reshape(16, 10)
@@ -192,9 +193,9 @@ def test_learned_identity_network_falls_back_to_lu(orc):
     z = np.zeros
     mlp = orc.MLP(z((hid, nin)), z(hid), z((hid, hid)), z(hid), z((nout, hid)), z(nout),
                   z(nin), np.ones(nin))
-    bl = orc.Bdf(p, linsol=orc.LS_LEARNED, mlp=mlp)
-    b64 = orc.Bdf(p)
-    bref = orc.Bdf(p, rtol=1e-10, atol=1e-14)
+    bl = orc.Bdf(p, linsol=orc.LS_LEARNED, mlp=mlp, nonneg=False)
+    b64 = orc.Bdf(p, nonneg=False)
+    bref = orc.Bdf(p, rtol=1e-10, atol=1e-14, nonneg=False)
     for b in (bl, b64, bref):
         assert b.integrate(p.t_end) == 0
     st = bl.stats()
@@ -214,3 +215,41 @@ def test_tstop_and_max_steps(orc):
     b = orc.Bdf(p)
     assert b.integrate(1e-3) == 0 and b.scalars()["t"] == 1e-3
     assert b.integrate(2e-3) == 0 and b.scalars()["t"] == 2e-3
+
+
+def test_nonnegativity_projection(orc):
+    """With the y >= 0 projection every accepted solution is non-negative, the
+    projected mass stays at the absolute-tolerance level, and the run agrees
+    with the unprojected one within the tolerance."""
+    p = W.random_network_batch(64, n=10, seed=77)
+    bp = orc.Bdf(p, nonneg=True)
+    bu = orc.Bdf(p, nonneg=False)
+    assert bp.integrate(p.t_end) == 0 and bu.integrate(p.t_end) == 0
+    y = bp.y()
+    assert y.min() >= 0.0
+    assert bp.stats()["nprojections"] > 0
+    drift = np.abs(y.reshape(64, 10).sum(1) - p.y0.reshape(64, 10).sum(1)).max()
+    assert drift <= 1e3 * p.atol
+    w = 1.0 / (p.rtol * np.abs(bu.y()) + p.atol)
+    assert np.sqrt(np.mean(((y - bu.y()) * w) ** 2)) <= 10.0
+
+
+def test_bimolecular_blowup_closed_form(orc):
+    """2A -> 2B with A < 0: dA/dt = -2 k A^2 has the closed form
+    A(t) = A0 / (1 + 2 k A0 t), which runs away to -infinity at
+    t* = 1 / (2 k |A0|).  The unprojected integrator follows the closed
+    form before t* and cannot pass it; this is why mass-action workloads use
+    the y >= 0 projection."""
+    nu = np.array([[2, 0]], np.int32)
+    mu = np.array([[0, 2]], np.int32)
+    k, A0 = 1e8, -1e-9
+    tstar = 1.0 / (2 * k * abs(A0))
+    p = one_cell_problem(nu, mu, [k], [A0, 1.0], rtol=1e-8, atol=1e-14)
+    b = orc.Bdf(p, nonneg=False)
+    assert b.integrate(0.5 * tstar) == 0
+    exact = A0 / (1 + 2 * k * A0 * 0.5 * tstar)
+    assert b.y()[0] == pytest.approx(exact, rel=1e-5)
+    assert b.y().sum() == pytest.approx(1.0 + A0, rel=1e-12)
+    b2 = orc.Bdf(p, nonneg=False, max_steps=3000)
+    st = b2.integrate(2 * tstar)
+    assert st != 0 and abs(b2.y()[0]) > 1e3 * abs(A0)

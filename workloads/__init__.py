@@ -131,7 +131,8 @@ class Problem(dict):
 
     Keys: topologies (list of (nu, mu)), cell_topo (int32[ncells]),
     rates (float64 concatenated per cell, R_c values each), y0 (float64
-    concatenated, n_c values each), rtol, atol, t0, t_end, qmax, label.
+    concatenated, n_c values each), rtol, atol, t0, t_end, qmax, nonneg
+    (non-negativity constraints on), label.
     """
     __getattr__ = dict.__getitem__
 
@@ -170,7 +171,7 @@ def robertson_batch(ncells: int = 1000, seed: int = BASE_SEED + 1,
     return Problem(topologies=[(nu, mu)], cell_topo=np.zeros(ncells, np.int32),
                    rates=rates.ravel().copy(), y0=y0.ravel().copy(),
                    rtol=1e-6, atol=1e-10, t0=0.0, t_end=10.0, qmax=2,
-                   label=f"robertson{ncells}x3")
+                   nonneg=True, label=f"robertson{ncells}x3")
 
 
 def random_network_batch(ncells: int, n: int = 10, seed: int = BASE_SEED + 3,
@@ -191,7 +192,7 @@ def random_network_batch(ncells: int, n: int = 10, seed: int = BASE_SEED + 3,
     y0 = simplex_states(rng, ncells, n).ravel()
     return Problem(topologies=[(nu, mu)], cell_topo=np.zeros(ncells, np.int32),
                    rates=rates.copy(), y0=y0.copy(), rtol=1e-6, atol=1e-10,
-                   t0=0.0, t_end=t_end, qmax=qmax,
+                   t0=0.0, t_end=t_end, qmax=qmax, nonneg=True,
                    label=f"net{ncells}x{n}")
 
 
@@ -216,7 +217,7 @@ def uneven_batch(total_unknowns: int, seed: int = BASE_SEED + 4,
     return Problem(topologies=topologies, cell_topo=cell_topo,
                    rates=np.concatenate(rates), y0=np.concatenate(y0),
                    rtol=1e-6, atol=1e-10, t0=0.0, t_end=t_end, qmax=5,
-                   label=f"uneven{total_unknowns}")
+                   nonneg=True, label=f"uneven{total_unknowns}")
 
 
 def learned_batch(ncells: int, n: int = 21, seed: int = BASE_SEED + 5,
