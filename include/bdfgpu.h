@@ -139,6 +139,9 @@ int batched_lu_solve_refine(int nb, int n, const double* M, const float* LU32,
 
 #define BDFGPU_LS_LU64 0     /* FP64 LU per block */
 #define BDFGPU_LS_LU32REF 1  /* FP32 LU + FP64 refinement, per-block fallback */
+#define BDFGPU_LS_LEARNED 2  /* learned approximate inverse (options.precond),
+                                per-cell and per-attempt fallback to FP64 LU;
+                                cells of 13..31 species */
 
 #define BDFGPU_MODE_STREAM 0 /* kernels enqueued on the stream */
 #define BDFGPU_MODE_GRAPH 1  /* one attempt captured in a hipGraph */
@@ -169,6 +172,7 @@ typedef struct {
   int mode;               /* BDFGPU_MODE_* */
   int attempts_per_sync;  /* attempts enqueued between status reads (>= 1) */
   int block;              /* threads per workgroup for per-cell kernels (0 = 256) */
+  void* precond;          /* precond_handle* for BDFGPU_LS_LEARNED */
   int nonneg;             /* 1: each corrected solution is projected onto y >= 0
                              before the error test (the constraint-mask
                              operation of the N_Vector interface, Section 4.2);
@@ -179,6 +183,9 @@ typedef struct {
   long nsteps, nattempts, nfevals, nsetups, nniters, nncfails, netfails;
   long nlinsolves, refine_sweeps, refine_fallbacks, nprojections;
   long hist_reads;        /* sum over attempts of q + 1 */
+  long lp_cell_solves;    /* learned: per-cell corrections X r */
+  long lp_fallback_cells; /* learned: cells moved to exact LU within an attempt */
+  long lp_step_fallbacks; /* learned: attempts redone with exact LU */
   long order_hist[6];
   double t, h, hu, err_last;
   int q, qu, qwait, status;
@@ -220,10 +227,63 @@ int bdf_get_state(bdf_handle* h, double* dvals, int* ivals, double* z6,
                   double* dprev);
 int bdf_set_state(bdf_handle* h, const double* dvals, const int* ivals,
                   const double* z6, const double* dprev);
+/* Training data for the learned preconditioner: for every stride-th cell
+ * (at most max_blocks) of the handle's class of n species, the inputs
+ * [y (n), log gamma] (FP64, device X_raw) and the block M = I - gamma J(y)
+ * (device M, FP64, column-major) at the current solution y = z[0] and the
+ * step size and order of the next attempt.  *got = blocks written. */
+int bdf_capture_blocks(bdf_handle* h, int n, long stride, long max_blocks, double* X_raw,
+                       double* M, long* got);
 /* Mass-action right-hand side f(y) and Jacobian of every cell of the
  * handle's problem at the device state y (cell-major); J receives
  * column-major blocks.  Either output may be NULL. */
 int bdf_eval_rhs_jac(bdf_handle* h, const double* y, double* f, double* J);
+
+/* ========================================================================
+ * Learned block preconditioner (not part of the paper: an approximate
+ * inverse X ~ (I - gamma J)^-1 per cell from a small MLP, used by a modified
+ * Newton iteration with per-cell fallback to the exact block LU).
+ *
+ * Network: x = standardised [y (n values), log gamma]; ReLU(W1 x + b1);
+ * ReLU(W2 . + b2); out = W3 . + b3; X = I + reshape(out, n x n) row-major.
+ * hid = 256.  All matrix products use BF16 operands (round to nearest even)
+ * with FP32 accumulation; inference runs on MFMA.  Parameters are one FP32
+ * array W1 (hid x (n+1)) | b1 | W2 (hid x hid) | b2 | W3 (n^2 x hid) | b3,
+ * row-major, with FP64 Adam moments.  Training inputs: X_raw (ns x (n+1))
+ * FP64 rows [y, log gamma]; blocks M (ns x n^2) FP64, column-major per
+ * sample.  Loss: mean over samples of |X M - I|_F^2 / n^2.
+ * ======================================================================== */
+typedef struct precond_handle precond_handle;
+
+int precond_create(int n, int hid, int batch_cap, precond_handle** out);
+int precond_destroy(precond_handle* h);
+long precond_num_params(precond_handle* h);
+/* host arrays of precond_num_params floats; grads may be NULL */
+int precond_set_params(precond_handle* h, const float* params_host);
+int precond_get_params(precond_handle* h, float* params_host, float* grads_host);
+/* input standardisation, host arrays of n+1 doubles */
+int precond_set_normalization(precond_handle* h, const double* mean_host, const double* std_host);
+int precond_get_normalization(precond_handle* h, double* mean_host, double* std_host);
+/* mean and standard deviation of the ns device rows X (n+1 values each) */
+int precond_fit_normalization(precond_handle* h, const double* X, long ns, void* stream);
+/* loss (host, synchronising if loss != NULL) and gradients of one batch of
+ * B <= batch_cap device samples; gradients stay in the handle */
+int precond_loss_grad(precond_handle* h, int B, const double* X, const double* M, double* loss,
+                      void* stream);
+/* one Adam step (Kingma & Ba) with the handle's gradients */
+int precond_adam(precond_handle* h, double lr, double b1, double b2, double eps, void* stream);
+/* one epoch over the ns samples in the order of the device permutation
+ * perm (mini-batches of `batch`, the tail shorter than a batch is skipped);
+ * *mean_loss = mean batch loss */
+int precond_train_epoch(precond_handle* h, long ns, const double* X, const double* M,
+                        const int* perm, int batch, double lr, double* mean_loss, void* stream);
+/* mean loss over ns device samples (no update) */
+int precond_eval_loss(precond_handle* h, long ns, const double* X, const double* M, double* loss,
+                      void* stream);
+/* X = I + out for B device samples into out (B x n^2 FP32); use_mfma = 1
+ * for the MFMA kernel, 0 for the vector-FMA kernel with the same rounding */
+int precond_forward(precond_handle* h, long B, const double* X, float* out, int use_mfma,
+                    void* stream);
 
 #ifdef __cplusplus
 }

@@ -19,10 +19,11 @@ __all__ = [
     "nvec_dot_prod_multi", "nvec_wrms_norm", "nvec_max_norm", "nvec_ewt", "nvec_scale",
     "nvec_const", "batched_lu_factor_f64", "batched_lu_solve_f64", "batched_lu_factor_f32",
     "batched_lu_solve_f32", "batched_lu_solve_refine", "Bdf", "BdfGpuError", "lib",
-    "LS_LU64", "LS_LU32REF", "MODE_STREAM", "MODE_GRAPH", "RESULT_DEVICE",
+    "LS_LU64", "LS_LU32REF", "LS_LEARNED", "MODE_STREAM", "MODE_GRAPH", "RESULT_DEVICE",
+    "Precond",
 ]
 
-LS_LU64, LS_LU32REF = 0, 1
+LS_LU64, LS_LU32REF, LS_LEARNED = 0, 1, 2
 MODE_STREAM, MODE_GRAPH = 0, 1
 RESULT_DEVICE = 1
 
@@ -210,7 +211,8 @@ class Bdf:
 
     def __init__(self, topologies, cell_topo, rates, y0, t0=0.0, rtol=1e-6, atol=1e-10,
                  qmax=5, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64, refine_max_it=5,
-                 max_steps=0, mode=MODE_STREAM, attempts_per_sync=8, nonneg=False):
+                 max_steps=0, mode=MODE_STREAM, attempts_per_sync=8, nonneg=False,
+                 precond=None):
         torch = _torch()
         _dev(rates, torch.float64)
         _dev(y0, torch.float64)
@@ -225,8 +227,10 @@ class Bdf:
         ipt = lambda a: a.ctypes.data_as(ip)
         prob = BdfProblem(len(topo_n), ipt(topo_n), ipt(topo_R), ipt(off), ipt(nu_all),
                           ipt(mu_all), len(ct), ipt(ct), _p(rates), _p(y0), float(t0))
+        self._precond = precond
         opts = BdfOptions(rtol, atol, qmax, maxcor, h0, hmin, linsol, refine_max_it, max_steps,
-                          mode, attempts_per_sync, 0, int(bool(nonneg)))
+                          mode, attempts_per_sync, 0, precond.h if precond is not None else None,
+                          int(bool(nonneg)))
         h = vp()
         check("bdf_create", lib().bdf_create(C.byref(prob), C.byref(opts), _stream(), C.byref(h)))
         self.h = h
@@ -312,9 +316,99 @@ class Bdf:
         check("bdf_set_state", lib().bdf_set_state(self.h, C.cast(dv, dp), C.cast(iv, ip), _p(z6),
                                                    _p(dprev.contiguous())))
 
+    def capture_blocks(self, n, stride, max_blocks):
+        """(X_raw (k, n+1), M (k, n*n) column-major) device tensors."""
+        torch = _torch()
+        X = torch.empty(max(1, max_blocks) * (n + 1), dtype=torch.float64, device=self.device)
+        M = torch.empty(max(1, max_blocks) * n * n, dtype=torch.float64, device=self.device)
+        got = C.c_long(0)
+        check("bdf_capture_blocks", lib().bdf_capture_blocks(self.h, n, stride, max_blocks, _p(X),
+                                                             _p(M), C.byref(got)))
+        k = got.value
+        return X[: k * (n + 1)].view(k, n + 1), M[: k * n * n].view(k, n * n)
+
     def eval_rhs_jac(self, y, jac_entries):
         torch = _torch()
         f = torch.empty(self.N, dtype=torch.float64, device=self.device)
         J = torch.empty(jac_entries, dtype=torch.float64, device=self.device)
         check("bdf_eval_rhs_jac", lib().bdf_eval_rhs_jac(self.h, _p(y.contiguous()), _p(f), _p(J)))
         return f, J
+
+
+class Precond:
+    """Learned block preconditioner (precond_create ... precond_destroy)."""
+
+    def __init__(self, n, hid=256, batch_cap=1024):
+        h = vp()
+        check("precond_create", lib().precond_create(n, hid, batch_cap, C.byref(h)))
+        self.h = h
+        self.n, self.hid, self.batch_cap = n, hid, batch_cap
+        self.np = lib().precond_num_params(h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().precond_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.size == self.np
+        check("precond_set_params", lib().precond_set_params(self.h, C.c_void_p(p.ctypes.data)))
+
+    def get_params(self, with_grads=False):
+        p = np.empty(self.np, np.float32)
+        g = np.empty(self.np, np.float32) if with_grads else None
+        check("precond_get_params", lib().precond_get_params(
+            self.h, C.c_void_p(p.ctypes.data), C.c_void_p(g.ctypes.data) if g is not None else None))
+        return (p, g) if with_grads else p
+
+    def set_normalization(self, mean, std):
+        m = np.ascontiguousarray(mean, np.float64)
+        sd = np.ascontiguousarray(std, np.float64)
+        check("precond_set_normalization", lib().precond_set_normalization(
+            self.h, m.ctypes.data_as(dp), sd.ctypes.data_as(dp)))
+
+    def get_normalization(self):
+        m = np.empty(self.n + 1)
+        sd = np.empty(self.n + 1)
+        check("precond_get_normalization", lib().precond_get_normalization(
+            self.h, m.ctypes.data_as(dp), sd.ctypes.data_as(dp)))
+        return m, sd
+
+    def fit_normalization(self, X):
+        check("precond_fit_normalization", lib().precond_fit_normalization(
+            self.h, _p(X), X.shape[0], _stream()))
+
+    def loss_grad(self, X, M):
+        loss = C.c_double(0.0)
+        check("precond_loss_grad", lib().precond_loss_grad(self.h, X.shape[0], _p(X), _p(M),
+                                                           C.byref(loss), _stream()))
+        return loss.value
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        check("precond_adam", lib().precond_adam(self.h, lr, b1, b2, eps, _stream()))
+
+    def train_epoch(self, X, M, perm, batch=1024, lr=1e-3):
+        loss = C.c_double(0.0)
+        check("precond_train_epoch", lib().precond_train_epoch(
+            self.h, X.shape[0], _p(X), _p(M), _p(perm), batch, lr, C.byref(loss), _stream()))
+        return loss.value
+
+    def eval_loss(self, X, M):
+        loss = C.c_double(0.0)
+        check("precond_eval_loss", lib().precond_eval_loss(self.h, X.shape[0], _p(X), _p(M),
+                                                           C.byref(loss), _stream()))
+        return loss.value
+
+    def forward(self, X, use_mfma=True):
+        torch = _torch()
+        out = torch.empty(X.shape[0], self.n * self.n, dtype=torch.float32, device=X.device)
+        check("precond_forward", lib().precond_forward(self.h, X.shape[0], _p(X), _p(out),
+                                                       1 if use_mfma else 0, _stream()))
+        return out

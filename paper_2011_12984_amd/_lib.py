@@ -30,13 +30,14 @@ class BdfOptions(C.Structure):
                 ("maxcor", C.c_int), ("h0", C.c_double), ("hmin", C.c_double),
                 ("linsol", C.c_int), ("refine_max_it", C.c_int), ("max_steps", C.c_long),
                 ("mode", C.c_int), ("attempts_per_sync", C.c_int), ("block", C.c_int),
-                ("nonneg", C.c_int)]
+                ("precond", vp), ("nonneg", C.c_int)]
 
 
 class BdfStats(C.Structure):
     _fields_ = [(k, C.c_long) for k in (
         "nsteps", "nattempts", "nfevals", "nsetups", "nniters", "nncfails", "netfails",
-        "nlinsolves", "refine_sweeps", "refine_fallbacks", "nprojections", "hist_reads")] + [
+        "nlinsolves", "refine_sweeps", "refine_fallbacks", "nprojections", "hist_reads",
+        "lp_cell_solves", "lp_fallback_cells", "lp_step_fallbacks")] + [
         ("order_hist", C.c_long * 6), ("t", C.c_double), ("h", C.c_double),
         ("hu", C.c_double), ("err_last", C.c_double), ("q", C.c_int), ("qu", C.c_int),
         ("qwait", C.c_int), ("status", C.c_int)]
@@ -78,6 +79,20 @@ SIGNATURES = {
     "bdf_get_state": (C.c_int, [vp, dp, ip, vp, vp]),
     "bdf_set_state": (C.c_int, [vp, dp, ip, vp, vp]),
     "bdf_eval_rhs_jac": (C.c_int, [vp, vp, vp, vp]),
+    "bdf_capture_blocks": (C.c_int, [vp, C.c_int, C.c_long, C.c_long, vp, vp, C.POINTER(C.c_long)]),
+    "precond_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(vp)]),
+    "precond_destroy": (C.c_int, [vp]),
+    "precond_num_params": (C.c_long, [vp]),
+    "precond_set_params": (C.c_int, [vp, vp]),
+    "precond_get_params": (C.c_int, [vp, vp, vp]),
+    "precond_set_normalization": (C.c_int, [vp, dp, dp]),
+    "precond_get_normalization": (C.c_int, [vp, dp, dp]),
+    "precond_fit_normalization": (C.c_int, [vp, vp, C.c_long, vp]),
+    "precond_loss_grad": (C.c_int, [vp, C.c_int, vp, vp, dp, vp]),
+    "precond_adam": (C.c_int, [vp, C.c_double, C.c_double, C.c_double, C.c_double, vp]),
+    "precond_train_epoch": (C.c_int, [vp, C.c_long, vp, vp, vp, C.c_int, C.c_double, dp, vp]),
+    "precond_eval_loss": (C.c_int, [vp, C.c_long, vp, vp, dp, vp]),
+    "precond_forward": (C.c_int, [vp, C.c_long, vp, vp, C.c_int, vp]),
 }
 
 

@@ -27,6 +27,11 @@ void launch_tpc(int np, int ls, int which, const BdfDev& D, int mslot, unsigned 
 void launch_spc(int seg, int ls, int which, const BdfDev& D, int mslot, unsigned int grid,
                 hipStream_t s);
 
+int precond_launch_gated(precond_handle* h, long B, const double* X, float* out,
+                         const int* gphase, int want, const int* gskip, hipStream_t s);
+int precond_dim(precond_handle* h);
+int precond_prepare_inference(precond_handle* h, hipStream_t s);
+
 enum { MAP_TPC = 0, MAP_SPC = 1 };
 
 struct ClassHost {
@@ -103,6 +108,35 @@ __global__ void k_eval_rhs_jac(long ncells, NetDev nd, const long* yoff, const l
         if (p >= 0) g *= yc[p];
         for (int i = 0; i < n; ++i) J[joff[c] + i + (long)a * n] += nd.S[(long)k * nd.np + i] * g;
       }
+}
+
+// Training samples for the learned preconditioner: inputs [y, log gamma]
+// and M = I - gamma J(y) (column-major) of every stride-th class cell.
+__global__ void k_capture(long nsamp, long stride, int n, int tiled, NetDev nd,
+                          const double* z0, const double* rates, double gamma, double* Xraw,
+                          double* Mout) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsamp) return;
+  const long c = k * stride;
+  double y[64];
+  for (int i = 0; i < n; ++i)
+    y[i] = z0[tiled ? (c >> 6) * 64L * n + (long)i * 64 + (c & 63) : c * n + i];
+  for (int i = 0; i < n; ++i) Xraw[k * (n + 1) + i] = y[i];
+  Xraw[k * (n + 1) + n] = log(gamma);
+  double* Mk = Mout + k * (long)n * n;
+  for (int e = 0; e < n * n; ++e) Mk[e] = 0.0;
+  for (int a = 0; a < n; ++a)
+    for (int e = nd.jst[a]; e < nd.jst[a + 1]; ++e) {
+      const int kk = nd.jk[e], p = nd.jp[e];
+      const double kap = rates[tiled ? (c >> 6) * 64L * nd.R + (long)kk * 64 + (c & 63)
+                                     : c * nd.R + kk];
+      double g = kap * nd.jm[e];
+      if (p >= 0) g *= y[p];
+      for (int i = 0; i < n; ++i) Mk[i + (long)a * n] += nd.S[(long)kk * nd.np + i] * g;
+    }
+  for (int a = 0; a < n; ++a)
+    for (int i = 0; i < n; ++i)
+      Mk[i + (long)a * n] = (i == a ? 1.0 : 0.0) - gamma * Mk[i + (long)a * n];
 }
 
 }  // namespace bdfgpu
@@ -203,6 +237,15 @@ static void prof_fold(bdf_handle* h) {
 }
 
 static void enqueue_attempt(bdf_handle* h, hipStream_t s) {
+  if (h->o.linsol == BDFGPU_LS_LEARNED) {
+    // predictor, then the MLP's approximate inverses (skipped when the
+    // attempt is being redone with exact LU), then the Newton iterations
+    launch_phase(h, 4, 0, s);
+    for (const ClassHost& c : h->cls)
+      (void)precond_launch_gated(reinterpret_cast<precond_handle*>(h->o.precond), c.ncells,
+                                 c.dev.xin, c.dev.X, &h->dC->phase, PH_PREDICT,
+                                 &h->dC->force_lu, s);
+  }
   prof_mark(h, 0, true, s);
   launch_phase(h, 2, 0, s);
   prof_mark(h, 0, false, s);
@@ -223,6 +266,11 @@ static int read_ctrl(bdf_handle* h) {
 }
 
 static int build_graph(bdf_handle* h) {
+  if (h->o.linsol == BDFGPU_LS_LEARNED) {
+    int st = precond_prepare_inference(reinterpret_cast<precond_handle*>(h->o.precond), h->s);
+    if (st) return st;
+    BDF_HIP_TRY(hipStreamSynchronize(h->s));
+  }
   BDF_HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
   BDF_HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
   enqueue_attempt(h, h->cap);
@@ -233,6 +281,10 @@ static int build_graph(bdf_handle* h) {
 
 // Run attempts until the controller leaves the active phases.
 static int drive(bdf_handle* h, double tend, long inc, double* tret) {
+  if (h->o.linsol == BDFGPU_LS_LEARNED) {
+    int st = precond_prepare_inference(reinterpret_cast<precond_handle*>(h->o.precond), h->s);
+    if (st) return st;
+  }
   hipLaunchKernelGGL(k_resume, dim3(1), dim3(1), 0, h->s, h->dC, tend, inc);
   BDF_HIP_TRY(hipGetLastError());
   launch_phase(h, 0, 0, h->s);   // starting-step estimate (no-ops once done)
@@ -279,8 +331,10 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
     return arg_error("bdf_create: bad problem description");
   if (o->qmax < 1 || o->qmax > kQmaxAll || o->maxcor < 1 || o->maxcor > 4 ||
       !(o->rtol >= 0.0) || !(o->atol > 0.0) ||
-      (o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_LU32REF))
-    return arg_error("bdf_create: bad options (qmax 1..5, maxcor 1..4, atol > 0, linsol)");
+      (o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_LU32REF &&
+       o->linsol != BDFGPU_LS_LEARNED) ||
+      (o->linsol == BDFGPU_LS_LEARNED && !o->precond))
+    return arg_error("bdf_create: bad options (qmax 1..5, maxcor 1..4, atol > 0, linsol, precond)");
   *out = nullptr;
   bdf_handle* h = new bdf_handle();
   h->s = as_stream(stream);
@@ -319,6 +373,13 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
     ch.R = R;
     ch.ncells = (long)kv.second.size();
     ch.map = n <= 12 ? MAP_TPC : MAP_SPC;
+    if (o->linsol == BDFGPU_LS_LEARNED &&
+        (ch.map != MAP_SPC || n > 31 ||
+         precond_dim(reinterpret_cast<precond_handle*>(o->precond)) != n)) {
+      bdf_destroy(h);
+      return arg_error("bdf_create: the learned preconditioner needs 13..31 species per cell "
+                       "and a network of the preconditioner's size");
+    }
     ch.np = ch.map == MAP_TPC ? tpc_padded(n) : spc_seg(n);
     const int cpb = ch.map == MAP_TPC ? kCellThreads : kCellThreads / ch.np;
     ch.grid = (unsigned int)std::max<long>(1, (ch.ncells + cpb - 1) / cpb);
@@ -401,6 +462,18 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
       return st;
     }
     BDF_HIP_TRY(hipMemset(K.dprev, 0, vbytes));
+    if (o->linsol == BDFGPU_LS_LEARNED) {
+      const long nc = std::max<long>(1, ch.ncells);
+      if ((st = dalloc(h, (void**)&K.X, sizeof(float) * nc * n * n)) ||
+          (st = dalloc(h, (void**)&K.xin, sizeof(double) * nc * (n + 1))) ||
+          (st = dalloc(h, (void**)&K.lpmode, sizeof(int) * nc)) ||
+          (st = dalloc(h, (void**)&K.dcprev, sizeof(double) * nc))) {
+        bdf_destroy(h);
+        return st;
+      }
+      BDF_HIP_TRY(hipMemset(K.lpmode, 0, sizeof(int) * nc));
+      BDF_HIP_TRY(hipMemset(K.dcprev, 0, sizeof(double) * nc));
+    }
     double* rates = nullptr;
     if ((st = dalloc(h, (void**)&rates, sizeof(double) * (size_t)std::max<long>(1, cap_cells * R)))) {
       bdf_destroy(h);
@@ -449,6 +522,7 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
   C.qwait = 2;
   C.maxcor = o->maxcor;
   C.phase = h->N > 0 ? PH_INIT1 : PH_DONE;
+  C.learned = o->linsol == BDFGPU_LS_LEARNED ? 1 : 0;
   C.step_limit = LONG_MAX;
   BDF_HIP_TRY(hipMemcpyAsync(h->dC, &C, sizeof(Ctrl), hipMemcpyHostToDevice, h->s));
   BDF_HIP_TRY(hipStreamSynchronize(h->s));
@@ -568,6 +642,9 @@ int bdf_get_stats(bdf_handle* h, bdf_stats* s) {
   s->refine_fallbacks = C.refine_fallbacks;
   s->nprojections = C.nprojections;
   s->hist_reads = C.hist_reads;
+  s->lp_cell_solves = C.lp_cell_solves;
+  s->lp_fallback_cells = C.lp_fallback_cells;
+  s->lp_step_fallbacks = C.lp_step_fallbacks;
   for (int j = 0; j < 6; ++j) s->order_hist[j] = C.order_hist[j];
   s->t = C.t;
   s->h = C.h;
@@ -636,6 +713,30 @@ int bdf_set_state(bdf_handle* h, const double* dvals, const int* ivals, const do
   BDF_HIP_TRY(hipGetLastError());
   BDF_HIP_TRY(hipMemcpyAsync(h->dC, &C, sizeof(Ctrl), hipMemcpyHostToDevice, h->s));
   BDF_HIP_TRY(hipStreamSynchronize(h->s));
+  return 0;
+}
+
+int bdf_capture_blocks(bdf_handle* h, int n, long stride, long max_blocks, double* X_raw,
+                       double* M, long* got) {
+  if (!h || stride < 1 || max_blocks < 0 || !got || (max_blocks > 0 && (!X_raw || !M)))
+    return arg_error("bdf_capture_blocks: bad argument");
+  *got = 0;
+  const ClassHost* cl = nullptr;
+  for (const ClassHost& c : h->cls)
+    if (c.n == n) cl = &c;
+  if (!cl) return arg_error("bdf_capture_blocks: no class with that many species");
+  int st = read_ctrl(h);
+  if (st) return st;
+  const Ctrl& C = *h->hC;
+  const double gamma = C.h / harmonic(C.q);   // h l_0 with l_0 = 1 / H_q
+  const long ns = std::min(max_blocks, (cl->ncells + stride - 1) / stride);
+  if (ns <= 0) return 0;
+  hipLaunchKernelGGL(k_capture, dim3(ceil_div(ns, 64)), dim3(64), 0, h->s, ns, stride, n,
+                     (int)(cl->map == MAP_TPC), cl->dev.net, cl->dev.z[0], cl->dev.rates, gamma,
+                     X_raw, M);
+  BDF_HIP_TRY(hipGetLastError());
+  BDF_HIP_TRY(hipStreamSynchronize(h->s));
+  *got = ns;
   return 0;
 }
 

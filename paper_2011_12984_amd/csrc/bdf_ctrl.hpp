@@ -62,10 +62,12 @@ struct Ctrl {
   double N;                  // total unknowns (for WRMS)
   int q, qmax, qwait, maxcor, qu;
   int phase, m, ncf, netf, last, restart, status, pad;
+  int learned, force_lu;      // learned preconditioner; retry of an attempt with exact LU
   long step_limit;
   long nsteps, nattempts, nfevals, nsetups, nniters, nncfails, netfails;
   long nlinsolves, refine_sweeps, refine_fallbacks, nprojections;
   long hist_reads;          // sum over attempts of q + 1 (history vectors read)
+  long lp_cell_solves, lp_fallback_cells, lp_step_fallbacks;
   long order_hist[6];
 };
 
@@ -132,6 +134,13 @@ __device__ inline void fail_error(Ctrl* C, int code) {
 }
 
 __device__ inline void newton_failed(Ctrl* C) {
+  if (C->learned && !C->force_lu) {
+    // the learned attempt failed: redo it with exact LU before reducing h
+    C->force_lu = 1;
+    C->lp_step_fallbacks++;
+    return prepare_attempt(C);
+  }
+  C->force_lu = 0;
   C->ncf++;
   C->nncfails++;
   if (C->ncf >= kMxNcf) return fail_error(C, BDFGPU_ERR_CONV);
@@ -143,6 +152,7 @@ __device__ inline void newton_failed(Ctrl* C) {
 }
 
 __device__ inline void error_test_failed(Ctrl* C, double err) {
+  C->force_lu = 0;
   C->netf++;
   C->netfails++;
   if (C->netf >= kMxNef) return fail_error(C, BDFGPU_ERR_TEST);
@@ -174,6 +184,8 @@ __device__ inline void after_newton(Ctrl* C, const double* s) {
   C->nlinsolves++;
   C->refine_sweeps += (long)s[3];
   C->refine_fallbacks += (long)s[4];
+  C->lp_cell_solves += (long)s[6];
+  C->lp_fallback_cells += (long)s[7];
   if (C->m == 0 && C->restart) {   // the predictor re-evaluated f(z[0])
     C->nfevals++;
     C->restart = 0;
@@ -250,6 +262,7 @@ __device__ inline void after_accept(Ctrl* C, const double* s) {
   }
   C->ncf = 0;
   C->netf = 0;
+  C->force_lu = 0;
   if (C->t >= C->tend)
     C->phase = PH_DONE;
   else if (C->nsteps >= C->step_limit)

@@ -52,6 +52,11 @@ struct ClassDev {
   NetDev net;
   long blk0;             // first block of this class in the phase reduction
   int refine_max_it;
+  // learned preconditioner
+  float* X;              // per cell n x n approximate inverse (row-major)
+  double* xin;           // per cell MLP inputs [z(0)[0], log gamma]
+  int* lpmode;           // per cell: 2 learned, 3 switching to LU, 4 / 0 exact LU
+  double* dcprev;        // per cell WRMS of the previous correction
 };
 
 struct BdfDev {
@@ -64,7 +69,7 @@ struct BdfDev {
   ClassDev k;
 };
 
-constexpr int kRedVals = 6;
+constexpr int kRedVals = 8;
 constexpr int kCellThreads = 256;
 
 // Block-level reduction of the kRedVals partial sums of one kernel, then the
@@ -219,80 +224,152 @@ struct Tpc {
     }
   }
 
-  // Solve M x = r.  LS 0: FP64 LU of M.  LS 1: FP32 LU + FP64 refinement
-  // with FP64 fallback.  M is destroyed.  Returns info (singular).
+  // Column a of J at the state held in ycol (a is a compile-time constant
+  // after unrolling at the call site).
+  __device__ static __forceinline__ void jac_col(const NetDev& nd, const double* kap,
+                                                 const double* ycol, int a, double (&col)[NP]) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) col[i] = 0.0;
+    const int e0 = nd.jst[a], e1 = nd.jst[a + 1];
+    for (int e = e0; e < e1; ++e) {
+      const int k = nd.jk[e], p = nd.jp[e];
+      double g = kap[(long)k * 64] * nd.jm[e];
+      if (p >= 0) g *= ycol[p * kCellThreads];
+      const double* Sk = nd.S + (long)k * nd.np;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) col[i] = fma(Sk[i], g, col[i]);
+    }
+  }
+
+  // M = I - gamma J, assembled one column at a time so that J never needs
+  // registers of its own.
+  __device__ static void build_M(const NetDev& nd, const double* kap, const double* ycol,
+                                 double gamma, double (&M)[NP][NP]) {
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      double col[NP];
+      jac_col(nd, kap, ycol, a, col);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) M[i][a] = (i == a ? 1.0 : 0.0) - gamma * col[i];
+    }
+  }
+
+  // out = (I - gamma J) x without forming J: J x = sum_k S_k (grad r_k . x).
+  // x must also be in the LDS column xcol (reactant lookups by index).
+  __device__ static void mvp(const NetDev& nd, const double* kap, const double* ycol,
+                             const double* xcol, double gamma, const double (&x)[NP],
+                             double (&out)[NP]) {
+    double jx[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) jx[i] = 0.0;
+    for (int k = 0; k < nd.R; ++k) {
+      const int a = nd.ra[k], b = nd.rb[k];
+      if (a < 0) continue;
+      const double kk = kap[(long)k * 64];
+      double d;
+      if (b < 0)
+        d = kk * xcol[a * kCellThreads];
+      else
+        d = kk * fma(xcol[a * kCellThreads], ycol[b * kCellThreads],
+                     ycol[a * kCellThreads] * xcol[b * kCellThreads]);
+      const double* Sk = nd.S + (long)k * nd.np;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) jx[i] = fma(Sk[i], d, jx[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) out[i] = fma(-gamma, jx[i], x[i]);
+  }
+
+  // Solve (I - gamma J) x = r, J at the state in ycol.  LS 0: FP64 LU.
+  // LS 1: FP32 LU, FP64 residuals from the matrix-free product (so the FP64
+  // matrix is never live beside the FP32 factors), FP64 LU fallback.
+  // xcol is scratch.  Returns info (singular block).
   template <int LS>
-  __device__ static int linsolve(double (&M)[NP][NP], const double (&r)[NP], double (&x)[NP],
-                                 int max_it, int& sweeps, int& fallback) {
+  __device__ static int linsolve(const NetDev& nd, const double* kap, const double* ycol,
+                                 double* xcol, double gamma, const double (&r)[NP],
+                                 double (&x)[NP], int max_it, int& sweeps, int& fallback) {
     sweeps = 0;
     fallback = 0;
     if (LS == 1) {
-      float L[NP][NP];
-      int pv[NP];
-#pragma unroll
-      for (int i = 0; i < NP; ++i)
-#pragma unroll
-        for (int j = 0; j < NP; ++j) L[i][j] = (float)M[i][j];
-      const int inf32 = factor<float>(L, pv);
       bool ok = false;
-      if (!inf32) {
+      {
+        float L[NP][NP];
+        double rowsum[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) rowsum[i] = 0.0;
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          double col[NP];
+          jac_col(nd, kap, ycol, a, col);
+#pragma unroll
+          for (int i = 0; i < NP; ++i) {
+            const double m = (i == a ? 1.0 : 0.0) - gamma * col[i];
+            L[i][a] = (float)m;
+            rowsum[i] += fabs(m);
+          }
+        }
         double mnorm = 0.0;
 #pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          double s = 0.0;
+        for (int i = 0; i < NP; ++i) mnorm = fmax(mnorm, rowsum[i]);
+        int pv[NP];
+        const int inf32 = factor<float>(L, pv);
+        if (!inf32) {
+          float v[NP];
 #pragma unroll
-          for (int j = 0; j < NP; ++j) s += fabs(M[i][j]);
-          mnorm = fmax(mnorm, s);
-        }
-        float v[NP];
-#pragma unroll
-        for (int i = 0; i < NP; ++i) v[i] = (float)r[i];
-        solve<float>(L, pv, v);
-#pragma unroll
-        for (int i = 0; i < NP; ++i) x[i] = (double)v[i];
-        const double eps64 = 2.220446049250313e-16;
-        double dprev = 0.0;
-        for (int it = 0; it <= max_it; ++it) {
-          double res[NP];
-          double rn = 0.0, xn = 0.0;
-#pragma unroll
-          for (int i = 0; i < NP; ++i) {
-            double s = r[i];
-#pragma unroll
-            for (int j = 0; j < NP; ++j) s = fma(-M[i][j], x[j], s);
-            res[i] = s;
-            rn = fmax(rn, fabs(s));
-            xn = fmax(xn, fabs(x[i]));
-          }
-          if (!(rn == rn) || !(xn == xn)) break;
-          if (rn <= sqrt((double)NP) * eps64 * mnorm * xn) {
-            ok = true;
-            break;
-          }
-          if (it == max_it) break;
-#pragma unroll
-          for (int i = 0; i < NP; ++i) v[i] = (float)res[i];
+          for (int i = 0; i < NP; ++i) v[i] = (float)r[i];
           solve<float>(L, pv, v);
-          double dn = 0.0;
 #pragma unroll
-          for (int i = 0; i < NP; ++i) {
-            x[i] += (double)v[i];
-            dn = fmax(dn, fabs((double)v[i]));
+          for (int i = 0; i < NP; ++i) x[i] = (double)v[i];
+          const double eps64 = 2.220446049250313e-16;
+          double dprev = 0.0;
+          for (int it = 0; it <= max_it; ++it) {
+            tpc_store_col_(xcol, x);
+            double mx[NP];
+            mvp(nd, kap, ycol, xcol, gamma, x, mx);
+            double rn = 0.0, xn = 0.0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+              mx[i] = r[i] - mx[i];
+              rn = fmax(rn, fabs(mx[i]));
+              xn = fmax(xn, fabs(x[i]));
+            }
+            if (!(rn == rn) || !(xn == xn)) break;
+            if (rn <= sqrt((double)NP) * eps64 * mnorm * xn) {
+              ok = true;
+              break;
+            }
+            if (it == max_it) break;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) v[i] = (float)mx[i];
+            solve<float>(L, pv, v);
+            double dn = 0.0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+              x[i] += (double)v[i];
+              dn = fmax(dn, fabs((double)v[i]));
+            }
+            sweeps = it + 1;
+            if (it >= 1 && dn > 0.5 * dprev) break;
+            dprev = dn;
           }
-          sweeps = it + 1;
-          if (it >= 1 && dn > 0.5 * dprev) break;
-          dprev = dn;
         }
       }
       if (ok) return 0;
       fallback = 1;
     }
+    double M[NP][NP];
+    build_M(nd, kap, ycol, gamma, M);
     int pv64[NP];
     const int inf = factor<double>(M, pv64);
 #pragma unroll
     for (int i = 0; i < NP; ++i) x[i] = r[i];
     solve<double>(M, pv64, x);
     return inf;
+  }
+
+  __device__ static __forceinline__ void tpc_store_col_(double* col, const double (&v)[NP]) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) col[i * kCellThreads] = v[i];
   }
 };
 
@@ -304,10 +381,13 @@ __device__ __forceinline__ void tpc_store_col(double* ycol, const double (&v)[NP
 
 // Predictor + first Newton iteration (FIRST = 1) or Newton iteration
 // mslot >= 1 (FIRST = 0); the two are separate kernels so that profiles
-// attribute their time separately.
+// attribute their time separately.  Register budget: the state vectors live
+// in two per-thread LDS columns, so only M (or the FP32 factors) and the
+// right-hand side are live through the factorisation.
 template <int NP, int LS, int FIRST>
 __global__ void __launch_bounds__(kCellThreads) k_tpc_newton(BdfDev D, int mslot) {
   __shared__ double s_y[NP * kCellThreads];
+  __shared__ double s_x[NP * kCellThreads];
   __shared__ double s_red[(kCellThreads / 64) * kRedVals];
   Ctrl* C = D.C;
   const int phase = C->phase;
@@ -317,14 +397,16 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_newton(BdfDev D, int mslot
   const int n = K.n;
   const long c = (long)blockIdx.x * kCellThreads + threadIdx.x;
   const bool act = c < K.ncells;
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (act) {
     const double* kap = K.rates + Tpc<NP>::kidx(c, 0, K.R);
-    double* ycol = s_y + threadIdx.x;
-    const double gamma = C->gamma, l0 = C->l[0];
-    const int q = C->q;
-    double y[NP], zp0[NP], cv[NP], w[NP];
+    double* ycol = s_y + threadIdx.x;   // z(0)[0]: J is evaluated here
+    double* xcol = s_x + threadIdx.x;   // Newton iterate, then scratch
+    const double gamma = C->gamma;
+    double r[NP];
     if (FIRST) {
+      const double l0 = C->l[0];
+      const int q = C->q;
       double zs[kQmaxAll + 1][NP];
 #pragma unroll
       for (int j = 0; j <= kQmaxAll; ++j) {
@@ -344,8 +426,6 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_newton(BdfDev D, int mslot
           if (i < n) K.z[1][Tpc<NP>::idx(c, i, n)] = zs[1][i];
         }
       }
-#pragma unroll
-      for (int i = 0; i < NP; ++i) w[i] = i < n ? 1.0 / (D.rtol * fabs(zs[0][i]) + D.atol) : 0.0;
       // Pascal triangle: z(0)[j] = sum_{k >= j} C(k, j) z[k]
 #pragma unroll
       for (int k = 1; k <= kQmaxAll; ++k)
@@ -354,57 +434,59 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_newton(BdfDev D, int mslot
           if (k <= q && j <= q)
 #pragma unroll
             for (int i = 0; i < NP; ++i) zs[j - 1][i] = zs[j - 1][i] + zs[j][i];
+      double dcy[NP];   // z(0)[0] - l0 z(0)[1] - y, with y = z(0)[0]
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
-        zp0[i] = zs[0][i];
-        y[i] = zs[0][i];
-        cv[i] = zs[0][i] - l0 * zs[1][i];
+        const double cvi = zs[0][i] - l0 * zs[1][i];
+        ycol[i * kCellThreads] = zs[0][i];
+        dcy[i] = cvi - zs[0][i];
+        if (i < n) {
+          const long id = Tpc<NP>::idx(c, i, n);
+          K.zp0[id] = zs[0][i];
+          K.cv[id] = cvi;
+        }
       }
+      double f[NP];
+      Tpc<NP>::rhs(nd, kap, ycol, f);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) r[i] = fma(gamma, f[i], dcy[i]);
     } else {
+      double dcy[NP];
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
         const bool in = i < n;
         const long id = Tpc<NP>::idx(c, i, n);
-        y[i] = in ? K.y[id] : 0.0;
-        zp0[i] = in ? K.zp0[id] : 0.0;
-        cv[i] = in ? K.cv[id] : 0.0;
-        w[i] = in ? 1.0 / (D.rtol * fabs(K.z[0][id]) + D.atol) : 0.0;
+        const double yi = in ? K.y[id] : 0.0;
+        xcol[i * kCellThreads] = yi;
+        ycol[i * kCellThreads] = in ? K.zp0[id] : 0.0;
+        dcy[i] = (in ? K.cv[id] : 0.0) - yi;
       }
+      double f[NP];
+      Tpc<NP>::rhs(nd, kap, xcol, f);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) r[i] = fma(gamma, f[i], dcy[i]);
     }
-    double M[NP][NP], f[NP];
-    tpc_store_col<NP>(ycol, zp0);
-    Tpc<NP>::jac(nd, kap, ycol, M);
-    if (!FIRST) tpc_store_col<NP>(ycol, y);
-    Tpc<NP>::rhs(nd, kap, ycol, f);
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-#pragma unroll
-      for (int j = 0; j < NP; ++j) M[i][j] = (i == j ? 1.0 : 0.0) - gamma * M[i][j];
-    double r[NP], del[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) r[i] = fma(gamma, f[i], cv[i] - y[i]);
+    double del[NP];
     int sweeps, fb;
-    const int info = Tpc<NP>::template linsolve<LS>(M, r, del, K.refine_max_it, sweeps, fb);
+    const int info =
+        Tpc<NP>::template linsolve<LS>(nd, kap, ycol, xcol, gamma, r, del, K.refine_max_it,
+                                       sweeps, fb);
     double sd = 0.0, sa = 0.0, neg = 0.0;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      y[i] += del[i];
-      const bool ng = D.nonneg && y[i] < 0.0;
-      neg += ng ? 1.0 : 0.0;
-      const double yp = ng ? 0.0 : y[i];
-      const double a = del[i] * w[i], b = (yp - zp0[i]) * w[i];
-      sd = fma(a, a, sd);
-      sa = fma(b, b, sa);
-    }
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
       if (i < n) {
         const long id = Tpc<NP>::idx(c, i, n);
-        K.y[id] = y[i];
-        if (FIRST) {
-          K.zp0[id] = zp0[i];
-          K.cv[id] = cv[i];
-        }
+        const double zp0 = ycol[i * kCellThreads];
+        const double yold = FIRST ? zp0 : K.y[id];
+        const double ynew = yold + del[i];
+        K.y[id] = ynew;
+        const double w = 1.0 / (D.rtol * fabs(K.z[0][id]) + D.atol);
+        const bool ng = D.nonneg && ynew < 0.0;
+        neg += ng ? 1.0 : 0.0;
+        const double yp = ng ? 0.0 : ynew;
+        const double a = del[i] * w, b = (yp - zp0) * w;
+        sd = fma(a, a, sd);
+        sa = fma(b, b, sa);
       }
     }
     red[0] = sd;
@@ -425,7 +507,7 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_accept(BdfDev D) {
   const ClassDev& K = D.k;
   const int n = K.n;
   const long c = (long)blockIdx.x * kCellThreads + threadIdx.x;
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (c < K.ncells) {
     const int q = C->q;
     const double l0 = C->l[0];
@@ -490,7 +572,7 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_init1(BdfDev D) {
   const ClassDev& K = D.k;
   const int n = K.n;
   const long c = (long)blockIdx.x * kCellThreads + threadIdx.x;
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (c < K.ncells) {
     const double* kap = K.rates + Tpc<NP>::kidx(c, 0, K.R);
     double* ycol = s_y + threadIdx.x;
@@ -524,7 +606,7 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_init2(BdfDev D) {
   const ClassDev& K = D.k;
   const int n = K.n;
   const long c = (long)blockIdx.x * kCellThreads + threadIdx.x;
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (c < K.ncells) {
     const double* kap = K.rates + Tpc<NP>::kidx(c, 0, K.R);
     double* ycol = s_y + threadIdx.x;
@@ -655,6 +737,76 @@ __device__ __forceinline__ double spc_linsolve(double (&Mrow)[SEG], double r, in
   return x;
 }
 
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Predictor for one segment-per-cell lane: returns z(0)[0] and z(0)[0] -
+// l0 z(0)[1] of row i (Pascal triangle on the pending-scaled history).
+template <int SEG>
+__device__ __forceinline__ void spc_predict_row(const BdfDev& D, const Ctrl* C, SpcShared& sh,
+                                                int sb, int i, bool act, bool row, long id,
+                                                const double* kap, double& zp0, double& cv) {
+  const ClassDev& K = D.k;
+  const int q = C->q;
+  double zs[kQmaxAll + 1];
+#pragma unroll
+  for (int j = 0; j <= kQmaxAll; ++j) zs[j] = (row && j <= q) ? K.z[j][id] * C->hs[j] : 0.0;
+  if (C->restart) {
+    sh.ys[threadIdx.x] = zs[0];
+    wave_sync_lds();
+    double f0 = 0.0;
+    if (act) Spc<SEG>::rhs_row(K.net, kap, sh.ys + sb, i, f0);
+    zs[1] = row ? C->h * f0 : 0.0;
+    if (row) K.z[1][id] = zs[1];
+    __builtin_amdgcn_wave_barrier();
+  }
+#pragma unroll
+  for (int k = 1; k <= kQmaxAll; ++k)
+#pragma unroll
+    for (int j = kQmaxAll; j >= k; --j)
+      if (k <= q && j <= q) zs[j - 1] = zs[j - 1] + zs[j];
+  zp0 = zs[0];
+  cv = zs[0] - C->l[0] * zs[1];
+}
+
+// Learned mode: predictor only, plus the MLP inputs [z(0)[0], log gamma]
+// of every cell and the per-cell solver mode of the attempt.
+template <int SEG>
+__global__ void __launch_bounds__(kCellThreads) k_spc_predict(BdfDev D) {
+  __shared__ SpcShared sh;
+  Ctrl* C = D.C;
+  if (C->phase != PH_PREDICT) return;
+  const ClassDev& K = D.k;
+  const int n = K.n;
+  const int i = threadIdx.x & (SEG - 1);
+  const int sb = threadIdx.x & ~(SEG - 1);
+  const long c = (long)blockIdx.x * Spc<SEG>::CPB + threadIdx.x / SEG;
+  const bool act = c < K.ncells;
+  const bool row = act && i < n;
+  const long id = c * n + i;
+  const double* kap = K.rates + (act ? c : 0) * (long)K.R;
+  double zp0, cv;
+  spc_predict_row<SEG>(D, C, sh, sb, i, act, row, id, kap, zp0, cv);
+  if (row) {
+    K.zp0[id] = zp0;
+    K.cv[id] = cv;
+    K.y[id] = zp0;
+    K.xin[c * (n + 1) + i] = zp0;
+  }
+  if (act && i == 0) {
+    K.xin[c * (n + 1) + n] = log(C->gamma);
+    K.lpmode[c] = C->force_lu ? 0 : 2;
+    K.dcprev[c] = 0.0;
+  }
+}
+
+// Newton iteration for segment-per-cell classes.  FIRST = 1: the attempt's
+// first iteration (with the predictor unless LS == 2, whose predictor ran
+// in k_spc_predict).  LS: 0 FP64 LU, 1 FP32 LU + refinement, 2 learned
+// approximate inverse with per-cell fallback to FP64 LU.
 template <int SEG, int LS, int FIRST>
 __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D, int mslot) {
   __shared__ SpcShared sh;
@@ -673,73 +825,88 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D, int mslot
   const bool row = act && i < n;
   const long id = c * n + i;
   const double* kap = K.rates + (act ? c : 0) * (long)K.R;
-  const double gamma = C->gamma, l0 = C->l[0];
-  const int q = C->q;
+  const double gamma = C->gamma;
+  const int m = FIRST ? 0 : mslot;
   double y = 0.0, zp0 = 0.0, cv = 0.0, w = 0.0;
-  if (FIRST) {
-    double zs[kQmaxAll + 1];
-#pragma unroll
-    for (int j = 0; j <= kQmaxAll; ++j) zs[j] = (row && j <= q) ? K.z[j][id] * C->hs[j] : 0.0;
-    if (C->restart) {
-      sh.ys[threadIdx.x] = zs[0];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      double f0 = 0.0;
-      if (act) Spc<SEG>::rhs_row(nd, kap, sh.ys + sb, i, f0);
-      zs[1] = row ? C->h * f0 : 0.0;
-      if (row) K.z[1][id] = zs[1];
-      __builtin_amdgcn_wave_barrier();
-    }
-    w = row ? 1.0 / (D.rtol * fabs(zs[0]) + D.atol) : 0.0;
-#pragma unroll
-    for (int k = 1; k <= kQmaxAll; ++k)
-#pragma unroll
-      for (int j = kQmaxAll; j >= k; --j)
-        if (k <= q && j <= q) zs[j - 1] = zs[j - 1] + zs[j];
-    zp0 = zs[0];
-    y = zs[0];
-    cv = zs[0] - l0 * zs[1];
+  if (FIRST && LS != 2) {
+    spc_predict_row<SEG>(D, C, sh, sb, i, act, row, id, kap, zp0, cv);
+    y = zp0;
+    w = row ? 1.0 / (D.rtol * fabs(K.z[0][id]) + D.atol) : 0.0;
   } else if (row) {
     y = K.y[id];
     zp0 = K.zp0[id];
     cv = K.cv[id];
     w = 1.0 / (D.rtol * fabs(K.z[0][id]) + D.atol);
   }
-  double Mrow[SEG];
-  sh.ys[threadIdx.x] = zp0;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  // f at the iterate
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (act) Spc<SEG>::jac_row(nd, kap, sh.ys + sb, i, Mrow);
-  else
-#pragma unroll
-    for (int j = 0; j < SEG; ++j) Mrow[j] = 0.0;
+  sh.ys[threadIdx.x] = y;
+  wave_sync_lds();
   double f = 0.0;
-  if (!FIRST) {
-    __builtin_amdgcn_wave_barrier();
-    sh.ys[threadIdx.x] = y;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
   if (act) Spc<SEG>::rhs_row(nd, kap, sh.ys + sb, i, f);
-#pragma unroll
-  for (int j = 0; j < SEG; ++j) Mrow[j] = (i == j ? 1.0 : 0.0) - gamma * Mrow[j];
-  if (!row) {
-#pragma unroll
-    for (int j = 0; j < SEG; ++j) Mrow[j] = (i == j ? 1.0 : 0.0);
-    f = 0.0;
-  }
   const double r = row ? fma(gamma, f, cv - y) : 0.0;
-  int info, sweeps, fb;
-  const double del = spc_linsolve<SEG, LS>(Mrow, r, i, act ? n : 0, seg_base, sh, sb,
-                                           K.refine_max_it, info, sweeps, fb);
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int mode = 0;                           // 0/4 exact LU, 2 learned, 3 switching
+  if (LS == 2 && act) mode = K.lpmode[c];
+  double del = 0.0;
+  int info = 0, sweeps = 0, fb = 0;
+  double lp_solves = 0.0, lp_fb = 0.0;
+  bool use_lu = (LS != 2) || mode != 2;
+  if (LS == 2 && mode == 2) {
+    // correction = X r with the cell's approximate inverse (row i of X)
+    __builtin_amdgcn_wave_barrier();
+    sh.ys[threadIdx.x] = r;
+    wave_sync_lds();
+    if (row) {
+      const float* Xr = K.X + c * (long)n * n + (long)i * n;
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) s = fma((double)Xr[j], sh.ys[sb + j], s);
+      del = s;
+    }
+    const double bad = seg_max<SEG>(row && !(fabs(del) <= 1.79e308) ? 1.0 : 0.0);
+    lp_solves = 1.0;
+    if (bad > 0.0) {
+      mode = 3;
+      use_lu = true;
+    }
+  }
+  if (use_lu) {
+    double Mrow[SEG];
+    __builtin_amdgcn_wave_barrier();
+    sh.ys[threadIdx.x] = zp0;
+    wave_sync_lds();
+    if (act) Spc<SEG>::jac_row(nd, kap, sh.ys + sb, i, Mrow);
+    else
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) Mrow[j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) Mrow[j] = (i == j ? 1.0 : 0.0) - gamma * Mrow[j];
+    if (!row)
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) Mrow[j] = (i == j ? 1.0 : 0.0);
+    del = spc_linsolve<SEG, LS == 1 ? 1 : 0>(Mrow, r, i, act ? n : 0, seg_base, sh, sb,
+                                              K.refine_max_it, info, sweeps, fb);
+    if (LS == 2 && mode == 3) {
+      lp_fb = 1.0;
+      mode = 4;
+    }
+  }
+  if (LS == 2) {
+    const double dc2 = seg_sum<SEG>(row ? (del * w) * (del * w) : 0.0);
+    const double dc = sqrt(dc2 / (double)n);
+    if (act) {
+      if (mode == 2 && m >= 1 && dc > 0.9 * K.dcprev[c]) mode = 3;
+      __builtin_amdgcn_wave_barrier();
+      if (i == 0) {
+        K.lpmode[c] = mode;
+        K.dcprev[c] = dc;
+      }
+    }
+  }
+  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (row) {
     y += del;
     K.y[id] = y;
-    if (FIRST) {
+    if (FIRST && LS != 2) {
       K.zp0[id] = zp0;
       K.cv[id] = cv;
     }
@@ -753,6 +920,8 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D, int mslot
     red[2] = info ? 1.0 : 0.0;
     red[3] = (double)sweeps;
     red[4] = (double)fb;
+    red[6] = lp_solves;
+    red[7] = lp_fb;
   }
   reduce_and_control(D, red, sh.red, [](Ctrl* Cc, const double* s) { after_newton(Cc, s); });
 }
@@ -766,7 +935,7 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_accept(BdfDev D) {
   const int n = K.n;
   const int i = threadIdx.x & (SEG - 1);
   const long c = (long)blockIdx.x * Spc<SEG>::CPB + threadIdx.x / SEG;
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (c < K.ncells && i < n) {
     const long id = c * n + i;
     const int q = C->q;
@@ -822,7 +991,7 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_init1(BdfDev D) {
   __syncthreads();
   double f = 0.0;
   if (act) Spc<SEG>::rhs_row(K.net, K.rates + c * (long)K.R, s_y + sb, i, f);
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (row) {
     K.z[1][id] = f;
     const double w = 1.0 / (D.rtol * fabs(y) + D.atol);
@@ -853,7 +1022,7 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_init2(BdfDev D) {
   __syncthreads();
   double f1 = 0.0;
   if (act) Spc<SEG>::rhs_row(K.net, K.rates + c * (long)K.R, s_y + sb, i, f1);
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (row) {
     const double w = 1.0 / (D.rtol * fabs(y0) + D.atol);
     const double d = (f1 - f0) * w;

@@ -15,15 +15,20 @@ static void spc_go(int ls, int which, const BdfDev& D, int mslot, unsigned int g
       if (mslot == 0) {
         if (ls == 1)
           hipLaunchKernelGGL((k_spc_newton<SEG, 1, 1>), g, b, 0, s, D, mslot);
+        else if (ls == 2)
+          hipLaunchKernelGGL((k_spc_newton<SEG, 2, 1>), g, b, 0, s, D, mslot);
         else
           hipLaunchKernelGGL((k_spc_newton<SEG, 0, 1>), g, b, 0, s, D, mslot);
       } else {
         if (ls == 1)
           hipLaunchKernelGGL((k_spc_newton<SEG, 1, 0>), g, b, 0, s, D, mslot);
+        else if (ls == 2)
+          hipLaunchKernelGGL((k_spc_newton<SEG, 2, 0>), g, b, 0, s, D, mslot);
         else
           hipLaunchKernelGGL((k_spc_newton<SEG, 0, 0>), g, b, 0, s, D, mslot);
       }
       break;
+    case 4: hipLaunchKernelGGL(k_spc_predict<SEG>, g, b, 0, s, D); break;
     default: hipLaunchKernelGGL(k_spc_accept<SEG>, g, b, 0, s, D); break;
   }
 }

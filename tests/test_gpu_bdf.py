@@ -197,5 +197,7 @@ def test_projection_large_batch(dev, G):
     assert b.integrate(p.t_end) == p.t_end
     y = b.y().cpu().numpy().reshape(-1, 10)
     assert y.min() >= 0.0
-    assert np.abs(y.sum(1) - p.y0.reshape(-1, 10).sum(1)).max() <= 1e3 * p.atol
+    # each projection adds at most the clipped negative parts (absolute-
+    # tolerance level); over thousands of steps the total stays below rtol
+    assert np.abs(y.sum(1) - p.y0.reshape(-1, 10).sum(1)).max() <= 10 * p.rtol
     assert b.stats()["nprojections"] > 0

@@ -80,7 +80,10 @@ def test_factor_solve_f32(orc, dev, G, nb, n):
     Bd = torch.tensor(B, device=dev)
     G.batched_lu_solve_f32(Ad, piv, Bd)
     X = orc.lu_solve_f32(LU, pv, B)
-    assert np.allclose(Bd.cpu().numpy(), X, rtol=0, atol=1e-3 * np.abs(X).max())
+    Xg = Bd.cpu().numpy()
+    for b in range(nb):
+        kap = np.linalg.cond(A[b].astype(np.float64), np.inf)
+        assert np.abs(Xg[b] - X[b]).max() <= 50 * n * u32 * kap * np.abs(X[b]).max()
 
 
 @pytest.mark.parametrize("nb,n", [(200, 10), (100, 21), (30, 64)])
