@@ -171,7 +171,7 @@ typedef struct {
   long max_steps;         /* per integrate call; 0 = unlimited */
   int mode;               /* BDFGPU_MODE_* */
   int attempts_per_sync;  /* attempts enqueued between status reads (>= 1) */
-  int block;              /* threads per workgroup for per-cell kernels (0 = 256) */
+  int block;              /* reserved, set to 0 */
   void* precond;          /* precond_handle* for BDFGPU_LS_LEARNED */
   int nonneg;             /* 1: each corrected solution is projected onto y >= 0
                              before the error test (the constraint-mask
@@ -209,9 +209,11 @@ int bdf_integrate(bdf_handle* h, double t_end, double* tret);
 int bdf_advance(bdf_handle* h, double t_end, long nsteps, double* tret, long* taken);
 /* Kernel timing with HIP events on the handle's stream (stream mode only):
  * on != 0 starts (and resets) timing of the three kernel groups of an
- * attempt: 0 predictor + first Newton iteration, 1 further Newton
- * iterations, 2 history update.  ms[3] receives the summed durations in
- * milliseconds, counts[3] the number of timed launches (host arrays). */
+ * attempt: 0 predictor, Jacobian, block factorisation and all Newton
+ * iterations (one fused launch per class), 1 learned mode only: predictor
+ * and MLP inference, 2 history update.  ms[3] receives the summed
+ * durations in milliseconds, counts[3] the number of timed launches (host
+ * arrays). */
 int bdf_set_profiling(bdf_handle* h, int on);
 int bdf_get_kernel_times(bdf_handle* h, double* ms, long* counts);
 /* Current solution z[0], cell-major, into the device array y (length N). */
@@ -222,7 +224,9 @@ int bdf_get_stats(bdf_handle* h, bdf_stats* s);
 long bdf_get_N(bdf_handle* h);
 /* Integrator state for exact single-step comparisons: scalars (host
  * arrays: dvals = {t, h}, ivals = {q, qwait}) and history z[0..5] plus the
- * previous correction, each a device array of N values, cell-major. */
+ * saved correction that the next order selection compares against (it is
+ * refreshed by the accepted step whose successor selects the order), each
+ * a device array of N values, cell-major. */
 int bdf_get_state(bdf_handle* h, double* dvals, int* ivals, double* z6,
                   double* dprev);
 int bdf_set_state(bdf_handle* h, const double* dvals, const int* ivals,

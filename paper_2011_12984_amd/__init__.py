@@ -281,12 +281,14 @@ class Bdf:
         check("bdf_set_profiling", lib().bdf_set_profiling(self.h, 1 if on else 0))
 
     def kernel_times(self):
-        """{group: (total_ms, launches)} for predictor, newton, accept."""
+        """{group: (total_ms, launches)}: "newton" (predictor, factorisation
+        and all Newton iterations), "learned" (predictor and MLP inference,
+        learned mode only), "accept" (history update)."""
         ms = (C.c_double * 3)()
         cnt = (C.c_long * 3)()
         check("bdf_get_kernel_times", lib().bdf_get_kernel_times(self.h, C.cast(ms, dp),
                                                                  C.cast(cnt, C.POINTER(C.c_long))))
-        return {k: (ms[i], cnt[i]) for i, k in enumerate(("predict", "newton", "accept"))}
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(("newton", "learned", "accept"))}
 
     def y(self):
         torch = _torch()
@@ -412,3 +414,54 @@ class Precond:
         check("precond_forward", lib().precond_forward(self.h, X.shape[0], _p(X), _p(out),
                                                        1 if use_mfma else 0, _stream()))
         return out
+
+
+# ---------------------------------------------------------------------------
+# Training pipeline of the learned preconditioner (host orchestration of the
+# C ABI: every step runs in the library's kernels)
+# ---------------------------------------------------------------------------
+
+def capture_training_set(bdf, n, nblocks, per_capture=4096, steps_between=8, t_end=None):
+    """Advance a plain integrator and capture blocks M = I - gamma J(y) with
+    their MLP inputs [y, log gamma] until `nblocks` are collected.  Each
+    capture takes every stride-th cell so that one capture yields at most
+    `per_capture` blocks.  Returns device tensors (X (k, n+1), M (k, n*n))."""
+    torch = _torch()
+    ncells = bdf.N // n
+    stride = max(1, ncells // per_capture)
+    Xs, Ms, got = [], [], 0
+    t_end = float("inf") if t_end is None else t_end
+    while got < nblocks:
+        X, M = bdf.capture_blocks(n, stride, min(per_capture, nblocks - got))
+        Xs.append(X.clone())
+        Ms.append(M.clone())
+        got += X.shape[0]
+        t, taken = bdf.advance(t_end, steps_between)
+        if taken == 0:
+            break
+    return torch.cat(Xs), torch.cat(Ms)
+
+
+def train_precond(pc, X, M, epochs=30, batch=1024, lr=1e-3, val_frac=0.1, seed=0):
+    """Split off a seeded random `val_frac` for validation, fit the input
+    normalisation on the training part, then `epochs` passes of mini-batch
+    Adam over seeded permutations.  Returns
+    {"train": [mean loss per epoch], "val": [held-out loss per epoch],
+    "val0": held-out loss before training}."""
+    torch = _torch()
+    ns = X.shape[0]
+    nval = int(ns * val_frac)
+    gen = torch.Generator(device=X.device)
+    gen.manual_seed(seed)
+    split = torch.randperm(ns, generator=gen, device=X.device)
+    iva, itr = split[:nval], split[nval:]
+    Xva, Mva = X.index_select(0, iva).contiguous(), M.index_select(0, iva).contiguous()
+    Xtr, Mtr = X.index_select(0, itr).contiguous(), M.index_select(0, itr).contiguous()
+    pc.fit_normalization(Xtr)
+    hist = {"train": [], "val": [], "val0": pc.eval_loss(Xva, Mva) if nval else None}
+    for _ in range(epochs):
+        perm = torch.randperm(Xtr.shape[0], generator=gen, device=X.device).to(torch.int32)
+        hist["train"].append(pc.train_epoch(Xtr, Mtr, perm, batch=batch, lr=lr))
+        if nval:
+            hist["val"].append(pc.eval_loss(Xva, Mva))
+    return hist

@@ -4,9 +4,10 @@
 // Cells are grouped by network topology into classes; every class gets its
 // own storage in the layout of its cell-to-lane mapping (tiled for thread
 // per cell, cell-major for segment per cell).  One step attempt is the fixed
-// launch sequence predictor, Newton 1..maxcor-1, accept over all classes;
-// kernels whose phase is not current return at once, so the same sequence
-// serves every outcome and can be captured once into a hipGraph.
+// launch sequence fused predictor + Newton, then history update, over all
+// classes (learned mode: predictor and MLP inference first); kernels whose
+// phase is not current return at once, so the same sequence serves every
+// outcome and can be captured once into a hipGraph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,10 +23,8 @@ namespace bdfgpu {
 
 int tpc_padded(int n);
 int spc_seg(int n);
-void launch_tpc(int np, int ls, int which, const BdfDev& D, int mslot, unsigned int grid,
-                hipStream_t s);
-void launch_spc(int seg, int ls, int which, const BdfDev& D, int mslot, unsigned int grid,
-                hipStream_t s);
+void launch_tpc(int np, int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s);
+void launch_spc(int seg, int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s);
 
 int precond_launch_gated(precond_handle* h, long B, const double* X, float* out,
                          const int* gphase, int want, const int* gskip, hipStream_t s);
@@ -152,6 +151,7 @@ struct bdf_handle {
   Ctrl* dC = nullptr;
   Ctrl* hC = nullptr;            // pinned mirror
   double* partials = nullptr;
+  double* gpartials = nullptr;
   unsigned int* counter = nullptr;
   unsigned int nblocks_total = 0;
   hipGraph_t graph = nullptr;
@@ -186,6 +186,7 @@ static BdfDev make_dev(bdf_handle* h, const ClassHost& c) {
   BdfDev D;
   D.C = h->dC;
   D.partials = h->partials;
+  D.gpartials = h->gpartials;
   D.counter = h->counter;
   D.nblocks_total = h->nblocks_total;
   D.rtol = h->o.rtol;
@@ -196,13 +197,13 @@ static BdfDev make_dev(bdf_handle* h, const ClassHost& c) {
   return D;
 }
 
-static void launch_phase(bdf_handle* h, int which, int mslot, hipStream_t s) {
+static void launch_phase(bdf_handle* h, int which, hipStream_t s) {
   for (const ClassHost& c : h->cls) {
     const BdfDev D = make_dev(h, c);
     if (c.map == MAP_TPC)
-      launch_tpc(c.np, h->o.linsol, which, D, mslot, c.grid, s);
+      launch_tpc(c.np, h->o.linsol, which, D, c.grid, s);
     else
-      launch_spc(c.np, h->o.linsol, which, D, mslot, c.grid, s);
+      launch_spc(c.np, h->o.linsol, which, D, c.grid, s);
   }
 }
 
@@ -240,22 +241,19 @@ static void enqueue_attempt(bdf_handle* h, hipStream_t s) {
   if (h->o.linsol == BDFGPU_LS_LEARNED) {
     // predictor, then the MLP's approximate inverses (skipped when the
     // attempt is being redone with exact LU), then the Newton iterations
-    launch_phase(h, 4, 0, s);
+    prof_mark(h, 1, true, s);
+    launch_phase(h, 4, s);
     for (const ClassHost& c : h->cls)
       (void)precond_launch_gated(reinterpret_cast<precond_handle*>(h->o.precond), c.ncells,
                                  c.dev.xin, c.dev.X, &h->dC->phase, PH_PREDICT,
                                  &h->dC->force_lu, s);
-  }
-  prof_mark(h, 0, true, s);
-  launch_phase(h, 2, 0, s);
-  prof_mark(h, 0, false, s);
-  for (int m = 1; m < h->o.maxcor; ++m) {
-    prof_mark(h, 1, true, s);
-    launch_phase(h, 2, m, s);
     prof_mark(h, 1, false, s);
   }
+  prof_mark(h, 0, true, s);
+  launch_phase(h, 2, s);
+  prof_mark(h, 0, false, s);
   prof_mark(h, 2, true, s);
-  launch_phase(h, 3, 0, s);
+  launch_phase(h, 3, s);
   prof_mark(h, 2, false, s);
 }
 
@@ -287,8 +285,8 @@ static int drive(bdf_handle* h, double tend, long inc, double* tret) {
   }
   hipLaunchKernelGGL(k_resume, dim3(1), dim3(1), 0, h->s, h->dC, tend, inc);
   BDF_HIP_TRY(hipGetLastError());
-  launch_phase(h, 0, 0, h->s);   // starting-step estimate (no-ops once done)
-  launch_phase(h, 1, 0, h->s);
+  launch_phase(h, 0, h->s);   // starting-step estimate (no-ops once done)
+  launch_phase(h, 1, h->s);
   BDF_HIP_TRY(hipGetLastError());
   const int per = std::max(1, h->o.attempts_per_sync);
   long last_progress = -1;
@@ -329,7 +327,7 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
   if (p->ncells < 0 || p->ntopo < 1 || !p->topo_n || !p->topo_R || !p->topo_off ||
       !p->nu_all || !p->mu_all || (p->ncells > 0 && (!p->cell_topo || !p->rates || !p->y0)))
     return arg_error("bdf_create: bad problem description");
-  if (o->qmax < 1 || o->qmax > kQmaxAll || o->maxcor < 1 || o->maxcor > 4 ||
+  if (o->qmax < 1 || o->qmax > kQmaxAll || o->maxcor < 1 || o->maxcor > kMaxCor ||
       !(o->rtol >= 0.0) || !(o->atol > 0.0) ||
       (o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_LU32REF &&
        o->linsol != BDFGPU_LS_LEARNED) ||
@@ -372,7 +370,9 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
     ch.n = n;
     ch.R = R;
     ch.ncells = (long)kv.second.size();
-    ch.map = n <= 12 ? MAP_TPC : MAP_SPC;
+    // thread per cell while the rates and evaluation point fit the LDS of a
+    // block, else segment per cell
+    ch.map = (n <= 12 && tpc_lds_bytes(tpc_padded(n), R, o->linsol) <= 65536) ? MAP_TPC : MAP_SPC;
     if (o->linsol == BDFGPU_LS_LEARNED &&
         (ch.map != MAP_SPC || n > 31 ||
          precond_dim(reinterpret_cast<precond_handle*>(o->precond)) != n)) {
@@ -381,7 +381,7 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
                        "and a network of the preconditioner's size");
     }
     ch.np = ch.map == MAP_TPC ? tpc_padded(n) : spc_seg(n);
-    const int cpb = ch.map == MAP_TPC ? kCellThreads : kCellThreads / ch.np;
+    const int cpb = ch.map == MAP_TPC ? kTpcThreads : kCellThreads / ch.np;
     ch.grid = (unsigned int)std::max<long>(1, (ch.ncells + cpb - 1) / cpb);
     ch.blk0 = blk;
     blk += ch.grid;
@@ -456,23 +456,24 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
       if ((st = dalloc(h, (void**)&K.z[j], vbytes))) { bdf_destroy(h); return st; }
       BDF_HIP_TRY(hipMemset(K.z[j], 0, vbytes));
     }
-    if ((st = dalloc(h, (void**)&K.dprev, vbytes)) || (st = dalloc(h, (void**)&K.zp0, vbytes)) ||
-        (st = dalloc(h, (void**)&K.cv, vbytes)) || (st = dalloc(h, (void**)&K.y, vbytes))) {
+    if ((st = dalloc(h, (void**)&K.dprev, vbytes))) {
       bdf_destroy(h);
       return st;
     }
     BDF_HIP_TRY(hipMemset(K.dprev, 0, vbytes));
+    for (int m = 0; m < o->maxcor; ++m)
+      if ((st = dalloc(h, (void**)&K.ys[m], vbytes))) {
+        bdf_destroy(h);
+        return st;
+      }
     if (o->linsol == BDFGPU_LS_LEARNED) {
       const long nc = std::max<long>(1, ch.ncells);
       if ((st = dalloc(h, (void**)&K.X, sizeof(float) * nc * n * n)) ||
           (st = dalloc(h, (void**)&K.xin, sizeof(double) * nc * (n + 1))) ||
-          (st = dalloc(h, (void**)&K.lpmode, sizeof(int) * nc)) ||
-          (st = dalloc(h, (void**)&K.dcprev, sizeof(double) * nc))) {
+          (st = dalloc(h, (void**)&K.zp0, vbytes)) || (st = dalloc(h, (void**)&K.cv, vbytes))) {
         bdf_destroy(h);
         return st;
       }
-      BDF_HIP_TRY(hipMemset(K.lpmode, 0, sizeof(int) * nc));
-      BDF_HIP_TRY(hipMemset(K.dcprev, 0, sizeof(double) * nc));
     }
     double* rates = nullptr;
     if ((st = dalloc(h, (void**)&rates, sizeof(double) * (size_t)std::max<long>(1, cap_cells * R)))) {
@@ -502,12 +503,15 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
     h->cls.push_back(ch);
   }
   h->nblocks_total = (unsigned int)blk;
-  if ((st = dalloc(h, (void**)&h->partials, sizeof(double) * kRedVals * std::max<long>(1, blk))) ||
-      (st = dalloc(h, (void**)&h->counter, 256)) || (st = dalloc(h, (void**)&h->dC, sizeof(Ctrl)))) {
+  const long ngroups = std::max<long>(1, (blk + kRedGroup - 1) / kRedGroup);
+  const size_t cbytes = sizeof(unsigned int) * (size_t)(1 + ngroups);
+  if ((st = dalloc(h, (void**)&h->partials, sizeof(double) * kRedMax * std::max<long>(1, blk))) ||
+      (st = dalloc(h, (void**)&h->gpartials, sizeof(double) * kRedMax * ngroups)) ||
+      (st = dalloc(h, (void**)&h->counter, cbytes)) || (st = dalloc(h, (void**)&h->dC, sizeof(Ctrl)))) {
     bdf_destroy(h);
     return st;
   }
-  BDF_HIP_TRY(hipMemset(h->counter, 0, 256));
+  BDF_HIP_TRY(hipMemset(h->counter, 0, cbytes));
   BDF_HIP_TRY(hipHostMalloc((void**)&h->hC, sizeof(Ctrl), hipHostMallocDefault));
   Ctrl C;
   memset(&C, 0, sizeof(C));

@@ -39,6 +39,8 @@ enum Phase : int {
 };
 
 constexpr int kQmaxAll = 5;
+constexpr int kMaxCor = 4;        // Newton iterations per attempt, at most
+constexpr int kRedPerIter = 8;     // reduced values per Newton iteration
 constexpr int kMxNcf = 10;
 constexpr int kMxNef = 7;
 constexpr double kCrDown = 0.3;
@@ -175,45 +177,55 @@ __device__ inline void error_test_failed(Ctrl* C, double err) {
   prepare_attempt(C);
 }
 
-// After Newton iteration m: sums of (delta w)^2, ((y - z(0)) w)^2 (y
-// projected onto y >= 0 when constrained), any singular block, refinement
-// sweeps and fallbacks, count of negative components.
-__device__ inline void after_newton(Ctrl* C, const double* s) {
-  C->nfevals++;
-  C->nniters++;
-  C->nlinsolves++;
-  C->refine_sweeps += (long)s[3];
-  C->refine_fallbacks += (long)s[4];
-  C->lp_cell_solves += (long)s[6];
-  C->lp_fallback_cells += (long)s[7];
-  if (C->m == 0 && C->restart) {   // the predictor re-evaluated f(z[0])
+// After the fused Newton kernel.  The kernel runs all maxcor iterations of
+// the attempt for every cell (each cell's iterates depend only on its own
+// block, gamma and the predicted state) and reduces, per iteration m, the
+// sums s[8m + j]: j = 0 (delta w)^2, 1 ((y - z(0)[0]) w)^2 with y projected
+// onto y >= 0 when constrained, 2 negative components, 3 refinement sweeps,
+// 4 refinement fallbacks, 5 learned-inverse solves, 6 learned-to-LU
+// switches; s[7] counts singular blocks.  The global convergence test is
+// then replayed iteration by iteration exactly as a sequential Newton loop
+// would take it, and C->m records the iteration whose iterate is the
+// corrected solution.  Iterates past that point were computed but are
+// unused, so the outcome equals that of stopping there.
+__device__ inline void after_newton_all(Ctrl* C, const double* s) {
+  if (C->restart) {   // the predictor re-evaluated f(z[0])
     C->nfevals++;
     C->restart = 0;
   }
-  const int m = C->m;
-  if (s[2] > 0.0) return newton_failed(C);       // singular block in the setup
-  const double d = sqrt(s[0] / C->N);
-  if (!(d == d) || d > 1e300) return newton_failed(C);
-  if (m > 0) {
-    const double ratio = d / C->dold;
-    C->crate = kCrDown * C->crate > ratio ? kCrDown * C->crate : ratio;
-  }
-  const double dcon = d * (C->crate < 1.0 ? C->crate : 1.0);
-  if (dcon <= kNlsCoef) {
-    if (s[5] > 0.0) C->nprojections++;
-    const double err = sqrt(s[1] / C->N) / C->l[0] * C->tq;
-    C->err = err;
-    if (err <= 1.0) {
-      C->phase = PH_ACCEPT;
-      return;
+  for (int m = 0; m < C->maxcor; ++m) {
+    const double* t = s + kRedPerIter * m;
+    C->nfevals++;
+    C->nniters++;
+    C->nlinsolves++;
+    C->refine_sweeps += (long)t[3];
+    C->refine_fallbacks += (long)t[4];
+    C->lp_cell_solves += (long)t[5];
+    C->lp_fallback_cells += (long)t[6];
+    if (m == 0 && s[7] > 0.0) return newton_failed(C);   // singular block in the setup
+    const double d = sqrt(t[0] / C->N);
+    if (!(d == d) || d > 1e300) return newton_failed(C);
+    if (m > 0) {
+      const double ratio = d / C->dold;
+      C->crate = kCrDown * C->crate > ratio ? kCrDown * C->crate : ratio;
     }
-    return error_test_failed(C, err);
+    const double dcon = d * (C->crate < 1.0 ? C->crate : 1.0);
+    if (dcon <= kNlsCoef) {
+      C->m = m;
+      if (t[2] > 0.0) C->nprojections++;
+      const double err = sqrt(t[1] / C->N) / C->l[0] * C->tq;
+      C->err = err;
+      if (err <= 1.0) {
+        C->phase = PH_ACCEPT;
+        return;
+      }
+      return error_test_failed(C, err);
+    }
+    if (m + 1 == C->maxcor) return newton_failed(C);
+    if (m >= 1 && d > kRdiv * C->dold) return newton_failed(C);
+    C->dold = d;
   }
-  if (m + 1 == C->maxcor) return newton_failed(C);
-  if (m >= 1 && d > kRdiv * C->dold) return newton_failed(C);
-  C->dold = d;
-  C->m = m + 1;
-  C->phase = PH_NEWTON;
+  newton_failed(C);
 }
 
 // After the history update: sums of (z_new[q] w)^2 and ((acor - acor_prev) w)^2.

@@ -1,18 +1,24 @@
 // Per-cell kernels of the grouped BDF step on gfx950.
 //
-// One step attempt runs: predictor + first Newton iteration, further Newton
-// iterations, then the history update.  Every kernel re-evaluates the
-// mass-action Jacobian at the predicted state and re-factors M = I - gamma J
-// of its cells in registers instead of storing the factors: a 10 x 10 FP64
-// factorisation costs ~700 flops but storing and re-reading it would cost
-// 1.6 kB of HBM traffic per cell and iteration.  HBM then carries only the
-// vectors of the method.
+// One step attempt is two launches over every class of cells:
+//  * k_*_newton: predictor, evaluation of J at the predicted state, one
+//    factorisation of M = I - gamma J per cell, then all maxcor Newton
+//    iterations with that factorisation.  A cell's iterates depend only on
+//    its own block, gamma and the predicted state, so the iterations need no
+//    global synchronisation; each iteration's norms are reduced separately
+//    and the controller replays the global convergence test on them
+//    (after_newton_all).  The factors never leave registers, and the state
+//    is read from HBM once per attempt instead of once per iteration.
+//  * k_*_accept: history update from the iterate the controller picked,
+//    with the norms for the order selection.
 //
 // Two mappings of cells to lanes:
 //  * thread per cell (TPC, n <= 12): the block lives in one lane's
 //    registers; vectors use a tiled layout (64 cells per tile, species-major
 //    inside the tile) so that every load and store is a full 512-byte
-//    wavefront access.
+//    wavefront access.  Reaction rates and the evaluation point sit in LDS
+//    columns so that the network's species and reaction indices (uniform
+//    over the wave, unknown at compile time) can address them.
 //  * segment per cell (SPC, 12 < n <= 64): one lane per row of the block in
 //    a segment of 16, 32 or 64 lanes (see spc.hpp); vectors are cell-major.
 #pragma once
@@ -45,9 +51,9 @@ struct ClassDev {
   int n, R;
   double* z[kQmaxAll + 1];
   double* dprev;
-  double* zp0;
-  double* cv;            // z(0)[0] - l0 z(0)[1]
-  double* y;             // Newton iterate
+  double* ys[kMaxCor];   // Newton iterate after iteration m
+  double* zp0;           // learned mode: z(0)[0] from the predictor kernel
+  double* cv;            // learned mode: z(0)[0] - l0 z(0)[1]
   const double* rates;
   NetDev net;
   long blk0;             // first block of this class in the phase reduction
@@ -55,66 +61,234 @@ struct ClassDev {
   // learned preconditioner
   float* X;              // per cell n x n approximate inverse (row-major)
   double* xin;           // per cell MLP inputs [z(0)[0], log gamma]
-  int* lpmode;           // per cell: 2 learned, 3 switching to LU, 4 / 0 exact LU
-  double* dcprev;        // per cell WRMS of the previous correction
 };
 
 struct BdfDev {
   Ctrl* C;
-  double* partials;
-  unsigned int* counter;
+  double* partials;      // [nblocks_total][kRedMax]
+  double* gpartials;     // [ngroups][kRedMax]
+  unsigned int* counter; // [0] groups done, [1 + g] blocks of group g done
   unsigned int nblocks_total;
   double rtol, atol;
   int nonneg;
   ClassDev k;
 };
 
-constexpr int kRedVals = 8;
-constexpr int kCellThreads = 256;
+constexpr int kRedVals = 8;                        // init and accept kernels
+constexpr int kRedNewton = kRedPerIter * kMaxCor;  // fused Newton kernels
+constexpr int kRedMax = kRedNewton;
+constexpr int kRedGroup = 256;                     // blocks per first-level group
+constexpr int kCellThreads = 256;                  // SPC blocks
+constexpr int kTpcThreads = 128;                   // TPC blocks
 
-// Block-level reduction of the kRedVals partial sums of one kernel, then the
-// device controller in the last block across all launches of the phase.
-template <typename F>
-__device__ __forceinline__ void reduce_and_control(const BdfDev& D, double (&v)[kRedVals],
-                                                   double* sh, F&& control) {
-  block_sum<kRedVals>(v, sh);
-  double tot[kRedVals];
-  const unsigned int gb = (unsigned int)(D.k.blk0 + blockIdx.x);
-  // the ticket/last-block protocol, with a global block index
-  __shared__ int am_last;
-  if (threadIdx.x == 0) {
+// Sum K values over the 64 lanes of a wave with K - 1 + (6 - log2 K)
+// exchanges instead of 6 K: each exchange step halves the number of values
+// a lane keeps.  On return lane l holds, in v[0], the total of value
+// index red_index<K>(l).  The order of additions is fixed.
+template <int K>
+__device__ __forceinline__ int red_index(int lane) {
+  int k = 0;
+  int cnt = K, bit = 32;
+  while (cnt > 1) {
+    cnt >>= 1;
+    if (lane & bit) k += cnt;
+    bit >>= 1;
+  }
+  return k;
+}
+
+template <int K, int CNT, int BIT>
+__device__ __forceinline__ void reduce_scatter_step(double (&v)[K], int lane) {
+  if constexpr (BIT >= 1) {
+    if constexpr (CNT > 1) {
+      constexpr int HALF = CNT / 2;
+      const bool upper = (lane & BIT) != 0;
 #pragma unroll
-    for (int k = 0; k < kRedVals; ++k) D.partials[(size_t)gb * kRedVals + k] = v[k];
+      for (int i = 0; i < HALF; ++i) {
+        const double send = upper ? v[i] : v[i + HALF];
+        const double keep = upper ? v[i + HALF] : v[i];
+        v[i] = keep + __shfl_xor(send, BIT, 64);
+      }
+      reduce_scatter_step<K, HALF, BIT / 2>(v, lane);
+    } else {
+      v[0] = v[0] + __shfl_xor(v[0], BIT, 64);
+      reduce_scatter_step<K, 1, BIT / 2>(v, lane);
+    }
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void wave_reduce_scatter(double (&v)[K]) {
+  reduce_scatter_step<K, K, 32>(v, threadIdx.x & 63);
+}
+
+// Block reduction of K partial sums, then a two-level deterministic tree
+// across all blocks of the phase (blocks of every class launch): groups of
+// kRedGroup blocks are summed by the last block of the group to finish, the
+// group sums by the last group to finish, whose first thread then runs the
+// controller.  Every sum is taken in a fixed order, so the result does not
+// depend on which block finishes last.
+template <int K, typename F>
+__device__ __forceinline__ void reduce_and_control(const BdfDev& D, double (&v)[K], double* sh,
+                                                   F&& control) {
+  static_assert(K <= kRedMax && (K & (K - 1)) == 0 && K <= 64, "reduction width");
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  wave_reduce_scatter<K>(v);
+  // lanes 0 .. K-1 (stepping by 64 / K) hold distinct indices
+  if ((lane & ((64 / K) - 1)) == 0) sh[wid * K + red_index<K>(lane)] = v[0];
+  __syncthreads();
+  __shared__ int s_flag;
+  const unsigned int gb = (unsigned int)(D.k.blk0 + blockIdx.x);
+  const unsigned int g = gb / kRedGroup;
+  const unsigned int ng = (D.nblocks_total + kRedGroup - 1) / kRedGroup;
+  const unsigned int gsz =
+      D.nblocks_total - g * kRedGroup < (unsigned int)kRedGroup ? D.nblocks_total - g * kRedGroup
+                                                                 : (unsigned int)kRedGroup;
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w * K + threadIdx.x];
+    D.partials[(size_t)gb * kRedMax + threadIdx.x] = s;
     __threadfence();
-    const unsigned int t = atomicAdd(D.counter, 1u);
-    am_last = (t == D.nblocks_total - 1);
   }
   __syncthreads();
-  if (!am_last) return;
-  __threadfence();
-  double acc[kRedVals];
-#pragma unroll
-  for (int k = 0; k < kRedVals; ++k) acc[k] = 0.0;
-  for (unsigned int b = threadIdx.x; b < D.nblocks_total; b += blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < kRedVals; ++k)
-      acc[k] += __hip_atomic_load(&D.partials[(size_t)b * kRedVals + k], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-  }
-  block_sum<kRedVals>(acc, sh);
   if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < kRedVals; ++k) tot[k] = acc[k];
-    *D.counter = 0u;
-    control(D.C, tot);
+    const unsigned int t = atomicAdd(&D.counter[1 + g], 1u);
+    s_flag = (t == gsz - 1);
+  }
+  __syncthreads();
+  if (!s_flag) return;
+  __threadfence();
+  // group level: wave w sums value indices k = w, w + nw, ...; lane b takes
+  // blocks b, b + 64, ... of the group
+  for (int k = wid; k < K; k += nw) {
+    double a = 0.0;
+    for (unsigned int b = lane; b < gsz; b += 64)
+      a += __hip_atomic_load(&D.partials[(size_t)(g * kRedGroup + b) * kRedMax + k],
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    a = wave_sum(a);
+    if (lane == 0) D.gpartials[(size_t)g * kRedMax + k] = a;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    D.counter[1 + g] = 0u;
+    __threadfence();
+    const unsigned int t = atomicAdd(&D.counter[0], 1u);
+    s_flag = (t == ng - 1);
+  }
+  __syncthreads();
+  if (!s_flag) return;
+  __threadfence();
+  for (int k = wid; k < K; k += nw) {
+    double a = 0.0;
+    for (unsigned int b = lane; b < ng; b += 64)
+      a += __hip_atomic_load(&D.gpartials[(size_t)b * kRedMax + k], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    a = wave_sum(a);
+    if (lane == 0) sh[k] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    D.counter[0] = 0u;
+    control(D.C, static_cast<const double*>(sh));
   }
 }
 
 // ===========================================================================
 // Thread per cell
 // ===========================================================================
+
+// Dense LU of one lane's NP x NP block in registers, partial pivoting with
+// the pivot rule of LAPACK getrf (first maximal |a_ik|).  Row exchanges
+// touch only the trailing columns k..NP-1 and the multipliers stay where
+// they were computed, as in LINPACK's factor/solve pair: the solve applies
+// exchange k just before elimination step k, which performs the same
+// floating-point operations on the same values as exchanging whole rows.
+// This saves the exchanges of the multiplier columns, and an exchange is
+// skipped altogether when no lane of the wave pivots on that row.  The
+// diagonal holds reciprocal pivots.  The recursion over k keeps every
+// register index a compile-time constant.
+template <int NP, typename T>
+struct TpcLU {
+  template <int K>
+  __device__ static __forceinline__ void step(T (&A)[NP][NP], int (&piv)[NP], int& info) {
+    if constexpr (K < NP) {
+      int p = K;
+      T amax = sabs(A[K][K]);
+#pragma unroll
+      for (int i = K + 1; i < NP; ++i) {
+        const T v = sabs(A[i][K]);
+        const bool gt = v > amax;
+        amax = gt ? v : amax;
+        p = gt ? i : p;
+      }
+      piv[K] = p;
+#pragma unroll
+      for (int i = K + 1; i < NP; ++i) {
+        if (__any(p == i)) {
+          const bool sw = (p == i);
+#pragma unroll
+          for (int j = K; j < NP; ++j) {
+            const T t = A[K][j];
+            A[K][j] = sw ? A[i][j] : t;
+            A[i][j] = sw ? t : A[i][j];
+          }
+        }
+      }
+      const T d = A[K][K];
+      const bool z = (d == T(0));
+      if (z && !info) info = K + 1;
+      const T rinv = T(1) / (z ? T(1) : d);
+      A[K][K] = rinv;
+#pragma unroll
+      for (int i = K + 1; i < NP; ++i) {
+        const T l = z ? A[i][K] : A[i][K] * rinv;
+        A[i][K] = l;
+#pragma unroll
+        for (int j = K + 1; j < NP; ++j) A[i][j] = fma(-l, A[K][j], A[i][j]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      step<K + 1>(A, piv, info);
+    }
+  }
+
+  __device__ static __forceinline__ int factor(T (&A)[NP][NP], int (&piv)[NP]) {
+    int info = 0;
+    step<0>(A, piv, info);
+    return info;
+  }
+
+  __device__ static __forceinline__ void solve(const T (&A)[NP][NP], const int (&piv)[NP],
+                                               T (&b)[NP]) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int p = piv[k];
+#pragma unroll
+      for (int i = k + 1; i < NP; ++i) {
+        if (__any(p == i)) {
+          const bool sw = (p == i);
+          const T t = b[k];
+          b[k] = sw ? b[i] : t;
+          b[i] = sw ? t : b[i];
+        }
+      }
+#pragma unroll
+      for (int i = k + 1; i < NP; ++i) b[i] = fma(-A[i][k], b[k], b[i]);
+    }
+#pragma unroll
+    for (int i = NP - 1; i >= 0; --i) {
+#pragma unroll
+      for (int j = i + 1; j < NP; ++j) b[i] = fma(-A[i][j], b[j], b[i]);
+      b[i] = b[i] * A[i][i];
+    }
+  }
+};
+
 template <int NP>
 struct Tpc {
+  static constexpr int T = kTpcThreads;   // LDS column stride
   // tiled index of species i of cell c (n species per cell)
   __device__ static __forceinline__ long idx(long c, int i, int n) {
     return (c >> 6) * 64L * n + (long)i * 64 + (c & 63);
@@ -123,155 +297,79 @@ struct Tpc {
     return (c >> 6) * 64L * R + (long)k * 64 + (c & 63);
   }
 
-  // ycol: this thread's LDS column (stride kCellThreads) holding the state
-  __device__ static void rhs(const NetDev& nd, const double* kap, const double* ycol,
+  // f at the state in ycol (LDS column, stride T); rates in kcol with
+  // stride ks (an LDS column, or the tiled rates in global memory).
+  __device__ static __forceinline__ void rhs(const NetDev& nd, const double* kcol, int ks, const double* ycol,
                              double (&f)[NP]) {
 #pragma unroll
     for (int i = 0; i < NP; ++i) f[i] = 0.0;
+#pragma unroll 2
     for (int k = 0; k < nd.R; ++k) {
       const int a = nd.ra[k], b = nd.rb[k];
-      double r = kap[(long)k * 64];
-      if (a >= 0) r *= ycol[a * kCellThreads];
-      if (b >= 0) r *= ycol[b * kCellThreads];
+      double r = kcol[k * ks];
+      if (a >= 0) r *= ycol[a * T];
+      if (b >= 0) r *= ycol[b * T];
       const double* Sk = nd.S + (long)k * nd.np;
 #pragma unroll
       for (int i = 0; i < NP; ++i) f[i] = fma(Sk[i], r, f[i]);
     }
   }
 
-  __device__ static void jac(const NetDev& nd, const double* kap, const double* ycol,
-                             double (&J)[NP][NP]) {
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-#pragma unroll
-      for (int j = 0; j < NP; ++j) J[i][j] = 0.0;
-#pragma unroll
-    for (int a = 0; a < NP; ++a) {
-      const int e0 = nd.jst[a], e1 = nd.jst[a + 1];
-      for (int e = e0; e < e1; ++e) {
-        const int k = nd.jk[e], p = nd.jp[e];
-        double g = kap[(long)k * 64] * nd.jm[e];
-        if (p >= 0) g *= ycol[p * kCellThreads];
-        const double* Sk = nd.S + (long)k * nd.np;
-#pragma unroll
-        for (int i = 0; i < NP; ++i) J[i][a] = fma(Sk[i], g, J[i][a]);
-      }
-    }
-  }
-
-  template <typename T>
-  __device__ static int factor(T (&A)[NP][NP], int (&piv)[NP]) {
-    int info = 0;
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      int p = k;
-      T amax = sabs(A[k][k]);
-#pragma unroll
-      for (int i = k + 1; i < NP; ++i) {
-        const T v = sabs(A[i][k]);
-        const bool gt = v > amax;
-        amax = gt ? v : amax;
-        p = gt ? i : p;
-      }
-      piv[k] = p;
-#pragma unroll
-      for (int i = k + 1; i < NP; ++i) {
-        const bool sw = (p == i);
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-          const T t = A[k][j];
-          A[k][j] = sw ? A[i][j] : t;
-          A[i][j] = sw ? t : A[i][j];
-        }
-      }
-      const T d = A[k][k];
-      const bool z = (d == T(0));
-      if (z && !info) info = k + 1;
-      const T dd = z ? T(1) : d;
-#pragma unroll
-      for (int i = k + 1; i < NP; ++i) {
-        const T l = z ? A[i][k] : A[i][k] / dd;
-        A[i][k] = l;
-#pragma unroll
-        for (int j = k + 1; j < NP; ++j) A[i][j] = fma(-l, A[k][j], A[i][j]);
-      }
-    }
-    return info;
-  }
-
-  template <typename T>
-  __device__ static void solve(const T (&A)[NP][NP], const int (&piv)[NP], T (&b)[NP]) {
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const int p = piv[k];
-#pragma unroll
-      for (int i = k + 1; i < NP; ++i) {
-        const bool sw = (p == i);
-        const T t = b[k];
-        b[k] = sw ? b[i] : t;
-        b[i] = sw ? t : b[i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-#pragma unroll
-      for (int j = 0; j < i; ++j) b[i] = fma(-A[i][j], b[j], b[i]);
-#pragma unroll
-    for (int i = NP - 1; i >= 0; --i) {
-#pragma unroll
-      for (int j = i + 1; j < NP; ++j) b[i] = fma(-A[i][j], b[j], b[i]);
-      b[i] = b[i] / A[i][i];
-    }
-  }
-
-  // Column a of J at the state held in ycol (a is a compile-time constant
-  // after unrolling at the call site).
-  __device__ static __forceinline__ void jac_col(const NetDev& nd, const double* kap,
+  // Column a of J at the state in ycol (a is a compile-time constant after
+  // unrolling at the call site).
+  __device__ static __forceinline__ void jac_col(const NetDev& nd, const double* kcol, int ks,
                                                  const double* ycol, int a, double (&col)[NP]) {
 #pragma unroll
     for (int i = 0; i < NP; ++i) col[i] = 0.0;
     const int e0 = nd.jst[a], e1 = nd.jst[a + 1];
+#pragma unroll 2
     for (int e = e0; e < e1; ++e) {
       const int k = nd.jk[e], p = nd.jp[e];
-      double g = kap[(long)k * 64] * nd.jm[e];
-      if (p >= 0) g *= ycol[p * kCellThreads];
+      double g = kcol[k * ks] * nd.jm[e];
+      if (p >= 0) g *= ycol[p * T];
       const double* Sk = nd.S + (long)k * nd.np;
 #pragma unroll
       for (int i = 0; i < NP; ++i) col[i] = fma(Sk[i], g, col[i]);
     }
   }
 
-  // M = I - gamma J, assembled one column at a time so that J never needs
-  // registers of its own.
-  __device__ static void build_M(const NetDev& nd, const double* kap, const double* ycol,
-                                 double gamma, double (&M)[NP][NP]) {
+  // M = I - gamma J, assembled one column at a time.
+  template <typename TT>
+  __device__ static __forceinline__ void build_M(const NetDev& nd, const double* kcol, int ks, const double* ycol,
+                                 double gamma, TT (&M)[NP][NP], double (&rowsum)[NP]) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) rowsum[i] = 0.0;
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
       double col[NP];
-      jac_col(nd, kap, ycol, a, col);
+      jac_col(nd, kcol, ks, ycol, a, col);
 #pragma unroll
-      for (int i = 0; i < NP; ++i) M[i][a] = (i == a ? 1.0 : 0.0) - gamma * col[i];
+      for (int i = 0; i < NP; ++i) {
+        const double m = (i == a ? 1.0 : 0.0) - gamma * col[i];
+        M[i][a] = (TT)m;
+        rowsum[i] += fabs(m);
+      }
     }
   }
 
   // out = (I - gamma J) x without forming J: J x = sum_k S_k (grad r_k . x).
   // x must also be in the LDS column xcol (reactant lookups by index).
-  __device__ static void mvp(const NetDev& nd, const double* kap, const double* ycol,
+  __device__ static __forceinline__ void mvp(const NetDev& nd, const double* kcol, int ks, const double* ycol,
                              const double* xcol, double gamma, const double (&x)[NP],
                              double (&out)[NP]) {
     double jx[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) jx[i] = 0.0;
+#pragma unroll 2
     for (int k = 0; k < nd.R; ++k) {
       const int a = nd.ra[k], b = nd.rb[k];
       if (a < 0) continue;
-      const double kk = kap[(long)k * 64];
+      const double kk = kcol[k * ks];
       double d;
       if (b < 0)
-        d = kk * xcol[a * kCellThreads];
+        d = kk * xcol[a * T];
       else
-        d = kk * fma(xcol[a * kCellThreads], ycol[b * kCellThreads],
-                     ycol[a * kCellThreads] * xcol[b * kCellThreads]);
+        d = kk * fma(xcol[a * T], ycol[b * T], ycol[a * T] * xcol[b * T]);
       const double* Sk = nd.S + (long)k * nd.np;
 #pragma unroll
       for (int i = 0; i < NP; ++i) jx[i] = fma(Sk[i], d, jx[i]);
@@ -280,145 +378,111 @@ struct Tpc {
     for (int i = 0; i < NP; ++i) out[i] = fma(-gamma, jx[i], x[i]);
   }
 
-  // Solve (I - gamma J) x = r, J at the state in ycol.  LS 0: FP64 LU.
-  // LS 1: FP32 LU, FP64 residuals from the matrix-free product (so the FP64
-  // matrix is never live beside the FP32 factors), FP64 LU fallback.
-  // xcol is scratch.  Returns info (singular block).
-  template <int LS>
-  __device__ static int linsolve(const NetDev& nd, const double* kap, const double* ycol,
-                                 double* xcol, double gamma, const double (&r)[NP],
-                                 double (&x)[NP], int max_it, int& sweeps, int& fallback) {
-    sweeps = 0;
-    fallback = 0;
-    if (LS == 1) {
-      bool ok = false;
-      {
-        float L[NP][NP];
-        double rowsum[NP];
+  __device__ static __forceinline__ void store_col(double* col, const double (&v)[NP]) {
 #pragma unroll
-        for (int i = 0; i < NP; ++i) rowsum[i] = 0.0;
-#pragma unroll
-        for (int a = 0; a < NP; ++a) {
-          double col[NP];
-          jac_col(nd, kap, ycol, a, col);
-#pragma unroll
-          for (int i = 0; i < NP; ++i) {
-            const double m = (i == a ? 1.0 : 0.0) - gamma * col[i];
-            L[i][a] = (float)m;
-            rowsum[i] += fabs(m);
-          }
-        }
-        double mnorm = 0.0;
-#pragma unroll
-        for (int i = 0; i < NP; ++i) mnorm = fmax(mnorm, rowsum[i]);
-        int pv[NP];
-        const int inf32 = factor<float>(L, pv);
-        if (!inf32) {
-          float v[NP];
-#pragma unroll
-          for (int i = 0; i < NP; ++i) v[i] = (float)r[i];
-          solve<float>(L, pv, v);
-#pragma unroll
-          for (int i = 0; i < NP; ++i) x[i] = (double)v[i];
-          const double eps64 = 2.220446049250313e-16;
-          double dprev = 0.0;
-          for (int it = 0; it <= max_it; ++it) {
-            tpc_store_col_(xcol, x);
-            double mx[NP];
-            mvp(nd, kap, ycol, xcol, gamma, x, mx);
-            double rn = 0.0, xn = 0.0;
-#pragma unroll
-            for (int i = 0; i < NP; ++i) {
-              mx[i] = r[i] - mx[i];
-              rn = fmax(rn, fabs(mx[i]));
-              xn = fmax(xn, fabs(x[i]));
-            }
-            if (!(rn == rn) || !(xn == xn)) break;
-            if (rn <= sqrt((double)NP) * eps64 * mnorm * xn) {
-              ok = true;
-              break;
-            }
-            if (it == max_it) break;
-#pragma unroll
-            for (int i = 0; i < NP; ++i) v[i] = (float)mx[i];
-            solve<float>(L, pv, v);
-            double dn = 0.0;
-#pragma unroll
-            for (int i = 0; i < NP; ++i) {
-              x[i] += (double)v[i];
-              dn = fmax(dn, fabs((double)v[i]));
-            }
-            sweeps = it + 1;
-            if (it >= 1 && dn > 0.5 * dprev) break;
-            dprev = dn;
-          }
-        }
-      }
-      if (ok) return 0;
-      fallback = 1;
-    }
-    double M[NP][NP];
-    build_M(nd, kap, ycol, gamma, M);
-    int pv64[NP];
-    const int inf = factor<double>(M, pv64);
-#pragma unroll
-    for (int i = 0; i < NP; ++i) x[i] = r[i];
-    solve<double>(M, pv64, x);
-    return inf;
-  }
-
-  __device__ static __forceinline__ void tpc_store_col_(double* col, const double (&v)[NP]) {
-#pragma unroll
-    for (int i = 0; i < NP; ++i) col[i * kCellThreads] = v[i];
+    for (int i = 0; i < NP; ++i) col[i * T] = v[i];
   }
 };
 
-template <int NP>
-__device__ __forceinline__ void tpc_store_col(double* ycol, const double (&v)[NP]) {
+// History loads.  A load under a runtime condition compiles to a branch with
+// a wait for that one load, which serialises the HBM round trips; so the
+// order q selects a compile-time variant, padded species read a clamped
+// (valid) address, and the results are selected afterwards.
+template <int NP, int Q>
+__device__ __forceinline__ void tpc_load_hist_q(const ClassDev& K, const Ctrl* C, long c, int n,
+                                                double (&zs)[kQmaxAll + 1][NP]) {
 #pragma unroll
-  for (int i = 0; i < NP; ++i) ycol[i * kCellThreads] = v[i];
+  for (int j = 0; j <= kQmaxAll; ++j) {
+    if (j <= Q) {
+      const double hsj = C->hs[j];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        const int ii = i < n ? i : n - 1;
+        const double v = K.z[j][Tpc<NP>::idx(c, ii, n)];
+        zs[j][i] = i < n ? v * hsj : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NP; ++i) zs[j][i] = 0.0;
+    }
+  }
 }
 
-// Predictor + first Newton iteration (FIRST = 1) or Newton iteration
-// mslot >= 1 (FIRST = 0); the two are separate kernels so that profiles
-// attribute their time separately.  Register budget: the state vectors live
-// in two per-thread LDS columns, so only M (or the FP32 factors) and the
-// right-hand side are live through the factorisation.
-template <int NP, int LS, int FIRST>
-__global__ void __launch_bounds__(kCellThreads) k_tpc_newton(BdfDev D, int mslot) {
-  __shared__ double s_y[NP * kCellThreads];
-  __shared__ double s_x[NP * kCellThreads];
-  __shared__ double s_red[(kCellThreads / 64) * kRedVals];
+template <int NP>
+__device__ __forceinline__ void tpc_load_hist(const ClassDev& K, const Ctrl* C, long c, int n,
+                                              int q, double (&zs)[kQmaxAll + 1][NP]) {
+  switch (q) {
+    case 1: tpc_load_hist_q<NP, 1>(K, C, c, n, zs); break;
+    case 2: tpc_load_hist_q<NP, 2>(K, C, c, n, zs); break;
+    case 3: tpc_load_hist_q<NP, 3>(K, C, c, n, zs); break;
+    case 4: tpc_load_hist_q<NP, 4>(K, C, c, n, zs); break;
+    default: tpc_load_hist_q<NP, 5>(K, C, c, n, zs); break;
+  }
+}
+
+// One species vector of a TPC cell, clamped loads (see above).
+template <int NP>
+__device__ __forceinline__ void tpc_load_vec(const double* v, long c, int n, double (&out)[NP]) {
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int ii = i < n ? i : n - 1;
+    const double x = v[Tpc<NP>::idx(c, ii, n)];
+    out[i] = i < n ? x : 0.0;
+  }
+}
+
+// Dynamic LDS of the TPC kernels: NP columns for the evaluation point, NP
+// for the refinement iterate (LS 1), R for the rates, each kTpcThreads wide.
+__host__ __device__ inline size_t tpc_lds_bytes(int np, int R, int ls) {
+  return sizeof(double) * (size_t)kTpcThreads * (size_t)(np * (ls == 1 ? 2 : 1) + R);
+}
+
+// Fused predictor + Newton iterations, thread per cell.  LS 0: FP64 LU kept
+// in registers.  LS 1: FP32 LU kept in registers; each solve is refined with
+// FP64 residuals from the matrix-free product (I - gamma J) x; a cell whose
+// refinement fails switches to FP64 LU, re-assembled and factored at every
+// later iteration of the attempt (rare: the FP64 factors would double the
+// register footprint if they were kept beside the FP32 ones).
+template <int NP, int LS>
+__global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
+  extern __shared__ double lds[];
+  __shared__ double s_red[(kTpcThreads / 64) * kRedNewton];
   Ctrl* C = D.C;
-  const int phase = C->phase;
-  if (FIRST ? phase != PH_PREDICT : (phase != PH_NEWTON || C->m != mslot)) return;
+  if (C->phase != PH_PREDICT) return;
   const ClassDev& K = D.k;
   const NetDev& nd = K.net;
-  const int n = K.n;
-  const long c = (long)blockIdx.x * kCellThreads + threadIdx.x;
+  const int n = K.n, R = K.R;
+  const long c = (long)blockIdx.x * kTpcThreads + threadIdx.x;
   const bool act = c < K.ncells;
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double* ycol = lds + threadIdx.x;                                  // evaluation point
+  double* xcol = lds + NP * kTpcThreads + threadIdx.x;               // LS 1 iterate
+  double* kcol = lds + (LS == 1 ? 2 : 1) * NP * kTpcThreads + threadIdx.x;
+  double red[kRedNewton];
+#pragma unroll
+  for (int k = 0; k < kRedNewton; ++k) red[k] = 0.0;
   if (act) {
-    const double* kap = K.rates + Tpc<NP>::kidx(c, 0, K.R);
-    double* ycol = s_y + threadIdx.x;   // z(0)[0]: J is evaluated here
-    double* xcol = s_x + threadIdx.x;   // Newton iterate, then scratch
+    for (int k0 = 0; k0 < R; k0 += 8) {   // 8 loads in flight per chunk
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = K.rates[Tpc<NP>::kidx(c, k0 + u < R ? k0 + u : R - 1, R)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + u < R) kcol[(k0 + u) * kTpcThreads] = v[u];
+    }
     const double gamma = C->gamma;
-    double r[NP];
-    if (FIRST) {
-      const double l0 = C->l[0];
-      const int q = C->q;
+    const double l0 = C->l[0];
+    const int q = C->q;
+    const int maxcor = C->maxcor;
+    double zp0[NP], cv[NP], w[NP];
+    {
       double zs[kQmaxAll + 1][NP];
+      tpc_load_hist<NP>(K, C, c, n, q, zs);
 #pragma unroll
-      for (int j = 0; j <= kQmaxAll; ++j) {
-        const double hsj = C->hs[j];
-#pragma unroll
-        for (int i = 0; i < NP; ++i)
-          zs[j][i] = (j <= q && i < n) ? K.z[j][Tpc<NP>::idx(c, i, n)] * hsj : 0.0;
-      }
+      for (int i = 0; i < NP; ++i) w[i] = i < n ? 1.0 / (D.rtol * fabs(zs[0][i]) + D.atol) : 0.0;
       if (C->restart) {
         double f0[NP];
-        tpc_store_col<NP>(ycol, zs[0]);
-        Tpc<NP>::rhs(nd, kap, ycol, f0);
+        Tpc<NP>::store_col(ycol, zs[0]);
+        Tpc<NP>::rhs(nd, kcol, kTpcThreads, ycol, f0);
         const double h = C->h;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
@@ -434,92 +498,154 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_newton(BdfDev D, int mslot
           if (k <= q && j <= q)
 #pragma unroll
             for (int i = 0; i < NP; ++i) zs[j - 1][i] = zs[j - 1][i] + zs[j][i];
-      double dcy[NP];   // z(0)[0] - l0 z(0)[1] - y, with y = z(0)[0]
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
-        const double cvi = zs[0][i] - l0 * zs[1][i];
-        ycol[i * kCellThreads] = zs[0][i];
-        dcy[i] = cvi - zs[0][i];
-        if (i < n) {
-          const long id = Tpc<NP>::idx(c, i, n);
-          K.zp0[id] = zs[0][i];
-          K.cv[id] = cvi;
+        zp0[i] = zs[0][i];
+        cv[i] = zs[0][i] - l0 * zs[1][i];
+      }
+    }
+    Tpc<NP>::store_col(ycol, zp0);
+    using TF = typename std::conditional<LS == 1, float, double>::type;
+    TF A[NP][NP];
+    int piv[NP];
+    double rowsum[NP];
+    Tpc<NP>::template build_M<TF>(nd, kcol, kTpcThreads, ycol, gamma, A, rowsum);
+    double mnorm = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) mnorm = fmax(mnorm, rowsum[i]);
+    const int info = TpcLU<NP, TF>::factor(A, piv);
+    bool fp64 = (LS == 1) && info != 0;   // LS 1: FP32 factor singular -> FP64 LU
+    bool sing = (LS == 0) && info != 0;
+    red[4] = fp64 ? 1.0 : 0.0;            // counted with the first iteration
+    double y[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) y[i] = zp0[i];
+    double* yev = LS == 1 ? xcol : ycol;   // LS 1 keeps z(0)[0] in ycol for J
+    for (int m = 0; m < maxcor; ++m) {
+      Tpc<NP>::store_col(yev, y);
+      double r[NP];
+      Tpc<NP>::rhs(nd, kcol, kTpcThreads, yev, r);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) r[i] = fma(gamma, r[i], cv[i] - y[i]);
+      double del[NP];
+      int sweeps = 0, fb = 0;
+      if constexpr (LS == 0) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) del[i] = r[i];
+        TpcLU<NP, TF>::solve(A, piv, del);
+      } else {
+        bool ok = false;
+        if (!fp64) {
+          float v[NP];
+#pragma unroll
+          for (int i = 0; i < NP; ++i) v[i] = (float)r[i];
+          TpcLU<NP, TF>::solve(A, piv, v);
+#pragma unroll
+          for (int i = 0; i < NP; ++i) del[i] = (double)v[i];
+          const double eps64 = 2.220446049250313e-16;
+          double dprv = 0.0;
+          for (int it = 0; it <= K.refine_max_it; ++it) {
+            Tpc<NP>::store_col(xcol, del);
+            double mx[NP];
+            Tpc<NP>::mvp(nd, kcol, kTpcThreads, ycol, xcol, gamma, del, mx);
+            double rn = 0.0, xn = 0.0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+              mx[i] = r[i] - mx[i];
+              rn = fmax(rn, fabs(mx[i]));
+              xn = fmax(xn, fabs(del[i]));
+            }
+            if (!(rn == rn) || !(xn == xn)) break;
+            if (rn <= sqrt((double)NP) * eps64 * mnorm * xn) {
+              ok = true;
+              break;
+            }
+            if (it == K.refine_max_it) break;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) v[i] = (float)mx[i];
+            TpcLU<NP, TF>::solve(A, piv, v);
+            double dn = 0.0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+              del[i] += (double)v[i];
+              dn = fmax(dn, fabs((double)v[i]));
+            }
+            sweeps = it + 1;
+            if (it >= 1 && dn > 0.5 * dprv) break;
+            dprv = dn;
+          }
+          if (!ok) {
+            fp64 = true;
+            fb = 1;
+          }
+        }
+        if (!ok) {
+          double M[NP][NP], rs[NP];
+          Tpc<NP>::template build_M<double>(nd, kcol, kTpcThreads, ycol, gamma, M, rs);
+          int pv[NP];
+          if (TpcLU<NP, double>::factor(M, pv)) sing = true;
+#pragma unroll
+          for (int i = 0; i < NP; ++i) del[i] = r[i];
+          TpcLU<NP, double>::solve(M, pv, del);
         }
       }
-      double f[NP];
-      Tpc<NP>::rhs(nd, kap, ycol, f);
-#pragma unroll
-      for (int i = 0; i < NP; ++i) r[i] = fma(gamma, f[i], dcy[i]);
-    } else {
-      double dcy[NP];
+      double sd = 0.0, sa = 0.0, neg = 0.0;
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
-        const bool in = i < n;
-        const long id = Tpc<NP>::idx(c, i, n);
-        const double yi = in ? K.y[id] : 0.0;
-        xcol[i * kCellThreads] = yi;
-        ycol[i * kCellThreads] = in ? K.zp0[id] : 0.0;
-        dcy[i] = (in ? K.cv[id] : 0.0) - yi;
+        if (i < n) {
+          y[i] += del[i];
+          K.ys[m][Tpc<NP>::idx(c, i, n)] = y[i];
+          const bool ng = D.nonneg && y[i] < 0.0;
+          neg += ng ? 1.0 : 0.0;
+          const double a = del[i] * w[i], b = ((ng ? 0.0 : y[i]) - zp0[i]) * w[i];
+          sd = fma(a, a, sd);
+          sa = fma(b, b, sa);
+        }
       }
-      double f[NP];
-      Tpc<NP>::rhs(nd, kap, xcol, f);
+      // m is not a compile-time constant: accumulate into every slot with
+      // a select so that red[] stays in registers
 #pragma unroll
-      for (int i = 0; i < NP; ++i) r[i] = fma(gamma, f[i], dcy[i]);
-    }
-    double del[NP];
-    int sweeps, fb;
-    const int info =
-        Tpc<NP>::template linsolve<LS>(nd, kap, ycol, xcol, gamma, r, del, K.refine_max_it,
-                                       sweeps, fb);
-    double sd = 0.0, sa = 0.0, neg = 0.0;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      if (i < n) {
-        const long id = Tpc<NP>::idx(c, i, n);
-        const double zp0 = ycol[i * kCellThreads];
-        const double yold = FIRST ? zp0 : K.y[id];
-        const double ynew = yold + del[i];
-        K.y[id] = ynew;
-        const double w = 1.0 / (D.rtol * fabs(K.z[0][id]) + D.atol);
-        const bool ng = D.nonneg && ynew < 0.0;
-        neg += ng ? 1.0 : 0.0;
-        const double yp = ng ? 0.0 : ynew;
-        const double a = del[i] * w, b = (yp - zp0) * w;
-        sd = fma(a, a, sd);
-        sa = fma(b, b, sa);
+      for (int mm = 0; mm < kMaxCor; ++mm) {
+        const bool hit = (mm == m);
+        red[kRedPerIter * mm + 0] += hit ? sd : 0.0;
+        red[kRedPerIter * mm + 1] += hit ? sa : 0.0;
+        red[kRedPerIter * mm + 2] += hit ? neg : 0.0;
+        red[kRedPerIter * mm + 3] += hit ? (double)sweeps : 0.0;
+        red[kRedPerIter * mm + 4] += hit ? (double)fb : 0.0;
       }
     }
-    red[0] = sd;
-    red[1] = sa;
-    red[2] = info ? 1.0 : 0.0;
-    red[3] = (double)sweeps;
-    red[4] = (double)fb;
-    red[5] = neg;
+    red[7] = sing ? 1.0 : 0.0;
   }
-  reduce_and_control(D, red, s_red, [](Ctrl* Cc, const double* s) { after_newton(Cc, s); });
+  reduce_and_control<kRedNewton>(D, red, s_red,
+                                 [](Ctrl* Cc, const double* s) { after_newton_all(Cc, s); });
 }
 
+// History update after an accepted attempt: z_new[j] = z(0)[j] + l_j acor
+// from the iterate of iteration C->m.  acor_prev is read only when the
+// order selection of this step needs it and written only when the next
+// step's does (the step after one with qwait == 2 is the only one that
+// reads it).
 template <int NP>
-__global__ void __launch_bounds__(kCellThreads) k_tpc_accept(BdfDev D) {
-  __shared__ double s_red[(kCellThreads / 64) * kRedVals];
+__global__ void __launch_bounds__(kTpcThreads) k_tpc_accept(BdfDev D) {
+  __shared__ double s_red[(kTpcThreads / 64) * kRedVals];
   Ctrl* C = D.C;
   if (C->phase != PH_ACCEPT) return;
   const ClassDev& K = D.k;
   const int n = K.n;
-  const long c = (long)blockIdx.x * kCellThreads + threadIdx.x;
+  const long c = (long)blockIdx.x * kTpcThreads + threadIdx.x;
   double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (c < K.ncells) {
     const int q = C->q;
     const double l0 = C->l[0];
-    const bool raise = (C->qwait == 1 && q < C->qmax);
+    const bool select = C->qwait == 1;
+    const bool raise = select && q < C->qmax;
+    const bool keep = C->qwait == 2;
     double zs[kQmaxAll + 1][NP];
-#pragma unroll
-    for (int j = 0; j <= kQmaxAll; ++j) {
-      const double hsj = C->hs[j];
-#pragma unroll
-      for (int i = 0; i < NP; ++i)
-        zs[j][i] = (j <= q && i < n) ? K.z[j][Tpc<NP>::idx(c, i, n)] * hsj : 0.0;
-    }
+    tpc_load_hist<NP>(K, C, c, n, q, zs);
+    double yv[NP];
+    tpc_load_vec<NP>(K.ys[C->m], c, n, yv);
+    double dp[NP];
+    if (raise) tpc_load_vec<NP>(K.dprev, c, n, dp);
     double w[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) w[i] = i < n ? 1.0 / (D.rtol * fabs(zs[0][i]) + D.atol) : 0.0;
@@ -535,10 +661,8 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_accept(BdfDev D) {
     for (int i = 0; i < NP; ++i) {
       if (i < n) {
         const long id = Tpc<NP>::idx(c, i, n);
-        const double yv = K.y[id];
-        const double yp = D.nonneg && yv < 0.0 ? 0.0 : yv;
+        const double yp = D.nonneg && yv[i] < 0.0 ? 0.0 : yv[i];
         const double acor = (yp - zs[0][i]) / l0;
-        const double dp = K.dprev[id];
         double znq = yp;
         K.z[0][id] = yp;   // z(0)[0] + l0 acor is the corrected solution itself
 #pragma unroll
@@ -549,29 +673,33 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_accept(BdfDev D) {
             if (j == q) znq = zn;
           }
         }
-        if (raise) K.z[q + 1][id] = C->craise * acor;
-        K.dprev[id] = acor;
-        const double a = znq * w[i], b = (acor - dp) * w[i];
+        if (raise) {
+          K.z[q + 1][id] = C->craise * acor;
+          const double b = (acor - dp[i]) * w[i];
+          sdd = fma(b, b, sdd);
+        }
+        if (keep) K.dprev[id] = acor;
+        const double a = znq * w[i];
         szq = fma(a, a, szq);
-        sdd = fma(b, b, sdd);
       }
     }
     red[0] = szq;
     red[1] = sdd;
   }
-  reduce_and_control(D, red, s_red, [](Ctrl* Cc, const double* s) { after_accept(Cc, s); });
+  reduce_and_control<kRedVals>(D, red, s_red,
+                               [](Ctrl* Cc, const double* s) { after_accept(Cc, s); });
 }
 
 // Starting step, part 1: f(y0) into z[1] (scaled later by h), norms of y0, f0.
 template <int NP>
-__global__ void __launch_bounds__(kCellThreads) k_tpc_init1(BdfDev D) {
-  __shared__ double s_y[NP * kCellThreads];
-  __shared__ double s_red[(kCellThreads / 64) * kRedVals];
+__global__ void __launch_bounds__(kTpcThreads) k_tpc_init1(BdfDev D) {
+  __shared__ double s_y[NP * kTpcThreads];
+  __shared__ double s_red[(kTpcThreads / 64) * kRedVals];
   Ctrl* C = D.C;
   if (C->phase != PH_INIT1) return;
   const ClassDev& K = D.k;
   const int n = K.n;
-  const long c = (long)blockIdx.x * kCellThreads + threadIdx.x;
+  const long c = (long)blockIdx.x * kTpcThreads + threadIdx.x;
   double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (c < K.ncells) {
     const double* kap = K.rates + Tpc<NP>::kidx(c, 0, K.R);
@@ -579,8 +707,8 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_init1(BdfDev D) {
     double y[NP], f[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) y[i] = i < n ? K.z[0][Tpc<NP>::idx(c, i, n)] : 0.0;
-    tpc_store_col<NP>(ycol, y);
-    Tpc<NP>::rhs(K.net, kap, ycol, f);
+    Tpc<NP>::store_col(ycol, y);
+    Tpc<NP>::rhs(K.net, kap, 64, ycol, f);
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
@@ -594,18 +722,19 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_init1(BdfDev D) {
     red[0] = s0;
     red[1] = s1;
   }
-  reduce_and_control(D, red, s_red, [](Ctrl* Cc, const double* s) { after_init1(Cc, s); });
+  reduce_and_control<kRedVals>(D, red, s_red,
+                               [](Ctrl* Cc, const double* s) { after_init1(Cc, s); });
 }
 
 template <int NP>
-__global__ void __launch_bounds__(kCellThreads) k_tpc_init2(BdfDev D) {
-  __shared__ double s_y[NP * kCellThreads];
-  __shared__ double s_red[(kCellThreads / 64) * kRedVals];
+__global__ void __launch_bounds__(kTpcThreads) k_tpc_init2(BdfDev D) {
+  __shared__ double s_y[NP * kTpcThreads];
+  __shared__ double s_red[(kTpcThreads / 64) * kRedVals];
   Ctrl* C = D.C;
   if (C->phase != PH_INIT2) return;
   const ClassDev& K = D.k;
   const int n = K.n;
-  const long c = (long)blockIdx.x * kCellThreads + threadIdx.x;
+  const long c = (long)blockIdx.x * kTpcThreads + threadIdx.x;
   double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (c < K.ncells) {
     const double* kap = K.rates + Tpc<NP>::kidx(c, 0, K.R);
@@ -621,8 +750,8 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_init2(BdfDev D) {
       w[i] = in ? 1.0 / (D.rtol * fabs(y0) + D.atol) : 0.0;
       y1[i] = y0 + h0 * f0[i];
     }
-    tpc_store_col<NP>(ycol, y1);
-    Tpc<NP>::rhs(K.net, kap, ycol, f1);
+    Tpc<NP>::store_col(ycol, y1);
+    Tpc<NP>::rhs(K.net, kap, 64, ycol, f1);
     double s0 = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
@@ -631,7 +760,8 @@ __global__ void __launch_bounds__(kCellThreads) k_tpc_init2(BdfDev D) {
     }
     red[0] = s0;
   }
-  reduce_and_control(D, red, s_red, [](Ctrl* Cc, const double* s) { after_init2(Cc, s); });
+  reduce_and_control<kRedVals>(D, red, s_red,
+                               [](Ctrl* Cc, const double* s) { after_init2(Cc, s); });
 }
 
 // ===========================================================================
@@ -641,10 +771,12 @@ template <int SEG>
 struct Spc {
   static constexpr int CPB = kCellThreads / SEG;   // cells per block
 
-  // lane i: f_i and row i of J at the segment's state in ys (LDS, SEG values)
-  __device__ static void rhs_row(const NetDev& nd, const double* kap, const double* ys, int i,
+  // lane i: f_i at the segment's state in ys (LDS, SEG values); rates of
+  // the cell in kap (LDS or global, contiguous)
+  __device__ static __forceinline__ void rhs_row(const NetDev& nd, const double* kap, const double* ys, int i,
                                  double& f) {
     f = 0.0;
+#pragma unroll 2
     for (int k = 0; k < nd.R; ++k) {
       const int a = nd.ra[k], b = nd.rb[k];
       double r = kap[k];
@@ -654,7 +786,7 @@ struct Spc {
     }
   }
 
-  __device__ static void jac_row(const NetDev& nd, const double* kap, const double* ys, int i,
+  __device__ static __forceinline__ void jac_row(const NetDev& nd, const double* kap, const double* ys, int i,
                                  double (&J)[SEG]) {
 #pragma unroll
     for (int a = 0; a < SEG; ++a) {
@@ -679,62 +811,12 @@ struct SpcShared {
   float prow32[kCellThreads];
   int wl[kCellThreads];
   int wl32[kCellThreads];
-  double red[(kCellThreads / 64) * kRedVals];
+  double red[(kCellThreads / 64) * kRedNewton];
 };
 
-// Solve M x = r for the segment's block; lane i holds row i of M and r_i.
-template <int SEG, int LS>
-__device__ __forceinline__ double spc_linsolve(double (&Mrow)[SEG], double r, int i, int n,
-                                               int seg_base, SpcShared& sh, int sb, int max_it,
-                                               int& info, int& sweeps, int& fallback) {
-  sweeps = 0;
-  fallback = 0;
-  double x = 0.0;
-  bool ok = false;
-  if (LS == 1) {
-    float L[SEG];
-#pragma unroll
-    for (int j = 0; j < SEG; ++j) L[j] = (float)Mrow[j];
-    int pos32, piv32;
-    const int inf32 = SpcLU<SEG, float>::factor(L, i, n, pos32, piv32, sh.prow32 + sb, sh.wl32 + sb);
-    if (!inf32) {
-      double rs = 0.0;
-#pragma unroll
-      for (int j = 0; j < SEG; ++j) rs += fabs(Mrow[j]);
-      const double mnorm = seg_max<SEG>(rs);
-      x = (double)SpcLU<SEG, float>::solve(L, i, seg_base, n, pos32, sh.wl32 + sb, (float)r);
-      const double eps64 = 2.220446049250313e-16;
-      double dprev = 0.0;
-      for (int it = 0; it <= max_it; ++it) {
-        double res = r;
-#pragma unroll
-        for (int j = 0; j < SEG; ++j) res = fma(-Mrow[j], __shfl(x, seg_base + j, 64), res);
-        const double rn = seg_max<SEG>(fabs(res));
-        const double xn = seg_max<SEG>(fabs(x));
-        if (!(rn == rn) || !(xn == xn)) break;
-        if (rn <= sqrt((double)n) * eps64 * mnorm * xn) {
-          ok = true;
-          break;
-        }
-        if (it == max_it) break;
-        const double d =
-            (double)SpcLU<SEG, float>::solve(L, i, seg_base, n, pos32, sh.wl32 + sb, (float)res);
-        x += d;
-        const double dn = seg_max<SEG>(fabs(d));
-        sweeps = it + 1;
-        if (it >= 1 && dn > 0.5 * dprev) break;
-        dprev = dn;
-      }
-    }
-    if (!ok) fallback = 1;
-  }
-  info = 0;
-  if (!ok) {
-    int pos, piv;
-    info = SpcLU<SEG, double>::factor(Mrow, i, n, pos, piv, sh.prow + sb, sh.wl + sb);
-    x = SpcLU<SEG, double>::solve(Mrow, i, seg_base, n, pos, sh.wl + sb, r);
-  }
-  return x;
+// Dynamic LDS of the SPC kernels: the rates of the block's cells.
+__host__ __device__ inline size_t spc_lds_bytes(int seg, int R) {
+  return sizeof(double) * (size_t)(kCellThreads / seg) * (size_t)(R > 0 ? R : 1);
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -743,25 +825,63 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Predictor for one segment-per-cell lane: returns z(0)[0] and z(0)[0] -
-// l0 z(0)[1] of row i (Pascal triangle on the pending-scaled history).
+// Copy the rates of the block's cells (cell-major, contiguous) into LDS.
+template <int SEG>
+__device__ __forceinline__ void spc_load_rates(const ClassDev& K, double* lk) {
+  const long c0 = (long)blockIdx.x * Spc<SEG>::CPB;
+  long cnt = (K.ncells - c0 < Spc<SEG>::CPB ? K.ncells - c0 : Spc<SEG>::CPB) * (long)K.R;
+  for (long t = threadIdx.x; t < cnt; t += blockDim.x) lk[t] = K.rates[c0 * K.R + t];
+  __syncthreads();
+}
+
+// History of one SPC lane: clamped index for padding lanes, compile-time
+// order (see the TPC history loads).
+template <int Q>
+__device__ __forceinline__ void spc_load_hist_q(const ClassDev& K, const Ctrl* C, long ids,
+                                                bool row, double (&zs)[kQmaxAll + 1]) {
+#pragma unroll
+  for (int j = 0; j <= kQmaxAll; ++j) {
+    if (j <= Q) {
+      const double v = K.z[j][ids];
+      zs[j] = row ? v * C->hs[j] : 0.0;
+    } else {
+      zs[j] = 0.0;
+    }
+  }
+}
+
+__device__ __forceinline__ void spc_load_hist(const ClassDev& K, const Ctrl* C, long ids, bool row,
+                                              int q, double (&zs)[kQmaxAll + 1]) {
+  switch (q) {
+    case 1: spc_load_hist_q<1>(K, C, ids, row, zs); break;
+    case 2: spc_load_hist_q<2>(K, C, ids, row, zs); break;
+    case 3: spc_load_hist_q<3>(K, C, ids, row, zs); break;
+    case 4: spc_load_hist_q<4>(K, C, ids, row, zs); break;
+    default: spc_load_hist_q<5>(K, C, ids, row, zs); break;
+  }
+}
+
+// Predictor for one segment-per-cell lane: z(0)[0] and z(0)[0] - l0 z(0)[1]
+// of row i (Pascal triangle on the pending-scaled history), and the error
+// weight from z[0].
 template <int SEG>
 __device__ __forceinline__ void spc_predict_row(const BdfDev& D, const Ctrl* C, SpcShared& sh,
                                                 int sb, int i, bool act, bool row, long id,
-                                                const double* kap, double& zp0, double& cv) {
+                                                const double* kap, double& zp0, double& cv,
+                                                double& w) {
   const ClassDev& K = D.k;
   const int q = C->q;
   double zs[kQmaxAll + 1];
-#pragma unroll
-  for (int j = 0; j <= kQmaxAll; ++j) zs[j] = (row && j <= q) ? K.z[j][id] * C->hs[j] : 0.0;
+  spc_load_hist(K, C, row ? id : 0, row, q, zs);
+  w = row ? 1.0 / (D.rtol * fabs(zs[0]) + D.atol) : 0.0;
   if (C->restart) {
+    __builtin_amdgcn_wave_barrier();
     sh.ys[threadIdx.x] = zs[0];
     wave_sync_lds();
     double f0 = 0.0;
     if (act) Spc<SEG>::rhs_row(K.net, kap, sh.ys + sb, i, f0);
     zs[1] = row ? C->h * f0 : 0.0;
     if (row) K.z[1][id] = zs[1];
-    __builtin_amdgcn_wave_barrier();
   }
 #pragma unroll
   for (int k = 1; k <= kQmaxAll; ++k)
@@ -773,9 +893,10 @@ __device__ __forceinline__ void spc_predict_row(const BdfDev& D, const Ctrl* C, 
 }
 
 // Learned mode: predictor only, plus the MLP inputs [z(0)[0], log gamma]
-// of every cell and the per-cell solver mode of the attempt.
+// of every cell.
 template <int SEG>
 __global__ void __launch_bounds__(kCellThreads) k_spc_predict(BdfDev D) {
+  extern __shared__ double lk[];
   __shared__ SpcShared sh;
   Ctrl* C = D.C;
   if (C->phase != PH_PREDICT) return;
@@ -783,36 +904,37 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_predict(BdfDev D) {
   const int n = K.n;
   const int i = threadIdx.x & (SEG - 1);
   const int sb = threadIdx.x & ~(SEG - 1);
-  const long c = (long)blockIdx.x * Spc<SEG>::CPB + threadIdx.x / SEG;
+  const int cb = threadIdx.x / SEG;
+  const long c = (long)blockIdx.x * Spc<SEG>::CPB + cb;
   const bool act = c < K.ncells;
   const bool row = act && i < n;
   const long id = c * n + i;
-  const double* kap = K.rates + (act ? c : 0) * (long)K.R;
-  double zp0, cv;
-  spc_predict_row<SEG>(D, C, sh, sb, i, act, row, id, kap, zp0, cv);
+  spc_load_rates<SEG>(K, lk);
+  const double* kap = lk + cb * K.R;
+  double zp0, cv, w;
+  spc_predict_row<SEG>(D, C, sh, sb, i, act, row, id, kap, zp0, cv, w);
   if (row) {
     K.zp0[id] = zp0;
     K.cv[id] = cv;
-    K.y[id] = zp0;
     K.xin[c * (n + 1) + i] = zp0;
   }
-  if (act && i == 0) {
-    K.xin[c * (n + 1) + n] = log(C->gamma);
-    K.lpmode[c] = C->force_lu ? 0 : 2;
-    K.dcprev[c] = 0.0;
-  }
+  if (act && i == 0) K.xin[c * (n + 1) + n] = log(C->gamma);
 }
 
-// Newton iteration for segment-per-cell classes.  FIRST = 1: the attempt's
-// first iteration (with the predictor unless LS == 2, whose predictor ran
-// in k_spc_predict).  LS: 0 FP64 LU, 1 FP32 LU + refinement, 2 learned
-// approximate inverse with per-cell fallback to FP64 LU.
-template <int SEG, int LS, int FIRST>
-__global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D, int mslot) {
+// Fused Newton iterations, segment per cell.  LS 0: FP64 LU factored once.
+// LS 1: FP32 LU factored once, each solve refined with FP64 residuals from
+// the FP64 rows; a cell whose refinement fails factors its FP64 rows in
+// place and uses them from then on.  LS 2: correction X r with the cell's
+// learned approximate inverse (X from the MLP, computed after the predictor
+// kernel); a cell switches to FP64 LU for the rest of the attempt when X r
+// is not finite, or from the second iteration on when its correction norm
+// does not fall below 0.9 times the previous one.
+template <int SEG, int LS>
+__global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
+  extern __shared__ double lk[];
   __shared__ SpcShared sh;
   Ctrl* C = D.C;
-  const int phase = C->phase;
-  if (FIRST ? phase != PH_PREDICT : (phase != PH_NEWTON || C->m != mslot)) return;
+  if (C->phase != PH_PREDICT) return;
   const ClassDev& K = D.k;
   const NetDev& nd = K.net;
   const int n = K.n;
@@ -820,61 +942,31 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D, int mslot
   const int i = lane & (SEG - 1);
   const int seg_base = lane & ~(SEG - 1);
   const int sb = threadIdx.x & ~(SEG - 1);
-  const long c = (long)blockIdx.x * Spc<SEG>::CPB + threadIdx.x / SEG;
+  const int cb = threadIdx.x / SEG;
+  const long c = (long)blockIdx.x * Spc<SEG>::CPB + cb;
   const bool act = c < K.ncells;           // uniform over the segment
   const bool row = act && i < n;
   const long id = c * n + i;
-  const double* kap = K.rates + (act ? c : 0) * (long)K.R;
+  spc_load_rates<SEG>(K, lk);
+  const double* kap = lk + cb * K.R;
   const double gamma = C->gamma;
-  const int m = FIRST ? 0 : mslot;
-  double y = 0.0, zp0 = 0.0, cv = 0.0, w = 0.0;
-  if (FIRST && LS != 2) {
-    spc_predict_row<SEG>(D, C, sh, sb, i, act, row, id, kap, zp0, cv);
-    y = zp0;
-    w = row ? 1.0 / (D.rtol * fabs(K.z[0][id]) + D.atol) : 0.0;
+  const int maxcor = C->maxcor;
+  double zp0 = 0.0, cv = 0.0, w = 0.0;
+  if (LS != 2) {
+    spc_predict_row<SEG>(D, C, sh, sb, i, act, row, id, kap, zp0, cv, w);
   } else if (row) {
-    y = K.y[id];
     zp0 = K.zp0[id];
     cv = K.cv[id];
     w = 1.0 / (D.rtol * fabs(K.z[0][id]) + D.atol);
   }
-  // f at the iterate
-  __builtin_amdgcn_wave_barrier();
-  sh.ys[threadIdx.x] = y;
-  wave_sync_lds();
-  double f = 0.0;
-  if (act) Spc<SEG>::rhs_row(nd, kap, sh.ys + sb, i, f);
-  const double r = row ? fma(gamma, f, cv - y) : 0.0;
-  int mode = 0;                           // 0/4 exact LU, 2 learned, 3 switching
-  if (LS == 2 && act) mode = K.lpmode[c];
-  double del = 0.0;
-  int info = 0, sweeps = 0, fb = 0;
-  double lp_solves = 0.0, lp_fb = 0.0;
-  bool use_lu = (LS != 2) || mode != 2;
-  if (LS == 2 && mode == 2) {
-    // correction = X r with the cell's approximate inverse (row i of X)
-    __builtin_amdgcn_wave_barrier();
-    sh.ys[threadIdx.x] = r;
-    wave_sync_lds();
-    if (row) {
-      const float* Xr = K.X + c * (long)n * n + (long)i * n;
-      double s = 0.0;
-      for (int j = 0; j < n; ++j) s = fma((double)Xr[j], sh.ys[sb + j], s);
-      del = s;
-    }
-    const double bad = seg_max<SEG>(row && !(fabs(del) <= 1.79e308) ? 1.0 : 0.0);
-    lp_solves = 1.0;
-    if (bad > 0.0) {
-      mode = 3;
-      use_lu = true;
-    }
-  }
-  if (use_lu) {
-    double Mrow[SEG];
+  // M = I - gamma J(z(0)[0]), row i in this lane (identity rows past n)
+  double Mrow[SEG];
+  auto assemble = [&]() {
     __builtin_amdgcn_wave_barrier();
     sh.ys[threadIdx.x] = zp0;
     wave_sync_lds();
-    if (act) Spc<SEG>::jac_row(nd, kap, sh.ys + sb, i, Mrow);
+    if (act)
+      Spc<SEG>::jac_row(nd, kap, sh.ys + sb, i, Mrow);
     else
 #pragma unroll
       for (int j = 0; j < SEG; ++j) Mrow[j] = 0.0;
@@ -883,47 +975,159 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D, int mslot
     if (!row)
 #pragma unroll
       for (int j = 0; j < SEG; ++j) Mrow[j] = (i == j ? 1.0 : 0.0);
-    del = spc_linsolve<SEG, LS == 1 ? 1 : 0>(Mrow, r, i, act ? n : 0, seg_base, sh, sb,
-                                              K.refine_max_it, info, sweeps, fb);
-    if (LS == 2 && mode == 3) {
-      lp_fb = 1.0;
-      mode = 4;
+  };
+  const int nn = act ? n : 0;
+  int pos = i, piv = i, info = 0;
+  // LS 1 state
+  float L[LS == 1 ? SEG : 1];
+  int pos32 = i, piv32 = i;
+  bool fp64 = LS == 0;
+  double mnorm = 0.0;
+  // LS 2 state
+  int mode = 0;                           // 2 learned, 3 switching to LU, 4 LU
+  bool factored = false;
+  double dcprev = 0.0;
+  if constexpr (LS == 0) {
+    assemble();
+    info = SpcLU<SEG, double>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+    factored = true;
+  } else if constexpr (LS == 1) {
+    assemble();
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) L[j] = (float)Mrow[j];
+    const int inf32 =
+        SpcLU<SEG, float>::factor(L, i, nn, pos32, piv32, sh.prow32 + sb, sh.wl32 + sb);
+    double rs = 0.0;
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) rs += fabs(Mrow[j]);
+    mnorm = seg_max<SEG>(rs);
+    if (inf32) {
+      fp64 = true;
+      info = SpcLU<SEG, double>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+    }
+  } else {
+    mode = (act && !C->force_lu) ? 2 : 4;
+    if (mode == 4) {
+      assemble();
+      info = SpcLU<SEG, double>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+      factored = true;
     }
   }
-  if (LS == 2) {
-    const double dc2 = seg_sum<SEG>(row ? (del * w) * (del * w) : 0.0);
-    const double dc = sqrt(dc2 / (double)n);
-    if (act) {
-      if (mode == 2 && m >= 1 && dc > 0.9 * K.dcprev[c]) mode = 3;
-      __builtin_amdgcn_wave_barrier();
-      if (i == 0) {
-        K.lpmode[c] = mode;
-        K.dcprev[c] = dc;
+  float Xrow[LS == 2 ? SEG : 1];
+  if constexpr (LS == 2) {
+#pragma unroll
+    for (int j = 0; j < SEG; ++j)
+      Xrow[j] = K.X[(row ? c * (long)n * n + (long)i * n : 0) + (j < n ? j : 0)];
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) Xrow[j] = (mode == 2 && row && j < n) ? Xrow[j] : 0.0f;
+  }
+  double red[kRedNewton];
+#pragma unroll
+  for (int k = 0; k < kRedNewton; ++k) red[k] = 0.0;
+  if (LS == 1 && act && i == 0 && fp64) red[4] = 1.0;   // FP32 factor singular at setup
+  double y = zp0;
+  for (int m = 0; m < maxcor; ++m) {
+    __builtin_amdgcn_wave_barrier();
+    sh.ys[threadIdx.x] = y;
+    wave_sync_lds();
+    double f = 0.0;
+    if (act) Spc<SEG>::rhs_row(nd, kap, sh.ys + sb, i, f);
+    const double r = row ? fma(gamma, f, cv - y) : 0.0;
+    double del = 0.0;
+    int sweeps = 0, fb = 0;
+    double lp_solves = 0.0, lp_fb = 0.0;
+    if constexpr (LS == 0) {
+      del = SpcLU<SEG, double>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
+    } else if constexpr (LS == 1) {
+      bool ok = false;
+      if (!fp64) {
+        double x = (double)SpcLU<SEG, float>::solve(L, i, seg_base, nn, pos32, sh.wl32 + sb,
+                                                    (float)r);
+        const double eps64 = 2.220446049250313e-16;
+        double dprv = 0.0;
+        for (int it = 0; it <= K.refine_max_it; ++it) {
+          double res = r;
+#pragma unroll
+          for (int j = 0; j < SEG; ++j) res = fma(-Mrow[j], __shfl(x, seg_base + j, 64), res);
+          const double rn = seg_max<SEG>(fabs(res));
+          const double xn = seg_max<SEG>(fabs(x));
+          if (!(rn == rn) || !(xn == xn)) break;
+          if (rn <= sqrt((double)n) * eps64 * mnorm * xn) {
+            ok = true;
+            break;
+          }
+          if (it == K.refine_max_it) break;
+          const double d = (double)SpcLU<SEG, float>::solve(L, i, seg_base, nn, pos32,
+                                                            sh.wl32 + sb, (float)res);
+          x += d;
+          const double dn = seg_max<SEG>(fabs(d));
+          sweeps = it + 1;
+          if (it >= 1 && dn > 0.5 * dprv) break;
+          dprv = dn;
+        }
+        del = x;
+        if (!ok) {
+          fb = 1;
+          fp64 = true;
+          info = SpcLU<SEG, double>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+        }
       }
+      if (!ok) del = SpcLU<SEG, double>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
+    } else {
+      if (mode == 2) {
+        // correction = X r with row i of the cell's approximate inverse
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) s = fma((double)Xrow[j], __shfl(r, seg_base + j, 64), s);
+        del = row ? s : 0.0;
+        const double bad = seg_max<SEG>(row && !(fabs(del) <= 1.79e308) ? 1.0 : 0.0);
+        lp_solves = act ? 1.0 : 0.0;
+        if (bad > 0.0) mode = 3;
+      }
+      if (mode != 2) {
+        if (!factored) {
+          assemble();
+          info = SpcLU<SEG, double>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+          factored = true;
+        }
+        del = SpcLU<SEG, double>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
+        if (mode == 3) {
+          lp_fb = 1.0;
+          mode = 4;
+        }
+      }
+      const double dc = sqrt(seg_sum<SEG>(row ? (del * w) * (del * w) : 0.0) / (double)n);
+      if (mode == 2 && m >= 1 && dc > 0.9 * dcprev) mode = 3;
+      dcprev = dc;
+    }
+    double sd = 0.0, sa = 0.0, neg = 0.0;
+    if (row) {
+      y += del;
+      K.ys[m][id] = y;
+      const bool ng = D.nonneg && y < 0.0;
+      const double a = del * w, b = ((ng ? 0.0 : y) - zp0) * w;
+      sd = a * a;
+      sa = b * b;
+      neg = ng ? 1.0 : 0.0;
+    }
+    const bool lead = act && i == 0;
+#pragma unroll
+    for (int mm = 0; mm < kMaxCor; ++mm) {
+      const bool hit = (mm == m);
+      red[kRedPerIter * mm + 0] += hit ? sd : 0.0;
+      red[kRedPerIter * mm + 1] += hit ? sa : 0.0;
+      red[kRedPerIter * mm + 2] += hit ? neg : 0.0;
+      red[kRedPerIter * mm + 3] += (hit && lead) ? (double)sweeps : 0.0;
+      red[kRedPerIter * mm + 4] += (hit && lead) ? (double)fb : 0.0;
+      red[kRedPerIter * mm + 5] += (hit && lead) ? lp_solves : 0.0;
+      red[kRedPerIter * mm + 6] += (hit && lead) ? lp_fb : 0.0;
     }
   }
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (row) {
-    y += del;
-    K.y[id] = y;
-    if (FIRST && LS != 2) {
-      K.zp0[id] = zp0;
-      K.cv[id] = cv;
-    }
-    const bool ng = D.nonneg && y < 0.0;
-    const double a = del * w, b = ((ng ? 0.0 : y) - zp0) * w;
-    red[0] = a * a;
-    red[1] = b * b;
-    red[5] = ng ? 1.0 : 0.0;
-  }
-  if (act && i == 0) {
-    red[2] = info ? 1.0 : 0.0;
-    red[3] = (double)sweeps;
-    red[4] = (double)fb;
-    red[6] = lp_solves;
-    red[7] = lp_fb;
-  }
-  reduce_and_control(D, red, sh.red, [](Ctrl* Cc, const double* s) { after_newton(Cc, s); });
+  // a singular FP64 factorisation fails the attempt (LS 1: only the FP64
+  // fallback can be singular; the FP32 factor then falls back)
+  if (act && i == 0) red[7] = info ? 1.0 : 0.0;
+  reduce_and_control<kRedNewton>(D, red, sh.red,
+                                 [](Ctrl* Cc, const double* s) { after_newton_all(Cc, s); });
 }
 
 template <int SEG>
@@ -940,19 +1144,21 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_accept(BdfDev D) {
     const long id = c * n + i;
     const int q = C->q;
     const double l0 = C->l[0];
+    const bool select = C->qwait == 1;
+    const bool raise = select && q < C->qmax;
+    const bool keep = C->qwait == 2;
     double zs[kQmaxAll + 1];
-#pragma unroll
-    for (int j = 0; j <= kQmaxAll; ++j) zs[j] = j <= q ? K.z[j][id] * C->hs[j] : 0.0;
+    spc_load_hist(K, C, id, true, q, zs);
+    const double yv = K.ys[C->m][id];
+    const double dp = raise ? K.dprev[id] : 0.0;
     const double w = 1.0 / (D.rtol * fabs(zs[0]) + D.atol);
 #pragma unroll
     for (int k = 1; k <= kQmaxAll; ++k)
 #pragma unroll
       for (int j = kQmaxAll; j >= k; --j)
         if (k <= q && j <= q) zs[j - 1] = zs[j - 1] + zs[j];
-    const double yv = K.y[id];
     const double yp = D.nonneg && yv < 0.0 ? 0.0 : yv;
     const double acor = (yp - zs[0]) / l0;
-    const double dp = K.dprev[id];
     double znq = yp;
     K.z[0][id] = yp;   // z(0)[0] + l0 acor is the corrected solution itself
 #pragma unroll
@@ -963,13 +1169,17 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_accept(BdfDev D) {
         if (j == q) znq = zn;
       }
     }
-    if (C->qwait == 1 && q < C->qmax) K.z[q + 1][id] = C->craise * acor;
-    K.dprev[id] = acor;
-    const double a = znq * w, b = (acor - dp) * w;
+    if (raise) {
+      K.z[q + 1][id] = C->craise * acor;
+      const double b = (acor - dp) * w;
+      red[1] = b * b;
+    }
+    if (keep) K.dprev[id] = acor;
+    const double a = znq * w;
     red[0] = a * a;
-    red[1] = b * b;
   }
-  reduce_and_control(D, red, s_red, [](Ctrl* Cc, const double* s) { after_accept(Cc, s); });
+  reduce_and_control<kRedVals>(D, red, s_red,
+                               [](Ctrl* Cc, const double* s) { after_accept(Cc, s); });
 }
 
 template <int SEG>
@@ -998,7 +1208,8 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_init1(BdfDev D) {
     red[0] = (y * w) * (y * w);
     red[1] = (f * w) * (f * w);
   }
-  reduce_and_control(D, red, s_red, [](Ctrl* Cc, const double* s) { after_init1(Cc, s); });
+  reduce_and_control<kRedVals>(D, red, s_red,
+                               [](Ctrl* Cc, const double* s) { after_init1(Cc, s); });
 }
 
 template <int SEG>
@@ -1028,7 +1239,8 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_init2(BdfDev D) {
     const double d = (f1 - f0) * w;
     red[0] = d * d;
   }
-  reduce_and_control(D, red, s_red, [](Ctrl* Cc, const double* s) { after_init2(Cc, s); });
+  reduce_and_control<kRedVals>(D, red, s_red,
+                               [](Ctrl* Cc, const double* s) { after_init2(Cc, s); });
 }
 
 }  // namespace bdfgpu

@@ -5,42 +5,32 @@
 namespace bdfgpu {
 
 template <int SEG>
-static void spc_go(int ls, int which, const BdfDev& D, int mslot, unsigned int grid,
-                   hipStream_t s) {
+static void spc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s) {
   const dim3 g(grid), b(kCellThreads);
+  const size_t lds = spc_lds_bytes(SEG, D.k.R);
   switch (which) {
     case 0: hipLaunchKernelGGL(k_spc_init1<SEG>, g, b, 0, s, D); break;
     case 1: hipLaunchKernelGGL(k_spc_init2<SEG>, g, b, 0, s, D); break;
     case 2:
-      if (mslot == 0) {
-        if (ls == 1)
-          hipLaunchKernelGGL((k_spc_newton<SEG, 1, 1>), g, b, 0, s, D, mslot);
-        else if (ls == 2)
-          hipLaunchKernelGGL((k_spc_newton<SEG, 2, 1>), g, b, 0, s, D, mslot);
-        else
-          hipLaunchKernelGGL((k_spc_newton<SEG, 0, 1>), g, b, 0, s, D, mslot);
-      } else {
-        if (ls == 1)
-          hipLaunchKernelGGL((k_spc_newton<SEG, 1, 0>), g, b, 0, s, D, mslot);
-        else if (ls == 2)
-          hipLaunchKernelGGL((k_spc_newton<SEG, 2, 0>), g, b, 0, s, D, mslot);
-        else
-          hipLaunchKernelGGL((k_spc_newton<SEG, 0, 0>), g, b, 0, s, D, mslot);
-      }
+      if (ls == 1)
+        hipLaunchKernelGGL((k_spc_newton<SEG, 1>), g, b, lds, s, D);
+      else if (ls == 2)
+        hipLaunchKernelGGL((k_spc_newton<SEG, 2>), g, b, lds, s, D);
+      else
+        hipLaunchKernelGGL((k_spc_newton<SEG, 0>), g, b, lds, s, D);
       break;
-    case 4: hipLaunchKernelGGL(k_spc_predict<SEG>, g, b, 0, s, D); break;
+    case 4: hipLaunchKernelGGL(k_spc_predict<SEG>, g, b, lds, s, D); break;
     default: hipLaunchKernelGGL(k_spc_accept<SEG>, g, b, 0, s, D); break;
   }
 }
 
 int spc_seg(int n) { return n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 0; }
 
-void launch_spc(int seg, int ls, int which, const BdfDev& D, int mslot, unsigned int grid,
-                hipStream_t s) {
+void launch_spc(int seg, int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s) {
   switch (seg) {
-    case 16: spc_go<16>(ls, which, D, mslot, grid, s); break;
-    case 32: spc_go<32>(ls, which, D, mslot, grid, s); break;
-    default: spc_go<64>(ls, which, D, mslot, grid, s); break;
+    case 16: spc_go<16>(ls, which, D, grid, s); break;
+    case 32: spc_go<32>(ls, which, D, grid, s); break;
+    default: spc_go<64>(ls, which, D, grid, s); break;
   }
 }
 

@@ -5,25 +5,19 @@
 namespace bdfgpu {
 
 template <int NP>
-static void tpc_go(int ls, int which, const BdfDev& D, int mslot, unsigned int grid,
-                   hipStream_t s) {
-  const dim3 g(grid), b(kCellThreads);
+static void tpc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s) {
+  const dim3 g(grid), b(kTpcThreads);
   switch (which) {
     case 0: hipLaunchKernelGGL(k_tpc_init1<NP>, g, b, 0, s, D); break;
     case 1: hipLaunchKernelGGL(k_tpc_init2<NP>, g, b, 0, s, D); break;
-    case 2:
-      if (mslot == 0) {
-        if (ls == 1)
-          hipLaunchKernelGGL((k_tpc_newton<NP, 1, 1>), g, b, 0, s, D, mslot);
-        else
-          hipLaunchKernelGGL((k_tpc_newton<NP, 0, 1>), g, b, 0, s, D, mslot);
-      } else {
-        if (ls == 1)
-          hipLaunchKernelGGL((k_tpc_newton<NP, 1, 0>), g, b, 0, s, D, mslot);
-        else
-          hipLaunchKernelGGL((k_tpc_newton<NP, 0, 0>), g, b, 0, s, D, mslot);
-      }
+    case 2: {
+      const size_t lds = tpc_lds_bytes(NP, D.k.R, ls);
+      if (ls == 1)
+        hipLaunchKernelGGL((k_tpc_newton<NP, 1>), g, b, lds, s, D);
+      else
+        hipLaunchKernelGGL((k_tpc_newton<NP, 0>), g, b, lds, s, D);
       break;
+    }
     default: hipLaunchKernelGGL(k_tpc_accept<NP>, g, b, 0, s, D); break;
   }
 }
@@ -32,15 +26,14 @@ int tpc_padded(int n) {
   return n <= 3 ? 3 : n <= 4 ? 4 : n <= 6 ? 6 : n <= 8 ? 8 : n <= 10 ? 10 : n <= 12 ? 12 : 0;
 }
 
-void launch_tpc(int np, int ls, int which, const BdfDev& D, int mslot, unsigned int grid,
-                hipStream_t s) {
+void launch_tpc(int np, int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s) {
   switch (np) {
-    case 3: tpc_go<3>(ls, which, D, mslot, grid, s); break;
-    case 4: tpc_go<4>(ls, which, D, mslot, grid, s); break;
-    case 6: tpc_go<6>(ls, which, D, mslot, grid, s); break;
-    case 8: tpc_go<8>(ls, which, D, mslot, grid, s); break;
-    case 10: tpc_go<10>(ls, which, D, mslot, grid, s); break;
-    default: tpc_go<12>(ls, which, D, mslot, grid, s); break;
+    case 3: tpc_go<3>(ls, which, D, grid, s); break;
+    case 4: tpc_go<4>(ls, which, D, grid, s); break;
+    case 6: tpc_go<6>(ls, which, D, grid, s); break;
+    case 8: tpc_go<8>(ls, which, D, grid, s); break;
+    case 10: tpc_go<10>(ls, which, D, grid, s); break;
+    default: tpc_go<12>(ls, which, D, grid, s); break;
   }
 }
 

@@ -80,7 +80,7 @@ struct SpcLU {
   // row[] holds this lane's row of L\U in column order, pos its position in
   // the permuted matrix, piv the LAPACK pivot of step k == r.  Returns info
   // (1-based first exactly-zero pivot, 0 if none).
-  __device__ static int factor(T (&row)[SEG], int r, int n, int& pos, int& piv, T* prow,
+  __device__ static __forceinline__ int factor(T (&row)[SEG], int r, int n, int& pos, int& piv, T* prow,
                                int* wl) {
     pos = r;
     piv = r;
@@ -147,7 +147,7 @@ struct SpcLU {
   // factors already in position order (lane r holds position r).  `val` is
   // this lane's right-hand-side entry, already permuted in the second case.
   // Returns component r of the solution.  row[] is left unchanged.
-  __device__ static T solve(T (&row)[SEG], int r, int seg_base, int n, int pos, const int* wl,
+  __device__ static __forceinline__ T solve(T (&row)[SEG], int r, int seg_base, int n, int pos, const int* wl,
                             T val) {
     const int nch = (n + CH - 1) / CH;
     for (int c = 0; c < NCH; ++c) {
@@ -182,7 +182,7 @@ struct SpcLU {
 
   // Solve with factors stored in LAPACK layout (lane r holds the row at
   // position r) and LAPACK pivots piv[0..n-1] in global memory.
-  __device__ static T solve_stored(T (&row)[SEG], int r, int seg_base, const int* piv, int n,
+  __device__ static __forceinline__ T solve_stored(T (&row)[SEG], int r, int seg_base, const int* piv, int n,
                                    T val) {
     for (int k = 0; k < n; ++k) {
       const int p = piv[k];

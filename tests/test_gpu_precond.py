@@ -1,0 +1,214 @@
+"""GPU parity of the learned block preconditioner against the CPU oracle.
+
+The MLP, its loss and Adam are not in the paper; the oracle's versions are
+pinned in test_oracle_mlp.py (finite differences, exact-inverse zero loss,
+Adam's closed-form first step).  Bars, from the arithmetic: every matrix
+product takes BF16 operands with FP32 accumulation on the GPU and FP64
+accumulation in the oracle, so pre-activations differ by ~1e-6 relative and
+a hidden activation whose value sits next to a BF16 rounding boundary can
+round one BF16 ulp (2^-8) the other way; a few such flips move an output by
+about 1e-3 of the output scale.  Outputs: max error <= 1e-2 of the largest
+output magnitude and mean error <= 1e-3 of it.  Loss: 1e-4 relative.
+Gradients (FP32 sums over a batch): relative 2-norm error <= 1e-2 per
+tensor.  Adam on identical gradients: FP32 rounding of the update, 1e-6
+relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N21 = 21
+
+
+def oracle_mlp(orc, params, mean, std, n=N21):
+    W1, b1, W2, b2, W3, b3 = W.mlp_split(params, n)
+    return orc.MLP(W1, b1, W2, b2, W3, b3, mean, std)
+
+
+def inputs(ns, n=N21, seed=11):
+    """Raw MLP inputs [y, log gamma]: y on the simplex, log gamma in
+    [-20, 0] (the range a stiff integration visits)."""
+    rng = W.rng_for(seed)
+    y = W.simplex_states(rng, ns, n)
+    lg = rng.uniform(-20.0, 0.0, size=(ns, 1))
+    return np.hstack([y, lg])
+
+
+def norm_of(X):
+    mean = X.mean(0)
+    std = X.std(0)
+    std[std < 1e-12] = 1.0
+    return mean, std
+
+
+def blocks(ns, n=N21, seed=12):
+    """Column-major M = I - gamma J stand-ins: I + random perturbation."""
+    rng = W.rng_for(seed)
+    A = np.eye(n)[None] + 0.3 * rng.uniform(-1.0, 1.0, size=(ns, n, n))
+    return A, np.ascontiguousarray(np.stack([a.ravel(order="F") for a in A]))
+
+
+@pytest.fixture(scope="module")
+def net(G, dev):
+    params = W.mlp_init(N21, seed=W.BASE_SEED + 6)
+    X = inputs(300)
+    mean, std = norm_of(X)
+    pc = G.Precond(N21, batch_cap=256)
+    pc.set_params(params)
+    pc.set_normalization(mean, std)
+    return pc, params, mean, std
+
+
+@pytest.mark.parametrize("ns", [1, 31, 300])
+def test_forward_mfma_and_vector_match_oracle(orc, dev, G, net, ns):
+    pc, params, mean, std = net
+    X = inputs(300)[:ns]
+    ref = oracle_mlp(orc, params, mean, std).forward(X)   # raw outputs
+    ref = ref + np.eye(N21).ravel()[None]                 # X = I + out
+    Xd = torch.tensor(X, device=dev)
+    for use_mfma in (True, False):
+        out = pc.forward(Xd, use_mfma=use_mfma).cpu().numpy().astype(np.float64)
+        scale = np.abs(ref).max()
+        err = np.abs(out - ref)
+        print(f"ns={ns} mfma={use_mfma}: max err {err.max() / scale:.2e}, "
+              f"mean {err.mean() / scale:.2e} of scale {scale:.3e}")
+        assert err.max() <= 1e-2 * scale
+        assert err.mean() <= 1e-3 * scale
+
+
+def test_forward_zero_rows_and_empty(dev, G, net):
+    pc, _, _, _ = net
+    out = pc.forward(torch.zeros((0, N21 + 1), dtype=torch.float64, device=dev))
+    assert out.shape == (0, N21 * N21)
+
+
+def test_loss_and_gradients_match_oracle(orc, dev, G, net):
+    pc, params, mean, std = net
+    B = 64
+    X = inputs(B, seed=21)
+    Mm, Mc = blocks(B, seed=22)
+    L_ref, g_ref = oracle_mlp(orc, params, mean, std).loss_grad(X, Mm)
+    pc.set_params(params)
+    L = pc.loss_grad(torch.tensor(X, device=dev), torch.tensor(Mc, device=dev))
+    _, g = pc.get_params(with_grads=True)
+    print(f"loss gpu {L:.8e} oracle {L_ref:.8e}")
+    assert L == pytest.approx(L_ref, rel=1e-4)
+    gparts = W.mlp_split(g, N21)
+    for name, a, b in zip(("W1", "b1", "W2", "b2", "W3", "b3"), gparts, g_ref):
+        rel = np.linalg.norm(a.astype(np.float64) - b) / max(np.linalg.norm(b), 1e-300)
+        print(f"  grad {name}: rel err {rel:.2e}")
+        assert rel <= 1e-2
+
+
+def test_adam_step_matches_oracle(orc, dev, G, net):
+    pc, params, mean, std = net
+    X = inputs(64, seed=31)
+    _, Mc = blocks(64, seed=32)
+    pc.set_params(params)   # also clears the moments
+    pc.loss_grad(torch.tensor(X, device=dev), torch.tensor(Mc, device=dev))
+    p0, g = pc.get_params(with_grads=True)
+    pc.adam(lr=1e-3)
+    p1 = pc.get_params()
+    pr = p0.copy()
+    m1 = np.zeros(pr.size)
+    m2 = np.zeros(pr.size)
+    orc.adam_step(pr, g.astype(np.float64), m1, m2, 1, lr=1e-3)
+    d = np.abs(p1.astype(np.float64) - pr.astype(np.float64))
+    assert d.max() <= 1e-6 * max(1.0, np.abs(pr).max())
+    # the first step moves every parameter with a nonzero gradient by ~lr
+    moved = np.abs(p1 - p0)[np.abs(g) > 1e-20]
+    assert np.median(moved) == pytest.approx(1e-3, rel=0.05)
+
+
+def test_fit_normalization(dev, G):
+    pc = G.Precond(N21, batch_cap=64)
+    X = inputs(500, seed=41)
+    pc.fit_normalization(torch.tensor(X, device=dev))
+    m, s = pc.get_normalization()
+    mr, sr = norm_of(X)
+    assert np.allclose(m, mr, rtol=1e-12, atol=1e-14)
+    assert np.allclose(s, sr, rtol=1e-10)
+    pc.close()
+
+
+def test_learned_mode_trajectory_matches_oracle(orc, dev, G):
+    """Learned mode with one fixed (untrained) network: per-cell X r,
+    switches to LU, and attempt-level LU retries, against the oracle's
+    learned mode with the same weights.  X differs by the FP32-vs-FP64
+    accumulation of the MLP, so decisions may flip; then both runs must be
+    equally accurate against a tight plain-LU reference."""
+    p = W.learned_batch(48, t_end=3e-3)
+    params = W.mlp_init(N21, seed=W.BASE_SEED + 6, out_scale=0.02)
+    Xs = np.hstack([p.y0.reshape(-1, N21), np.full((48, 1), -8.0)])
+    mean, std = norm_of(Xs)
+    std[:] = np.maximum(std, 0.1)
+    ob = orc.Bdf(p, linsol=orc.LS_LEARNED, mlp=oracle_mlp(orc, params, mean, std))
+    assert ob.integrate(p.t_end) == 0
+    pc = G.Precond(N21, batch_cap=128)
+    pc.set_params(params)
+    pc.set_normalization(mean, std)
+    gb = G.Bdf.from_problem(p, device=dev, linsol=G.LS_LEARNED, precond=pc)
+    assert gb.integrate(p.t_end) == p.t_end
+    so, sg = ob.stats(), gb.stats()
+    print("oracle", {k: so[k] for k in ("nsteps", "nattempts", "nniters", "lp_cell_solves",
+                                        "lp_fallback_cells", "lp_step_fallbacks")})
+    print("gpu   ", {k: sg[k] for k in ("nsteps", "nattempts", "nniters", "lp_cell_solves",
+                                        "lp_fallback_cells", "lp_step_fallbacks")})
+    assert sg["lp_cell_solves"] > 0
+    yg, yo = gb.y().cpu().numpy(), ob.y()
+    ref = orc.Bdf(p, rtol=p.rtol * 1e-3, atol=p.atol * 1e-3)
+    assert ref.integrate(p.t_end) == 0
+    yr = ref.y()
+    w = lambda a: float(np.sqrt(np.mean(((a - yr) / (p.rtol * np.abs(yr) + p.atol)) ** 2)))
+    print(f"error vs reference: gpu {w(yg):.3e} oracle {w(yo):.3e}")
+    assert w(yg) <= max(3.0 * w(yo), 1.0)
+    assert abs(so["nsteps"] - sg["nsteps"]) <= max(3, 0.15 * so["nsteps"])
+    gb.close()
+    pc.close()
+
+
+def test_training_reduces_loss_and_helps_newton(dev, G):
+    """The pipeline the learned form uses: blocks captured from a plain run,
+    normalisation fitted on them, a few epochs of the GPU training kernels,
+    then the trained network in the integrator.  The trained network must
+    lower the held-out loss and let more cells finish their Newton
+    iterations on X r than the untrained network does."""
+    p = W.learned_batch(4096, t_end=1.0)
+    plain = G.Bdf.from_problem(p, device=dev)
+    X, M = G.capture_training_set(plain, N21, 12288, per_capture=512, steps_between=12,
+                                  t_end=p.t_end)
+    plain.close()
+    pc = G.Precond(N21, batch_cap=256)
+    init = W.mlp_init(N21, seed=W.BASE_SEED + 6, out_scale=0.02)
+    pc.set_params(init)
+    hist = G.train_precond(pc, X, M, epochs=12, batch=256, lr=1e-3, seed=7)
+    l0, l1 = hist["val0"], hist["val"][-1]
+    print(f"{X.shape[0]} blocks: held-out loss {l0:.4e} -> {l1:.4e} "
+          f"(train {hist['train'][0]:.4e} -> {hist['train'][-1]:.4e})")
+    assert l1 < 0.5 * l0
+
+    def run(pcx):
+        b = G.Bdf.from_problem(W.learned_batch(4096, t_end=0.1), device=dev,
+                               linsol=G.LS_LEARNED, precond=pcx)
+        assert b.integrate(0.1) == 0.1
+        s = b.stats()
+        b.close()
+        return s
+
+    st = run(pc)
+    pu = G.Precond(N21, batch_cap=256)
+    pu.set_params(init)
+    mean, std = pc.get_normalization()
+    pu.set_normalization(mean, std)
+    su = run(pu)
+    frac = lambda s: s["lp_fallback_cells"] / max(s["lp_cell_solves"], 1)
+    print(f"trained: fallback {frac(st):.3f}, step retries {st['lp_step_fallbacks']}, "
+          f"steps {st['nsteps']}, iters {st['nniters']}; untrained: fallback {frac(su):.3f}, "
+          f"step retries {su['lp_step_fallbacks']}, steps {su['nsteps']}, iters {su['nniters']}")
+    assert frac(st) < frac(su)
+    pc.close()
+    pu.close()

@@ -281,3 +281,39 @@ def torch_uniform_device(shape, seed: int, device, lo=-1.0, hi=1.0,
     t = torch.empty(shape, dtype=dtype or torch.float64, device=device)
     t.uniform_(lo, hi, generator=g)
     return t
+
+
+# --------------------------------------------------------------------------
+# Initial weights of the learned preconditioner's MLP
+# --------------------------------------------------------------------------
+
+def mlp_init(n: int, hid: int = 256, seed: int = BASE_SEED + 6, out_scale: float = 1.0):
+    """He-uniform initial weights (limit sqrt(6 / fan_in)), zero biases, as
+    one FP32 array laid out W1 (hid x (n+1)) | b1 | W2 (hid x hid) | b2 |
+    W3 (n^2 x hid) | b3, row-major.  out_scale multiplies W3 (a small value
+    starts training near X = I)."""
+    rng = rng_for(seed)
+    nin, nout = n + 1, n * n
+
+    def he(fan_in, shape):
+        lim = np.sqrt(6.0 / fan_in)
+        return rng.uniform(-lim, lim, size=shape)
+
+    W1 = he(nin, (hid, nin))
+    W2 = he(hid, (hid, hid))
+    W3 = he(hid, (nout, hid)) * out_scale
+    parts = [W1.ravel(), np.zeros(hid), W2.ravel(), np.zeros(hid), W3.ravel(), np.zeros(nout)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_split(params, n: int, hid: int = 256):
+    """Views (W1, b1, W2, b2, W3, b3) of a flat parameter array."""
+    nin, nout = n + 1, n * n
+    shapes = [(hid, nin), (hid,), (hid, hid), (hid,), (nout, hid), (nout,)]
+    out, o = [], 0
+    for s in shapes:
+        k = int(np.prod(s))
+        out.append(np.asarray(params[o:o + k]).reshape(s))
+        o += k
+    assert o == len(params)
+    return out
