@@ -40,9 +40,9 @@ def time_advance(b, t_end, steps, torch):
     return time.perf_counter() - t0, taken, t
 
 
-def bdf_leg(G, W, torch, prob, dev, warmup, steps, linsol):
+def bdf_leg(G, W, torch, prob, dev, warmup, steps, linsol, precond=None):
     b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_STREAM, attempts_per_sync=16,
-                           linsol=linsol, maxcor=MAXCOR)
+                           linsol=linsol, maxcor=MAXCOR, precond=precond)
     b.advance(prob.t_end, warmup)
     s0 = b.stats()
     dt, taken, t = time_advance(b, prob.t_end, steps, torch)
@@ -60,6 +60,9 @@ def fused_ops(G, W, torch, dev, n=1 << 26, warm=10, reps=50):
     out8 = torch.empty(8, dtype=torch.float64, device=dev)
     out1 = torch.empty(1, dtype=torch.float64, device=dev)
     ops = {
+        # device-to-device copy by the runtime: the streaming bandwidth this
+        # GPU reaches in practice, for context beside the 8 TB/s peak
+        "copy_reference": (lambda: z.copy_(X[0]), 2 * 8 * n),
         "linear_combination_16": (lambda: G.nvec_linear_combination(c, X, z), 17 * 8 * n),
         "dot_prod_multi_1x8": (lambda: G.nvec_dot_prod_multi(X[0], X[1:9], out=out8), 9 * 8 * n),
         "wrms_norm": (lambda: G.nvec_wrms_norm(X[2], w, out=out1), 2 * 8 * n),
@@ -79,6 +82,9 @@ def fused_ops(G, W, torch, dev, n=1 << 26, warm=10, reps=50):
         gbs = nbytes / (ms * 1e-3) / 1e9
         res[name] = {"GB_per_s": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
                      "ms": round(ms, 4), "bytes": nbytes}
+    cp = res["copy_reference"]["GB_per_s"]
+    for name in res:
+        res[name]["frac_of_copy"] = round(res[name]["GB_per_s"] / cp, 4)
     del X, z, w
     torch.cuda.empty_cache()
     return res
@@ -108,6 +114,105 @@ def cpu_baseline(W, prob_full, ncells=1024, budget_s=12.0, max_steps=4000):
             "sample": f"first {ncells} cells of the same 2^20-cell workload, {steps} steps "
                       f"from t=0 in {dt:.1f} s (serial C, FP64, FP64 LU)"}
 
+def wrms(a, b, rtol, atol):
+    import numpy as np
+    w = 1.0 / (rtol * np.abs(b) + atol)
+    return float(np.sqrt(np.mean(((a - b) * w) ** 2)))
+
+
+def accuracy_vs_fp64(G, W, torch, dev, make, t_end, **kw):
+    """End-state difference (WRMS, and its largest per-cell value) between
+    a run with the given linear solver and the FP64-LU run on the same
+    problem to the same t_end."""
+    import numpy as np
+    prob = make()
+    ref = G.Bdf.from_problem(prob, device=dev)
+    ref.integrate(t_end)
+    yr = ref.y().cpu().numpy()
+    sr = ref.stats()
+    ref.close()
+    b = G.Bdf.from_problem(prob, device=dev, **kw)
+    b.integrate(t_end)
+    y = b.y().cpu().numpy()
+    s = b.stats()
+    b.close()
+    n = prob.sizes[0]
+    per = np.sqrt(np.mean((((y - yr) / (prob.rtol * np.abs(yr) + prob.atol)) ** 2).reshape(-1, n), 1))
+    return {"cells": int(prob.ncells), "t_end": t_end, "wrms_diff": round(wrms(y, yr, prob.rtol, prob.atol), 6),
+            "max_cell_wrms_diff": round(float(per.max()), 6),
+            "steps": [int(s["nsteps"]), int(sr["nsteps"])]}
+
+
+def uneven_leg(G, W, torch, dev, warmup, steps):
+    """Blocks of 4..64 species (2^22 unknowns), FP32 LU + refinement,
+    hipGraph-captured attempts, launch mode and small-block mapping chosen
+    by the library's autotuner."""
+    prob = W.uneven_batch(1 << 22)
+    t0 = time.perf_counter()
+    b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_GRAPH, attempts_per_sync=16,
+                           linsol=G.LS_LU32REF, launch=G.LAUNCH_AUTO, maxcor=MAXCOR)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    tu = b.tuning()
+    b.advance(prob.t_end, warmup)
+    s0 = b.stats()
+    dt, taken, t = time_advance(b, prob.t_end, steps, torch)
+    s1 = b.stats()
+    b.close()
+    names = {(0, 0): "per_class_tpc", (0, 1): "per_class_spc16", (1, 0): "one_launch_tpc",
+             (1, 1): "one_launch_spc16"}
+    return {"cells": prob.ncells, "unknowns": prob.N, "value": round(prob.ncells * taken / dt, 1),
+            "unit": "cell-steps/s", "ms_per_step": round(1e3 * dt / max(taken, 1), 4),
+            "chosen": names[(tu["launch"], tu["map_small"])],
+            "candidates_ms_per_step": {names[k]: round(v, 4) for k, v in tu["ms_per_step"].items()},
+            "create_and_tune_s": round(t_tune, 2),
+            "attempts_per_step": round((s1["nattempts"] - s0["nattempts"]) / max(taken, 1), 4),
+            "refine_sweeps": s1["refine_sweeps"] - s0["refine_sweeps"],
+            "refine_fallbacks": s1["refine_fallbacks"] - s0["refine_fallbacks"]}
+
+
+def learned_leg(G, W, torch, dev, cells, warmup, steps, epochs, nblocks):
+    """cfg: 2^20 cells x 21 species (one network and rate vector, cells differ
+    in their state); MLP trained on `nblocks` blocks captured from the plain
+    solver; learned modified Newton vs plain FP64 LU on the same GPU."""
+    n = 21
+    prob = W.learned_batch(cells, n=n)
+    t0 = time.perf_counter()
+    plain = G.Bdf.from_problem(prob, device=dev, attempts_per_sync=16)
+    X, M = G.capture_training_set(plain, n, nblocks, per_capture=8192, steps_between=8,
+                                  t_end=prob.t_end)
+    plain.close()
+    t_cap = time.perf_counter() - t0
+    pc = G.Precond(n, batch_cap=1024)
+    pc.set_params(W.mlp_init(n, out_scale=0.02))
+    t0 = time.perf_counter()
+    hist = G.train_precond(pc, X, M, epochs=epochs, batch=1024, lr=1e-3, seed=20246)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del X, M
+    torch.cuda.empty_cache()
+    out = {"cells": cells, "species": n, "training_blocks": int(nblocks), "epochs": epochs,
+           "capture_s": round(t_cap, 2), "train_s": round(t_train, 2),
+           "val_loss": [round(hist["val0"], 6), round(hist["val"][-1], 6)]}
+    for name, kw in (("plain_lu", {}), ("learned", {"linsol": G.LS_LEARNED, "precond": pc})):
+        b, dt, taken, s0, s1 = bdf_leg(G, W, torch, prob, dev, warmup, steps,
+                                       kw.get("linsol", G.LS_LU64), precond=kw.get("precond"))
+        d = {k: s1[k] - s0[k] for k in ("nsteps", "nattempts", "nniters", "lp_cell_solves",
+                                        "lp_fallback_cells", "lp_step_fallbacks")}
+        out[name] = {"value": round(cells * taken / dt, 1), "unit": "cell-steps/s",
+                     "ms_per_step": round(1e3 * dt / max(taken, 1), 4),
+                     "newton_iters_per_step": round(d["nniters"] / max(taken, 1), 4),
+                     "attempts_per_step": round(d["nattempts"] / max(taken, 1), 4)}
+        if name == "learned":
+            out[name]["cell_fallback_rate"] = round(d["lp_fallback_cells"] / max(d["lp_cell_solves"], 1), 6)
+            out[name]["attempt_lu_retries"] = int(d["lp_step_fallbacks"])
+        b.close()
+    out["accuracy_vs_fp64"] = accuracy_vs_fp64(
+        G, W, torch, dev, lambda: W.learned_batch(1 << 14, n=n), 1e-2,
+        linsol=G.LS_LEARNED, precond=pc)
+    pc.close()
+    return out
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -118,6 +223,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fused", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--learned-epochs", type=int, default=30)
+    ap.add_argument("--learned-blocks", type=int, default=1 << 18)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -182,12 +291,26 @@ def main():
                     "fp64_fallback_rate": round(fb / max(solves, 1), 6),
                     "attempts": s321["nattempts"] - s320["nattempts"]}
         b32.close()
+        out_fp32["accuracy_vs_fp64"] = accuracy_vs_fp64(
+            G, W, torch, dev, lambda: W.random_network_batch(1 << 16, n=10, seed=W.BASE_SEED + 3),
+            1e-3, linsol=G.LS_LU32REF)
         torch.cuda.empty_cache()
 
     fused = None
     if not args.no_fused:
         log("fused N_Vector microbenchmark")
         fused = fused_ops(G, W, torch, dev)
+
+    uneven = None
+    if not args.no_uneven:
+        log("uneven batch leg (autotuned launch, hipGraph, FP32-refined LU)")
+        uneven = uneven_leg(G, W, torch, dev, args.warmup, min(args.steps, 200))
+
+    learned = None
+    if not args.no_learned:
+        log("learned preconditioner leg (capture, training, learned vs plain LU)")
+        learned = learned_leg(G, W, torch, dev, args.cells, args.warmup, min(args.steps, 200),
+                              args.learned_epochs, args.learned_blocks)
 
     cpu = None
     if not args.no_cpu:
@@ -211,6 +334,8 @@ def main():
         "cpu_baseline": cpu,
         "fp32_refined": out_fp32,
         "fused_ops": fused,
+        "uneven": uneven,
+        "learned": learned,
     }
     print(json.dumps(line), flush=True)
 

@@ -146,6 +146,13 @@ int batched_lu_solve_refine(int nb, int n, const double* M, const float* LU32,
 #define BDFGPU_MODE_STREAM 0 /* kernels enqueued on the stream */
 #define BDFGPU_MODE_GRAPH 1  /* one attempt captured in a hipGraph */
 
+#define BDFGPU_LAUNCH_PER_CLASS 0 /* one launch per class of cells and phase */
+#define BDFGPU_LAUNCH_FUSED 1     /* one launch over every class per phase (blocks
+                                     of uneven sizes together; <= 8 classes, not
+                                     with the learned preconditioner) */
+#define BDFGPU_LAUNCH_AUTO 2      /* bdf_create times the candidate launch modes and
+                                     small-block mappings and keeps the fastest */
+
 typedef struct {
   int ntopo;              /* number of network topologies */
   const int* topo_n;      /* host [ntopo]: species per topology (1..64) */
@@ -171,12 +178,14 @@ typedef struct {
   long max_steps;         /* per integrate call; 0 = unlimited */
   int mode;               /* BDFGPU_MODE_* */
   int attempts_per_sync;  /* attempts enqueued between status reads (>= 1) */
-  int block;              /* reserved, set to 0 */
+  int launch;             /* BDFGPU_LAUNCH_* */
   void* precond;          /* precond_handle* for BDFGPU_LS_LEARNED */
   int nonneg;             /* 1: each corrected solution is projected onto y >= 0
                              before the error test (the constraint-mask
                              operation of the N_Vector interface, Section 4.2);
                              initial values must then be >= 0 */
+  int map_small;          /* 0: classes of <= 12 species use one lane per cell
+                             (block in registers); 1: a 16-lane segment per cell */
 } bdf_options;
 
 typedef struct {
@@ -199,6 +208,11 @@ typedef struct bdf_handle bdf_handle;
 int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream,
                bdf_handle** out);
 int bdf_destroy(bdf_handle* h);
+/* Launch configuration in use (launch: BDFGPU_LAUNCH_PER_CLASS or _FUSED;
+ * map_small as in bdf_options) and, after BDFGPU_LAUNCH_AUTO, the timed
+ * ms per step of each candidate: ms_per_step[2 * launch + map_small]
+ * (host array of 4; -1 where not tried or not possible). */
+int bdf_get_tuning(bdf_handle* h, int* launch, int* map_small, double* ms_per_step);
 /* One accepted internal step that does not pass t_end (the last step lands
  * on t_end exactly).  *tret = t after the step (host). */
 int bdf_step(bdf_handle* h, double t_end, double* tret);

@@ -20,11 +20,13 @@ __all__ = [
     "nvec_const", "batched_lu_factor_f64", "batched_lu_solve_f64", "batched_lu_factor_f32",
     "batched_lu_solve_f32", "batched_lu_solve_refine", "Bdf", "BdfGpuError", "lib",
     "LS_LU64", "LS_LU32REF", "LS_LEARNED", "MODE_STREAM", "MODE_GRAPH", "RESULT_DEVICE",
+    "LAUNCH_PER_CLASS", "LAUNCH_FUSED", "LAUNCH_AUTO", "capture_training_set", "train_precond",
     "Precond",
 ]
 
 LS_LU64, LS_LU32REF, LS_LEARNED = 0, 1, 2
 MODE_STREAM, MODE_GRAPH = 0, 1
+LAUNCH_PER_CLASS, LAUNCH_FUSED, LAUNCH_AUTO = 0, 1, 2
 RESULT_DEVICE = 1
 
 
@@ -212,7 +214,7 @@ class Bdf:
     def __init__(self, topologies, cell_topo, rates, y0, t0=0.0, rtol=1e-6, atol=1e-10,
                  qmax=5, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64, refine_max_it=5,
                  max_steps=0, mode=MODE_STREAM, attempts_per_sync=8, nonneg=False,
-                 precond=None):
+                 precond=None, launch=LAUNCH_PER_CLASS, map_small=0):
         torch = _torch()
         _dev(rates, torch.float64)
         _dev(y0, torch.float64)
@@ -229,8 +231,9 @@ class Bdf:
                           ipt(mu_all), len(ct), ipt(ct), _p(rates), _p(y0), float(t0))
         self._precond = precond
         opts = BdfOptions(rtol, atol, qmax, maxcor, h0, hmin, linsol, refine_max_it, max_steps,
-                          mode, attempts_per_sync, 0, precond.h if precond is not None else None,
-                          int(bool(nonneg)))
+                          mode, attempts_per_sync, launch,
+                          precond.h if precond is not None else None, int(bool(nonneg)),
+                          int(map_small))
         h = vp()
         check("bdf_create", lib().bdf_create(C.byref(prob), C.byref(opts), _stream(), C.byref(h)))
         self.h = h
@@ -279,6 +282,15 @@ class Bdf:
 
     def set_profiling(self, on=True):
         check("bdf_set_profiling", lib().bdf_set_profiling(self.h, 1 if on else 0))
+
+    def tuning(self):
+        """{"launch": 0/1, "map_small": 0/1, "ms_per_step": {(launch, map_small): ms}}"""
+        la, ms = C.c_int(0), C.c_int(0)
+        t = (C.c_double * 4)()
+        check("bdf_get_tuning", lib().bdf_get_tuning(self.h, C.byref(la), C.byref(ms),
+                                                     C.cast(t, dp)))
+        return {"launch": la.value, "map_small": ms.value,
+                "ms_per_step": {(k // 2, k % 2): t[k] for k in range(4) if t[k] >= 0}}
 
     def kernel_times(self):
         """{group: (total_ms, launches)}: "newton" (predictor, factorisation

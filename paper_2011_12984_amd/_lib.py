@@ -29,8 +29,8 @@ class BdfOptions(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("qmax", C.c_int),
                 ("maxcor", C.c_int), ("h0", C.c_double), ("hmin", C.c_double),
                 ("linsol", C.c_int), ("refine_max_it", C.c_int), ("max_steps", C.c_long),
-                ("mode", C.c_int), ("attempts_per_sync", C.c_int), ("block", C.c_int),
-                ("precond", vp), ("nonneg", C.c_int)]
+                ("mode", C.c_int), ("attempts_per_sync", C.c_int), ("launch", C.c_int),
+                ("precond", vp), ("nonneg", C.c_int), ("map_small", C.c_int)]
 
 
 class BdfStats(C.Structure):
@@ -68,6 +68,7 @@ SIGNATURES = {
     "batched_lu_solve_refine": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]),
     "bdf_create": (C.c_int, [C.POINTER(BdfProblem), C.POINTER(BdfOptions), vp, C.POINTER(vp)]),
     "bdf_destroy": (C.c_int, [vp]),
+    "bdf_get_tuning": (C.c_int, [vp, ip, ip, dp]),
     "bdf_step": (C.c_int, [vp, C.c_double, dp]),
     "bdf_integrate": (C.c_int, [vp, C.c_double, dp]),
     "bdf_advance": (C.c_int, [vp, C.c_double, C.c_long, dp, C.POINTER(C.c_long)]),

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbdfgpu.so")
-SOURCES = ["nvec.hip", "lu.hip", "bdf.hip", "bdf_tpc.hip", "bdf_spc.hip", "precond.hip"]
+SOURCES = ["nvec.hip", "lu.hip", "bdf.hip", "bdf_tpc.hip", "bdf_spc.hip", "bdf_multi.hip",
+           "precond.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -16,7 +16,10 @@
 #include <map>
 #include <vector>
 
+#include <chrono>
+
 #include "bdf_dev.hpp"
+#include "bdf_multi.hpp"
 #include "common.hpp"
 
 namespace bdfgpu {
@@ -36,8 +39,10 @@ enum { MAP_TPC = 0, MAP_SPC = 1 };
 struct ClassHost {
   int topo, n, R, map, np;      // np: TPC padded size or SPC segment
   long ncells;
-  unsigned int grid;
+  unsigned int grid;            // blocks of the class's own launches
   long blk0;
+  int kind;                     // mapping in the single launch over all classes
+  long mblocks, mblk0;          // blocks and first block in that launch
   long* d_yoff = nullptr;       // user-layout offset of each class cell's y
   long* d_roff = nullptr;       // user-layout offset of each class cell's rates
   ClassDev dev;
@@ -152,8 +157,15 @@ struct bdf_handle {
   Ctrl* hC = nullptr;            // pinned mirror
   double* partials = nullptr;
   double* gpartials = nullptr;
-  unsigned int* counter = nullptr;
-  unsigned int nblocks_total = 0;
+  unsigned int nblocks_total = 0;  // per-class launches
+  unsigned int nblocks_multi = 0;  // single launch over all classes
+  bool fused = false;              // launch mode in use
+  bool fusable = false;
+  size_t multi_lds[4] = {0, 0, 0, 0};
+  // autotuning record: candidate (launch, map_small) -> ms per step (-1 if
+  // not tried) and the choice
+  double tune_ms[4] = {-1, -1, -1, -1};
+  int tune_launch = 0, tune_map_small = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<void*> allocs;
@@ -186,9 +198,7 @@ static BdfDev make_dev(bdf_handle* h, const ClassHost& c) {
   BdfDev D;
   D.C = h->dC;
   D.partials = h->partials;
-  D.gpartials = h->gpartials;
-  D.counter = h->counter;
-  D.nblocks_total = h->nblocks_total;
+  D.nblocks_total = h->fused ? h->nblocks_multi : h->nblocks_total;
   D.rtol = h->o.rtol;
   D.atol = h->o.atol;
   D.nonneg = h->o.nonneg ? 1 : 0;
@@ -197,7 +207,60 @@ static BdfDev make_dev(bdf_handle* h, const ClassHost& c) {
   return D;
 }
 
+static void launch_phase_kernels(bdf_handle* h, int which, hipStream_t s);
+
+// Sums of the phase's block partials and the controller (which 0..3).
+static void launch_control(bdf_handle* h, int which, hipStream_t s) {
+  static const int want[4] = {PH_INIT1, PH_INIT2, PH_PREDICT, PH_ACCEPT};
+  const unsigned int nb = h->fused ? h->nblocks_multi : h->nblocks_total;
+  const unsigned int ng = (nb + kRedGroup - 1) / kRedGroup;
+  const int K = which == 2 ? kRedNewton : kRedVals;
+  if (K == kRedNewton)
+    hipLaunchKernelGGL(k_reduce_groups<kRedNewton>, dim3(ng), dim3(256), 0, s, h->dC, want[which],
+                       h->partials, nb, h->gpartials);
+  else
+    hipLaunchKernelGGL(k_reduce_groups<kRedVals>, dim3(ng), dim3(256), 0, s, h->dC, want[which],
+                       h->partials, nb, h->gpartials);
+  switch (which) {
+    case 0:
+      hipLaunchKernelGGL((k_control<kRedVals, 0>), dim3(1), dim3(256), 0, s, h->dC, want[0],
+                         h->gpartials, ng);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_control<kRedVals, 1>), dim3(1), dim3(256), 0, s, h->dC, want[1],
+                         h->gpartials, ng);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_control<kRedNewton, 2>), dim3(1), dim3(256), 0, s, h->dC, want[2],
+                         h->gpartials, ng);
+      break;
+    default:
+      hipLaunchKernelGGL((k_control<kRedVals, 3>), dim3(1), dim3(256), 0, s, h->dC, want[3],
+                         h->gpartials, ng);
+      break;
+  }
+}
+
 static void launch_phase(bdf_handle* h, int which, hipStream_t s) {
+  launch_phase_kernels(h, which, s);
+  if (which <= 3) launch_control(h, which, s);
+}
+
+static void launch_phase_kernels(bdf_handle* h, int which, hipStream_t s) {
+  if (h->fused && which <= 3) {
+    MultiDev M;
+    memset(&M, 0, sizeof(M));
+    M.ncls = (int)h->cls.size();
+    for (int k = 0; k < M.ncls; ++k) {
+      const ClassHost& c = h->cls[k];
+      M.k[k] = c.dev;
+      M.kind[k] = c.kind;
+      M.bend[k] = c.mblk0 + c.mblocks;
+    }
+    M.base = make_dev(h, h->cls[0]);
+    launch_multi(h->o.linsol, which, M, h->nblocks_multi, h->multi_lds[which], s);
+    return;
+  }
   for (const ClassHost& c : h->cls) {
     const BdfDev D = make_dev(h, c);
     if (c.map == MAP_TPC)
@@ -250,11 +313,13 @@ static void enqueue_attempt(bdf_handle* h, hipStream_t s) {
     prof_mark(h, 1, false, s);
   }
   prof_mark(h, 0, true, s);
-  launch_phase(h, 2, s);
+  launch_phase_kernels(h, 2, s);
   prof_mark(h, 0, false, s);
+  launch_control(h, 2, s);
   prof_mark(h, 2, true, s);
-  launch_phase(h, 3, s);
+  launch_phase_kernels(h, 3, s);
   prof_mark(h, 2, false, s);
+  launch_control(h, 3, s);
 }
 
 static int read_ctrl(bdf_handle* h) {
@@ -322,7 +387,8 @@ static int drive(bdf_handle* h, double tend, long inc, double* tret) {
 
 extern "C" {
 
-int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_handle** out) {
+static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
+                       bdf_handle** out) {
   if (!p || !o || !out) return arg_error("bdf_create: null argument");
   if (p->ncells < 0 || p->ntopo < 1 || !p->topo_n || !p->topo_R || !p->topo_off ||
       !p->nu_all || !p->mu_all || (p->ncells > 0 && (!p->cell_topo || !p->rates || !p->y0)))
@@ -354,7 +420,7 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
   // classes: one per topology that has cells
   std::map<int, std::vector<long>> members;
   for (long c = 0; c < p->ncells; ++c) members[p->cell_topo[c]].push_back(c);
-  long blk = 0;
+  long blk = 0, mblk = 0;
   int st = 0;
   for (auto& kv : members) {
     const int t = kv.first;
@@ -372,7 +438,14 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
     ch.ncells = (long)kv.second.size();
     // thread per cell while the rates and evaluation point fit the LDS of a
     // block, else segment per cell
-    ch.map = (n <= 12 && tpc_lds_bytes(tpc_padded(n), R, o->linsol) <= 65536) ? MAP_TPC : MAP_SPC;
+    ch.map = (!o->map_small && n <= 12 &&
+              tpc_newton_lds(tpc_padded(n), R, o->linsol, kTpcThreads) <= 65536)
+                 ? MAP_TPC
+                 : MAP_SPC;
+    if (ch.map == MAP_SPC && spc_lds_bytes(spc_seg(n), R) > 65536) {
+      bdf_destroy(h);
+      return arg_error("bdf_create: too many reactions for the block's LDS");
+    }
     if (o->linsol == BDFGPU_LS_LEARNED &&
         (ch.map != MAP_SPC || n > 31 ||
          precond_dim(reinterpret_cast<precond_handle*>(o->precond)) != n)) {
@@ -385,6 +458,10 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
     ch.grid = (unsigned int)std::max<long>(1, (ch.ncells + cpb - 1) / cpb);
     ch.blk0 = blk;
     blk += ch.grid;
+    ch.kind = multi_kind(ch.map == MAP_TPC, ch.np);
+    ch.mblocks = multi_blocks(ch.kind, ch.np, ch.ncells);
+    ch.mblk0 = mblk;
+    mblk += ch.mblocks;
     // network tables
     const int np = ch.np;
     std::vector<double> S((size_t)R * np, 0.0);
@@ -503,15 +580,37 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
     h->cls.push_back(ch);
   }
   h->nblocks_total = (unsigned int)blk;
-  const long ngroups = std::max<long>(1, (blk + kRedGroup - 1) / kRedGroup);
-  const size_t cbytes = sizeof(unsigned int) * (size_t)(1 + ngroups);
-  if ((st = dalloc(h, (void**)&h->partials, sizeof(double) * kRedMax * std::max<long>(1, blk))) ||
+  h->nblocks_multi = (unsigned int)mblk;
+  // one launch over all classes: at most kMaxClasses classes, no learned
+  // mode, LDS within one workgroup's limit
+  int dev = 0, lds_max = 0;
+  BDF_HIP_TRY(hipGetDevice(&dev));
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+          hipSuccess ||
+      lds_max < 65536)
+    lds_max = 65536;
+  h->fusable = h->cls.size() >= 1 && h->cls.size() <= (size_t)kMaxClasses &&
+               o->linsol != BDFGPU_LS_LEARNED;
+  for (int w = 0; w < 4 && h->fusable; ++w) {
+    size_t mx = 0;
+    for (const ClassHost& c : h->cls) mx = std::max(mx, multi_lds(c.kind, c.np, c.R, o->linsol, w));
+    h->multi_lds[w] = mx;
+    if (mx > (size_t)lds_max) h->fusable = false;
+  }
+  if (o->launch == BDFGPU_LAUNCH_FUSED && !h->fusable) {
+    bdf_destroy(h);
+    return arg_error("bdf_create: one launch over all classes needs <= 8 classes, no learned "
+                     "preconditioner and per-block LDS within the device limit");
+  }
+  h->fused = o->launch == BDFGPU_LAUNCH_FUSED;
+  const long bmax = std::max(blk, mblk);
+  const long ngroups = std::max<long>(1, (bmax + kRedGroup - 1) / kRedGroup);
+  if ((st = dalloc(h, (void**)&h->partials, sizeof(double) * kRedMax * std::max<long>(1, bmax))) ||
       (st = dalloc(h, (void**)&h->gpartials, sizeof(double) * kRedMax * ngroups)) ||
-      (st = dalloc(h, (void**)&h->counter, cbytes)) || (st = dalloc(h, (void**)&h->dC, sizeof(Ctrl)))) {
+      (st = dalloc(h, (void**)&h->dC, sizeof(Ctrl)))) {
     bdf_destroy(h);
     return st;
   }
-  BDF_HIP_TRY(hipMemset(h->counter, 0, cbytes));
   BDF_HIP_TRY(hipHostMalloc((void**)&h->hC, sizeof(Ctrl), hipHostMallocDefault));
   Ctrl C;
   memset(&C, 0, sizeof(C));
@@ -538,6 +637,76 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
     }
   }
   *out = h;
+  return 0;
+}
+
+// Autotuning by trial: every candidate launch configuration (per-class
+// launches or one launch over all classes; thread per cell or a 16-lane
+// segment per cell for classes of <= 12 species) is built from the same
+// problem, stepped a few times from the initial state and timed; the
+// fastest is then built for the caller.
+static constexpr int kTuneWarm = 4, kTuneSteps = 12;
+
+int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_handle** out) {
+  if (!p || !o || !out) return arg_error("bdf_create: null argument");
+  if (o->launch != BDFGPU_LAUNCH_AUTO) return create_impl(p, o, stream, out);
+  bool small = false;
+  for (long c = 0; c < p->ncells && !small; ++c) {
+    const int t = p->cell_topo ? p->cell_topo[c] : -1;
+    if (t >= 0 && t < p->ntopo && p->topo_n[t] <= 12) small = true;
+  }
+  double ms[4] = {-1.0, -1.0, -1.0, -1.0};
+  double best = 1e300;
+  int bl = 0, bm = 0;
+  for (int launch = 0; launch < 2; ++launch)
+    for (int msm = 0; msm < (small ? 2 : 1); ++msm) {
+      bdf_options o2 = *o;
+      o2.launch = launch;
+      o2.map_small = msm;
+      o2.mode = BDFGPU_MODE_STREAM;
+      bdf_handle* t = nullptr;
+      int st = create_impl(p, &o2, stream, &t);
+      if (st) {
+        if (launch == 1) continue;   // no single launch for this problem
+        return st;
+      }
+      double tr = 0.0;
+      long taken = 0;
+      st = bdf_advance(t, 1e300, kTuneWarm, &tr, &taken);
+      double dt = 1e300;
+      if (st == 0) {
+        (void)hipStreamSynchronize(t->s);
+        const auto t0 = std::chrono::steady_clock::now();
+        st = bdf_advance(t, 1e300, kTuneSteps, &tr, &taken);
+        (void)hipStreamSynchronize(t->s);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (st == 0 && taken > 0)
+          dt = std::chrono::duration<double, std::milli>(t1 - t0).count() / (double)taken;
+      }
+      bdf_destroy(t);
+      ms[2 * launch + msm] = dt < 1e300 ? dt : -1.0;
+      if (dt < best) {
+        best = dt;
+        bl = launch;
+        bm = msm;
+      }
+    }
+  bdf_options o3 = *o;
+  o3.launch = bl;
+  o3.map_small = bm;
+  int st = create_impl(p, &o3, stream, out);
+  if (st) return st;
+  for (int k = 0; k < 4; ++k) (*out)->tune_ms[k] = ms[k];
+  (*out)->tune_launch = bl;
+  (*out)->tune_map_small = bm;
+  return 0;
+}
+
+int bdf_get_tuning(bdf_handle* h, int* launch, int* map_small, double* ms_per_step) {
+  if (!h || !launch || !map_small || !ms_per_step) return arg_error("bdf_get_tuning: bad argument");
+  *launch = h->fused ? 1 : 0;
+  *map_small = h->o.map_small;
+  for (int k = 0; k < 4; ++k) ms_per_step[k] = h->tune_ms[k];
   return 0;
 }
 

@@ -66,8 +66,6 @@ struct ClassDev {
 struct BdfDev {
   Ctrl* C;
   double* partials;      // [nblocks_total][kRedMax]
-  double* gpartials;     // [ngroups][kRedMax]
-  unsigned int* counter; // [0] groups done, [1 + g] blocks of group g done
   unsigned int nblocks_total;
   double rtol, atol;
   int nonneg;
@@ -122,15 +120,17 @@ __device__ __forceinline__ void wave_reduce_scatter(double (&v)[K]) {
   reduce_scatter_step<K, K, 32>(v, threadIdx.x & 63);
 }
 
-// Block reduction of K partial sums, then a two-level deterministic tree
-// across all blocks of the phase (blocks of every class launch): groups of
-// kRedGroup blocks are summed by the last block of the group to finish, the
-// group sums by the last group to finish, whose first thread then runs the
-// controller.  Every sum is taken in a fixed order, so the result does not
-// depend on which block finishes last.
-template <int K, typename F>
-__device__ __forceinline__ void reduce_and_control(const BdfDev& D, double (&v)[K], double* sh,
-                                                   F&& control) {
+// Block reduction of K partial sums, stored with plain stores at
+// partials[gb][0..K) (gb: the block's index among all blocks of every
+// launch of the phase).  The sums over blocks and the controller run in the
+// two small kernels that follow the phase (k_reduce_groups, k_control):
+// publishing a block's partials to the last block of the same launch would
+// need a device-scope release fence per block, which writes back the L2's
+// dirty lines and makes write-heavy kernels many times slower on gfx950;
+// the kernel boundary publishes everything once.
+template <int K>
+__device__ __forceinline__ void block_partials(const BdfDev& D, unsigned int gb, double (&v)[K],
+                                               double* sh) {
   static_assert(K <= kRedMax && (K & (K - 1)) == 0 && K <= 64, "reduction width");
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -139,60 +139,53 @@ __device__ __forceinline__ void reduce_and_control(const BdfDev& D, double (&v)[
   // lanes 0 .. K-1 (stepping by 64 / K) hold distinct indices
   if ((lane & ((64 / K) - 1)) == 0) sh[wid * K + red_index<K>(lane)] = v[0];
   __syncthreads();
-  __shared__ int s_flag;
-  const unsigned int gb = (unsigned int)(D.k.blk0 + blockIdx.x);
-  const unsigned int g = gb / kRedGroup;
-  const unsigned int ng = (D.nblocks_total + kRedGroup - 1) / kRedGroup;
-  const unsigned int gsz =
-      D.nblocks_total - g * kRedGroup < (unsigned int)kRedGroup ? D.nblocks_total - g * kRedGroup
-                                                                 : (unsigned int)kRedGroup;
   if (threadIdx.x < K) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += sh[w * K + threadIdx.x];
     D.partials[(size_t)gb * kRedMax + threadIdx.x] = s;
-    __threadfence();
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int t = atomicAdd(&D.counter[1 + g], 1u);
-    s_flag = (t == gsz - 1);
-  }
-  __syncthreads();
-  if (!s_flag) return;
-  __threadfence();
-  // group level: wave w sums value indices k = w, w + nw, ...; lane b takes
-  // blocks b, b + 64, ... of the group
-  for (int k = wid; k < K; k += nw) {
+}
+
+// First level: group g sums the partials of blocks [g*kRedGroup, ...) in
+// a fixed order (wave w takes value indices w, w+4, ...).
+template <int K>
+__global__ void __launch_bounds__(256) k_reduce_groups(const Ctrl* C, int want,
+                                                        const double* partials,
+                                                        unsigned int nblocks, double* gpartials) {
+  if (C->phase != want) return;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const unsigned int b0 = blockIdx.x * kRedGroup;
+  const unsigned int cnt = nblocks - b0 < (unsigned int)kRedGroup ? nblocks - b0 : kRedGroup;
+  for (int k = wid; k < K; k += 4) {
     double a = 0.0;
-    for (unsigned int b = lane; b < gsz; b += 64)
-      a += __hip_atomic_load(&D.partials[(size_t)(g * kRedGroup + b) * kRedMax + k],
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll 4
+    for (unsigned int b = lane; b < cnt; b += 64) a += partials[(size_t)(b0 + b) * kRedMax + k];
     a = wave_sum(a);
-    if (lane == 0) D.gpartials[(size_t)g * kRedMax + k] = a;
+    if (lane == 0) gpartials[(size_t)blockIdx.x * kRedMax + k] = a;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    D.counter[1 + g] = 0u;
-    __threadfence();
-    const unsigned int t = atomicAdd(&D.counter[0], 1u);
-    s_flag = (t == ng - 1);
-  }
-  __syncthreads();
-  if (!s_flag) return;
-  __threadfence();
-  for (int k = wid; k < K; k += nw) {
+}
+
+// Second level and the controller (one block).  WHICH: 0 starting step part
+// 1, 1 part 2, 2 fused Newton, 3 history update.
+template <int K, int WHICH>
+__global__ void __launch_bounds__(256) k_control(Ctrl* C, int want, const double* gpartials,
+                                                  unsigned int ngroups) {
+  if (C->phase != want) return;
+  __shared__ double tot[K];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = wid; k < K; k += 4) {
     double a = 0.0;
-    for (unsigned int b = lane; b < ng; b += 64)
-      a += __hip_atomic_load(&D.gpartials[(size_t)b * kRedMax + k], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll 4
+    for (unsigned int b = lane; b < ngroups; b += 64) a += gpartials[(size_t)b * kRedMax + k];
     a = wave_sum(a);
-    if (lane == 0) sh[k] = a;
+    if (lane == 0) tot[k] = a;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    D.counter[0] = 0u;
-    control(D.C, static_cast<const double*>(sh));
+    if (WHICH == 0) after_init1(C, tot);
+    else if (WHICH == 1) after_init2(C, tot);
+    else if (WHICH == 2) after_newton_all(C, tot);
+    else after_accept(C, tot);
   }
 }
 
@@ -286,9 +279,9 @@ struct TpcLU {
   }
 };
 
-template <int NP>
+template <int NP, int TB = kTpcThreads>
 struct Tpc {
-  static constexpr int T = kTpcThreads;   // LDS column stride
+  static constexpr int T = TB;            // LDS column stride (threads per block)
   // tiled index of species i of cell c (n species per cell)
   __device__ static __forceinline__ long idx(long c, int i, int n) {
     return (c >> 6) * 64L * n + (long)i * 64 + (c & 63);
@@ -431,10 +424,20 @@ __device__ __forceinline__ void tpc_load_vec(const double* v, long c, int n, dou
   }
 }
 
-// Dynamic LDS of the TPC kernels: NP columns for the evaluation point, NP
-// for the refinement iterate (LS 1), R for the rates, each kTpcThreads wide.
-__host__ __device__ inline size_t tpc_lds_bytes(int np, int R, int ls) {
-  return sizeof(double) * (size_t)kTpcThreads * (size_t)(np * (ls == 1 ? 2 : 1) + R);
+// Dynamic LDS of the TPC kernels (tb threads per block): the fused Newton
+// kernel keeps NP columns for the evaluation point, NP for the refinement
+// iterate (LS 1) and R for the rates, then the reduction scratch; the
+// starting-step kernels NP columns and the scratch; the history update only
+// the scratch.
+__host__ __device__ inline size_t tpc_newton_lds(int np, int R, int ls, int tb) {
+  return sizeof(double) *
+         ((size_t)tb * (size_t)(np * (ls == 1 ? 2 : 1) + R) + (size_t)(tb / 64) * kRedNewton);
+}
+__host__ __device__ inline size_t tpc_init_lds(int np, int tb) {
+  return sizeof(double) * ((size_t)tb * np + (size_t)(tb / 64) * kRedVals);
+}
+__host__ __device__ inline size_t tpc_accept_lds(int tb) {
+  return sizeof(double) * (size_t)(tb / 64) * kRedVals;
 }
 
 // Fused predictor + Newton iterations, thread per cell.  LS 0: FP64 LU kept
@@ -443,20 +446,20 @@ __host__ __device__ inline size_t tpc_lds_bytes(int np, int R, int ls) {
 // refinement fails switches to FP64 LU, re-assembled and factored at every
 // later iteration of the attempt (rare: the FP64 factors would double the
 // register footprint if they were kept beside the FP32 ones).
-template <int NP, int LS>
-__global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
-  extern __shared__ double lds[];
-  __shared__ double s_red[(kTpcThreads / 64) * kRedNewton];
+template <int NP, int LS, int TB>
+__device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, double* lds) {
+  using TP = Tpc<NP, TB>;
   Ctrl* C = D.C;
-  if (C->phase != PH_PREDICT) return;
   const ClassDev& K = D.k;
   const NetDev& nd = K.net;
   const int n = K.n, R = K.R;
-  const long c = (long)blockIdx.x * kTpcThreads + threadIdx.x;
+  const long c = blk * TB + threadIdx.x;
   const bool act = c < K.ncells;
-  double* ycol = lds + threadIdx.x;                                  // evaluation point
-  double* xcol = lds + NP * kTpcThreads + threadIdx.x;               // LS 1 iterate
-  double* kcol = lds + (LS == 1 ? 2 : 1) * NP * kTpcThreads + threadIdx.x;
+  constexpr int F = LS == 1 ? 2 : 1;
+  double* ycol = lds + threadIdx.x;                 // evaluation point
+  double* xcol = lds + NP * TB + threadIdx.x;       // LS 1 iterate
+  double* kcol = lds + F * NP * TB + threadIdx.x;   // rates
+  double* s_red = lds + (size_t)(F * NP + R) * TB;
   double red[kRedNewton];
 #pragma unroll
   for (int k = 0; k < kRedNewton; ++k) red[k] = 0.0;
@@ -464,10 +467,10 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
     for (int k0 = 0; k0 < R; k0 += 8) {   // 8 loads in flight per chunk
       double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = K.rates[Tpc<NP>::kidx(c, k0 + u < R ? k0 + u : R - 1, R)];
+      for (int u = 0; u < 8; ++u) v[u] = K.rates[TP::kidx(c, k0 + u < R ? k0 + u : R - 1, R)];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (k0 + u < R) kcol[(k0 + u) * kTpcThreads] = v[u];
+        if (k0 + u < R) kcol[(k0 + u) * TB] = v[u];
     }
     const double gamma = C->gamma;
     const double l0 = C->l[0];
@@ -481,13 +484,13 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
       for (int i = 0; i < NP; ++i) w[i] = i < n ? 1.0 / (D.rtol * fabs(zs[0][i]) + D.atol) : 0.0;
       if (C->restart) {
         double f0[NP];
-        Tpc<NP>::store_col(ycol, zs[0]);
-        Tpc<NP>::rhs(nd, kcol, kTpcThreads, ycol, f0);
+        TP::store_col(ycol, zs[0]);
+        TP::rhs(nd, kcol, TB, ycol, f0);
         const double h = C->h;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
           zs[1][i] = h * f0[i];
-          if (i < n) K.z[1][Tpc<NP>::idx(c, i, n)] = zs[1][i];
+          if (i < n) K.z[1][TP::idx(c, i, n)] = zs[1][i];
         }
       }
       // Pascal triangle: z(0)[j] = sum_{k >= j} C(k, j) z[k]
@@ -504,12 +507,12 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
         cv[i] = zs[0][i] - l0 * zs[1][i];
       }
     }
-    Tpc<NP>::store_col(ycol, zp0);
+    TP::store_col(ycol, zp0);
     using TF = typename std::conditional<LS == 1, float, double>::type;
     TF A[NP][NP];
     int piv[NP];
     double rowsum[NP];
-    Tpc<NP>::template build_M<TF>(nd, kcol, kTpcThreads, ycol, gamma, A, rowsum);
+    TP::template build_M<TF>(nd, kcol, TB, ycol, gamma, A, rowsum);
     double mnorm = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) mnorm = fmax(mnorm, rowsum[i]);
@@ -522,9 +525,9 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
     for (int i = 0; i < NP; ++i) y[i] = zp0[i];
     double* yev = LS == 1 ? xcol : ycol;   // LS 1 keeps z(0)[0] in ycol for J
     for (int m = 0; m < maxcor; ++m) {
-      Tpc<NP>::store_col(yev, y);
+      TP::store_col(yev, y);
       double r[NP];
-      Tpc<NP>::rhs(nd, kcol, kTpcThreads, yev, r);
+      TP::rhs(nd, kcol, TB, yev, r);
 #pragma unroll
       for (int i = 0; i < NP; ++i) r[i] = fma(gamma, r[i], cv[i] - y[i]);
       double del[NP];
@@ -545,9 +548,9 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
           const double eps64 = 2.220446049250313e-16;
           double dprv = 0.0;
           for (int it = 0; it <= K.refine_max_it; ++it) {
-            Tpc<NP>::store_col(xcol, del);
+            TP::store_col(xcol, del);
             double mx[NP];
-            Tpc<NP>::mvp(nd, kcol, kTpcThreads, ycol, xcol, gamma, del, mx);
+            TP::mvp(nd, kcol, TB, ycol, xcol, gamma, del, mx);
             double rn = 0.0, xn = 0.0;
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
@@ -581,7 +584,7 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
         }
         if (!ok) {
           double M[NP][NP], rs[NP];
-          Tpc<NP>::template build_M<double>(nd, kcol, kTpcThreads, ycol, gamma, M, rs);
+          TP::template build_M<double>(nd, kcol, TB, ycol, gamma, M, rs);
           int pv[NP];
           if (TpcLU<NP, double>::factor(M, pv)) sing = true;
 #pragma unroll
@@ -594,7 +597,7 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
       for (int i = 0; i < NP; ++i) {
         if (i < n) {
           y[i] += del[i];
-          K.ys[m][Tpc<NP>::idx(c, i, n)] = y[i];
+          K.ys[m][TP::idx(c, i, n)] = y[i];
           const bool ng = D.nonneg && y[i] < 0.0;
           neg += ng ? 1.0 : 0.0;
           const double a = del[i] * w[i], b = ((ng ? 0.0 : y[i]) - zp0[i]) * w[i];
@@ -616,8 +619,14 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
     }
     red[7] = sing ? 1.0 : 0.0;
   }
-  reduce_and_control<kRedNewton>(D, red, s_red,
-                                 [](Ctrl* Cc, const double* s) { after_newton_all(Cc, s); });
+  block_partials<kRedNewton>(D, (unsigned int)(D.k.blk0 + blk), red, s_red);
+}
+
+template <int NP, int LS>
+__global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
+  extern __shared__ double lds[];
+  if (D.C->phase != PH_PREDICT) return;
+  tpc_newton_body<NP, LS, kTpcThreads>(D, blockIdx.x, lds);
 }
 
 // History update after an accepted attempt: z_new[j] = z(0)[j] + l_j acor
@@ -625,14 +634,13 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
 // order selection of this step needs it and written only when the next
 // step's does (the step after one with qwait == 2 is the only one that
 // reads it).
-template <int NP>
-__global__ void __launch_bounds__(kTpcThreads) k_tpc_accept(BdfDev D) {
-  __shared__ double s_red[(kTpcThreads / 64) * kRedVals];
+template <int NP, int TB>
+__device__ __forceinline__ void tpc_accept_body(const BdfDev& D, long blk, double* lds) {
+  double* s_red = lds;
   Ctrl* C = D.C;
-  if (C->phase != PH_ACCEPT) return;
   const ClassDev& K = D.k;
   const int n = K.n;
-  const long c = (long)blockIdx.x * kTpcThreads + threadIdx.x;
+  const long c = blk * TB + threadIdx.x;
   double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (c < K.ncells) {
     const int q = C->q;
@@ -686,34 +694,39 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_accept(BdfDev D) {
     red[0] = szq;
     red[1] = sdd;
   }
-  reduce_and_control<kRedVals>(D, red, s_red,
-                               [](Ctrl* Cc, const double* s) { after_accept(Cc, s); });
+  block_partials<kRedVals>(D, (unsigned int)(D.k.blk0 + blk), red, s_red);
+}
+
+template <int NP>
+__global__ void __launch_bounds__(kTpcThreads) k_tpc_accept(BdfDev D) {
+  extern __shared__ double lds[];
+  if (D.C->phase != PH_ACCEPT) return;
+  tpc_accept_body<NP, kTpcThreads>(D, blockIdx.x, lds);
 }
 
 // Starting step, part 1: f(y0) into z[1] (scaled later by h), norms of y0, f0.
-template <int NP>
-__global__ void __launch_bounds__(kTpcThreads) k_tpc_init1(BdfDev D) {
-  __shared__ double s_y[NP * kTpcThreads];
-  __shared__ double s_red[(kTpcThreads / 64) * kRedVals];
+template <int NP, int TB>
+__device__ __forceinline__ void tpc_init1_body(const BdfDev& D, long blk, double* lds) {
+  double* s_y = lds;
+  double* s_red = lds + NP * TB;
   Ctrl* C = D.C;
-  if (C->phase != PH_INIT1) return;
   const ClassDev& K = D.k;
   const int n = K.n;
-  const long c = (long)blockIdx.x * kTpcThreads + threadIdx.x;
+  const long c = blk * TB + threadIdx.x;
   double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (c < K.ncells) {
-    const double* kap = K.rates + Tpc<NP>::kidx(c, 0, K.R);
+    const double* kap = K.rates + Tpc<NP, TB>::kidx(c, 0, K.R);
     double* ycol = s_y + threadIdx.x;
     double y[NP], f[NP];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) y[i] = i < n ? K.z[0][Tpc<NP>::idx(c, i, n)] : 0.0;
-    Tpc<NP>::store_col(ycol, y);
-    Tpc<NP>::rhs(K.net, kap, 64, ycol, f);
+    for (int i = 0; i < NP; ++i) y[i] = i < n ? K.z[0][Tpc<NP, TB>::idx(c, i, n)] : 0.0;
+    Tpc<NP, TB>::store_col(ycol, y);
+    Tpc<NP, TB>::rhs(K.net, kap, 64, ycol, f);
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
       if (i < n) {
-        K.z[1][Tpc<NP>::idx(c, i, n)] = f[i];
+        K.z[1][Tpc<NP, TB>::idx(c, i, n)] = f[i];
         const double w = 1.0 / (D.rtol * fabs(y[i]) + D.atol);
         s0 = fma(y[i] * w, y[i] * w, s0);
         s1 = fma(f[i] * w, f[i] * w, s1);
@@ -722,36 +735,41 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_init1(BdfDev D) {
     red[0] = s0;
     red[1] = s1;
   }
-  reduce_and_control<kRedVals>(D, red, s_red,
-                               [](Ctrl* Cc, const double* s) { after_init1(Cc, s); });
+  block_partials<kRedVals>(D, (unsigned int)(D.k.blk0 + blk), red, s_red);
 }
 
 template <int NP>
-__global__ void __launch_bounds__(kTpcThreads) k_tpc_init2(BdfDev D) {
-  __shared__ double s_y[NP * kTpcThreads];
-  __shared__ double s_red[(kTpcThreads / 64) * kRedVals];
+__global__ void __launch_bounds__(kTpcThreads) k_tpc_init1(BdfDev D) {
+  extern __shared__ double lds[];
+  if (D.C->phase != PH_INIT1) return;
+  tpc_init1_body<NP, kTpcThreads>(D, blockIdx.x, lds);
+}
+
+template <int NP, int TB>
+__device__ __forceinline__ void tpc_init2_body(const BdfDev& D, long blk, double* lds) {
+  double* s_y = lds;
+  double* s_red = lds + NP * TB;
   Ctrl* C = D.C;
-  if (C->phase != PH_INIT2) return;
   const ClassDev& K = D.k;
   const int n = K.n;
-  const long c = (long)blockIdx.x * kTpcThreads + threadIdx.x;
+  const long c = blk * TB + threadIdx.x;
   double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (c < K.ncells) {
-    const double* kap = K.rates + Tpc<NP>::kidx(c, 0, K.R);
+    const double* kap = K.rates + Tpc<NP, TB>::kidx(c, 0, K.R);
     double* ycol = s_y + threadIdx.x;
     const double h0 = C->hnw_h0;
     double y1[NP], f0[NP], f1[NP], w[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
       const bool in = i < n;
-      const long id = Tpc<NP>::idx(c, i, n);
+      const long id = Tpc<NP, TB>::idx(c, i, n);
       const double y0 = in ? K.z[0][id] : 0.0;
       f0[i] = in ? K.z[1][id] : 0.0;
       w[i] = in ? 1.0 / (D.rtol * fabs(y0) + D.atol) : 0.0;
       y1[i] = y0 + h0 * f0[i];
     }
-    Tpc<NP>::store_col(ycol, y1);
-    Tpc<NP>::rhs(K.net, kap, 64, ycol, f1);
+    Tpc<NP, TB>::store_col(ycol, y1);
+    Tpc<NP, TB>::rhs(K.net, kap, 64, ycol, f1);
     double s0 = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
@@ -760,8 +778,14 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_init2(BdfDev D) {
     }
     red[0] = s0;
   }
-  reduce_and_control<kRedVals>(D, red, s_red,
-                               [](Ctrl* Cc, const double* s) { after_init2(Cc, s); });
+  block_partials<kRedVals>(D, (unsigned int)(D.k.blk0 + blk), red, s_red);
+}
+
+template <int NP>
+__global__ void __launch_bounds__(kTpcThreads) k_tpc_init2(BdfDev D) {
+  extern __shared__ double lds[];
+  if (D.C->phase != PH_INIT2) return;
+  tpc_init2_body<NP, kTpcThreads>(D, blockIdx.x, lds);
 }
 
 // ===========================================================================
@@ -771,33 +795,37 @@ template <int SEG>
 struct Spc {
   static constexpr int CPB = kCellThreads / SEG;   // cells per block
 
-  // lane i: f_i at the segment's state in ys (LDS, SEG values); rates of
-  // the cell in kap (LDS or global, contiguous)
-  __device__ static __forceinline__ void rhs_row(const NetDev& nd, const double* kap, const double* ys, int i,
-                                 double& f) {
+  // lane i: f_i at the segment's state in ys (LDS, SEG values); kap: the
+  // cell's rates, St: the stoichiometry staged in LDS as St[k * SEG + i]
+  // (FP32 holds the small integer entries exactly)
+  __device__ static __forceinline__ void rhs_row(const NetDev& nd, const double* kap,
+                                                 const float* St, const double* ys, int i,
+                                                 double& f) {
     f = 0.0;
-#pragma unroll 2
+#pragma unroll 4
     for (int k = 0; k < nd.R; ++k) {
       const int a = nd.ra[k], b = nd.rb[k];
       double r = kap[k];
       if (a >= 0) r *= ys[a];
       if (b >= 0) r *= ys[b];
-      f = fma(nd.S[(long)k * nd.np + i], r, f);
+      f = fma((double)St[k * SEG + i], r, f);
     }
   }
 
-  __device__ static __forceinline__ void jac_row(const NetDev& nd, const double* kap, const double* ys, int i,
-                                 double (&J)[SEG]) {
+  __device__ static __forceinline__ void jac_row(const NetDev& nd, const double* kap,
+                                                 const float* St, const double* ys, int i,
+                                                 double (&J)[SEG]) {
 #pragma unroll
     for (int a = 0; a < SEG; ++a) {
       double acc = 0.0;
       if (a < nd.n) {
         const int e0 = nd.jst[a], e1 = nd.jst[a + 1];
+#pragma unroll 2
         for (int e = e0; e < e1; ++e) {
           const int k = nd.jk[e], p = nd.jp[e];
           double g = kap[k] * nd.jm[e];
           if (p >= 0) g *= ys[p];
-          acc = fma(nd.S[(long)k * nd.np + i], g, acc);
+          acc = fma((double)St[k * SEG + i], g, acc);
         }
       }
       J[a] = acc;
@@ -814,9 +842,13 @@ struct SpcShared {
   double red[(kCellThreads / 64) * kRedNewton];
 };
 
-// Dynamic LDS of the SPC kernels: the rates of the block's cells.
+// Dynamic LDS of the SPC kernels: the shared scratch, then the rates of the
+// block's cells (CPB x R, FP64), then the stoichiometry (R x SEG; its entries
+// are small integers, exact in FP32).
 __host__ __device__ inline size_t spc_lds_bytes(int seg, int R) {
-  return sizeof(double) * (size_t)(kCellThreads / seg) * (size_t)(R > 0 ? R : 1);
+  const size_t r = (size_t)(R > 0 ? R : 1);
+  return sizeof(SpcShared) + sizeof(double) * (size_t)(kCellThreads / seg) * r +
+         sizeof(float) * r * seg;
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -825,12 +857,23 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Copy the rates of the block's cells (cell-major, contiguous) into LDS.
+// Carve the dynamic LDS and stage the rates of the block's cells
+// (cell-major, contiguous) and the class stoichiometry.
 template <int SEG>
-__device__ __forceinline__ void spc_load_rates(const ClassDev& K, double* lk) {
-  const long c0 = (long)blockIdx.x * Spc<SEG>::CPB;
-  long cnt = (K.ncells - c0 < Spc<SEG>::CPB ? K.ncells - c0 : Spc<SEG>::CPB) * (long)K.R;
-  for (long t = threadIdx.x; t < cnt; t += blockDim.x) lk[t] = K.rates[c0 * K.R + t];
+__device__ __forceinline__ void spc_stage(const ClassDev& K, long blk, double* lds,
+                                          SpcShared*& sh, double*& lk, float*& St) {
+  sh = reinterpret_cast<SpcShared*>(lds);
+  lk = lds + sizeof(SpcShared) / sizeof(double);
+  const int R = K.R;
+  St = reinterpret_cast<float*>(lk + (size_t)Spc<SEG>::CPB * (R > 0 ? R : 1));
+  const long c0 = blk * Spc<SEG>::CPB;
+  const long cnt = (K.ncells - c0 < Spc<SEG>::CPB ? K.ncells - c0 : Spc<SEG>::CPB) * (long)R;
+  for (long t = threadIdx.x; t < cnt; t += blockDim.x) lk[t] = K.rates[c0 * R + t];
+  const int np = K.net.np;
+  for (int t = threadIdx.x; t < R * SEG; t += blockDim.x) {
+    const int k = t / SEG, i = t - k * SEG;
+    St[t] = i < np ? (float)K.net.S[(long)k * np + i] : 0.0f;
+  }
   __syncthreads();
 }
 
@@ -867,8 +910,8 @@ __device__ __forceinline__ void spc_load_hist(const ClassDev& K, const Ctrl* C, 
 template <int SEG>
 __device__ __forceinline__ void spc_predict_row(const BdfDev& D, const Ctrl* C, SpcShared& sh,
                                                 int sb, int i, bool act, bool row, long id,
-                                                const double* kap, double& zp0, double& cv,
-                                                double& w) {
+                                                const double* kap, const float* St,
+                                                double& zp0, double& cv, double& w) {
   const ClassDev& K = D.k;
   const int q = C->q;
   double zs[kQmaxAll + 1];
@@ -879,7 +922,7 @@ __device__ __forceinline__ void spc_predict_row(const BdfDev& D, const Ctrl* C, 
     sh.ys[threadIdx.x] = zs[0];
     wave_sync_lds();
     double f0 = 0.0;
-    if (act) Spc<SEG>::rhs_row(K.net, kap, sh.ys + sb, i, f0);
+    if (act) Spc<SEG>::rhs_row(K.net, kap, St, sh.ys + sb, i, f0);
     zs[1] = row ? C->h * f0 : 0.0;
     if (row) K.z[1][id] = zs[1];
   }
@@ -895,30 +938,37 @@ __device__ __forceinline__ void spc_predict_row(const BdfDev& D, const Ctrl* C, 
 // Learned mode: predictor only, plus the MLP inputs [z(0)[0], log gamma]
 // of every cell.
 template <int SEG>
-__global__ void __launch_bounds__(kCellThreads) k_spc_predict(BdfDev D) {
-  extern __shared__ double lk[];
-  __shared__ SpcShared sh;
+__device__ __forceinline__ void spc_predict_body(const BdfDev& D, long blk, double* lds) {
   Ctrl* C = D.C;
-  if (C->phase != PH_PREDICT) return;
   const ClassDev& K = D.k;
   const int n = K.n;
   const int i = threadIdx.x & (SEG - 1);
   const int sb = threadIdx.x & ~(SEG - 1);
   const int cb = threadIdx.x / SEG;
-  const long c = (long)blockIdx.x * Spc<SEG>::CPB + cb;
+  const long c = blk * Spc<SEG>::CPB + cb;
   const bool act = c < K.ncells;
   const bool row = act && i < n;
   const long id = c * n + i;
-  spc_load_rates<SEG>(K, lk);
+  SpcShared* shp;
+  double* lk;
+  float* St;
+  spc_stage<SEG>(K, blk, lds, shp, lk, St);
   const double* kap = lk + cb * K.R;
   double zp0, cv, w;
-  spc_predict_row<SEG>(D, C, sh, sb, i, act, row, id, kap, zp0, cv, w);
+  spc_predict_row<SEG>(D, C, *shp, sb, i, act, row, id, kap, St, zp0, cv, w);
   if (row) {
     K.zp0[id] = zp0;
     K.cv[id] = cv;
     K.xin[c * (n + 1) + i] = zp0;
   }
   if (act && i == 0) K.xin[c * (n + 1) + n] = log(C->gamma);
+}
+
+template <int SEG>
+__global__ void __launch_bounds__(kCellThreads) k_spc_predict(BdfDev D) {
+  extern __shared__ double lds[];
+  if (D.C->phase != PH_PREDICT) return;
+  spc_predict_body<SEG>(D, blockIdx.x, lds);
 }
 
 // Fused Newton iterations, segment per cell.  LS 0: FP64 LU factored once.
@@ -930,11 +980,8 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_predict(BdfDev D) {
 // is not finite, or from the second iteration on when its correction norm
 // does not fall below 0.9 times the previous one.
 template <int SEG, int LS>
-__global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
-  extern __shared__ double lk[];
-  __shared__ SpcShared sh;
+__device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, double* lds) {
   Ctrl* C = D.C;
-  if (C->phase != PH_PREDICT) return;
   const ClassDev& K = D.k;
   const NetDev& nd = K.net;
   const int n = K.n;
@@ -943,17 +990,21 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
   const int seg_base = lane & ~(SEG - 1);
   const int sb = threadIdx.x & ~(SEG - 1);
   const int cb = threadIdx.x / SEG;
-  const long c = (long)blockIdx.x * Spc<SEG>::CPB + cb;
+  const long c = blk * Spc<SEG>::CPB + cb;
   const bool act = c < K.ncells;           // uniform over the segment
   const bool row = act && i < n;
   const long id = c * n + i;
-  spc_load_rates<SEG>(K, lk);
+  SpcShared* shp;
+  double* lk;
+  float* St;
+  spc_stage<SEG>(K, blk, lds, shp, lk, St);
+  SpcShared& sh = *shp;
   const double* kap = lk + cb * K.R;
   const double gamma = C->gamma;
   const int maxcor = C->maxcor;
   double zp0 = 0.0, cv = 0.0, w = 0.0;
   if (LS != 2) {
-    spc_predict_row<SEG>(D, C, sh, sb, i, act, row, id, kap, zp0, cv, w);
+    spc_predict_row<SEG>(D, C, sh, sb, i, act, row, id, kap, St, zp0, cv, w);
   } else if (row) {
     zp0 = K.zp0[id];
     cv = K.cv[id];
@@ -966,7 +1017,7 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
     sh.ys[threadIdx.x] = zp0;
     wave_sync_lds();
     if (act)
-      Spc<SEG>::jac_row(nd, kap, sh.ys + sb, i, Mrow);
+      Spc<SEG>::jac_row(nd, kap, St, sh.ys + sb, i, Mrow);
     else
 #pragma unroll
       for (int j = 0; j < SEG; ++j) Mrow[j] = 0.0;
@@ -1031,7 +1082,7 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
     sh.ys[threadIdx.x] = y;
     wave_sync_lds();
     double f = 0.0;
-    if (act) Spc<SEG>::rhs_row(nd, kap, sh.ys + sb, i, f);
+    if (act) Spc<SEG>::rhs_row(nd, kap, St, sh.ys + sb, i, f);
     const double r = row ? fma(gamma, f, cv - y) : 0.0;
     double del = 0.0;
     int sweeps = 0, fb = 0;
@@ -1076,10 +1127,10 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
     } else {
       if (mode == 2) {
         // correction = X r with row i of the cell's approximate inverse
-        double s = 0.0;
+        double sx = 0.0;
 #pragma unroll
-        for (int j = 0; j < SEG; ++j) s = fma((double)Xrow[j], __shfl(r, seg_base + j, 64), s);
-        del = row ? s : 0.0;
+        for (int j = 0; j < SEG; ++j) sx = fma((double)Xrow[j], __shfl(r, seg_base + j, 64), sx);
+        del = row ? sx : 0.0;
         const double bad = seg_max<SEG>(row && !(fabs(del) <= 1.79e308) ? 1.0 : 0.0);
         lp_solves = act ? 1.0 : 0.0;
         if (bad > 0.0) mode = 3;
@@ -1126,19 +1177,28 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
   // a singular FP64 factorisation fails the attempt (LS 1: only the FP64
   // fallback can be singular; the FP32 factor then falls back)
   if (act && i == 0) red[7] = info ? 1.0 : 0.0;
-  reduce_and_control<kRedNewton>(D, red, sh.red,
-                                 [](Ctrl* Cc, const double* s) { after_newton_all(Cc, s); });
+  block_partials<kRedNewton>(D, (unsigned int)(K.blk0 + blk), red, sh.red);
+}
+
+template <int SEG, int LS>
+__global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
+  extern __shared__ double lds[];
+  if (D.C->phase != PH_PREDICT) return;
+  spc_newton_body<SEG, LS>(D, blockIdx.x, lds);
+}
+
+__host__ __device__ inline size_t spc_accept_lds() {
+  return sizeof(double) * (size_t)(kCellThreads / 64) * kRedVals;
 }
 
 template <int SEG>
-__global__ void __launch_bounds__(kCellThreads) k_spc_accept(BdfDev D) {
-  __shared__ double s_red[(kCellThreads / 64) * kRedVals];
+__device__ __forceinline__ void spc_accept_body(const BdfDev& D, long blk, double* lds) {
+  double* s_red = lds;
   Ctrl* C = D.C;
-  if (C->phase != PH_ACCEPT) return;
   const ClassDev& K = D.k;
   const int n = K.n;
   const int i = threadIdx.x & (SEG - 1);
-  const long c = (long)blockIdx.x * Spc<SEG>::CPB + threadIdx.x / SEG;
+  const long c = blk * Spc<SEG>::CPB + threadIdx.x / SEG;
   double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (c < K.ncells && i < n) {
     const long id = c * n + i;
@@ -1178,69 +1238,69 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_accept(BdfDev D) {
     const double a = znq * w;
     red[0] = a * a;
   }
-  reduce_and_control<kRedVals>(D, red, s_red,
-                               [](Ctrl* Cc, const double* s) { after_accept(Cc, s); });
+  block_partials<kRedVals>(D, (unsigned int)(K.blk0 + blk), red, s_red);
+}
+
+template <int SEG>
+__global__ void __launch_bounds__(kCellThreads) k_spc_accept(BdfDev D) {
+  extern __shared__ double lds[];
+  if (D.C->phase != PH_ACCEPT) return;
+  spc_accept_body<SEG>(D, blockIdx.x, lds);
+}
+
+// Starting step, part 1 (f(y0) into z[1], norms of y0 and f0) and part 2
+// (norm of f(y0 + h0 f0) - f0).
+template <int SEG, int PART>
+__device__ __forceinline__ void spc_init_body(const BdfDev& D, long blk, double* lds) {
+  Ctrl* C = D.C;
+  const ClassDev& K = D.k;
+  const int n = K.n;
+  const int i = threadIdx.x & (SEG - 1);
+  const int sb = threadIdx.x & ~(SEG - 1);
+  const int cb = threadIdx.x / SEG;
+  const long c = blk * Spc<SEG>::CPB + cb;
+  const bool act = c < K.ncells;
+  const bool row = act && i < n;
+  const long id = c * n + i;
+  SpcShared* shp;
+  double* lk;
+  float* St;
+  spc_stage<SEG>(K, blk, lds, shp, lk, St);
+  SpcShared& sh = *shp;
+  const double* kap = lk + cb * K.R;
+  const double y0 = row ? K.z[0][id] : 0.0;
+  const double f0 = (PART == 2 && row) ? K.z[1][id] : 0.0;
+  sh.ys[threadIdx.x] = PART == 1 ? y0 : y0 + C->hnw_h0 * f0;
+  __syncthreads();
+  double f = 0.0;
+  if (act) Spc<SEG>::rhs_row(K.net, kap, St, sh.ys + sb, i, f);
+  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (row) {
+    const double w = 1.0 / (D.rtol * fabs(y0) + D.atol);
+    if (PART == 1) {
+      K.z[1][id] = f;
+      red[0] = (y0 * w) * (y0 * w);
+      red[1] = (f * w) * (f * w);
+    } else {
+      const double d = (f - f0) * w;
+      red[0] = d * d;
+    }
+  }
+  block_partials<kRedVals>(D, (unsigned int)(K.blk0 + blk), red, sh.red);
 }
 
 template <int SEG>
 __global__ void __launch_bounds__(kCellThreads) k_spc_init1(BdfDev D) {
-  __shared__ double s_y[kCellThreads];
-  __shared__ double s_red[(kCellThreads / 64) * kRedVals];
-  Ctrl* C = D.C;
-  if (C->phase != PH_INIT1) return;
-  const ClassDev& K = D.k;
-  const int n = K.n;
-  const int i = threadIdx.x & (SEG - 1);
-  const int sb = threadIdx.x & ~(SEG - 1);
-  const long c = (long)blockIdx.x * Spc<SEG>::CPB + threadIdx.x / SEG;
-  const bool act = c < K.ncells;
-  const bool row = act && i < n;
-  const long id = c * n + i;
-  const double y = row ? K.z[0][id] : 0.0;
-  s_y[threadIdx.x] = y;
-  __syncthreads();
-  double f = 0.0;
-  if (act) Spc<SEG>::rhs_row(K.net, K.rates + c * (long)K.R, s_y + sb, i, f);
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (row) {
-    K.z[1][id] = f;
-    const double w = 1.0 / (D.rtol * fabs(y) + D.atol);
-    red[0] = (y * w) * (y * w);
-    red[1] = (f * w) * (f * w);
-  }
-  reduce_and_control<kRedVals>(D, red, s_red,
-                               [](Ctrl* Cc, const double* s) { after_init1(Cc, s); });
+  extern __shared__ double lds[];
+  if (D.C->phase != PH_INIT1) return;
+  spc_init_body<SEG, 1>(D, blockIdx.x, lds);
 }
 
 template <int SEG>
 __global__ void __launch_bounds__(kCellThreads) k_spc_init2(BdfDev D) {
-  __shared__ double s_y[kCellThreads];
-  __shared__ double s_red[(kCellThreads / 64) * kRedVals];
-  Ctrl* C = D.C;
-  if (C->phase != PH_INIT2) return;
-  const ClassDev& K = D.k;
-  const int n = K.n;
-  const int i = threadIdx.x & (SEG - 1);
-  const int sb = threadIdx.x & ~(SEG - 1);
-  const long c = (long)blockIdx.x * Spc<SEG>::CPB + threadIdx.x / SEG;
-  const bool act = c < K.ncells;
-  const bool row = act && i < n;
-  const long id = c * n + i;
-  const double h0 = C->hnw_h0;
-  const double y0 = row ? K.z[0][id] : 0.0;
-  const double f0 = row ? K.z[1][id] : 0.0;
-  s_y[threadIdx.x] = y0 + h0 * f0;
-  __syncthreads();
-  double f1 = 0.0;
-  if (act) Spc<SEG>::rhs_row(K.net, K.rates + c * (long)K.R, s_y + sb, i, f1);
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (row) {
-    const double w = 1.0 / (D.rtol * fabs(y0) + D.atol);
-    const double d = (f1 - f0) * w;
-    red[0] = d * d;
-  }
-  reduce_and_control<kRedVals>(D, red, s_red,
-                               [](Ctrl* Cc, const double* s) { after_init2(Cc, s); });
+  extern __shared__ double lds[];
+  if (D.C->phase != PH_INIT2) return;
+  spc_init_body<SEG, 2>(D, blockIdx.x, lds);
 }
 
 }  // namespace bdfgpu

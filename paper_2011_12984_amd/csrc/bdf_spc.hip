@@ -9,8 +9,8 @@ static void spc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStr
   const dim3 g(grid), b(kCellThreads);
   const size_t lds = spc_lds_bytes(SEG, D.k.R);
   switch (which) {
-    case 0: hipLaunchKernelGGL(k_spc_init1<SEG>, g, b, 0, s, D); break;
-    case 1: hipLaunchKernelGGL(k_spc_init2<SEG>, g, b, 0, s, D); break;
+    case 0: hipLaunchKernelGGL(k_spc_init1<SEG>, g, b, lds, s, D); break;
+    case 1: hipLaunchKernelGGL(k_spc_init2<SEG>, g, b, lds, s, D); break;
     case 2:
       if (ls == 1)
         hipLaunchKernelGGL((k_spc_newton<SEG, 1>), g, b, lds, s, D);
@@ -20,7 +20,7 @@ static void spc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStr
         hipLaunchKernelGGL((k_spc_newton<SEG, 0>), g, b, lds, s, D);
       break;
     case 4: hipLaunchKernelGGL(k_spc_predict<SEG>, g, b, lds, s, D); break;
-    default: hipLaunchKernelGGL(k_spc_accept<SEG>, g, b, 0, s, D); break;
+    default: hipLaunchKernelGGL(k_spc_accept<SEG>, g, b, spc_accept_lds(), s, D); break;
   }
 }
 

@@ -7,18 +7,19 @@ namespace bdfgpu {
 template <int NP>
 static void tpc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s) {
   const dim3 g(grid), b(kTpcThreads);
+  const size_t ilds = tpc_init_lds(NP, kTpcThreads);
   switch (which) {
-    case 0: hipLaunchKernelGGL(k_tpc_init1<NP>, g, b, 0, s, D); break;
-    case 1: hipLaunchKernelGGL(k_tpc_init2<NP>, g, b, 0, s, D); break;
+    case 0: hipLaunchKernelGGL(k_tpc_init1<NP>, g, b, ilds, s, D); break;
+    case 1: hipLaunchKernelGGL(k_tpc_init2<NP>, g, b, ilds, s, D); break;
     case 2: {
-      const size_t lds = tpc_lds_bytes(NP, D.k.R, ls);
+      const size_t lds = tpc_newton_lds(NP, D.k.R, ls, kTpcThreads);
       if (ls == 1)
         hipLaunchKernelGGL((k_tpc_newton<NP, 1>), g, b, lds, s, D);
       else
         hipLaunchKernelGGL((k_tpc_newton<NP, 0>), g, b, lds, s, D);
       break;
     }
-    default: hipLaunchKernelGGL(k_tpc_accept<NP>, g, b, 0, s, D); break;
+    default: hipLaunchKernelGGL(k_tpc_accept<NP>, g, b, tpc_accept_lds(kTpcThreads), s, D); break;
   }
 }
 

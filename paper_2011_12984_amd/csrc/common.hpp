@@ -67,47 +67,6 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* sh) {
   __syncthreads();
 }
 
-// Cross-block completion: every block stores its K partials, then takes a
-// ticket; the block holding the last ticket sums all partials in block
-// order (deterministic) and resets the counter for the next launch.
-// Returns true (block-uniform) in the last block; `out` then holds the sums
-// in thread 0.
-template <int K>
-__device__ __forceinline__ bool last_block_reduce(const double (&part)[K],
-                                                  double* partials,
-                                                  unsigned int* counter,
-                                                  unsigned int nblocks,
-                                                  double (&out)[K], double* sh) {
-  __shared__ int am_last;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) partials[(size_t)blockIdx.x * K + k] = part[k];
-    __threadfence();
-    unsigned int t = atomicAdd(counter, 1u);
-    am_last = (t == nblocks - 1);
-  }
-  __syncthreads();
-  if (!am_last) return false;
-  __threadfence();
-  double acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  // each thread sums a strided subset in block order, then a fixed tree
-  for (unsigned int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      acc[k] += __hip_atomic_load(&partials[(size_t)b * K + k], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-  }
-  block_sum<K>(acc, sh);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = acc[k];
-    *counter = 0u;
-  }
-  return true;
-}
-
 inline unsigned int ceil_div(long a, long b) { return (unsigned int)((a + b - 1) / b); }
 
 }  // namespace bdfgpu

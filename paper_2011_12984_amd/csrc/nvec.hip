@@ -1,6 +1,6 @@
-// N_Vector operations for gfx950: streaming kernels and two-level
-// (wavefront shuffle, then LDS, then one last-block pass over per-block
-// partials) reductions.
+// N_Vector operations for gfx950: streaming kernels and two-pass reductions
+// (wavefront shuffle and LDS to one partial per block, then one finishing
+// block that sums the partials in block order).
 //
 // The paper groups vector operations into streaming operations and
 // reductions (Section 2); reductions are completed on the GPU and the scalar
@@ -38,16 +38,15 @@ int arg_error(const char* msg) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-device reduction scratch: per-block partials, a ticket counter, a
-// device result slot and a pinned host result buffer.
+// Per-device reduction scratch: per-block partials, a device result slot
+// and a pinned host result buffer.
 // ---------------------------------------------------------------------------
-constexpr int kRedBlocks = 2048;   // upper bound on blocks of a reduction
+constexpr int kRedBlocks = 8192;   // upper bound on blocks of a reduction
 constexpr int kRedK = 8;           // values per block
 constexpr int kMaxDev = 64;
 
 struct RedScratch {
   double* partials = nullptr;
-  unsigned int* counter = nullptr;
   double* dres = nullptr;
   double* hres = nullptr;
 };
@@ -62,8 +61,6 @@ static int get_red_scratch(RedScratch** out) {
   RedScratch& r = g_red[dev];
   if (!r.partials) {
     BDF_HIP_TRY(hipMalloc(&r.partials, sizeof(double) * kRedBlocks * kRedK));
-    BDF_HIP_TRY(hipMalloc(&r.counter, 256));
-    BDF_HIP_TRY(hipMemset(r.counter, 0, 256));
     BDF_HIP_TRY(hipMalloc(&r.dres, sizeof(double) * kRedK));
     BDF_HIP_TRY(hipHostMalloc(&r.hres, sizeof(double) * kRedK, hipHostMallocDefault));
     BDF_HIP_TRY(hipDeviceSynchronize());
@@ -85,13 +82,14 @@ static inline bool aligned16(const void* p) {
   return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }
 
-// Launch shape for memory-bound kernels: enough 256-thread blocks to keep
-// every CU busy with a grid-stride loop, never more than the data needs.
+// Launch shape for memory-bound kernels: one 16-byte unit per thread.  A
+// grid as large as the data beat every grid-stride shape (1K..32K blocks)
+// in a sweep on MI355X: the hardware dispatcher keeps more requests in
+// flight than a long-running loop does.
 constexpr int kStreamThreads = 256;
 static unsigned int stream_blocks(long nunits) {
   long want = (nunits + kStreamThreads - 1) / kStreamThreads;
-  long cap = 256L * 16L;   // 256 CUs, 16 blocks each
-  return (unsigned int)std::max(1L, std::min(want, cap));
+  return (unsigned int)std::max(1L, std::min(want, 1L << 24));
 }
 
 // ---------------------------------------------------------------------------
@@ -194,23 +192,31 @@ __global__ void k_const(long n, double c, double* z) {
 }
 
 // ---------------------------------------------------------------------------
-// Reductions.  Per-thread FP64 partials -> wave shuffle -> LDS -> per-block
-// partial in HBM -> the last block to finish sums the block partials in
-// block order.  One launch, no float atomics, deterministic for a given
-// launch shape.
+// Reductions.  Per-thread FP64 partials -> wave shuffle -> LDS -> one
+// partial per block (plain stores) -> k_finish: one block sums the partials
+// in block order.  No float atomics and no per-block device-scope fence
+// (each would write back the L2); deterministic for a given launch shape.
 // ---------------------------------------------------------------------------
 struct DotArgs {
   const double* Y[8];
 };
 
+template <int K>
+__device__ __forceinline__ void store_block_partials(double (&acc)[K], double* sh,
+                                                     double* partials) {
+  block_sum<K>(acc, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) partials[(size_t)blockIdx.x * kRedK + k] = acc[k];
+}
+
 template <int NV>
 __global__ void __launch_bounds__(256) k_dot_prod_multi(long n, const double* __restrict__ x,
-                                                        DotArgs A, double* partials,
-                                                        unsigned int* counter, double* out) {
-  __shared__ double sh[4 * 8];
-  double acc[8];
+                                                        DotArgs A, double* partials) {
+  __shared__ double sh[4 * NV];
+  double acc[NV];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
   const long stride = (long)gridDim.x * blockDim.x;
   const long n2 = n >> 1;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
@@ -226,18 +232,11 @@ __global__ void __launch_bounds__(256) k_dot_prod_multi(long n, const double* __
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = fma(x[n - 1], A.Y[j][n - 1], acc[j]);
   }
-  block_sum<8>(acc, sh);
-  double tot[8];
-  if (last_block_reduce<8>(acc, partials, counter, gridDim.x, tot, sh)) {
-    if (threadIdx.x == 0)
-#pragma unroll
-      for (int j = 0; j < NV; ++j) out[j] = tot[j];
-  }
+  store_block_partials<NV>(acc, sh, partials);
 }
 
 __global__ void __launch_bounds__(256) k_wrms(long n, const double* __restrict__ x,
-                                              const double* __restrict__ w, double* partials,
-                                              unsigned int* counter, double* out) {
+                                              const double* __restrict__ w, double* partials) {
   __shared__ double sh[4];
   double acc[1] = {0.0};
   const long stride = (long)gridDim.x * blockDim.x;
@@ -253,40 +252,28 @@ __global__ void __launch_bounds__(256) k_wrms(long n, const double* __restrict__
     double a = x[n - 1] * w[n - 1];
     acc[0] = fma(a, a, acc[0]);
   }
-  block_sum<1>(acc, sh);
-  double tot[1];
-  if (last_block_reduce<1>(acc, partials, counter, gridDim.x, tot, sh)) {
-    if (threadIdx.x == 0) out[0] = sqrt(tot[0] / (double)n);
-  }
+  store_block_partials<1>(acc, sh, partials);
 }
 
 // scalar-load variants for vectors that are not 16-byte aligned
 template <int NV>
 __global__ void __launch_bounds__(256) k_dot_prod_multi_u(long n, const double* x, DotArgs A,
-                                                          double* partials,
-                                                          unsigned int* counter, double* out) {
-  __shared__ double sh[4 * 8];
-  double acc[8];
+                                                          double* partials) {
+  __shared__ double sh[4 * NV];
+  double acc[NV];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
   const long stride = (long)gridDim.x * blockDim.x;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double xv = x[i];
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = fma(xv, A.Y[j][i], acc[j]);
   }
-  block_sum<8>(acc, sh);
-  double tot[8];
-  if (last_block_reduce<8>(acc, partials, counter, gridDim.x, tot, sh)) {
-    if (threadIdx.x == 0)
-#pragma unroll
-      for (int j = 0; j < NV; ++j) out[j] = tot[j];
-  }
+  store_block_partials<NV>(acc, sh, partials);
 }
 
 __global__ void __launch_bounds__(256) k_wrms_u(long n, const double* x, const double* w,
-                                                double* partials, unsigned int* counter,
-                                                double* out) {
+                                                double* partials) {
   __shared__ double sh[4];
   double acc[1] = {0.0};
   const long stride = (long)gridDim.x * blockDim.x;
@@ -294,15 +281,10 @@ __global__ void __launch_bounds__(256) k_wrms_u(long n, const double* x, const d
     double a = x[i] * w[i];
     acc[0] = fma(a, a, acc[0]);
   }
-  block_sum<1>(acc, sh);
-  double tot[1];
-  if (last_block_reduce<1>(acc, partials, counter, gridDim.x, tot, sh)) {
-    if (threadIdx.x == 0) out[0] = sqrt(tot[0] / (double)n);
-  }
+  store_block_partials<1>(acc, sh, partials);
 }
 
-__global__ void __launch_bounds__(256) k_maxnorm(long n, const double* x, double* partials,
-                                                 unsigned int* counter, double* out) {
+__global__ void __launch_bounds__(256) k_maxnorm(long n, const double* x, double* partials) {
   __shared__ double sh[4];
   double m = 0.0;
   const long stride = (long)gridDim.x * blockDim.x;
@@ -312,43 +294,34 @@ __global__ void __launch_bounds__(256) k_maxnorm(long n, const double* x, double
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) sh[wid] = m;
   __syncthreads();
-  double acc[1] = {0.0};
   if (threadIdx.x == 0) {
     double v = 0.0;
     for (int k = 0; k < (int)(blockDim.x >> 6); ++k) v = fmax(v, sh[k]);
-    acc[0] = v;
+    partials[(size_t)blockIdx.x * kRedK] = v;
   }
-  __syncthreads();
-  // the max of non-negative values is order independent; reuse the
-  // block-partial protocol with a max in the final pass
-  __shared__ int am_last;
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = acc[0];
-    __threadfence();
-    unsigned int t = atomicAdd(counter, 1u);
-    am_last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!am_last) return;
-  __threadfence();
-  double v = 0.0;
-  for (unsigned int b = threadIdx.x; b < gridDim.x; b += blockDim.x)
-    v = fmax(v, __hip_atomic_load(&partials[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  v = wave_max(v);
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = 0.0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r = fmax(r, sh[k]);
-    out[0] = r;
-    *counter = 0u;
+}
+
+// One block: value k of the result is the sum (op 0), the square root of
+// the mean (op 1, WRMS: divided by n) or the maximum (op 2) over the nb
+// block partials, in block order.  Wave w takes k = w, w + 16, ...
+__global__ void __launch_bounds__(1024) k_finish(int nv, unsigned int nb, int op, long n,
+                                                 const double* partials, double* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = wid; k < nv; k += 16) {
+    double a = 0.0;
+#pragma unroll 4
+    for (unsigned int b = lane; b < nb; b += 64) {
+      const double v = partials[(size_t)b * kRedK + k];
+      a = op == 2 ? fmax(a, v) : a + v;
+    }
+    a = op == 2 ? wave_max(a) : wave_sum(a);
+    if (lane == 0) out[k] = op == 1 ? sqrt(a / (double)n) : a;
   }
 }
 
 static unsigned int red_blocks(long nunits) {
   long want = (nunits + kStreamThreads - 1) / kStreamThreads;
-  long cap = 256L * 4L;   // one wave of blocks on every CU keeps HBM busy
-  return (unsigned int)std::max(1L, std::min(want, std::min(cap, (long)kRedBlocks)));
+  return (unsigned int)std::max(1L, std::min(want, (long)kRedBlocks));
 }
 
 // Finish a reduction: copy nv results to the host and wait, or leave them in
@@ -493,17 +466,19 @@ int nvec_dot_prod_multi(int nv, const double* x, const double* const* Y, double*
   dim3 g(red_blocks(al ? (n >> 1) + 1 : n)), b(256);
   if (al) {
     switch (nv) {
-#define DP_CASE(K) case K: hipLaunchKernelGGL(k_dot_prod_multi<K>, g, b, 0, s, n, x, A, r->partials, r->counter, r->dres); break;
+#define DP_CASE(K) case K: hipLaunchKernelGGL(k_dot_prod_multi<K>, g, b, 0, s, n, x, A, r->partials); break;
       DP_CASE(1) DP_CASE(2) DP_CASE(3) DP_CASE(4) DP_CASE(5) DP_CASE(6) DP_CASE(7) DP_CASE(8)
 #undef DP_CASE
     }
   } else {
     switch (nv) {
-#define DP_CASE(K) case K: hipLaunchKernelGGL(k_dot_prod_multi_u<K>, g, b, 0, s, n, x, A, r->partials, r->counter, r->dres); break;
+#define DP_CASE(K) case K: hipLaunchKernelGGL(k_dot_prod_multi_u<K>, g, b, 0, s, n, x, A, r->partials); break;
       DP_CASE(1) DP_CASE(2) DP_CASE(3) DP_CASE(4) DP_CASE(5) DP_CASE(6) DP_CASE(7) DP_CASE(8)
 #undef DP_CASE
     }
   }
+  BDF_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, nv, g.x, 0, n, r->partials, r->dres);
   BDF_HIP_TRY(hipGetLastError());
   return finish_reduction(r, nv, d, flags, s);
 }
@@ -526,9 +501,11 @@ int nvec_wrms_norm(long n, const double* x, const double* w, double* out, int fl
   bool al = aligned16(x) && aligned16(w);
   dim3 g(red_blocks(al ? (n >> 1) + 1 : n)), b(256);
   if (al)
-    hipLaunchKernelGGL(k_wrms, g, b, 0, s, n, x, w, r->partials, r->counter, r->dres);
+    hipLaunchKernelGGL(k_wrms, g, b, 0, s, n, x, w, r->partials);
   else
-    hipLaunchKernelGGL(k_wrms_u, g, b, 0, s, n, x, w, r->partials, r->counter, r->dres);
+    hipLaunchKernelGGL(k_wrms_u, g, b, 0, s, n, x, w, r->partials);
+  BDF_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, 1, g.x, 1, n, r->partials, r->dres);
   BDF_HIP_TRY(hipGetLastError());
   return finish_reduction(r, 1, out, flags, s);
 }
@@ -547,8 +524,9 @@ int nvec_max_norm(long n, const double* x, double* out, int flags, void* stream)
   RedScratch* r = nullptr;
   int st = get_red_scratch(&r);
   if (st) return st;
-  hipLaunchKernelGGL(k_maxnorm, dim3(red_blocks(n)), dim3(256), 0, s, n, x, r->partials,
-                     r->counter, r->dres);
+  const unsigned int gm = red_blocks(n);
+  hipLaunchKernelGGL(k_maxnorm, dim3(gm), dim3(256), 0, s, n, x, r->partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, 1, gm, 2, n, r->partials, r->dres);
   BDF_HIP_TRY(hipGetLastError());
   return finish_reduction(r, 1, out, flags, s);
 }

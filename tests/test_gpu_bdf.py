@@ -132,19 +132,58 @@ def test_trajectory_network10_fp32_refined(orc, dev, G):
     assert gb.stats()["refine_sweeps"] > 0
 
 
-def test_trajectory_uneven(orc, dev, G):
-    compare_trajectory(orc, dev, G, W.uneven_batch(1 << 12, seed=9))
+@pytest.mark.parametrize("launch,map_small,linsol", [
+    (0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 1), (1, 0, 1)])
+def test_trajectory_uneven(orc, dev, G, launch, map_small, linsol):
+    """Blocks of 4..64 species: per-class launches or one launch over every
+    class, thread per cell or 16-lane segments for the small classes, FP64
+    or FP32-refined LU."""
+    compare_trajectory(orc, dev, G, W.uneven_batch(1 << 12, seed=9), launch=launch,
+                       map_small=map_small, linsol=linsol)
+
+
+def test_fused_launch_graph_bitwise_equal_to_stream(dev, G):
+    p = W.uneven_batch(1 << 13, seed=19)
+    a = gpu_bdf(G, p, dev, mode=G.MODE_STREAM, launch=G.LAUNCH_FUSED, linsol=1)
+    b = gpu_bdf(G, p, dev, mode=G.MODE_GRAPH, launch=G.LAUNCH_FUSED, linsol=1,
+                attempts_per_sync=5)
+    for t in (1e-3, 1e-1, p.t_end):
+        a.integrate(t)
+        b.integrate(t)
+    assert a.stats()["nsteps"] == b.stats()["nsteps"]
+    assert torch.equal(a.y(), b.y())
+
+
+def test_autotune_keeps_the_fastest_candidate(orc, dev, G):
+    p = W.uneven_batch(1 << 12, seed=29)
+    b = gpu_bdf(G, p, dev, launch=G.LAUNCH_AUTO, linsol=1, mode=G.MODE_GRAPH)
+    tu = b.tuning()
+    print(tu)
+    ms = tu["ms_per_step"]
+    assert len(ms) >= 2          # both small-block mappings, and the launch modes possible
+    best = min(ms, key=ms.get)
+    assert (tu["launch"], tu["map_small"]) == best
+    assert b.integrate(p.t_end) == p.t_end
+    ob = orc.Bdf(p, linsol=1)
+    assert ob.integrate(p.t_end) == 0
+    ref = orc.Bdf(p, rtol=p.rtol * 1e-3, atol=p.atol * 1e-3)
+    assert ref.integrate(p.t_end) == 0
+    yr = ref.y()
+    eg = wrms_diff(b.y().cpu().numpy(), yr, p.rtol, p.atol)
+    eo = wrms_diff(ob.y(), yr, p.rtol, p.atol)
+    assert eg <= max(3.0 * eo, 1.0)
 
 
 def test_trajectory_n21(orc, dev, G):
     compare_trajectory(orc, dev, G, W.learned_batch(64, seed=12))
 
 
-def test_small_odd_sizes(orc, dev, G):
+@pytest.mark.parametrize("map_small", [0, 1])
+def test_small_odd_sizes(orc, dev, G, map_small):
     # n = 1 (padded thread-per-cell), n = 5, and a ragged last tile
     for n, cells in ((1, 65), (5, 130), (2, 3)):
         p = W.linear_chain_batch(cells, n, seed=n)
-        compare_trajectory(orc, dev, G, p)
+        compare_trajectory(orc, dev, G, p, map_small=map_small)
 
 
 def test_graph_mode_bitwise_equal_to_stream(dev, G):
