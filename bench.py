@@ -225,6 +225,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run nvec_scale (a plain copy, 512 MiB in and out) 5 times: "
+                         "the reference for HBM byte counters")
     ap.add_argument("--learned-epochs", type=int, default=30)
     ap.add_argument("--learned-blocks", type=int, default=1 << 18)
     args = ap.parse_args()
@@ -240,6 +243,15 @@ def main():
 
     dev = torch.device("cuda:0")
     G.lib()
+    if args.copy_calibration:
+        x = W.torch_uniform_device(1 << 26, seed=5, device=dev)
+        z = torch.empty_like(x)
+        for _ in range(5):
+            G.nvec_scale(1.0, x, z)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"kernel": "k_scale", "bytes_read": 8 << 26,
+                                               "bytes_written": 8 << 26, "launches": 5}}))
+        return
     log("generating workload")
     prob = W.random_network_batch(args.cells, n=10, seed=W.BASE_SEED + 3)
     n, R = 10, 20

@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbdfgpu.so")
+# BDFGPU_LIB selects another build of the same library (for A/B timing)
+LIB_PATH = os.environ.get("BDFGPU_LIB") or os.path.join(HERE, "libbdfgpu.so")
 
 _lib = None
 

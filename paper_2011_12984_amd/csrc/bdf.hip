@@ -422,6 +422,13 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   for (long c = 0; c < p->ncells; ++c) members[p->cell_topo[c]].push_back(c);
   long blk = 0, mblk = 0;
   int st = 0;
+  // per-workgroup LDS limit (160 KiB on gfx950; 64 KiB assumed if unknown)
+  int dev = 0, lds_max = 0;
+  BDF_HIP_TRY(hipGetDevice(&dev));
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+          hipSuccess ||
+      lds_max < 65536)
+    lds_max = 65536;
   for (auto& kv : members) {
     const int t = kv.first;
     const int n = p->topo_n[t], R = p->topo_R[t];
@@ -439,10 +446,10 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     // thread per cell while the rates and evaluation point fit the LDS of a
     // block, else segment per cell
     ch.map = (!o->map_small && n <= 12 &&
-              tpc_newton_lds(tpc_padded(n), R, o->linsol, kTpcThreads) <= 65536)
+              tpc_newton_lds(tpc_padded(n), R, o->linsol, kTpcThreads) <= (size_t)lds_max)
                  ? MAP_TPC
                  : MAP_SPC;
-    if (ch.map == MAP_SPC && spc_lds_bytes(spc_seg(n), R) > 65536) {
+    if (ch.map == MAP_SPC && spc_lds_bytes(spc_seg(n), R) > (size_t)lds_max) {
       bdf_destroy(h);
       return arg_error("bdf_create: too many reactions for the block's LDS");
     }
@@ -583,12 +590,6 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   h->nblocks_multi = (unsigned int)mblk;
   // one launch over all classes: at most kMaxClasses classes, no learned
   // mode, LDS within one workgroup's limit
-  int dev = 0, lds_max = 0;
-  BDF_HIP_TRY(hipGetDevice(&dev));
-  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
-          hipSuccess ||
-      lds_max < 65536)
-    lds_max = 65536;
   h->fusable = h->cls.size() >= 1 && h->cls.size() <= (size_t)kMaxClasses &&
                o->linsol != BDFGPU_LS_LEARNED;
   for (int w = 0; w < 4 && h->fusable; ++w) {

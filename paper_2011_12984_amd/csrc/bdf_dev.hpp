@@ -146,40 +146,53 @@ __device__ __forceinline__ void block_partials(const BdfDev& D, unsigned int gb,
   }
 }
 
-// First level: group g sums the partials of blocks [g*kRedGroup, ...) in
-// a fixed order (wave w takes value indices w, w+4, ...).
+// First level: group g sums the partials of blocks [g*kRedGroup, ...) in a
+// fixed order: thread b loads block b's K values (all loads in flight at
+// once), then a fixed reduction tree over the block.
 template <int K>
-__global__ void __launch_bounds__(256) k_reduce_groups(const Ctrl* C, int want,
-                                                        const double* partials,
-                                                        unsigned int nblocks, double* gpartials) {
+__global__ void __launch_bounds__(kRedGroup) k_reduce_groups(const Ctrl* C, int want,
+                                                              const double* partials,
+                                                              unsigned int nblocks,
+                                                              double* gpartials) {
   if (C->phase != want) return;
+  __shared__ double sh[(kRedGroup / 64) * K];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const unsigned int b0 = blockIdx.x * kRedGroup;
-  const unsigned int cnt = nblocks - b0 < (unsigned int)kRedGroup ? nblocks - b0 : kRedGroup;
-  for (int k = wid; k < K; k += 4) {
-    double a = 0.0;
-#pragma unroll 4
-    for (unsigned int b = lane; b < cnt; b += 64) a += partials[(size_t)(b0 + b) * kRedMax + k];
-    a = wave_sum(a);
-    if (lane == 0) gpartials[(size_t)blockIdx.x * kRedMax + k] = a;
+  const unsigned int b = blockIdx.x * kRedGroup + threadIdx.x;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = b < nblocks ? partials[(size_t)b * kRedMax + k] : 0.0;
+  wave_reduce_scatter<K>(v);
+  if ((lane & ((64 / K) - 1)) == 0) sh[wid * K + red_index<K>(lane)] = v[0];
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kRedGroup / 64; ++w) t += sh[w * K + threadIdx.x];
+    gpartials[(size_t)blockIdx.x * kRedMax + threadIdx.x] = t;
   }
 }
 
-// Second level and the controller (one block).  WHICH: 0 starting step part
-// 1, 1 part 2, 2 fused Newton, 3 history update.
+// Second level and the controller (one block of 256 threads; thread t adds
+// groups t, t + 256, ... in order, then the fixed tree).  WHICH: 0 starting
+// step part 1, 1 part 2, 2 fused Newton, 3 history update.
 template <int K, int WHICH>
 __global__ void __launch_bounds__(256) k_control(Ctrl* C, int want, const double* gpartials,
                                                   unsigned int ngroups) {
   if (C->phase != want) return;
+  __shared__ double sh[4 * K];
   __shared__ double tot[K];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int k = wid; k < K; k += 4) {
-    double a = 0.0;
-#pragma unroll 4
-    for (unsigned int b = lane; b < ngroups; b += 64) a += gpartials[(size_t)b * kRedMax + k];
-    a = wave_sum(a);
-    if (lane == 0) tot[k] = a;
-  }
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (unsigned int b = threadIdx.x; b < ngroups; b += 256)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += gpartials[(size_t)b * kRedMax + k];
+  wave_reduce_scatter<K>(v);
+  if ((lane & ((64 / K) - 1)) == 0) sh[wid * K + red_index<K>(lane)] = v[0];
+  __syncthreads();
+  if (threadIdx.x < K) tot[threadIdx.x] = sh[threadIdx.x] + sh[K + threadIdx.x] +
+                                          sh[2 * K + threadIdx.x] + sh[3 * K + threadIdx.x];
   __syncthreads();
   if (threadIdx.x == 0) {
     if (WHICH == 0) after_init1(C, tot);
@@ -326,10 +339,12 @@ struct Tpc {
     }
   }
 
-  // M = I - gamma J, assembled one column at a time.
-  template <typename TT>
-  __device__ static __forceinline__ void build_M(const NetDev& nd, const double* kcol, int ks, const double* ycol,
-                                 double gamma, TT (&M)[NP][NP], double (&rowsum)[NP]) {
+  // M = I - gamma J, assembled one column at a time; ROWSUM: also the row
+  // sums of |M| (for the FP32 refinement's stopping test).
+  template <typename TT, bool ROWSUM>
+  __device__ static __forceinline__ void build_M(const NetDev& nd, const double* kcol, int ks,
+                                                 const double* ycol, double gamma,
+                                                 TT (&M)[NP][NP], double (&rowsum)[NP]) {
 #pragma unroll
     for (int i = 0; i < NP; ++i) rowsum[i] = 0.0;
 #pragma unroll
@@ -340,7 +355,7 @@ struct Tpc {
       for (int i = 0; i < NP; ++i) {
         const double m = (i == a ? 1.0 : 0.0) - gamma * col[i];
         M[i][a] = (TT)m;
-        rowsum[i] += fabs(m);
+        if (ROWSUM) rowsum[i] += fabs(m);
       }
     }
   }
@@ -512,7 +527,7 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
     TF A[NP][NP];
     int piv[NP];
     double rowsum[NP];
-    TP::template build_M<TF>(nd, kcol, TB, ycol, gamma, A, rowsum);
+    TP::template build_M<TF, LS == 1>(nd, kcol, TB, ycol, gamma, A, rowsum);
     double mnorm = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) mnorm = fmax(mnorm, rowsum[i]);
@@ -584,7 +599,7 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
         }
         if (!ok) {
           double M[NP][NP], rs[NP];
-          TP::template build_M<double>(nd, kcol, TB, ycol, gamma, M, rs);
+          TP::template build_M<double, false>(nd, kcol, TB, ycol, gamma, M, rs);
           int pv[NP];
           if (TpcLU<NP, double>::factor(M, pv)) sing = true;
 #pragma unroll

@@ -4,6 +4,15 @@
 
 namespace bdfgpu {
 
+// Dynamic LDS above 64 KiB is requested explicitly (once per kernel).
+template <typename KF>
+static void raise_lds(KF* kern, size_t lds, size_t& raised) {
+  if (lds > raised &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
+    raised = lds;
+}
+
 template <int SEG>
 static void spc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s) {
   const dim3 g(grid), b(kCellThreads);
@@ -12,12 +21,19 @@ static void spc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStr
     case 0: hipLaunchKernelGGL(k_spc_init1<SEG>, g, b, lds, s, D); break;
     case 1: hipLaunchKernelGGL(k_spc_init2<SEG>, g, b, lds, s, D); break;
     case 2:
-      if (ls == 1)
+      if (ls == 1) {
+        static size_t r1 = 65536;
+        raise_lds(&k_spc_newton<SEG, 1>, lds, r1);
         hipLaunchKernelGGL((k_spc_newton<SEG, 1>), g, b, lds, s, D);
-      else if (ls == 2)
+      } else if (ls == 2) {
+        static size_t r2 = 65536;
+        raise_lds(&k_spc_newton<SEG, 2>, lds, r2);
         hipLaunchKernelGGL((k_spc_newton<SEG, 2>), g, b, lds, s, D);
-      else
+      } else {
+        static size_t r0 = 65536;
+        raise_lds(&k_spc_newton<SEG, 0>, lds, r0);
         hipLaunchKernelGGL((k_spc_newton<SEG, 0>), g, b, lds, s, D);
+      }
       break;
     case 4: hipLaunchKernelGGL(k_spc_predict<SEG>, g, b, lds, s, D); break;
     default: hipLaunchKernelGGL(k_spc_accept<SEG>, g, b, spc_accept_lds(), s, D); break;

@@ -4,6 +4,18 @@
 
 namespace bdfgpu {
 
+// Dynamic LDS above 64 KiB (gfx950 has 160 KiB per workgroup) is requested
+// explicitly; the first launch that needs it raises the kernel's limit.
+template <int NP, int LS>
+static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
+  static size_t raised = 65536;
+  if (lds > raised &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tpc_newton<NP, LS>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
+    raised = lds;
+  hipLaunchKernelGGL((k_tpc_newton<NP, LS>), g, b, lds, s, D);
+}
+
 template <int NP>
 static void tpc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s) {
   const dim3 g(grid), b(kTpcThreads);
@@ -14,9 +26,9 @@ static void tpc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStr
     case 2: {
       const size_t lds = tpc_newton_lds(NP, D.k.R, ls, kTpcThreads);
       if (ls == 1)
-        hipLaunchKernelGGL((k_tpc_newton<NP, 1>), g, b, lds, s, D);
+        go_newton<NP, 1>(D, g, b, lds, s);
       else
-        hipLaunchKernelGGL((k_tpc_newton<NP, 0>), g, b, lds, s, D);
+        go_newton<NP, 0>(D, g, b, lds, s);
       break;
     }
     default: hipLaunchKernelGGL(k_tpc_accept<NP>, g, b, tpc_accept_lds(kTpcThreads), s, D); break;

@@ -301,21 +301,39 @@ __global__ void __launch_bounds__(256) k_maxnorm(long n, const double* x, double
   }
 }
 
-// One block: value k of the result is the sum (op 0), the square root of
-// the mean (op 1, WRMS: divided by n) or the maximum (op 2) over the nb
-// block partials, in block order.  Wave w takes k = w, w + 16, ...
+// One block of 1024 threads: value k of the result is the sum (op 0), the
+// square root of the mean (op 1, WRMS: divided by n) or the maximum (op 2)
+// over the nb block partials.  Thread t takes partials t, t + 1024, ... in
+// order (all nv values at once), then a fixed tree over the block.
 __global__ void __launch_bounds__(1024) k_finish(int nv, unsigned int nb, int op, long n,
                                                  const double* partials, double* out) {
+  __shared__ double sh[16 * kRedK];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int k = wid; k < nv; k += 16) {
-    double a = 0.0;
-#pragma unroll 4
-    for (unsigned int b = lane; b < nb; b += 64) {
-      const double v = partials[(size_t)b * kRedK + k];
-      a = op == 2 ? fmax(a, v) : a + v;
+  double v[kRedK];
+#pragma unroll
+  for (int k = 0; k < kRedK; ++k) v[k] = 0.0;
+  for (unsigned int b = threadIdx.x; b < nb; b += 1024) {
+#pragma unroll
+    for (int k = 0; k < kRedK; ++k) {
+      if (k < nv) {
+        const double x = partials[(size_t)b * kRedK + k];
+        v[k] = op == 2 ? fmax(v[k], x) : v[k] + x;
+      }
     }
-    a = op == 2 ? wave_max(a) : wave_sum(a);
-    if (lane == 0) out[k] = op == 1 ? sqrt(a / (double)n) : a;
+  }
+#pragma unroll
+  for (int k = 0; k < kRedK; ++k) {
+    if (k < nv) {
+      const double r = op == 2 ? wave_max(v[k]) : wave_sum(v[k]);
+      if (lane == 0) sh[wid * kRedK + k] = r;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    const int k = threadIdx.x;
+    double a = 0.0;
+    for (int w = 0; w < 16; ++w) a = op == 2 ? fmax(a, sh[w * kRedK + k]) : a + sh[w * kRedK + k];
+    out[k] = op == 1 ? sqrt(a / (double)n) : a;
   }
 }
 
