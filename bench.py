@@ -26,6 +26,11 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 MAXCOR = 3
+# HBM bytes per launch of the fused Newton kernel at 2^20 cells and order 5,
+# from FETCH_SIZE/WRITE_SIZE counter runs scaled by a plain copy kernel
+# (profiles/traffic_k_tpc_newton_2p20cells_n10.md); set to None when the
+# kernel changes until the counters are taken again
+MEASURED_TRAFFIC_BYTES = 925.97e6
 
 
 def log(*a):
@@ -281,7 +286,8 @@ def main():
     roofline = {"bound": "hbm",
                 "kernel": "k_tpc_newton<10,0> (predictor, J, LU, 3 Newton iterations)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": MEASURED_TRAFFIC_BYTES if args.cells == 1 << 20 else None,
                 "avg_launch_ms": round(avg_ms, 4), "launches": p_cnt,
                 "algorithmic_bytes_per_launch": int(bytes_per_launch),
                 "mean_q_plus_1": round(q1, 3),
