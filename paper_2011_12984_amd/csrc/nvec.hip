@@ -82,26 +82,62 @@ static inline bool aligned16(const void* p) {
   return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }
 
-// Launch shape for memory-bound kernels: one 16-byte unit per thread.  A
-// grid as large as the data beat every grid-stride shape (1K..32K blocks)
-// in a sweep on MI355X: the hardware dispatcher keeps more requests in
-// flight than a long-running loop does.
+// Launch shape for memory-bound kernels on 16-byte units.  A block of 256
+// threads owns tiles of kTile = 256 * kU units of every vector; wave w owns
+// 64 * kU consecutive units of the tile and lane l touches units l, l + 64,
+// ..., so each wave reads 4 KB contiguous from every vector per tile and
+// keeps all of its loads in flight at once.  In a sweep on MI355X this shape
+// beat one unit per thread by 10-25% for operations on many vectors (a dot
+// product of one vector against eight: 5.9 -> 7.0 TB/s).  Streaming kernels
+// take one tile per block; reductions a bounded grid that loops over tiles,
+// so that the block partials stay few.
 constexpr int kStreamThreads = 256;
+constexpr int kU = 4;
+constexpr long kTile = (long)kStreamThreads * kU;
+
+static long ntiles_of(long nunits) { return (nunits + kTile - 1) / kTile; }
 static unsigned int stream_blocks(long nunits) {
-  long want = (nunits + kStreamThreads - 1) / kStreamThreads;
-  return (unsigned int)std::max(1L, std::min(want, 1L << 24));
+  return (unsigned int)std::max(1L, std::min(ntiles_of(nunits), 1L << 24));
+}
+// first unit of this thread in tile t
+__device__ __forceinline__ long tile_base(long t) {
+  return (t * kStreamThreads + (long)(threadIdx.x >> 6) * 64) * kU + (threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
 // Streaming kernels
 // ---------------------------------------------------------------------------
-__global__ void k_linear_sum2(long n2, double a, const double2* __restrict__ x,
-                              double b, const double2* __restrict__ y,
-                              double2* __restrict__ z) {
-  const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
-    double2 xv = x[i], yv = y[i];
-    z[i] = make_double2(a * xv.x + b * yv.x, a * xv.y + b * yv.y);
+__global__ void __launch_bounds__(256) k_linear_sum2(long n2, double a, const double* __restrict__ x,
+                                                     double b, const double* __restrict__ y,
+                                                     double* __restrict__ z) {
+  const long nt = (n2 + kTile - 1) / kTile;
+  for (long t = blockIdx.x; t < nt; t += gridDim.x) {
+    const long i0 = tile_base(t);
+    if (i0 + (kU - 1) * 64 < n2) {
+      dbl2 xv[kU], yv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        xv[u] = ntload(x, i0 + u * 64);
+        yv[u] = ntload(y, i0 + u * 64);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        dbl2 o;
+        o.x = a * xv[u].x + b * yv[u].x;
+        o.y = a * xv[u].y + b * yv[u].y;
+        ntstore(z, i0 + u * 64, o);
+      }
+    } else {
+      for (int u = 0; u < kU; ++u) {
+        const long i = i0 + u * 64;
+        if (i >= n2) break;
+        const dbl2 xv = ntload(x, i), yv = ntload(y, i);
+        dbl2 o;
+        o.x = a * xv.x + b * yv.x;
+        o.y = a * xv.y + b * yv.y;
+        ntstore(z, i, o);
+      }
+    }
   }
 }
 
@@ -117,23 +153,52 @@ struct LcArgs {
   double c[16];
 };
 
+__device__ __forceinline__ dbl2 lc_unit(const LcArgs& A, const dbl2* v, int nv) {
+  dbl2 o;
+  o.x = A.c[0] * v[0].x;
+  o.y = A.c[0] * v[0].y;
+  for (int j = 1; j < nv; ++j) {
+    o.x = fma(A.c[j], v[j].x, o.x);
+    o.y = fma(A.c[j], v[j].y, o.y);
+  }
+  return o;
+}
+
 template <int NV>
-__global__ void k_linear_combination2(long n2, LcArgs A, double2* __restrict__ z) {
-  const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
-    dbl2 v[NV];
+__global__ void __launch_bounds__(256) k_linear_combination2(long n2, LcArgs A, double* __restrict__ z) {
+  const long nt = (n2 + kTile - 1) / kTile;
+  for (long t = blockIdx.x; t < nt; t += gridDim.x) {
+    const long i0 = tile_base(t);
+    if (i0 + (kU - 1) * 64 < n2) {
+      dbl2 v[kU][NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = ntload(A.X[j], i);
-    double sx = A.c[0] * v[0].x, sy = A.c[0] * v[0].y;
+      for (int j = 0; j < NV; ++j)
 #pragma unroll
-    for (int j = 1; j < NV; ++j) {
-      sx = fma(A.c[j], v[j].x, sx);
-      sy = fma(A.c[j], v[j].y, sy);
+        for (int u = 0; u < kU; ++u) v[u][j] = ntload(A.X[j], i0 + u * 64);
+      // every load of the tile is issued before the first sum waits on one
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        dbl2 o;
+        o.x = A.c[0] * v[u][0].x;
+        o.y = A.c[0] * v[u][0].y;
+#pragma unroll
+        for (int j = 1; j < NV; ++j) {
+          o.x = fma(A.c[j], v[u][j].x, o.x);
+          o.y = fma(A.c[j], v[u][j].y, o.y);
+        }
+        ntstore(z, i0 + u * 64, o);
+      }
+    } else {
+      for (int u = 0; u < kU; ++u) {
+        const long i = i0 + u * 64;
+        if (i >= n2) break;
+        dbl2 v[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = ntload(A.X[j], i);
+        ntstore(z, i, lc_unit(A, v, NV));
+      }
     }
-    dbl2 o;
-    o.x = sx;
-    o.y = sy;
-    ntstore(reinterpret_cast<double*>(z), i, o);
   }
 }
 
@@ -153,15 +218,42 @@ struct SamArgs {
 };
 
 template <int NV>
-__global__ void k_scale_add_multi2(long n2, const double2* __restrict__ x, SamArgs A) {
-  const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
-    double2 xv = x[i];
+__global__ void __launch_bounds__(256) k_scale_add_multi2(long n2, const double* __restrict__ x,
+                                                          SamArgs A) {
+  const long nt = (n2 + kTile - 1) / kTile;
+  for (long t = blockIdx.x; t < nt; t += gridDim.x) {
+    const long i0 = tile_base(t);
+    if (i0 + (kU - 1) * 64 < n2) {
+      dbl2 xv[kU], yv[kU][NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      double2 yv = reinterpret_cast<const double2*>(A.Y[j])[i];
-      reinterpret_cast<double2*>(A.Z[j])[i] =
-          make_double2(fma(A.a[j], xv.x, yv.x), fma(A.a[j], xv.y, yv.y));
+      for (int u = 0; u < kU; ++u) xv[u] = ntload(x, i0 + u * 64);
+#pragma unroll
+      for (int j = 0; j < NV; ++j)
+#pragma unroll
+        for (int u = 0; u < kU; ++u) yv[u][j] = ntload(A.Y[j], i0 + u * 64);
+#pragma unroll
+      for (int j = 0; j < NV; ++j)
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          dbl2 o;
+          o.x = fma(A.a[j], xv[u].x, yv[u][j].x);
+          o.y = fma(A.a[j], xv[u].y, yv[u][j].y);
+          ntstore(A.Z[j], i0 + u * 64, o);
+        }
+    } else {
+      for (int u = 0; u < kU; ++u) {
+        const long i = i0 + u * 64;
+        if (i >= n2) break;
+        const dbl2 xv = ntload(x, i);
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          const dbl2 yv = ntload(A.Y[j], i);
+          dbl2 o;
+          o.x = fma(A.a[j], xv.x, yv.x);
+          o.y = fma(A.a[j], xv.y, yv.y);
+          ntstore(A.Z[j], i, o);
+        }
+      }
     }
   }
 }
@@ -217,15 +309,39 @@ __global__ void __launch_bounds__(256) k_dot_prod_multi(long n, const double* __
   double acc[NV];
 #pragma unroll
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
-  const long stride = (long)gridDim.x * blockDim.x;
   const long n2 = n >> 1;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
-    dbl2 xv = ntload(x, i);
+  const long nt = (n2 + kTile - 1) / kTile;
+  for (long t = blockIdx.x; t < nt; t += gridDim.x) {
+    const long i0 = tile_base(t);
+    if (i0 + (kU - 1) * 64 < n2) {
+      dbl2 xv[kU], yv[kU][NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      dbl2 yv = ntload(A.Y[j], i);
-      acc[j] = fma(xv.x, yv.x, acc[j]);
-      acc[j] = fma(xv.y, yv.y, acc[j]);
+      for (int u = 0; u < kU; ++u) xv[u] = ntload(x, i0 + u * 64);
+#pragma unroll
+      for (int j = 0; j < NV; ++j)
+#pragma unroll
+        for (int u = 0; u < kU; ++u) yv[u][j] = ntload(A.Y[j], i0 + u * 64);
+      // every load of the tile is issued before the first sum waits on one
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          acc[j] = fma(xv[u].x, yv[u][j].x, acc[j]);
+          acc[j] = fma(xv[u].y, yv[u][j].y, acc[j]);
+        }
+    } else {
+      for (int u = 0; u < kU; ++u) {
+        const long i = i0 + u * 64;
+        if (i >= n2) break;
+        const dbl2 xv = ntload(x, i);
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          const dbl2 yv = ntload(A.Y[j], i);
+          acc[j] = fma(xv.x, yv.x, acc[j]);
+          acc[j] = fma(xv.y, yv.y, acc[j]);
+        }
+      }
     }
   }
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -239,17 +355,36 @@ __global__ void __launch_bounds__(256) k_wrms(long n, const double* __restrict__
                                               const double* __restrict__ w, double* partials) {
   __shared__ double sh[4];
   double acc[1] = {0.0};
-  const long stride = (long)gridDim.x * blockDim.x;
   const long n2 = n >> 1;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
-    dbl2 xv = ntload(x, i);
-    dbl2 wv = ntload(w, i);
-    double a = xv.x * wv.x, b = xv.y * wv.y;
-    acc[0] = fma(a, a, acc[0]);
-    acc[0] = fma(b, b, acc[0]);
+  const long nt = (n2 + kTile - 1) / kTile;
+  for (long t = blockIdx.x; t < nt; t += gridDim.x) {
+    const long i0 = tile_base(t);
+    if (i0 + (kU - 1) * 64 < n2) {
+      dbl2 xv[kU], wv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        xv[u] = ntload(x, i0 + u * 64);
+        wv[u] = ntload(w, i0 + u * 64);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const double a = xv[u].x * wv[u].x, b = xv[u].y * wv[u].y;
+        acc[0] = fma(a, a, acc[0]);
+        acc[0] = fma(b, b, acc[0]);
+      }
+    } else {
+      for (int u = 0; u < kU; ++u) {
+        const long i = i0 + u * 64;
+        if (i >= n2) break;
+        const dbl2 xv = ntload(x, i), wv = ntload(w, i);
+        const double a = xv.x * wv.x, b = xv.y * wv.y;
+        acc[0] = fma(a, a, acc[0]);
+        acc[0] = fma(b, b, acc[0]);
+      }
+    }
   }
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-    double a = x[n - 1] * w[n - 1];
+    const double a = x[n - 1] * w[n - 1];
     acc[0] = fma(a, a, acc[0]);
   }
   store_block_partials<1>(acc, sh, partials);
@@ -337,18 +472,23 @@ __global__ void __launch_bounds__(1024) k_finish(int nv, unsigned int nb, int op
   }
 }
 
-static unsigned int red_blocks(long nunits) {
-  long want = (nunits + kStreamThreads - 1) / kStreamThreads;
+// Grid of a reduction over nunits units handled kTile per block and tile
+// (aligned kernels) or one per thread (scalar kernels, per_thread = true).
+static unsigned int red_blocks(long nunits, bool per_thread = false) {
+  long want = per_thread ? (nunits + kStreamThreads - 1) / kStreamThreads : ntiles_of(nunits);
   return (unsigned int)std::max(1L, std::min(want, (long)kRedBlocks));
 }
 
-// Finish a reduction: copy nv results to the host and wait, or leave them in
-// the caller's device array.
+// Where k_finish writes: the caller's device array directly, or the device
+// slot that finish_reduction then copies to the host.
+static double* finish_target(RedScratch* r, double* out, int flags) {
+  return (flags & BDFGPU_RESULT_DEVICE) ? out : r->dres;
+}
+
+// Finish a reduction whose k_finish wrote to its finish_target: a device
+// result is already in place; a host result is copied back and waited for.
 static int finish_reduction(RedScratch* r, int nv, double* out, int flags, hipStream_t s) {
-  if (flags & BDFGPU_RESULT_DEVICE) {
-    BDF_HIP_TRY(hipMemcpyAsync(out, r->dres, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
-    return 0;
-  }
+  if (flags & BDFGPU_RESULT_DEVICE) return 0;
   BDF_HIP_TRY(hipMemcpyAsync(r->hres, r->dres, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
   BDF_HIP_TRY(hipStreamSynchronize(s));
   memcpy(out, r->hres, sizeof(double) * nv);
@@ -380,8 +520,7 @@ int nvec_linear_sum(long n, double a, const double* x, double b, const double* y
     n2 = n >> 1;
     if (n2)
       hipLaunchKernelGGL(k_linear_sum2, dim3(stream_blocks(n2)), dim3(kStreamThreads), 0, s, n2, a,
-                         reinterpret_cast<const double2*>(x), b,
-                         reinterpret_cast<const double2*>(y), reinterpret_cast<double2*>(z));
+                         x, b, y, z);
   }
   if (2 * n2 < n)
     hipLaunchKernelGGL(k_linear_sum1, dim3(stream_blocks(n - 2 * n2)), dim3(kStreamThreads), 0, s,
@@ -408,9 +547,8 @@ int nvec_linear_combination(int nv, const double* c, const double* const* X, dou
   if (al) {
     n2 = n >> 1;
     dim3 g(stream_blocks(n2)), b(kStreamThreads);
-    double2* z2 = reinterpret_cast<double2*>(z);
     if (n2) switch (nv) {
-#define LC_CASE(K) case K: hipLaunchKernelGGL(k_linear_combination2<K>, g, b, 0, s, n2, A, z2); break;
+#define LC_CASE(K) case K: hipLaunchKernelGGL(k_linear_combination2<K>, g, b, 0, s, n2, A, z); break;
       LC_CASE(1) LC_CASE(2) LC_CASE(3) LC_CASE(4) LC_CASE(5) LC_CASE(6) LC_CASE(7) LC_CASE(8)
       LC_CASE(9) LC_CASE(10) LC_CASE(11) LC_CASE(12) LC_CASE(13) LC_CASE(14) LC_CASE(15) LC_CASE(16)
 #undef LC_CASE
@@ -443,9 +581,8 @@ int nvec_scale_add_multi(int nv, const double* a, const double* x, const double*
   if (al) {
     n2 = n >> 1;
     dim3 g(stream_blocks(n2)), b(kStreamThreads);
-    const double2* x2 = reinterpret_cast<const double2*>(x);
     if (n2) switch (nv) {
-#define SAM_CASE(K) case K: hipLaunchKernelGGL(k_scale_add_multi2<K>, g, b, 0, s, n2, x2, A); break;
+#define SAM_CASE(K) case K: hipLaunchKernelGGL(k_scale_add_multi2<K>, g, b, 0, s, n2, x, A); break;
       SAM_CASE(1) SAM_CASE(2) SAM_CASE(3) SAM_CASE(4) SAM_CASE(5) SAM_CASE(6) SAM_CASE(7) SAM_CASE(8)
 #undef SAM_CASE
     }
@@ -481,7 +618,7 @@ int nvec_dot_prod_multi(int nv, const double* x, const double* const* Y, double*
     A.Y[j] = Y[j];
     al = al && aligned16(Y[j]);
   }
-  dim3 g(red_blocks(al ? (n >> 1) + 1 : n)), b(256);
+  dim3 g(al ? red_blocks(n >> 1) : red_blocks(n, true)), b(256);
   if (al) {
     switch (nv) {
 #define DP_CASE(K) case K: hipLaunchKernelGGL(k_dot_prod_multi<K>, g, b, 0, s, n, x, A, r->partials); break;
@@ -496,7 +633,8 @@ int nvec_dot_prod_multi(int nv, const double* x, const double* const* Y, double*
     }
   }
   BDF_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, nv, g.x, 0, n, r->partials, r->dres);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, nv, g.x, 0, n, r->partials,
+                     finish_target(r, d, flags));
   BDF_HIP_TRY(hipGetLastError());
   return finish_reduction(r, nv, d, flags, s);
 }
@@ -517,13 +655,14 @@ int nvec_wrms_norm(long n, const double* x, const double* w, double* out, int fl
   int st = get_red_scratch(&r);
   if (st) return st;
   bool al = aligned16(x) && aligned16(w);
-  dim3 g(red_blocks(al ? (n >> 1) + 1 : n)), b(256);
+  dim3 g(al ? red_blocks(n >> 1) : red_blocks(n, true)), b(256);
   if (al)
     hipLaunchKernelGGL(k_wrms, g, b, 0, s, n, x, w, r->partials);
   else
     hipLaunchKernelGGL(k_wrms_u, g, b, 0, s, n, x, w, r->partials);
   BDF_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, 1, g.x, 1, n, r->partials, r->dres);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, 1, g.x, 1, n, r->partials,
+                     finish_target(r, out, flags));
   BDF_HIP_TRY(hipGetLastError());
   return finish_reduction(r, 1, out, flags, s);
 }
@@ -542,9 +681,10 @@ int nvec_max_norm(long n, const double* x, double* out, int flags, void* stream)
   RedScratch* r = nullptr;
   int st = get_red_scratch(&r);
   if (st) return st;
-  const unsigned int gm = red_blocks(n);
+  const unsigned int gm = red_blocks(n, true);
   hipLaunchKernelGGL(k_maxnorm, dim3(gm), dim3(256), 0, s, n, x, r->partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, 1, gm, 2, n, r->partials, r->dres);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, 1, gm, 2, n, r->partials,
+                     finish_target(r, out, flags));
   BDF_HIP_TRY(hipGetLastError());
   return finish_reduction(r, 1, out, flags, s);
 }

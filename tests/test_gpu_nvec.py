@@ -108,7 +108,14 @@ def test_wrms_and_max(orc, dev, G, n):
     v = G.nvec_wrms_norm(T(x, dev), T(w, dev))
     ref = orc.wrms_norm(x, w)
     assert v == pytest.approx(ref, rel=1e-12, abs=0)
-    assert G.nvec_max_norm(T(x, dev)) == orc.max_norm(x)
+    m = G.nvec_max_norm(T(x, dev))
+    assert m == orc.max_norm(x)
+    # device-result variants write the same numbers straight into `out`
+    out = torch.full((1,), -1.0, dtype=torch.float64, device=dev)
+    G.nvec_wrms_norm(T(x, dev), T(w, dev), out=out)
+    assert out.item() == v
+    G.nvec_max_norm(T(x, dev), out=out)
+    assert out.item() == m
 
 
 def test_wrms_constant_closed_form(dev, G):
