@@ -28,9 +28,8 @@ HBM_PEAK_GBS = 8000.0
 MAXCOR = 3
 # HBM bytes per launch of the fused Newton kernel at 2^20 cells and order 5,
 # from FETCH_SIZE/WRITE_SIZE counter runs scaled by a plain copy kernel
-# (profiles/traffic_k_tpc_newton_2p20cells_n10.md); set to None when the
-# kernel changes until the counters are taken again
-MEASURED_TRAFFIC_BYTES = 925.97e6
+# (profiles/); None when the kernel has changed since the counters were taken
+MEASURED_TRAFFIC_BYTES = None
 
 
 def log(*a):
@@ -45,9 +44,10 @@ def time_advance(b, t_end, steps, torch):
     return time.perf_counter() - t0, taken, t
 
 
-def bdf_leg(G, W, torch, prob, dev, warmup, steps, linsol, precond=None):
-    b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_STREAM, attempts_per_sync=16,
-                           linsol=linsol, maxcor=MAXCOR, precond=precond)
+def bdf_leg(G, W, torch, prob, dev, warmup, steps, linsol, precond=None, jit=True, graph=False):
+    b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_GRAPH if graph else G.MODE_STREAM,
+                           attempts_per_sync=16, linsol=linsol, maxcor=MAXCOR, precond=precond,
+                           jit=jit)
     b.advance(prob.t_end, warmup)
     s0 = b.stats()
     dt, taken, t = time_advance(b, prob.t_end, steps, torch)
@@ -148,14 +148,14 @@ def accuracy_vs_fp64(G, W, torch, dev, make, t_end, **kw):
             "steps": [int(s["nsteps"]), int(sr["nsteps"])]}
 
 
-def uneven_leg(G, W, torch, dev, warmup, steps):
+def uneven_leg(G, W, torch, dev, warmup, steps, jit=True):
     """Blocks of 4..64 species (2^22 unknowns), FP32 LU + refinement,
     hipGraph-captured attempts, launch mode and small-block mapping chosen
     by the library's autotuner."""
     prob = W.uneven_batch(1 << 22)
     t0 = time.perf_counter()
     b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_GRAPH, attempts_per_sync=16,
-                           linsol=G.LS_LU32REF, launch=G.LAUNCH_AUTO, maxcor=MAXCOR)
+                           linsol=G.LS_LU32REF, launch=G.LAUNCH_AUTO, maxcor=MAXCOR, jit=jit)
     torch.cuda.synchronize()
     t_tune = time.perf_counter() - t0
     tu = b.tuning()
@@ -230,6 +230,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--graph", action="store_true")
+    ap.add_argument("--no-jit", action="store_true",
+                    help="generic table-driven Newton kernels instead of network-specialised ones")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run nvec_scale (a plain copy, 512 MiB in and out) 5 times: "
                          "the reference for HBM byte counters")
@@ -262,7 +265,8 @@ def main():
     n, R = 10, 20
 
     log("FP64 LU leg")
-    b, dt, taken, s0, s1 = bdf_leg(G, W, torch, prob, dev, args.warmup, args.steps, G.LS_LU64)
+    b, dt, taken, s0, s1 = bdf_leg(G, W, torch, prob, dev, args.warmup, args.steps, G.LS_LU64,
+                                   jit=not args.no_jit, graph=args.graph)
     value = args.cells * taken / dt
     ms_per_step = 1e3 * dt / max(taken, 1)
     attempts = s1["nattempts"] - s0["nattempts"]
@@ -284,7 +288,9 @@ def main():
     avg_ms = p_ms / max(p_cnt, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm",
-                "kernel": "k_tpc_newton<10,0> (predictor, J, LU, 3 Newton iterations)",
+                "kernel": ("k_tpc_newton<10,0>" if args.no_jit else
+                           "bdf_newton_net (k_tpc_newton<10,0> specialised to the network)")
+                          + " (predictor, J, LU, 3 Newton iterations)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": MEASURED_TRAFFIC_BYTES if args.cells == 1 << 20 else None,
@@ -299,7 +305,7 @@ def main():
     if not args.no_fp32:
         log("FP32 LU + refinement leg")
         b32, dt32, taken32, s320, s321 = bdf_leg(G, W, torch, prob, dev, args.warmup, args.steps,
-                                                 G.LS_LU32REF)
+                                                 G.LS_LU32REF, jit=not args.no_jit)
         sweeps = s321["refine_sweeps"] - s320["refine_sweeps"]
         fb = s321["refine_fallbacks"] - s320["refine_fallbacks"]
         solves = (s321["nniters"] - s320["nniters"]) * args.cells
@@ -322,7 +328,7 @@ def main():
     uneven = None
     if not args.no_uneven:
         log("uneven batch leg (autotuned launch, hipGraph, FP32-refined LU)")
-        uneven = uneven_leg(G, W, torch, dev, args.warmup, min(args.steps, 200))
+        uneven = uneven_leg(G, W, torch, dev, args.warmup, min(args.steps, 200), jit=not args.no_jit)
 
     learned = None
     if not args.no_learned:
@@ -347,6 +353,7 @@ def main():
                    "cells": args.cells, "species": n, "reactions": R,
                    "attempts_per_step": round(attempts / max(taken, 1), 4),
                    "newton_iters_per_step": round(niters / max(taken, 1), 4),
+                   "network_specialised_kernels": not args.no_jit,
                    "t_reached": t_after},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -186,6 +186,19 @@ typedef struct {
                              initial values must then be >= 0 */
   int map_small;          /* 0: classes of <= 12 species use one lane per cell
                              (block in registers); 1: a 16-lane segment per cell */
+  int jit;                /* 1: bdf_create generates, for each one-lane-per-cell
+                             class, a Newton kernel with the class's network
+                             written out as straight-line code (the device-side
+                             right-hand side and Jacobian callbacks a user
+                             supplies, Section 6, here derived from nu and mu),
+                             compiles it with hipcc
+                             ($HIPCC, else /opt/rocm/bin/hipcc; about 4 s per
+                             new network) into a shared library cached under
+                             $BDFGPU_JIT_DIR (else $TMPDIR/bdfgpu-jit-<uid>)
+                             and loads it; results are bitwise those of the
+                             generic kernel.  0: generic kernels only.  Error
+                             BDFGPU_ERR_HIP with the end of the compiler log if
+                             compilation or loading fails. */
 } bdf_options;
 
 typedef struct {

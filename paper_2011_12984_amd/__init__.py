@@ -209,12 +209,13 @@ class Bdf:
 
     topologies: list of (nu, mu) integer arrays of shape (R, n);
     cell_topo: int array (ncells,); rates, y0: float64 device tensors
-    (concatenated per cell)."""
+    (concatenated per cell).  jit: compile network-specialised Newton
+    kernels for the one-lane-per-cell classes (bitwise the same results)."""
 
     def __init__(self, topologies, cell_topo, rates, y0, t0=0.0, rtol=1e-6, atol=1e-10,
                  qmax=5, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64, refine_max_it=5,
                  max_steps=0, mode=MODE_STREAM, attempts_per_sync=8, nonneg=False,
-                 precond=None, launch=LAUNCH_PER_CLASS, map_small=0):
+                 precond=None, launch=LAUNCH_PER_CLASS, map_small=0, jit=False):
         torch = _torch()
         _dev(rates, torch.float64)
         _dev(y0, torch.float64)
@@ -233,7 +234,7 @@ class Bdf:
         opts = BdfOptions(rtol, atol, qmax, maxcor, h0, hmin, linsol, refine_max_it, max_steps,
                           mode, attempts_per_sync, launch,
                           precond.h if precond is not None else None, int(bool(nonneg)),
-                          int(map_small))
+                          int(map_small), int(bool(jit)))
         h = vp()
         check("bdf_create", lib().bdf_create(C.byref(prob), C.byref(opts), _stream(), C.byref(h)))
         self.h = h

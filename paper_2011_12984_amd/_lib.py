@@ -31,7 +31,8 @@ class BdfOptions(C.Structure):
                 ("maxcor", C.c_int), ("h0", C.c_double), ("hmin", C.c_double),
                 ("linsol", C.c_int), ("refine_max_it", C.c_int), ("max_steps", C.c_long),
                 ("mode", C.c_int), ("attempts_per_sync", C.c_int), ("launch", C.c_int),
-                ("precond", vp), ("nonneg", C.c_int), ("map_small", C.c_int)]
+                ("precond", vp), ("nonneg", C.c_int), ("map_small", C.c_int),
+                ("jit", C.c_int)]
 
 
 class BdfStats(C.Structure):

@@ -19,6 +19,7 @@
 #include <chrono>
 
 #include "bdf_dev.hpp"
+#include "bdf_jit.hpp"
 #include "bdf_multi.hpp"
 #include "common.hpp"
 
@@ -45,6 +46,7 @@ struct ClassHost {
   long mblocks, mblk0;          // blocks and first block in that launch
   long* d_yoff = nullptr;       // user-layout offset of each class cell's y
   long* d_roff = nullptr;       // user-layout offset of each class cell's rates
+  NetLaunch jit = nullptr;      // network-specialised Newton kernel, if any
   ClassDev dev;
 };
 
@@ -262,8 +264,10 @@ static void launch_phase_kernels(bdf_handle* h, int which, hipStream_t s) {
     return;
   }
   for (const ClassHost& c : h->cls) {
-    const BdfDev D = make_dev(h, c);
-    if (c.map == MAP_TPC)
+    BdfDev D = make_dev(h, c);
+    if (c.map == MAP_TPC && which == 2 && c.jit) {
+      c.jit(&D, c.grid, (unsigned int)tpc_newton_lds(c.np, c.R, h->o.linsol, kTpcThreads), s);
+    } else if (c.map == MAP_TPC)
       launch_tpc(c.np, h->o.linsol, which, D, c.grid, s);
     else
       launch_spc(c.np, h->o.linsol, which, D, c.grid, s);
@@ -461,6 +465,14 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
                        "and a network of the preconditioner's size");
     }
     ch.np = ch.map == MAP_TPC ? tpc_padded(n) : spc_seg(n);
+    // network-specialised Newton kernel
+    if (o->jit && ch.map == MAP_TPC) {
+      st = jit_newton(net_newton_source(nu, mu, n, R, ch.np, o->linsol), &ch.jit);
+      if (st) {
+        bdf_destroy(h);
+        return st;
+      }
+    }
     const int cpb = ch.map == MAP_TPC ? kTpcThreads : kCellThreads / ch.np;
     ch.grid = (unsigned int)std::max<long>(1, (ch.ncells + cpb - 1) / cpb);
     ch.blk0 = blk;

@@ -353,7 +353,7 @@ struct Tpc {
       jac_col(nd, kcol, ks, ycol, a, col);
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
-        const double m = (i == a ? 1.0 : 0.0) - gamma * col[i];
+        const double m = fma(-gamma, col[i], i == a ? 1.0 : 0.0);
         M[i][a] = (TT)m;
         if (ROWSUM) rowsum[i] += fabs(m);
       }
@@ -389,6 +389,32 @@ struct Tpc {
   __device__ static __forceinline__ void store_col(double* col, const double (&v)[NP]) {
 #pragma unroll
     for (int i = 0; i < NP; ++i) col[i * T] = v[i];
+  }
+};
+
+// Network evaluation policy of the thread-per-cell Newton kernel: f, M =
+// I - gamma J and (I - gamma J) x for the cell's network.  NetTables reads
+// the network from the NetDev tables at run time (any network); a class can
+// instead bring a policy generated for its own network (straight-line code
+// with the species and reaction indices as constants), which must compute
+// the same operations in the same order so that both give identical bits.
+struct NetTables {
+  template <int NP, int T>
+  __device__ static __forceinline__ void rhs(const NetDev& nd, const double* kcol, int ks,
+                                             const double* ycol, double (&f)[NP]) {
+    Tpc<NP, T>::rhs(nd, kcol, ks, ycol, f);
+  }
+  template <int NP, int T, typename TT, bool ROWSUM>
+  __device__ static __forceinline__ void build_M(const NetDev& nd, const double* kcol, int ks,
+                                                 const double* ycol, double gamma,
+                                                 TT (&M)[NP][NP], double (&rowsum)[NP]) {
+    Tpc<NP, T>::template build_M<TT, ROWSUM>(nd, kcol, ks, ycol, gamma, M, rowsum);
+  }
+  template <int NP, int T>
+  __device__ static __forceinline__ void mvp(const NetDev& nd, const double* kcol, int ks,
+                                             const double* ycol, const double* xcol, double gamma,
+                                             const double (&x)[NP], double (&out)[NP]) {
+    Tpc<NP, T>::mvp(nd, kcol, ks, ycol, xcol, gamma, x, out);
   }
 };
 
@@ -461,7 +487,7 @@ __host__ __device__ inline size_t tpc_accept_lds(int tb) {
 // refinement fails switches to FP64 LU, re-assembled and factored at every
 // later iteration of the attempt (rare: the FP64 factors would double the
 // register footprint if they were kept beside the FP32 ones).
-template <int NP, int LS, int TB>
+template <int NP, int LS, int TB, class Net = NetTables>
 __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, double* lds) {
   using TP = Tpc<NP, TB>;
   Ctrl* C = D.C;
@@ -500,7 +526,7 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
       if (C->restart) {
         double f0[NP];
         TP::store_col(ycol, zs[0]);
-        TP::rhs(nd, kcol, TB, ycol, f0);
+        Net::template rhs<NP, TB>(nd, kcol, TB, ycol, f0);
         const double h = C->h;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
@@ -527,7 +553,7 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
     TF A[NP][NP];
     int piv[NP];
     double rowsum[NP];
-    TP::template build_M<TF, LS == 1>(nd, kcol, TB, ycol, gamma, A, rowsum);
+    Net::template build_M<NP, TB, TF, LS == 1>(nd, kcol, TB, ycol, gamma, A, rowsum);
     double mnorm = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) mnorm = fmax(mnorm, rowsum[i]);
@@ -542,7 +568,7 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
     for (int m = 0; m < maxcor; ++m) {
       TP::store_col(yev, y);
       double r[NP];
-      TP::rhs(nd, kcol, TB, yev, r);
+      Net::template rhs<NP, TB>(nd, kcol, TB, yev, r);
 #pragma unroll
       for (int i = 0; i < NP; ++i) r[i] = fma(gamma, r[i], cv[i] - y[i]);
       double del[NP];
@@ -565,7 +591,7 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
           for (int it = 0; it <= K.refine_max_it; ++it) {
             TP::store_col(xcol, del);
             double mx[NP];
-            TP::mvp(nd, kcol, TB, ycol, xcol, gamma, del, mx);
+            Net::template mvp<NP, TB>(nd, kcol, TB, ycol, xcol, gamma, del, mx);
             double rn = 0.0, xn = 0.0;
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
@@ -599,7 +625,7 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
         }
         if (!ok) {
           double M[NP][NP], rs[NP];
-          TP::template build_M<double, false>(nd, kcol, TB, ycol, gamma, M, rs);
+          Net::template build_M<NP, TB, double, false>(nd, kcol, TB, ycol, gamma, M, rs);
           int pv[NP];
           if (TpcLU<NP, double>::factor(M, pv)) sing = true;
 #pragma unroll
