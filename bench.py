@@ -29,7 +29,7 @@ MAXCOR = 3
 # HBM bytes per launch of the fused Newton kernel at 2^20 cells and order 5,
 # from FETCH_SIZE/WRITE_SIZE counter runs scaled by a plain copy kernel
 # (profiles/); None when the kernel has changed since the counters were taken
-MEASURED_TRAFFIC_BYTES = None
+MEASURED_TRAFFIC_BYTES = 925.6e6
 
 
 def log(*a):
@@ -289,11 +289,12 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm",
                 "kernel": ("k_tpc_newton<10,0>" if args.no_jit else
-                           "bdf_newton_net (k_tpc_newton<10,0> specialised to the network)")
+                           "bdf_newton_net_np10_ls0 (k_tpc_newton<10,0> specialised to the network)")
                           + " (predictor, J, LU, 3 Newton iterations)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": MEASURED_TRAFFIC_BYTES if args.cells == 1 << 20 else None,
+                "traffic": (MEASURED_TRAFFIC_BYTES if args.cells == 1 << 20 and not args.no_jit
+                            else None),
                 "avg_launch_ms": round(avg_ms, 4), "launches": p_cnt,
                 "algorithmic_bytes_per_launch": int(bytes_per_launch),
                 "mean_q_plus_1": round(q1, 3),

@@ -209,7 +209,10 @@ std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np
        "    for (int i = 0; i < NP; ++i) out[i] = fma(-gamma, jx[i], x[i]);\n"
        "  }\n};\n}  // namespace bdfgpu\n\n";
 
-  o << "__global__ void __launch_bounds__(bdfgpu::kTpcThreads) bdf_newton_net(bdfgpu::BdfDev D) {\n"
+  // named by block size and solver so that profiles keep the variants apart
+  const std::string kname = "bdf_newton_net_np" + std::to_string(np) + "_ls" + std::to_string(ls);
+  o << "__global__ void __launch_bounds__(bdfgpu::kTpcThreads) " << kname
+    << "(bdfgpu::BdfDev D) {\n"
        "  extern __shared__ double lds[];\n"
        "  if (D.C->phase != bdfgpu::PH_PREDICT) return;\n"
        "  bdfgpu::tpc_newton_body<"
@@ -219,12 +222,14 @@ std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np
        "extern \"C\" void bdf_newton_net_launch(const bdfgpu::BdfDev* D, unsigned int grid,\n"
        "                                      unsigned int lds, hipStream_t s) {\n"
        "  static unsigned int raised = 65536;\n"
-       "  if (lds > raised && hipFuncSetAttribute(reinterpret_cast<const void*>(&bdf_newton_net),\n"
+       "  if (lds > raised && hipFuncSetAttribute(reinterpret_cast<const void*>(&"
+    << kname
+    << "),\n"
        "                                          hipFuncAttributeMaxDynamicSharedMemorySize,\n"
        "                                          (int)lds) == hipSuccess)\n"
        "    raised = lds;\n"
-       "  hipLaunchKernelGGL(bdf_newton_net, dim3(grid), dim3(bdfgpu::kTpcThreads), lds, s, *D);\n"
-       "}\n";
+       "  hipLaunchKernelGGL("
+    << kname << ", dim3(grid), dim3(bdfgpu::kTpcThreads), lds, s, *D);\n}\n";
   return o.str();
 }
 

@@ -13,7 +13,7 @@ struct BdfDev;
 // kTpcThreads, lds bytes of dynamic LDS, on stream s.
 typedef void (*NetLaunch)(const BdfDev* D, unsigned int grid, unsigned int lds, hipStream_t s);
 
-// HIP source of the fused Newton kernel bdf_newton_net for one
+// HIP source of the fused Newton kernel bdf_newton_net_np<np>_ls<ls> for one
 // mass-action network: nu, mu are the R x n reactant and product
 // stoichiometries (row-major, at most two reactant molecules per reaction),
 // np the padded block size of the thread-per-cell kernels, ls the linear
