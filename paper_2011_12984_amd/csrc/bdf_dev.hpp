@@ -487,7 +487,12 @@ __host__ __device__ inline size_t tpc_accept_lds(int tb) {
 // refinement fails switches to FP64 LU, re-assembled and factored at every
 // later iteration of the attempt (rare: the FP64 factors would double the
 // register footprint if they were kept beside the FP32 ones).
-template <int NP, int LS, int TB, class Net = NetTables>
+//
+// RC: rates loaded in the same batch as the history (a kernel generated for
+// one network passes its R); the rest follow in chunks of 8.  Every wave
+// issues these loads before it waits on any of them, so their HBM round
+// trips overlap; at one wave per SIMD a serial round trip costs the SIMD.
+template <int NP, int LS, int TB, class Net = NetTables, int RC = 8>
 __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, double* lds) {
   using TP = Tpc<NP, TB>;
   Ctrl* C = D.C;
@@ -505,13 +510,11 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
 #pragma unroll
   for (int k = 0; k < kRedNewton; ++k) red[k] = 0.0;
   if (act) {
-    for (int k0 = 0; k0 < R; k0 += 8) {   // 8 loads in flight per chunk
-      double v[8];
+    const int r0 = R < RC ? R : RC;   // rates in the first batch
+    double rv[RC];
+    if (r0 > 0) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = K.rates[TP::kidx(c, k0 + u < R ? k0 + u : R - 1, R)];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (k0 + u < R) kcol[(k0 + u) * TB] = v[u];
+      for (int u = 0; u < RC; ++u) rv[u] = K.rates[TP::kidx(c, u < r0 ? u : r0 - 1, R)];
     }
     const double gamma = C->gamma;
     const double l0 = C->l[0];
@@ -521,6 +524,17 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
     {
       double zs[kQmaxAll + 1][NP];
       tpc_load_hist<NP>(K, C, c, n, q, zs);
+#pragma unroll
+      for (int u = 0; u < RC; ++u)
+        if (u < r0) kcol[u * TB] = rv[u];
+      for (int k0 = RC; k0 < R; k0 += 8) {   // 8 loads in flight per chunk
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = K.rates[TP::kidx(c, k0 + u < R ? k0 + u : R - 1, R)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (k0 + u < R) kcol[(k0 + u) * TB] = v[u];
+      }
 #pragma unroll
       for (int i = 0; i < NP; ++i) w[i] = i < n ? 1.0 / (D.rtol * fabs(zs[0][i]) + D.atol) : 0.0;
       if (C->restart) {

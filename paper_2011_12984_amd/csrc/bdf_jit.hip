@@ -216,8 +216,8 @@ std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np
        "  extern __shared__ double lds[];\n"
        "  if (D.C->phase != bdfgpu::PH_PREDICT) return;\n"
        "  bdfgpu::tpc_newton_body<"
-    << np << ", " << ls
-    << ", bdfgpu::kTpcThreads, bdfgpu::NetGen>(D, blockIdx.x, lds);\n}\n\n"
+    << np << ", " << ls << ", bdfgpu::kTpcThreads, bdfgpu::NetGen, " << (R < 1 ? 1 : R > 24 ? 24 : R)
+    << ">(D, blockIdx.x, lds);\n}\n\n"
        "// dynamic LDS above 64 KiB is requested once per process\n"
        "extern \"C\" void bdf_newton_net_launch(const bdfgpu::BdfDev* D, unsigned int grid,\n"
        "                                      unsigned int lds, hipStream_t s) {\n"
