@@ -492,7 +492,7 @@ __host__ __device__ inline size_t tpc_accept_lds(int tb) {
 // one network passes its R); the rest follow in chunks of 8.  Every wave
 // issues these loads before it waits on any of them, so their HBM round
 // trips overlap; at one wave per SIMD a serial round trip costs the SIMD.
-template <int NP, int LS, int TB, class Net = NetTables, int RC = 8>
+template <int NP, int LS, int TB, class Net = NetTables, int RC = 24>
 __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, double* lds) {
   using TP = Tpc<NP, TB>;
   Ctrl* C = D.C;

@@ -14,6 +14,7 @@
 // by |X M - I|.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -66,6 +67,7 @@ struct Precond {
   float *xs = nullptr, *a1 = nullptr, *h1 = nullptr, *a2 = nullptr, *h2 = nullptr, *out = nullptr;
   float *dout = nullptr, *dh = nullptr, *dh2 = nullptr;
   double* lossbuf = nullptr;
+  double* statpart = nullptr;    // kStatBlocks x nin partial column sums
   double* bx = nullptr;          // gathered batch inputs
   double* bm = nullptr;          // gathered batch blocks
   std::vector<void*> allocs;
@@ -207,12 +209,23 @@ __global__ void __launch_bounds__(64) k_loss_grad(int B, int n, const float* out
 }
 
 // column sums: g[n] (+)= sum_b D[b][n]
-__global__ void k_colsum(int B, int N, const float* D, float* g) {
-  const int nidx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (nidx >= N) return;
-  float s = 0.f;
-  for (int b = 0; b < B; ++b) s += D[(long)b * N + nidx];
-  g[nidx] = s;
+// g[j] = sum_b D[b][j] (bias gradients).  A block of 1024 threads takes
+// 64 columns; thread (slice s, column j) sums rows s, s + 16, ... in order,
+// then the 16 slices are summed in order.
+__global__ void __launch_bounds__(1024) k_colsum(int B, int N, const float* D, float* g) {
+  __shared__ float sh[16][64];
+  const int cj = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + cj;
+  float a = 0.f;
+  if (j < N)
+    for (int b = sl; b < B; b += 16) a += D[(long)b * N + j];
+  sh[sl][cj] = a;
+  __syncthreads();
+  if (sl == 0 && j < N) {
+    float t = 0.f;
+    for (int k = 0; k < 16; ++k) t += sh[k][cj];
+    g[j] = t;
+  }
 }
 
 // dh = dh * (a > 0)
@@ -253,20 +266,48 @@ __global__ void k_gather(int B, int w, const double* src, const int* perm, doubl
 
 // per-column mean and standard deviation over ns samples (one thread per
 // column, FP64 two-pass)
-__global__ void k_mean_std(long ns, int w, const double* X, double* mean, double* stdv) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= w) return;
-  double s = 0.0;
-  for (long b = 0; b < ns; ++b) s += X[b * w + i];
-  const double mu = s / (double)ns;
-  double v = 0.0;
-  for (long b = 0; b < ns; ++b) {
-    const double d = X[b * w + i] - mu;
-    v += d * d;
+// Column statistics of an ns x w FP64 matrix (w <= 32) in two passes, each
+// a per-block partial over a fixed chunk of rows (pass 0: sum of x; pass 1:
+// sum of (x - mean)^2) and one finishing block that sums the partials in
+// block order.  Thread t of a block takes column t % w of rows t / w,
+// t / w + 256 / w, ...; the block then sums its rows per column in order.
+constexpr int kStatBlocks = 1024;
+__global__ void __launch_bounds__(256) k_col_partial(long ns, int w, int pass, const double* X,
+                                                     const double* mean, double* part) {
+  __shared__ double sh[256];
+  const int t = threadIdx.x, rpi = 256 / w, c = t % w, rl = t / w;
+  const long chunk = (ns + gridDim.x - 1) / gridDim.x;
+  const long r0 = (long)blockIdx.x * chunk;
+  const long r1 = r0 + chunk < ns ? r0 + chunk : ns;
+  double acc = 0.0;
+  if (rl < rpi) {
+    const double mu = pass ? mean[c] : 0.0;
+    for (long r = r0 + rl; r < r1; r += rpi) {
+      const double v = X[r * w + c];
+      acc += pass ? (v - mu) * (v - mu) : v;
+    }
   }
-  double sd = sqrt(v / (double)(ns > 1 ? ns : 1));
-  mean[i] = mu;
-  stdv[i] = sd > 1e-12 ? sd : 1.0;
+  sh[t] = acc;
+  __syncthreads();
+  if (t < w) {
+    double a = 0.0;
+    for (int j = 0; j < rpi; ++j) a += sh[j * w + t];
+    part[(long)blockIdx.x * w + t] = a;
+  }
+}
+
+__global__ void k_col_finish(int nb, long ns, int w, int pass, const double* part, double* mean,
+                             double* stdv) {
+  const int c = threadIdx.x;
+  if (c >= w) return;
+  double a = 0.0;
+  for (int b = 0; b < nb; ++b) a += part[(long)b * w + c];
+  if (pass == 0) {
+    mean[c] = a / (double)ns;
+  } else {
+    const double sd = sqrt(a / (double)(ns > 1 ? ns : 1));
+    stdv[c] = sd > 1e-12 ? sd : 1.0;
+  }
 }
 
 // FP32 master weights -> padded BF16 copies for inference
@@ -479,19 +520,19 @@ static int loss_grad(Precond* p, int B, const double* bx, const double* bm, hipS
   hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(64), 0, s, B, p->lossbuf + 1, p->lossbuf);
   // backward (FP32; products with the BF16-rounded weights used forward)
   gemm(s, NO, H, B, p->dout, NO, 1, p->h2, H, 0, Gd + p->off_W3, H, 0, 0);       // gW3 = dout^T h2
-  hipLaunchKernelGGL(k_colsum, dim3(ceil_div(NO, 256)), dim3(256), 0, s, B, NO, p->dout,
+  hipLaunchKernelGGL(k_colsum, dim3(ceil_div(NO, 64)), dim3(1024), 0, s, B, NO, p->dout,
                      Gd + p->off_b3);
   gemm(s, B, H, NO, p->dout, NO, 0, P + p->off_W3, H, 0, p->dh2, H, 1, 0);      // dh2 = dout W3
   hipLaunchKernelGGL(k_relu_bwd, dim3(ceil_div((long)B * H, 256)), dim3(256), 0, s, (long)B * H,
                      p->dh2, p->a2);
   gemm(s, H, H, B, p->dh2, H, 1, p->h1, H, 0, Gd + p->off_W2, H, 0, 0);          // gW2
-  hipLaunchKernelGGL(k_colsum, dim3(ceil_div(H, 256)), dim3(256), 0, s, B, H, p->dh2,
+  hipLaunchKernelGGL(k_colsum, dim3(ceil_div(H, 64)), dim3(1024), 0, s, B, H, p->dh2,
                      Gd + p->off_b2);
   gemm(s, B, H, H, p->dh2, H, 0, P + p->off_W2, H, 0, p->dh, H, 1, 0);          // dh1
   hipLaunchKernelGGL(k_relu_bwd, dim3(ceil_div((long)B * H, 256)), dim3(256), 0, s, (long)B * H,
                      p->dh, p->a1);
   gemm(s, H, nin, B, p->dh, H, 1, p->xs, nin, 0, Gd + p->off_W1, nin, 0, 0);     // gW1
-  hipLaunchKernelGGL(k_colsum, dim3(ceil_div(H, 256)), dim3(256), 0, s, B, H, p->dh,
+  hipLaunchKernelGGL(k_colsum, dim3(ceil_div(H, 64)), dim3(1024), 0, s, B, H, p->dh,
                      Gd + p->off_b1);
   BDF_HIP_TRY(hipGetLastError());
   return 0;
@@ -570,6 +611,7 @@ int precond_create(int n, int hid, int batch_cap, precond_handle** out) {
       (st = pc_alloc(p, (void**)&p->dh, sizeof(float) * B * hid)) ||
       (st = pc_alloc(p, (void**)&p->dh2, sizeof(float) * B * hid)) ||
       (st = pc_alloc(p, (void**)&p->lossbuf, sizeof(double) * (B + 1))) ||
+      (st = pc_alloc(p, (void**)&p->statpart, sizeof(double) * kStatBlocks * p->nin)) ||
       (st = pc_alloc(p, (void**)&p->bx, sizeof(double) * B * p->nin)) ||
       (st = pc_alloc(p, (void**)&p->bm, sizeof(double) * B * p->nout))) {
     precond_destroy(h);
@@ -632,8 +674,15 @@ int precond_get_normalization(precond_handle* h, double* mean_host, double* std_
 
 int precond_fit_normalization(precond_handle* h, const double* X, long ns, void* stream) {
   if (!h || !X || ns < 1) return arg_error("precond_fit_normalization: bad argument");
-  hipLaunchKernelGGL(k_mean_std, dim3(1), dim3(64), 0, as_stream(stream), ns, h->p.nin, X,
-                     h->p.in_mean, h->p.in_std);
+  hipStream_t s = as_stream(stream);
+  const int w = h->p.nin;
+  const int nb = (int)std::min<long>(kStatBlocks, ns);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_col_partial, dim3(nb), dim3(256), 0, s, ns, w, pass, X, h->p.in_mean,
+                       h->p.statpart);
+    hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(64), 0, s, nb, ns, w, pass, h->p.statpart,
+                       h->p.in_mean, h->p.in_std);
+  }
   BDF_HIP_TRY(hipGetLastError());
   return 0;
 }
