@@ -246,11 +246,12 @@ struct TpcLU {
       const T d = A[K][K];
       const bool z = (d == T(0));
       if (z && !info) info = K + 1;
+      // a zero pivot leaves the column as it is: rinv is then exactly 1
       const T rinv = T(1) / (z ? T(1) : d);
       A[K][K] = rinv;
 #pragma unroll
       for (int i = K + 1; i < NP; ++i) {
-        const T l = z ? A[i][K] : A[i][K] * rinv;
+        const T l = A[i][K] * rinv;
         A[i][K] = l;
 #pragma unroll
         for (int j = K + 1; j < NP; ++j) A[i][j] = fma(-l, A[K][j], A[i][j]);
