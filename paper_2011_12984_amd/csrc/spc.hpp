@@ -30,14 +30,72 @@ struct SegOf {
 template <typename T>
 __device__ __forceinline__ T sabs(T v) { return v < T(0) ? -v : v; }
 
-template <int SEG, typename T>
-__device__ __forceinline__ T seg_max(T v) {
-#pragma unroll
-  for (int off = SEG / 2; off >= 1; off >>= 1) {
-    T o = __shfl_xor(v, off, SEG);
-    v = o > v ? o : v;
+// The value x holds in the lane paired with this one at level L of a
+// butterfly over aligned groups of lanes: L = 0 and 1 pair lanes i ^ 1 and
+// i ^ 2 (DPP quad permutes), L = 2 and 3 mirror 8- and 16-lane groups
+// (i <-> 7 - i, i <-> 15 - i), L = 4 and 5 pair i ^ 16 and i ^ 32
+// (v_permlane16/32_swap).  All are VALU lane moves, without the LDS-crossbar
+// round trip of a shuffle.  After levels 0..L, a commutative and associative
+// combine has reduced every aligned group of 2^(L+1) lanes, and every lane of
+// the group holds the same bits.  The lanes of a group must be active.
+template <int L>
+__device__ __forceinline__ int lane_pair(int x) {
+  if constexpr (L == 0) {
+    return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+  } else if constexpr (L == 1) {
+    return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+  } else if constexpr (L == 2) {
+    return __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);   // row_half_mirror
+  } else if constexpr (L == 3) {
+    return __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false);   // row_mirror
+  } else if constexpr (L == 4) {
+    // [0]: the even 16-lane rows' values in every row, [1]: the odd rows'
+    const auto e = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (threadIdx.x & 16) ? e[0] : e[1];
+  } else {
+    // [0]: the lower 32 lanes' values in both halves, [1]: the upper ones'
+    const auto e = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (threadIdx.x & 32) ? e[0] : e[1];
   }
-  return v;
+}
+
+template <int L, typename T>
+__device__ __forceinline__ T lane_pair_t(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, lane_pair<L>(__builtin_bit_cast(int, v)));
+  } else {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)lane_pair<L>((int)(unsigned)b);
+    const unsigned hi = (unsigned)lane_pair<L>((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
+}
+
+template <int SEG, typename T, int L = 0>
+__device__ __forceinline__ T seg_max(T v) {
+  if constexpr ((2 << L) <= SEG) {
+    const T o = lane_pair_t<L>(v);
+    return seg_max<SEG, T, L + 1>(o > v ? o : v);
+  } else {
+    return v;
+  }
+}
+
+// Arg-max over the segment of (v, smallest key on ties); bl carries the
+// winning lane.  The order is total, so the winner does not depend on the
+// pairing.
+template <int SEG, typename T, int L = 0>
+__device__ __forceinline__ void seg_argmax(T& v, int& key, int& bl) {
+  if constexpr ((2 << L) <= SEG) {
+    const T ov = lane_pair_t<L>(v);
+    const int ok = lane_pair<L>(key);
+    const int ol = lane_pair<L>(bl);
+    const bool take = (ov > v) || (ov == v && ok < key);
+    v = take ? ov : v;
+    key = take ? ok : key;
+    bl = take ? ol : bl;
+    seg_argmax<SEG, T, L + 1>(v, key, bl);
+  }
 }
 
 template <int SEG, typename T>
@@ -99,16 +157,7 @@ struct SpcLU {
           if (!(v == v)) v = T(__builtin_inf());
           int key = done ? 0x7fffffff : pos;
           int bl = r;
-#pragma unroll
-          for (int off = SEG / 2; off >= 1; off >>= 1) {
-            const T ov = __shfl_xor(v, off, SEG);
-            const int ok = __shfl_xor(key, off, SEG);
-            const int ol = __shfl_xor(bl, off, SEG);
-            const bool take = (ov > v) || (ov == v && ok < key);
-            v = take ? ov : v;
-            key = take ? ok : key;
-            bl = take ? ol : bl;
-          }
+          seg_argmax<SEG>(v, key, bl);
           if (r == k) piv = key;
           if (r == bl) {
             prow[kk] = row[kk];
