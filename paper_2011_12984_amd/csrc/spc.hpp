@@ -98,6 +98,32 @@ __device__ __forceinline__ void seg_argmax(T& v, int& key, int& bl) {
   }
 }
 
+template <typename T>
+__device__ __forceinline__ T readlane_t(T v, int lane) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+  } else {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
+}
+
+// val from lane src of this lane's segment (src the same for every lane of
+// the segment).  A whole-wave segment reads it with v_readlane, a short VALU
+// latency on the serial chains of the triangular solves (such kernels run at
+// one wave per SIMD); smaller segments, whose kernels keep more waves per
+// SIMD to cover the latency, use one crossbar shuffle.
+template <int SEG, typename T>
+__device__ __forceinline__ T seg_bcast(T val, int seg_base, int src) {
+  if constexpr (SEG == 64) {
+    return readlane_t(val, __builtin_amdgcn_readfirstlane(src) & 63);
+  } else {
+    return __shfl(val, seg_base + src, 64);
+  }
+}
+
 template <int SEG, typename T>
 __device__ __forceinline__ T seg_sum(T v) {
 #pragma unroll
@@ -205,7 +231,7 @@ struct SpcLU {
         for (int kk = 0; kk < CH; ++kk) {
           const int k = c * CH + kk;
           const int src = wl ? wl[k] : k;
-          const T yk = __shfl(val, seg_base + src, 64);
+          const T yk = seg_bcast<SEG>(val, seg_base, src);
           if (pos > k) val = fma(-row[kk], yk, val);
         }
       }
@@ -220,7 +246,7 @@ struct SpcLU {
           const int k = c * CH + kk;
           if (pos == k) val = val / row[kk];
           const int src = wl ? wl[k] : k;
-          const T xk = __shfl(val, seg_base + src, 64);
+          const T xk = seg_bcast<SEG>(val, seg_base, src);
           if (pos < k) val = fma(-row[kk], xk, val);
           if (r == k) x = xk;
         }
