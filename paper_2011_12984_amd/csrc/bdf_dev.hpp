@@ -193,13 +193,24 @@ __global__ void __launch_bounds__(256) k_control(Ctrl* C, int want, const double
   __syncthreads();
   if (threadIdx.x < K) tot[threadIdx.x] = sh[threadIdx.x] + sh[K + threadIdx.x] +
                                           sh[2 * K + threadIdx.x] + sh[3 * K + threadIdx.x];
+  // the controller is serial scalar code with many dependent accesses to the
+  // control block: it runs on a copy in LDS, copied in and out by the block
+  static_assert(sizeof(Ctrl) % sizeof(long) == 0, "Ctrl is copied in 8-byte words");
+  constexpr int kWords = (int)(sizeof(Ctrl) / sizeof(long));
+  __shared__ long cw[kWords];
+  const long* cg = reinterpret_cast<const long*>(C);
+  for (int t = threadIdx.x; t < kWords; t += blockDim.x) cw[t] = cg[t];
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (WHICH == 0) after_init1(C, tot);
-    else if (WHICH == 1) after_init2(C, tot);
-    else if (WHICH == 2) after_newton_all(C, tot);
-    else after_accept(C, tot);
+    Ctrl* L = reinterpret_cast<Ctrl*>(cw);
+    if (WHICH == 0) after_init1(L, tot);
+    else if (WHICH == 1) after_init2(L, tot);
+    else if (WHICH == 2) after_newton_all(L, tot);
+    else after_accept(L, tot);
   }
+  __syncthreads();
+  long* cgw = reinterpret_cast<long*>(C);
+  for (int t = threadIdx.x; t < kWords; t += blockDim.x) cgw[t] = cw[t];
 }
 
 // ===========================================================================
