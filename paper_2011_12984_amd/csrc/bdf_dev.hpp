@@ -879,11 +879,12 @@ struct Spc {
     }
   }
 
+  template <int NC>
   __device__ static __forceinline__ void jac_row(const NetDev& nd, const double* kap,
                                                  const float* St, const double* ys, int i,
-                                                 double (&J)[SEG]) {
+                                                 double (&J)[NC]) {
 #pragma unroll
-    for (int a = 0; a < SEG; ++a) {
+    for (int a = 0; a < NC; ++a) {
       double acc = 0.0;
       if (a < nd.n) {
         const int e0 = nd.jst[a], e1 = nd.jst[a + 1];
@@ -1046,7 +1047,8 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_predict(BdfDev D) {
 // kernel); a cell switches to FP64 LU for the rest of the attempt when X r
 // is not finite, or from the second iteration on when its correction norm
 // does not fall below 0.9 times the previous one.
-template <int SEG, int LS>
+// NC: columns held per lane (n rounded up to a multiple of 8, at most SEG).
+template <int SEG, int LS, int NC = SEG>
 __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, double* lds) {
   Ctrl* C = D.C;
   const ClassDev& K = D.k;
@@ -1078,26 +1080,26 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
     w = 1.0 / (D.rtol * fabs(K.z[0][id]) + D.atol);
   }
   // M = I - gamma J(z(0)[0]), row i in this lane (identity rows past n)
-  double Mrow[SEG];
+  double Mrow[NC];
   auto assemble = [&]() {
     __builtin_amdgcn_wave_barrier();
     sh.ys[threadIdx.x] = zp0;
     wave_sync_lds();
     if (act)
-      Spc<SEG>::jac_row(nd, kap, St, sh.ys + sb, i, Mrow);
+      Spc<SEG>::template jac_row<NC>(nd, kap, St, sh.ys + sb, i, Mrow);
     else
 #pragma unroll
-      for (int j = 0; j < SEG; ++j) Mrow[j] = 0.0;
+      for (int j = 0; j < NC; ++j) Mrow[j] = 0.0;
 #pragma unroll
-    for (int j = 0; j < SEG; ++j) Mrow[j] = (i == j ? 1.0 : 0.0) - gamma * Mrow[j];
+    for (int j = 0; j < NC; ++j) Mrow[j] = (i == j ? 1.0 : 0.0) - gamma * Mrow[j];
     if (!row)
 #pragma unroll
-      for (int j = 0; j < SEG; ++j) Mrow[j] = (i == j ? 1.0 : 0.0);
+      for (int j = 0; j < NC; ++j) Mrow[j] = (i == j ? 1.0 : 0.0);
   };
   const int nn = act ? n : 0;
   int pos = i, piv = i, info = 0;
   // LS 1 state
-  float L[LS == 1 ? SEG : 1];
+  float L[LS == 1 ? NC : 1];
   int pos32 = i, piv32 = i;
   bool fp64 = LS == 0;
   double mnorm = 0.0;
@@ -1107,37 +1109,37 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   double dcprev = 0.0;
   if constexpr (LS == 0) {
     assemble();
-    info = SpcLU<SEG, double>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+    info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
     factored = true;
   } else if constexpr (LS == 1) {
     assemble();
 #pragma unroll
-    for (int j = 0; j < SEG; ++j) L[j] = (float)Mrow[j];
+    for (int j = 0; j < NC; ++j) L[j] = (float)Mrow[j];
     const int inf32 =
-        SpcLU<SEG, float>::factor(L, i, nn, pos32, piv32, sh.prow32 + sb, sh.wl32 + sb);
+        SpcLU<SEG, float, NC>::factor(L, i, nn, pos32, piv32, sh.prow32 + sb, sh.wl32 + sb);
     double rs = 0.0;
 #pragma unroll
-    for (int j = 0; j < SEG; ++j) rs += fabs(Mrow[j]);
+    for (int j = 0; j < NC; ++j) rs += fabs(Mrow[j]);
     mnorm = seg_max<SEG>(rs);
     if (inf32) {
       fp64 = true;
-      info = SpcLU<SEG, double>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+      info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
     }
   } else {
     mode = (act && !C->force_lu) ? 2 : 4;
     if (mode == 4) {
       assemble();
-      info = SpcLU<SEG, double>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+      info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
       factored = true;
     }
   }
-  float Xrow[LS == 2 ? SEG : 1];
+  float Xrow[LS == 2 ? NC : 1];
   if constexpr (LS == 2) {
 #pragma unroll
-    for (int j = 0; j < SEG; ++j)
+    for (int j = 0; j < NC; ++j)
       Xrow[j] = K.X[(row ? c * (long)n * n + (long)i * n : 0) + (j < n ? j : 0)];
 #pragma unroll
-    for (int j = 0; j < SEG; ++j) Xrow[j] = (mode == 2 && row && j < n) ? Xrow[j] : 0.0f;
+    for (int j = 0; j < NC; ++j) Xrow[j] = (mode == 2 && row && j < n) ? Xrow[j] : 0.0f;
   }
   double red[kRedNewton];
 #pragma unroll
@@ -1155,18 +1157,18 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
     int sweeps = 0, fb = 0;
     double lp_solves = 0.0, lp_fb = 0.0;
     if constexpr (LS == 0) {
-      del = SpcLU<SEG, double>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
+      del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
     } else if constexpr (LS == 1) {
       bool ok = false;
       if (!fp64) {
-        double x = (double)SpcLU<SEG, float>::solve(L, i, seg_base, nn, pos32, sh.wl32 + sb,
+        double x = (double)SpcLU<SEG, float, NC>::solve(L, i, seg_base, nn, pos32, sh.wl32 + sb,
                                                     (float)r);
         const double eps64 = 2.220446049250313e-16;
         double dprv = 0.0;
         for (int it = 0; it <= K.refine_max_it; ++it) {
           double res = r;
 #pragma unroll
-          for (int j = 0; j < SEG; ++j) res = fma(-Mrow[j], __shfl(x, seg_base + j, 64), res);
+          for (int j = 0; j < NC; ++j) res = fma(-Mrow[j], __shfl(x, seg_base + j, 64), res);
           const double rn = seg_max<SEG>(fabs(res));
           const double xn = seg_max<SEG>(fabs(x));
           if (!(rn == rn) || !(xn == xn)) break;
@@ -1175,7 +1177,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
             break;
           }
           if (it == K.refine_max_it) break;
-          const double d = (double)SpcLU<SEG, float>::solve(L, i, seg_base, nn, pos32,
+          const double d = (double)SpcLU<SEG, float, NC>::solve(L, i, seg_base, nn, pos32,
                                                             sh.wl32 + sb, (float)res);
           x += d;
           const double dn = seg_max<SEG>(fabs(d));
@@ -1187,16 +1189,16 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
         if (!ok) {
           fb = 1;
           fp64 = true;
-          info = SpcLU<SEG, double>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+          info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
         }
       }
-      if (!ok) del = SpcLU<SEG, double>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
+      if (!ok) del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
     } else {
       if (mode == 2) {
         // correction = X r with row i of the cell's approximate inverse
         double sx = 0.0;
 #pragma unroll
-        for (int j = 0; j < SEG; ++j) sx = fma((double)Xrow[j], __shfl(r, seg_base + j, 64), sx);
+        for (int j = 0; j < NC; ++j) sx = fma((double)Xrow[j], __shfl(r, seg_base + j, 64), sx);
         del = row ? sx : 0.0;
         const double bad = seg_max<SEG>(row && !(fabs(del) <= 1.79e308) ? 1.0 : 0.0);
         lp_solves = act ? 1.0 : 0.0;
@@ -1205,10 +1207,10 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
       if (mode != 2) {
         if (!factored) {
           assemble();
-          info = SpcLU<SEG, double>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+          info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
           factored = true;
         }
-        del = SpcLU<SEG, double>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
+        del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
         if (mode == 3) {
           lp_fb = 1.0;
           mode = 4;
@@ -1247,11 +1249,11 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   block_partials<kRedNewton>(D, (unsigned int)(K.blk0 + blk), red, sh.red);
 }
 
-template <int SEG, int LS>
+template <int SEG, int LS, int NC = SEG>
 __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
   extern __shared__ double lds[];
   if (D.C->phase != PH_PREDICT) return;
-  spc_newton_body<SEG, LS>(D, blockIdx.x, lds);
+  spc_newton_body<SEG, LS, NC>(D, blockIdx.x, lds);
 }
 
 __host__ __device__ inline size_t spc_accept_lds() {

@@ -1,5 +1,6 @@
 // Segment-per-cell instantiations of the BDF step kernels (blocks of 13 to
-// 64 species in segments of 16, 32 or 64 lanes).
+// 64 species in segments of 16, 32 or 64 lanes; the Newton kernel also by
+// the row width each lane holds).
 #include "bdf_dev.hpp"
 
 namespace bdfgpu {
@@ -13,6 +14,32 @@ static void raise_lds(KF* kern, size_t lds, size_t& raised) {
     raised = lds;
 }
 
+template <int SEG, int LS, int NC>
+static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
+  static size_t raised = 65536;
+  raise_lds(&k_spc_newton<SEG, LS, NC>, lds, raised);
+  hipLaunchKernelGGL((k_spc_newton<SEG, LS, NC>), g, b, lds, s, D);
+}
+
+// Row width of the Newton kernel: n rounded up to a multiple of 8, within
+// the widths instantiated for the segment.
+template <int SEG, int LS>
+static void newton_nc(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
+  const int nc = (D.k.n + 7) / 8 * 8;
+  if constexpr (SEG == 16) {
+    if (nc <= 8) return go_newton<16, LS, 8>(D, g, b, lds, s);
+    return go_newton<16, LS, 16>(D, g, b, lds, s);
+  } else if constexpr (SEG == 32) {
+    if (nc <= 24) return go_newton<32, LS, 24>(D, g, b, lds, s);
+    return go_newton<32, LS, 32>(D, g, b, lds, s);
+  } else {
+    if (nc <= 40) return go_newton<64, LS, 40>(D, g, b, lds, s);
+    if (nc <= 48) return go_newton<64, LS, 48>(D, g, b, lds, s);
+    if (nc <= 56) return go_newton<64, LS, 56>(D, g, b, lds, s);
+    return go_newton<64, LS, 64>(D, g, b, lds, s);
+  }
+}
+
 template <int SEG>
 static void spc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s) {
   const dim3 g(grid), b(kCellThreads);
@@ -21,19 +48,12 @@ static void spc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStr
     case 0: hipLaunchKernelGGL(k_spc_init1<SEG>, g, b, lds, s, D); break;
     case 1: hipLaunchKernelGGL(k_spc_init2<SEG>, g, b, lds, s, D); break;
     case 2:
-      if (ls == 1) {
-        static size_t r1 = 65536;
-        raise_lds(&k_spc_newton<SEG, 1>, lds, r1);
-        hipLaunchKernelGGL((k_spc_newton<SEG, 1>), g, b, lds, s, D);
-      } else if (ls == 2) {
-        static size_t r2 = 65536;
-        raise_lds(&k_spc_newton<SEG, 2>, lds, r2);
-        hipLaunchKernelGGL((k_spc_newton<SEG, 2>), g, b, lds, s, D);
-      } else {
-        static size_t r0 = 65536;
-        raise_lds(&k_spc_newton<SEG, 0>, lds, r0);
-        hipLaunchKernelGGL((k_spc_newton<SEG, 0>), g, b, lds, s, D);
-      }
+      if (ls == 1)
+        newton_nc<SEG, 1>(D, g, b, lds, s);
+      else if (ls == 2)
+        newton_nc<SEG, 2>(D, g, b, lds, s);
+      else
+        newton_nc<SEG, 0>(D, g, b, lds, s);
       break;
     case 4: hipLaunchKernelGGL(k_spc_predict<SEG>, g, b, lds, s, D); break;
     default: hipLaunchKernelGGL(k_spc_accept<SEG>, g, b, spc_accept_lds(), s, D); break;

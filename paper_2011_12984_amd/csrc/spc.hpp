@@ -131,29 +131,33 @@ __device__ __forceinline__ T seg_sum(T v) {
   return v;
 }
 
-template <int SEG, typename T>
+// NC: columns each lane holds (a multiple of CH, at most SEG): blocks of n
+// <= NC rows use NC columns, and the lanes of the segment past NC hold no
+// row and never pivot.
+template <int SEG, typename T, int NC = SEG>
 struct SpcLU {
   static constexpr int CH = SEG < 8 ? SEG : 8;
-  static constexpr int NCH = SEG / CH;
+  static constexpr int NCH = NC / CH;
+  static_assert(NC % CH == 0 && NC <= SEG, "row width");
 
-  __device__ static __forceinline__ void rotl(T (&row)[SEG]) {
+  __device__ static __forceinline__ void rotl(T (&row)[NC]) {
     if (NCH == 1) return;
     T tmp[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) tmp[c] = row[c];
 #pragma unroll
-    for (int j = 0; j < SEG - CH; ++j) row[j] = row[j + CH];
+    for (int j = 0; j < NC - CH; ++j) row[j] = row[j + CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) row[SEG - CH + c] = tmp[c];
+    for (int c = 0; c < CH; ++c) row[NC - CH + c] = tmp[c];
   }
 
-  __device__ static __forceinline__ void rotr(T (&row)[SEG]) {
+  __device__ static __forceinline__ void rotr(T (&row)[NC]) {
     if (NCH == 1) return;
     T tmp[CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) tmp[c] = row[SEG - CH + c];
+    for (int c = 0; c < CH; ++c) tmp[c] = row[NC - CH + c];
 #pragma unroll
-    for (int j = SEG - 1; j >= CH; --j) row[j] = row[j - CH];
+    for (int j = NC - 1; j >= CH; --j) row[j] = row[j - CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) row[c] = tmp[c];
   }
@@ -164,16 +168,16 @@ struct SpcLU {
   // row[] holds this lane's row of L\U in column order, pos its position in
   // the permuted matrix, piv the LAPACK pivot of step k == r.  Returns info
   // (1-based first exactly-zero pivot, 0 if none).
-  __device__ static __forceinline__ int factor(T (&row)[SEG], int r, int n, int& pos, int& piv, T* prow,
+  __device__ static __forceinline__ int factor(T (&row)[NC], int r, int n, int& pos, int& piv, T* prow,
                                int* wl) {
     pos = r;
     piv = r;
-    bool done = false;
+    bool done = r >= NC;
     int info = 0;
     const int nch = (n + CH - 1) / CH;
     for (int c = 0; c < NCH; ++c) {
       if (c < nch) {
-        const int lim = SEG - c * CH;   // rotated columns >= lim hold L of earlier chunks
+        const int lim = NC - c * CH;    // rotated columns >= lim hold L of earlier chunks
 #pragma unroll
         for (int kk = 0; kk < CH; ++kk) {
           const int k = c * CH + kk;
@@ -188,7 +192,7 @@ struct SpcLU {
           if (r == bl) {
             prow[kk] = row[kk];
 #pragma unroll
-            for (int j = kk + 1; j < SEG; ++j) prow[j] = j < lim ? row[j] : T(0);
+            for (int j = kk + 1; j < NC; ++j) prow[j] = j < lim ? row[j] : T(0);
             wl[k] = bl;
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -206,7 +210,7 @@ struct SpcLU {
             const T l = row[kk] / d;
             row[kk] = l;
 #pragma unroll
-            for (int j = kk + 1; j < SEG; ++j) row[j] = fma(-l, prow[j], row[j]);
+            for (int j = kk + 1; j < NC; ++j) row[j] = fma(-l, prow[j], row[j]);
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
@@ -222,7 +226,7 @@ struct SpcLU {
   // factors already in position order (lane r holds position r).  `val` is
   // this lane's right-hand-side entry, already permuted in the second case.
   // Returns component r of the solution.  row[] is left unchanged.
-  __device__ static __forceinline__ T solve(T (&row)[SEG], int r, int seg_base, int n, int pos, const int* wl,
+  __device__ static __forceinline__ T solve(T (&row)[NC], int r, int seg_base, int n, int pos, const int* wl,
                             T val) {
     const int nch = (n + CH - 1) / CH;
     for (int c = 0; c < NCH; ++c) {
@@ -257,7 +261,7 @@ struct SpcLU {
 
   // Solve with factors stored in LAPACK layout (lane r holds the row at
   // position r) and LAPACK pivots piv[0..n-1] in global memory.
-  __device__ static __forceinline__ T solve_stored(T (&row)[SEG], int r, int seg_base, const int* piv, int n,
+  __device__ static __forceinline__ T solve_stored(T (&row)[NC], int r, int seg_base, const int* piv, int n,
                                    T val) {
     for (int k = 0; k < n; ++k) {
       const int p = piv[k];
