@@ -908,7 +908,20 @@ struct SpcShared {
   int wl[kCellThreads];
   int wl32[kCellThreads];
   double red[(kCellThreads / 64) * kRedNewton];
+  double wsum[(kCellThreads / 64) * kRedNewton];   // per-wave Newton sums
 };
+
+// v summed over the wave (every lane gets the same bits) and added by lane 0
+// to *s; all 64 lanes must be active.
+__device__ __forceinline__ void wave_add(double v, double* s) {
+  v += lane_pair_t<0>(v);
+  v += lane_pair_t<1>(v);
+  v += lane_pair_t<2>(v);
+  v += lane_pair_t<3>(v);
+  v += lane_pair_t<4>(v);
+  v += lane_pair_t<5>(v);
+  if ((threadIdx.x & 63) == 0) *s += v;
+}
 
 // Dynamic LDS of the SPC kernels: the shared scratch, then the rates of the
 // block's cells (CPB x R, FP64), then the stoichiometry (R x SEG; its entries
@@ -1068,6 +1081,17 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   float* St;
   spc_stage<SEG>(K, blk, lds, shp, lk, St);
   SpcShared& sh = *shp;
+  // Each iteration's norms: with the FP32 and learned solvers they are
+  // summed over the wave at once and kept in LDS (the iteration number is
+  // not a compile-time index, and per-lane accumulators for every iteration
+  // cost registers those kernels need to run two or three waves per SIMD);
+  // the FP64 kernel, which gains no wave from that, keeps per-lane sums.
+  constexpr bool kLdsSums = LS != 0;
+  double* wsum = sh.wsum + (threadIdx.x >> 6) * kRedNewton;
+  if (kLdsSums && lane < kRedNewton) wsum[lane] = 0.0;
+  double red[kRedNewton];
+#pragma unroll
+  for (int k = 0; k < kRedNewton; ++k) red[k] = 0.0;
   const double* kap = lk + cb * K.R;
   const double gamma = C->gamma;
   const int maxcor = C->maxcor;
@@ -1141,10 +1165,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
 #pragma unroll
     for (int j = 0; j < NC; ++j) Xrow[j] = (mode == 2 && row && j < n) ? Xrow[j] : 0.0f;
   }
-  double red[kRedNewton];
-#pragma unroll
-  for (int k = 0; k < kRedNewton; ++k) red[k] = 0.0;
-  if (LS == 1 && act && i == 0 && fp64) red[4] = 1.0;   // FP32 factor singular at setup
+  if (LS == 1 && fp64 && act && i == 0) wsum[4] = 1.0;   // FP32 factor singular at setup
   double y = zp0;
   for (int m = 0; m < maxcor; ++m) {
     __builtin_amdgcn_wave_barrier();
@@ -1231,26 +1252,51 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
       neg = ng ? 1.0 : 0.0;
     }
     const bool lead = act && i == 0;
+    if constexpr (kLdsSums) {
+      double* ws = wsum + kRedPerIter * m;
+      wave_add(sd, ws + 0);
+      wave_add(sa, ws + 1);
+      wave_add(neg, ws + 2);
+      if constexpr (LS == 1) {
+        wave_add(lead ? (double)sweeps : 0.0, ws + 3);
+        wave_add(lead ? (double)fb : 0.0, ws + 4);
+      }
+      if constexpr (LS == 2) {
+        wave_add(lead ? lp_solves : 0.0, ws + 5);
+        wave_add(lead ? lp_fb : 0.0, ws + 6);
+      }
+    } else {
 #pragma unroll
-    for (int mm = 0; mm < kMaxCor; ++mm) {
-      const bool hit = (mm == m);
-      red[kRedPerIter * mm + 0] += hit ? sd : 0.0;
-      red[kRedPerIter * mm + 1] += hit ? sa : 0.0;
-      red[kRedPerIter * mm + 2] += hit ? neg : 0.0;
-      red[kRedPerIter * mm + 3] += (hit && lead) ? (double)sweeps : 0.0;
-      red[kRedPerIter * mm + 4] += (hit && lead) ? (double)fb : 0.0;
-      red[kRedPerIter * mm + 5] += (hit && lead) ? lp_solves : 0.0;
-      red[kRedPerIter * mm + 6] += (hit && lead) ? lp_fb : 0.0;
+      for (int mm = 0; mm < kMaxCor; ++mm) {
+        const bool hit = (mm == m);
+        red[kRedPerIter * mm + 0] += hit ? sd : 0.0;
+        red[kRedPerIter * mm + 1] += hit ? sa : 0.0;
+        red[kRedPerIter * mm + 2] += hit ? neg : 0.0;
+      }
     }
+  }
+  if constexpr (kLdsSums) {
+#pragma unroll
+    for (int k = 0; k < kRedNewton; ++k) red[k] = lane == 0 ? wsum[k] : 0.0;
   }
   // a singular FP64 factorisation fails the attempt (LS 1: only the FP64
   // fallback can be singular; the FP32 factor then falls back)
-  if (act && i == 0) red[7] = info ? 1.0 : 0.0;
+  red[7] = (act && i == 0 && info) ? 1.0 : 0.0;
   block_partials<kRedNewton>(D, (unsigned int)(K.blk0 + blk), red, sh.red);
 }
 
 template <int SEG, int LS, int NC = SEG>
 __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
+  extern __shared__ double lds[];
+  if (D.C->phase != PH_PREDICT) return;
+  spc_newton_body<SEG, LS, NC>(D, blockIdx.x, lds);
+}
+
+// The same kernel asked to fit two waves per SIMD (256 registers), for
+// instantiations that need only a few registers more than that.
+template <int SEG, int LS, int NC = SEG>
+__global__ void __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(2)))
+k_spc_newton_w2(BdfDev D) {
   extern __shared__ double lds[];
   if (D.C->phase != PH_PREDICT) return;
   spc_newton_body<SEG, LS, NC>(D, blockIdx.x, lds);
