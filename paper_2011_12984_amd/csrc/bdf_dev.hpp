@@ -77,7 +77,7 @@ constexpr int kRedNewton = kRedPerIter * kMaxCor;  // fused Newton kernels
 constexpr int kRedMax = kRedNewton;
 constexpr int kRedGroup = 256;                     // blocks per first-level group
 constexpr int kCellThreads = 256;                  // SPC blocks
-constexpr int kTpcThreads = 128;                   // TPC blocks
+constexpr int kTpcThreads = 64;                    // TPC blocks (one wave)
 
 // Sum K values over the 64 lanes of a wave with K - 1 + (6 - log2 K)
 // exchanges instead of 6 K: each exchange step halves the number of values
@@ -227,6 +227,12 @@ __global__ void __launch_bounds__(256) k_control(Ctrl* C, int want, const double
 // skipped altogether when no lane of the wave pivots on that row.  The
 // diagonal holds reciprocal pivots.  The recursion over k keeps every
 // register index a compile-time constant.
+// Marks a wave-uniform branch whose body must not be turned into selects:
+// row exchanges are rare, and executing their selects unconditionally (as
+// the compiler otherwise does for short bodies) costs every wave the full
+// exchange code of every row pair.
+__device__ __forceinline__ void keep_branch() { asm volatile(""); }
+
 template <int NP, typename T>
 struct TpcLU {
   template <int K>
@@ -245,6 +251,7 @@ struct TpcLU {
 #pragma unroll
       for (int i = K + 1; i < NP; ++i) {
         if (__any(p == i)) {
+          keep_branch();
           const bool sw = (p == i);
 #pragma unroll
           for (int j = K; j < NP; ++j) {
@@ -286,6 +293,7 @@ struct TpcLU {
 #pragma unroll
       for (int i = k + 1; i < NP; ++i) {
         if (__any(p == i)) {
+          keep_branch();
           const bool sw = (p == i);
           const T t = b[k];
           b[k] = sw ? b[i] : t;
