@@ -78,6 +78,7 @@ constexpr int kRedMax = kRedNewton;
 constexpr int kRedGroup = 256;                     // blocks per first-level group
 constexpr int kCellThreads = 256;                  // SPC blocks
 constexpr int kTpcThreads = 64;                    // TPC blocks (one wave)
+constexpr int kAcceptChunk = 16;                  // species per chunk of the TPC history update
 
 // Sum K values over the 64 lanes of a wave with K - 1 + (6 - log2 K)
 // exchanges instead of 6 K: each exchange step halves the number of values
@@ -709,62 +710,111 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
 // order selection of this step needs it and written only when the next
 // step's does (the step after one with qwait == 2 is the only one that
 // reads it).
-template <int NP, int TB>
-__device__ __forceinline__ void tpc_accept_body(const BdfDev& D, long blk, double* lds) {
-  double* s_red = lds;
-  Ctrl* C = D.C;
+// History update of one cell at order Q (a compile-time constant, so the
+// loads, Pascal sums and stores carry no run-time order tests), CH species
+// at a time: each chunk's loads go out together, then its prediction,
+// correction and stores.  Chunks of 2..5 species hold fewer registers and
+// run more waves per SIMD, but at 10 species one chunk (all rows of the
+// history in flight) measured as fast or slightly faster, so kAcceptChunk
+// covers every thread-per-cell size.  Per element the operations, and the
+// order of the two norm sums over species, do not depend on CH.
+template <int NP, int TB, int Q, int CH>
+__device__ __forceinline__ void tpc_accept_q(const BdfDev& D, long c, const double* ysrc, double& szq,
+                                             double& sdd) {
+  const Ctrl* C = D.C;
   const ClassDev& K = D.k;
   const int n = K.n;
-  const long c = blk * TB + threadIdx.x;
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (c < K.ncells) {
-    const int q = C->q;
-    const double l0 = C->l[0];
-    const bool select = C->qwait == 1;
-    const bool raise = select && q < C->qmax;
-    const bool keep = C->qwait == 2;
-    double zs[kQmaxAll + 1][NP];
-    tpc_load_hist<NP>(K, C, c, n, q, zs);
-    double yv[NP];
-    tpc_load_vec<NP>(K.ys[C->m], c, n, yv);
-    double dp[NP];
-    if (raise) tpc_load_vec<NP>(K.dprev, c, n, dp);
-    double w[NP];
+  const double l0 = C->l[0];
+  const bool select = C->qwait == 1;
+  const bool raise = Q < kQmaxAll && select && Q < C->qmax;
+  const bool keep = C->qwait == 2;
+  double hs[Q + 1], lj[Q + 1];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) w[i] = i < n ? 1.0 / (D.rtol * fabs(zs[0][i]) + D.atol) : 0.0;
+  for (int j = 0; j <= Q; ++j) {
+    hs[j] = C->hs[j];
+    lj[j] = C->l[j];
+  }
+  const double craise = C->craise;
 #pragma unroll
-    for (int k = 1; k <= kQmaxAll; ++k)
+  for (int i0 = 0; i0 < NP; i0 += CH) {
+    double zs[Q + 1][CH], yv[CH], dp[CH];
 #pragma unroll
-      for (int j = kQmaxAll; j >= k; --j)
-        if (k <= q && j <= q)
+    for (int u = 0; u < CH; ++u) {
+      const int i = i0 + u;
+      const int ii = i < n ? i : n - 1;
+      const long id = Tpc<NP, TB>::idx(c, ii, n);
 #pragma unroll
-          for (int i = 0; i < NP; ++i) zs[j - 1][i] = zs[j - 1][i] + zs[j][i];
-    double szq = 0.0, sdd = 0.0;
+      for (int j = 0; j <= Q; ++j) {
+        const double v = i < NP ? K.z[j][id] : 0.0;
+        zs[j][u] = i < n ? v * hs[j] : 0.0;
+      }
+      const double y = i < NP ? ysrc[id] : 0.0;
+      yv[u] = i < n ? y : 0.0;
+    }
+    if (raise) {
 #pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      if (i < n) {
-        const long id = Tpc<NP>::idx(c, i, n);
-        const double yp = D.nonneg && yv[i] < 0.0 ? 0.0 : yv[i];
-        const double acor = (yp - zs[0][i]) / l0;
+      for (int u = 0; u < CH; ++u) {
+        const int i = i0 + u;
+        const double x = i < NP ? K.dprev[Tpc<NP, TB>::idx(c, i < n ? i : n - 1, n)] : 0.0;
+        dp[u] = i < n ? x : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = i0 + u;
+      if (i < NP && i < n) {
+        const double w = 1.0 / (D.rtol * fabs(zs[0][u]) + D.atol);
+        // Pascal triangle: z(0)[j] = sum_{k >= j} C(k, j) z[k]
+#pragma unroll
+        for (int k = 1; k <= Q; ++k)
+#pragma unroll
+          for (int j = Q; j >= k; --j) zs[j - 1][u] = zs[j - 1][u] + zs[j][u];
+        const long id = Tpc<NP, TB>::idx(c, i, n);
+        const double yp = D.nonneg && yv[u] < 0.0 ? 0.0 : yv[u];
+        const double acor = (yp - zs[0][u]) / l0;
         double znq = yp;
         K.z[0][id] = yp;   // z(0)[0] + l0 acor is the corrected solution itself
 #pragma unroll
-        for (int j = 1; j <= kQmaxAll; ++j) {
-          if (j <= q) {
-            const double zn = fma(C->l[j], acor, zs[j][i]);
-            K.z[j][id] = zn;
-            if (j == q) znq = zn;
+        for (int j = 1; j <= Q; ++j) {
+          const double zn = fma(lj[j], acor, zs[j][u]);
+          K.z[j][id] = zn;
+          if (j == Q) znq = zn;
+        }
+        if constexpr (Q < kQmaxAll) {
+          if (raise) {
+            K.z[Q + 1][id] = craise * acor;
+            const double b = (acor - dp[u]) * w;
+            sdd = fma(b, b, sdd);
           }
         }
-        if (raise) {
-          K.z[q + 1][id] = C->craise * acor;
-          const double b = (acor - dp[i]) * w[i];
-          sdd = fma(b, b, sdd);
-        }
         if (keep) K.dprev[id] = acor;
-        const double a = znq * w[i];
+        const double a = znq * w;
         szq = fma(a, a, szq);
       }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int NP, int TB>
+__device__ __forceinline__ void tpc_accept_body(const BdfDev& D, long blk, double* lds) {
+  constexpr int CH = kAcceptChunk < NP ? kAcceptChunk : NP;
+  double* s_red = lds;
+  const ClassDev& K = D.k;
+  const long c = blk * TB + threadIdx.x;
+  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (c < K.ncells) {
+    double szq = 0.0, sdd = 0.0;
+    // the iterate to accept (looked up here, once: indexing the pointer
+    // array inside the order-specialised bodies made the compiler copy the
+    // kernel arguments to scratch)
+    const double* ysrc = K.ys[D.C->m];
+    switch (D.C->q) {
+      case 1: tpc_accept_q<NP, TB, 1, CH>(D, c, ysrc, szq, sdd); break;
+      case 2: tpc_accept_q<NP, TB, 2, CH>(D, c, ysrc, szq, sdd); break;
+      case 3: tpc_accept_q<NP, TB, 3, CH>(D, c, ysrc, szq, sdd); break;
+      case 4: tpc_accept_q<NP, TB, 4, CH>(D, c, ysrc, szq, sdd); break;
+      default: tpc_accept_q<NP, TB, 5, CH>(D, c, ysrc, szq, sdd); break;
     }
     red[0] = szq;
     red[1] = sdd;
