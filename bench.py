@@ -29,7 +29,7 @@ MAXCOR = 3
 # HBM bytes per launch of the fused Newton kernel at 2^20 cells and order 5,
 # from FETCH_SIZE/WRITE_SIZE counter runs scaled by a plain copy kernel
 # (profiles/); None when the kernel has changed since the counters were taken
-MEASURED_TRAFFIC_BYTES = 925.6e6
+MEASURED_TRAFFIC_BYTES = 927.6e6
 
 
 def log(*a):
