@@ -273,12 +273,21 @@ def main():
     niters = s1["nniters"] - s0["nniters"]
 
     log("profiling the dominant kernel")
-    b.set_profiling(True)
-    ps0 = b.stats()
-    pdt, ptaken, _ = time_advance(b, prob.t_end, min(args.steps, 100), torch)
-    ps1 = b.stats()
-    kt = b.kernel_times()
-    b.set_profiling(False)
+    pb = b
+    if args.graph:
+        # launches inside a captured graph cannot be bracketed with events:
+        # time the same kernels on a stream-mode handle of the same workload
+        pb = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_STREAM, attempts_per_sync=16,
+                                linsol=G.LS_LU64, maxcor=MAXCOR, jit=not args.no_jit)
+        pb.advance(prob.t_end, args.warmup)
+    pb.set_profiling(True)
+    ps0 = pb.stats()
+    pdt, ptaken, _ = time_advance(pb, prob.t_end, min(args.steps, 100), torch)
+    ps1 = pb.stats()
+    kt = pb.kernel_times()
+    pb.set_profiling(False)
+    if pb is not b:
+        pb.close()
     p_ms, p_cnt = kt["newton"]
     p_att = ps1["nattempts"] - ps0["nattempts"]
     q1 = (ps1["hist_reads"] - ps0["hist_reads"]) / max(p_att, 1)   # mean q + 1
