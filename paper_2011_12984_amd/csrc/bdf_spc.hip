@@ -17,9 +17,10 @@ static void raise_lds(KF* kern, size_t lds, size_t& raised) {
 template <int SEG, int LS, int NC>
 static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
   static size_t raised = 65536;
-  // learned mode at 24 columns needs one register more than two waves per
-  // SIMD allow; the occupancy hint makes it fit without spilling
-  constexpr bool w2 = SEG == 32 && LS == 2 && NC == 24;
+  // learned mode at 24 columns and the FP32-refined solver at 48 columns
+  // need a few registers more than two waves per SIMD allow; the occupancy
+  // hint makes them fit without spilling
+  constexpr bool w2 = (SEG == 32 && LS == 2 && NC == 24) || (SEG == 64 && LS == 1 && NC == 48);
   if constexpr (w2) {
     raise_lds(&k_spc_newton_w2<SEG, LS, NC>, lds, raised);
     hipLaunchKernelGGL((k_spc_newton_w2<SEG, LS, NC>), g, b, lds, s, D);
