@@ -20,7 +20,7 @@ static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s
   // learned mode at 24 columns and the FP32-refined solver at 48 columns
   // need a few registers more than two waves per SIMD allow; the occupancy
   // hint makes them fit without spilling
-  constexpr bool w2 = (SEG == 32 && LS == 2 && NC == 24) || (SEG == 64 && LS == 1 && NC == 48);
+  constexpr bool w2 = (SEG == 32 && LS == 2 && NC == 24) || (SEG == 64 && LS == 1 && (NC == 48 || NC == 64));
   if constexpr (w2) {
     raise_lds(&k_spc_newton_w2<SEG, LS, NC>, lds, raised);
     hipLaunchKernelGGL((k_spc_newton_w2<SEG, LS, NC>), g, b, lds, s, D);

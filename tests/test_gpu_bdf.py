@@ -95,7 +95,8 @@ def compare_trajectory(orc, dev, G, p, **kw):
     * a flipped decision: both runs must be equally accurate against a
       tight-tolerance oracle run, and take a comparable number of steps."""
     lin = kw.pop("linsol", 0)
-    ob = orc.Bdf(p, linsol=lin)
+    rmi = kw.get("refine_max_it", 5)
+    ob = orc.Bdf(p, linsol=lin, refine_max_it=rmi)
     assert ob.integrate(p.t_end) == 0
     gb = gpu_bdf(G, p, dev, linsol=lin, **kw)
     t = gb.integrate(p.t_end)
@@ -140,6 +141,20 @@ def test_trajectory_uneven(orc, dev, G, launch, map_small, linsol):
     or FP32-refined LU."""
     compare_trajectory(orc, dev, G, W.uneven_batch(1 << 12, seed=9), launch=launch,
                        map_small=map_small, linsol=linsol)
+
+
+@pytest.mark.parametrize("launch", [0, 1])
+def test_trajectory_uneven_fp32_fallback_path(orc, dev, G, launch):
+    """One refinement sweep allowed: a block that needs a second one to pass
+    the FP64 residual test goes to FP64 LU for the rest of the attempt, so
+    the classes (4..64 species) run the FP64 fallback inside their
+    FP32-refined Newton kernels."""
+    p = W.uneven_batch(1 << 12, seed=9)
+    assert int(np.max(p.sizes)) == 64
+    ob, gb = compare_trajectory(orc, dev, G, p, launch=launch, linsol=1, refine_max_it=1)
+    st = gb.stats()
+    print("fallbacks", st["refine_fallbacks"], "sweeps", st["refine_sweeps"])
+    assert st["refine_fallbacks"] > 0
 
 
 def test_fused_launch_graph_bitwise_equal_to_stream(dev, G):
