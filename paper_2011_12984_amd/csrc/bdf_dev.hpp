@@ -1350,11 +1350,13 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
   spc_newton_body<SEG, LS, NC>(D, blockIdx.x, lds);
 }
 
-// The same kernel asked to fit two waves per SIMD (256 registers), for
-// instantiations that need only a few registers more than that.
-template <int SEG, int LS, int NC = SEG>
-__global__ void __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(2)))
-k_spc_newton_w2(BdfDev D) {
+// The same kernel asked to fit W waves per SIMD (512 / W registers), for
+// instantiations that need only a few registers more than that, or whose
+// excess belongs to a rarely taken path (the FP64 fallback of the
+// FP32-refined solver), around which the compiler places the spills.
+template <int SEG, int LS, int NC, int W>
+__global__ void __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(W)))
+k_spc_newton_w(BdfDev D) {
   extern __shared__ double lds[];
   if (D.C->phase != PH_PREDICT) return;
   spc_newton_body<SEG, LS, NC>(D, blockIdx.x, lds);

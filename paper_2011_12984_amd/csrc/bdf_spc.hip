@@ -14,16 +14,29 @@ static void raise_lds(KF* kern, size_t lds, size_t& raised) {
     raised = lds;
 }
 
+// Waves per SIMD asked of the segment Newton kernel (0: as many as its
+// registers allow).  Learned mode at 24 columns and the FP32-refined solver
+// at 48 and 64 columns need more registers than two waves allow, mostly for
+// paths that rarely run (the FP64 fallback); the hint makes them fit, with
+// spills around those paths.  The FP32-refined 16-, 24- and 32-column
+// kernels sit a few registers above four, three and three waves.
+template <int SEG, int LS, int NC>
+constexpr int newton_waves() {
+  if (SEG == 32 && LS == 2 && NC == 24) return 2;
+  if (SEG == 64 && LS == 1 && (NC == 48 || NC == 64)) return 2;
+  if (SEG == 32 && LS == 1 && NC == 24) return 3;
+  if (SEG == 32 && LS == 1 && NC == 32) return 3;
+  if (SEG == 16 && LS == 1 && NC == 16) return 4;
+  return 0;
+}
+
 template <int SEG, int LS, int NC>
 static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
   static size_t raised = 65536;
-  // learned mode at 24 columns and the FP32-refined solver at 48 columns
-  // need a few registers more than two waves per SIMD allow; the occupancy
-  // hint makes them fit without spilling
-  constexpr bool w2 = (SEG == 32 && LS == 2 && NC == 24) || (SEG == 64 && LS == 1 && (NC == 48 || NC == 64));
-  if constexpr (w2) {
-    raise_lds(&k_spc_newton_w2<SEG, LS, NC>, lds, raised);
-    hipLaunchKernelGGL((k_spc_newton_w2<SEG, LS, NC>), g, b, lds, s, D);
+  constexpr int w = newton_waves<SEG, LS, NC>();
+  if constexpr (w > 0) {
+    raise_lds(&k_spc_newton_w<SEG, LS, NC, w>, lds, raised);
+    hipLaunchKernelGGL((k_spc_newton_w<SEG, LS, NC, w>), g, b, lds, s, D);
   } else {
     raise_lds(&k_spc_newton<SEG, LS, NC>, lds, raised);
     hipLaunchKernelGGL((k_spc_newton<SEG, LS, NC>), g, b, lds, s, D);
