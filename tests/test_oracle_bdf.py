@@ -200,7 +200,7 @@ def test_learned_identity_network_falls_back_to_lu(orc):
         assert b.integrate(p.t_end) == 0
     st = bl.stats()
     assert st["lp_fallback_cells"] > 0 or st["lp_step_fallbacks"] > 0
-    # two valid step sequences differ by about the global error: judge both
+    # two valid step sequences differ by about the global error: compare both
     # against a tight-tolerance run, in units of the requested tolerance
     ref = bref.y()
     w = 1.0 / (p.rtol * np.abs(ref) + p.atol)
