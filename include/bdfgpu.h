@@ -181,9 +181,13 @@ typedef struct {
   int launch;             /* BDFGPU_LAUNCH_* */
   void* precond;          /* precond_handle* for BDFGPU_LS_LEARNED */
   int nonneg;             /* 1: each corrected solution is projected onto y >= 0
-                             before the error test (the constraint-mask
-                             operation of the N_Vector interface, Section 4.2);
-                             initial values must then be >= 0 */
+                             before the error test; the projection enters the
+                             correction, so the history stays consistent.  A
+                             project reading, not a method of the paper (its
+                             N_Vector constraint-mask operation only flags
+                             violations); it keeps bimolecular mass action
+                             from running away after a component turns
+                             negative.  Initial values must then be >= 0 */
   int map_small;          /* 0: classes of <= 12 species use one lane per cell
                              (block in registers); 1: a 16-lane segment per cell */
   int jit;                /* 1: bdf_create generates, for each one-lane-per-cell

@@ -69,7 +69,8 @@ class OrcOptions(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("qmax", C.c_int),
                 ("maxcor", C.c_int), ("h0", C.c_double), ("linsol", C.c_int),
                 ("refine_max_it", C.c_int), ("max_steps", C.c_long),
-                ("hmin", C.c_double), ("mlp", C.POINTER(OrcMLP)), ("nonneg", C.c_int)]
+                ("hmin", C.c_double), ("mlp", C.POINTER(OrcMLP)), ("nonneg", C.c_int),
+                ("fixed_step", C.c_int)]
 
 
 class OrcStats(C.Structure):
@@ -88,7 +89,9 @@ class OrcStats(C.Structure):
 class OrcScalars(C.Structure):
     _fields_ = [("t", C.c_double), ("h", C.c_double), ("err_last", C.c_double),
                 ("q", C.c_int), ("qwait", C.c_int), ("qprime_pending", C.c_int),
-                ("initialized", C.c_int), ("hu", C.c_double), ("qu", C.c_int)]
+                ("initialized", C.c_int), ("hu", C.c_double), ("qu", C.c_int),
+                ("err_qm1", C.c_double), ("err_qp1", C.c_double),
+                ("eta_proposed", C.c_double), ("q_proposed", C.c_int)]
 
 
 def _declare(L):
@@ -130,6 +133,7 @@ def _declare(L):
     L.orc_bdf_step.argtypes = [C.c_void_p, C.c_double]
     L.orc_bdf_integrate.restype = C.c_int
     L.orc_bdf_integrate.argtypes = [C.c_void_p, C.c_double]
+    L.orc_bdf_init.argtypes = [C.c_void_p, C.c_double]
     L.orc_bdf_get_y.argtypes = [C.c_void_p, dp]
     L.orc_bdf_get_stats.argtypes = [C.c_void_p, C.POINTER(OrcStats)]
     L.orc_bdf_get_scalars.argtypes = [C.c_void_p, C.POINTER(OrcScalars)]
@@ -418,7 +422,7 @@ class Bdf:
 
     def __init__(self, prob, rtol=None, atol=None, qmax=None, maxcor=3, h0=0.0,
                  linsol=LS_LU64, refine_max_it=5, max_steps=0, hmin=0.0,
-                 mlp: MLP | None = None, nonneg=None):
+                 mlp: MLP | None = None, nonneg=None, fixed_step=False):
         self._keep = []
         topo_n = np.array([nu.shape[1] for nu, _ in prob.topologies], np.int32)
         topo_R = np.array([nu.shape[0] for nu, _ in prob.topologies], np.int32)
@@ -441,7 +445,8 @@ class Bdf:
                                prob.qmax if qmax is None else qmax, maxcor, h0,
                                linsol, refine_max_it, max_steps, hmin,
                                C.pointer(mlp.s) if mlp is not None else None,
-                               int(prob.get("nonneg", False) if nonneg is None else nonneg))
+                               int(prob.get("nonneg", False) if nonneg is None else nonneg),
+                               int(bool(fixed_step)))
         self.h = lib().orc_bdf_create(C.byref(self.prob), C.byref(self.opts))
         self.N = lib().orc_bdf_N(self.h)
 
@@ -458,6 +463,10 @@ class Bdf:
 
     def integrate(self, t_end):
         return lib().orc_bdf_integrate(self.h, t_end)
+
+    def init(self, t_end):
+        """Starting step and history, as the first step computes them."""
+        lib().orc_bdf_init(self.h, t_end)
 
     def y(self):
         y = np.empty(self.N)

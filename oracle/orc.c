@@ -507,6 +507,8 @@ struct orc_bdf {
   double *X, *dcell_prev;
   double t, h, err_last, hu;
   int q, qwait, qu, initialized;
+  double err_qm1, err_qp1, eta_prop;
+  int q_prop;
   orc_stats st;
 };
 
@@ -585,6 +587,8 @@ orc_bdf* orc_bdf_create(const orc_problem* p, const orc_options* o) {
   b->dcell_prev = (double*)calloc((size_t)nc + 1, sizeof(double));
   if (o->linsol == ORC_LS_LEARNED) b->X = (double*)calloc(NM, sizeof(double));
   b->t = p->t0;
+  b->err_qm1 = b->err_qp1 = -1.0;
+  b->eta_prop = 1.0;
   memcpy(b->z[0], p->y0, sizeof(double) * (size_t)b->N);
   return b;
 }
@@ -853,9 +857,10 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
       continue;
     }
     if (b->o.nonneg) {
-      /* inequality constraints y >= 0 (the constraint-mask vector operation
-       * of the N_Vector interface): the corrected solution is projected onto
-       * the constraint before the error test; the projection enters the
+      /* y >= 0 by projection (a project reading: the paper states no such
+       * step, and its constraint-mask vector operation only flags
+       * violations): the corrected solution is projected onto the
+       * constraint before the error test; the projection enters the
        * correction, so the whole history stays consistent with it */
       int any = 0;
       for (long i = 0; i < N; ++i)
@@ -906,16 +911,26 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
     double etaq = 1.0 / (pow(BIAS_Q * err, 1.0 / (double)(q + 1)) + ADDON);
     double eta = etaq;
     int qnew = q;
+    b->err_qm1 = -1.0;
+    b->err_qp1 = -1.0;
+    if (b->o.fixed_step) {
+      memcpy(b->dprev, b->acor, sizeof(double) * (size_t)N);
+      b->eta_prop = 1.0;
+      b->q_prop = q;
+      return 0;
+    }
     if (b->qwait == 0) {
       b->qwait = 2;
       double etaqm1 = 0.0, etaqp1 = 0.0;
       if (q > 1) {
         double e = wrms(b, b->z[q]) * factorial(q - 1) / harmonic(q - 1);
+        b->err_qm1 = e;
         etaqm1 = 1.0 / (pow(BIAS_QM1 * e, 1.0 / (double)q) + ADDON);
       }
       if (q < b->o.qmax) {
         for (long i = 0; i < N; ++i) b->tmp[i] = b->acor[i] - b->dprev[i];
         double e = wrms(b, b->tmp) / ((double)(q + 2) * harmonic(q + 1) * harmonic(q + 1));
+        b->err_qp1 = e;
         etaqp1 = 1.0 / (pow(BIAS_QP1 * e, 1.0 / (double)(q + 2)) + ADDON);
       }
       if (etaq >= etaqm1 && etaq >= etaqp1) {
@@ -926,6 +941,8 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
         eta = etaqp1; qnew = q + 1;
       }
     }
+    b->eta_prop = eta;
+    b->q_prop = qnew;
     if (eta >= THRESH) {
       if (eta > ETA_MAX) eta = ETA_MAX;
       if (qnew == q + 1) {
@@ -963,6 +980,12 @@ void orc_bdf_get_scalars(const orc_bdf* b, orc_scalars* s) {
   s->t = b->t; s->h = b->h; s->err_last = b->err_last;
   s->q = b->q; s->qwait = b->qwait; s->qprime_pending = 0;
   s->initialized = b->initialized; s->hu = b->hu; s->qu = b->qu;
+  s->err_qm1 = b->err_qm1; s->err_qp1 = b->err_qp1;
+  s->eta_proposed = b->eta_prop; s->q_proposed = b->q_prop;
+}
+
+void orc_bdf_init(orc_bdf* b, double t_end) {
+  if (!b->initialized) initialize(b, t_end);
 }
 
 void orc_bdf_set_scalars(orc_bdf* b, const orc_scalars* s) {

@@ -115,6 +115,8 @@ typedef struct {
   double hmin;
   const orc_mlp* mlp;  /* learned mode */
   int nonneg;        /* 1: corrected solutions projected onto y >= 0 */
+  int fixed_step;    /* 1: accepted steps keep h and q (no step-size or order
+                        selection); used only by the convergence-order pins */
 } orc_options;
 
 typedef struct {
@@ -142,8 +144,16 @@ typedef struct {
   double t, h, err_last;
   int q, qwait, qprime_pending, initialized;
   double hu; int qu;     /* last accepted step */
+  /* order-selection estimates of the last accepted step (-1 when the step
+   * did not select an order, or the order had no such neighbour) and the
+   * growth factor that selection proposed before the hysteresis test */
+  double err_qm1, err_qp1, eta_proposed;
+  int q_proposed;
 } orc_scalars;
 void orc_bdf_get_scalars(const orc_bdf* b, orc_scalars* s);
+/* computes the starting step and history (as the first step would) without
+ * stepping; a no-op once initialised */
+void orc_bdf_init(orc_bdf* b, double t_end);
 void orc_bdf_set_scalars(orc_bdf* b, const orc_scalars* s);
 /* history z[j] (j = 0..5) and previous correction; each N doubles */
 void orc_bdf_get_history(const orc_bdf* b, double* z6, double* dprev);
