@@ -77,6 +77,19 @@ int nvec_scale_add_multi(int nv, const double* a, const double* x,
 /* d[j] = sum_i x_i Y[j]_i, 1 <= nv <= 8.  d: host (sync) or device. */
 int nvec_dot_prod_multi(int nv, const double* x, const double* const* Y,
                         double* d, long n, int flags, void* stream);
+/* nvec_dot_prod_multi for callers that cannot allocate: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * calls no hipMalloc, hipFree or allocating library routine: its block
+ * partials live in a static array of the library's device memory
+ * (8192 blocks x 8 doubles = 512 KiB per device, held until the process
+ * ends); the reduction grid never exceeds it, whatever n.  d is a DEVICE
+ * array of nv doubles, written asynchronously on `stream`.  1 <= nv <= 8,
+ * else BDFGPU_ERR_ARG.  All calls on one device share that array, which
+ * keeps the last call's partials: calls that overlap on one GPU (two
+ * streams, or two host threads) race and must be serialised by the caller.
+ * n == 0 writes zeros. */
+int nvec_dot_prod_multi_noalloc(int nv, const double* x, const double* const* Y,
+                                double* d, long n, void* stream);
 /* out = sqrt(sum_i (x_i w_i)^2 / n).  out: host (sync) or device. */
 int nvec_wrms_norm(long n, const double* x, const double* w, double* out,
                    int flags, void* stream);

@@ -16,7 +16,7 @@ from ._lib import BdfGpuError, BdfOptions, BdfProblem, BdfStats, check, dp, ip, 
 
 __all__ = [
     "nvec_linear_sum", "nvec_linear_combination", "nvec_scale_add_multi",
-    "nvec_dot_prod_multi", "nvec_wrms_norm", "nvec_max_norm", "nvec_ewt", "nvec_scale",
+    "nvec_dot_prod_multi", "nvec_dot_prod_multi_noalloc", "nvec_wrms_norm", "nvec_max_norm", "nvec_ewt", "nvec_scale",
     "nvec_const", "batched_lu_factor_f64", "batched_lu_solve_f64", "batched_lu_factor_f32",
     "batched_lu_solve_f32", "batched_lu_solve_refine", "Bdf", "BdfGpuError", "lib",
     "LS_LU64", "LS_LU32REF", "LS_LEARNED", "MODE_STREAM", "MODE_GRAPH", "RESULT_DEVICE",
@@ -110,6 +110,18 @@ def nvec_dot_prod_multi(x, Y, out=None):
     check("nvec_dot_prod_multi",
           lib().nvec_dot_prod_multi(len(Y), _p(x), _ptr_array(Y), _p(out), x.numel(), RESULT_DEVICE,
                                     _stream()))
+    return out
+
+
+def nvec_dot_prod_multi_noalloc(x, Y, out):
+    """Dots into the device tensor `out` without any allocation by the
+    library (static per-device scratch; overlapping calls on one GPU race)."""
+    torch = _torch()
+    for t in [x, out] + list(Y):
+        _dev(t, torch.float64)
+    check("nvec_dot_prod_multi_noalloc",
+          lib().nvec_dot_prod_multi_noalloc(len(Y), _p(x), _ptr_array(Y), _p(out), x.numel(),
+                                            _stream()))
     return out
 
 

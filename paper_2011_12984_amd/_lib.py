@@ -58,6 +58,7 @@ SIGNATURES = {
     "nvec_linear_combination": (C.c_int, [C.c_int, dp, C.POINTER(vp), vp, C.c_long, vp]),
     "nvec_scale_add_multi": (C.c_int, [C.c_int, dp, vp, C.POINTER(vp), C.POINTER(vp), C.c_long, vp]),
     "nvec_dot_prod_multi": (C.c_int, [C.c_int, vp, C.POINTER(vp), vp, C.c_long, C.c_int, vp]),
+    "nvec_dot_prod_multi_noalloc": (C.c_int, [C.c_int, vp, C.POINTER(vp), vp, C.c_long, vp]),
     "nvec_wrms_norm": (C.c_int, [C.c_long, vp, vp, vp, C.c_int, vp]),
     "nvec_max_norm": (C.c_int, [C.c_long, vp, vp, C.c_int, vp]),
     "nvec_ewt": (C.c_int, [C.c_long, C.c_double, C.c_double, vp, vp, vp]),

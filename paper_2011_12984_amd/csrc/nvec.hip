@@ -53,6 +53,30 @@ struct RedScratch {
 static RedScratch g_red[kMaxDev];
 static std::mutex g_red_mu;
 
+// Reduction scratch that needs no allocation, for nvec_dot_prod_multi_noalloc:
+// block partials in the library's static device memory (kRedBlocks x kRedK
+// doubles = 512 KiB, held by every device the library runs on until the
+// process ends).  Host code uses only the per-device address obtained with
+// hipGetSymbolAddress, never the array's name.
+static __device__ __align__(256) double scratch[kRedBlocks * kRedK];
+static double* g_scratch_ptr[kMaxDev];
+static std::mutex g_scratch_mu;
+
+static int get_static_scratch(double** out) {
+  int dev = 0;
+  BDF_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDev) return arg_error("device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    BDF_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return arg_error("static reduction scratch has no device address");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
 static int get_red_scratch(RedScratch** out) {
   int dev = 0;
   BDF_HIP_TRY(hipGetDevice(&dev));
@@ -495,6 +519,40 @@ static int finish_reduction(RedScratch* r, int nv, double* out, int flags, hipSt
   return 0;
 }
 
+// Blocks of the dot-product kernels for n elements (aligned: 16-byte units).
+static unsigned int dot_grid(long n, bool al) {
+  return al ? red_blocks(n >> 1) : red_blocks(n, true);
+}
+
+// Multiple dot products: block partials into `partials` (at most kRedBlocks
+// blocks of kRedK values), then k_finish sums them into the device array out.
+static hipError_t launch_dot(int nv, const double* x, const DotArgs& A, bool al, long n,
+                             double* partials, double* out, hipStream_t s) {
+  dim3 g(dot_grid(n, al)), b(256);
+  if (al) {
+    switch (nv) {
+#define DP_CASE(K) case K: hipLaunchKernelGGL(k_dot_prod_multi<K>, g, b, 0, s, n, x, A, partials); break;
+      DP_CASE(1) DP_CASE(2) DP_CASE(3) DP_CASE(4) DP_CASE(5) DP_CASE(6) DP_CASE(7) DP_CASE(8)
+#undef DP_CASE
+    }
+  } else {
+    switch (nv) {
+#define DP_CASE(K) case K: hipLaunchKernelGGL(k_dot_prod_multi_u<K>, g, b, 0, s, n, x, A, partials); break;
+      DP_CASE(1) DP_CASE(2) DP_CASE(3) DP_CASE(4) DP_CASE(5) DP_CASE(6) DP_CASE(7) DP_CASE(8)
+#undef DP_CASE
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, nv, g.x, 0, n, partials, out);
+  return hipGetLastError();
+}
+
+// out[0..k) = 0 (a kernel rather than a memset, so that it can be captured)
+__global__ void k_zero(int k, double* out) {
+  if ((int)threadIdx.x < k) out[threadIdx.x] = 0.0;
+}
+
 }  // namespace bdfgpu
 
 using namespace bdfgpu;
@@ -618,25 +676,35 @@ int nvec_dot_prod_multi(int nv, const double* x, const double* const* Y, double*
     A.Y[j] = Y[j];
     al = al && aligned16(Y[j]);
   }
-  dim3 g(al ? red_blocks(n >> 1) : red_blocks(n, true)), b(256);
-  if (al) {
-    switch (nv) {
-#define DP_CASE(K) case K: hipLaunchKernelGGL(k_dot_prod_multi<K>, g, b, 0, s, n, x, A, r->partials); break;
-      DP_CASE(1) DP_CASE(2) DP_CASE(3) DP_CASE(4) DP_CASE(5) DP_CASE(6) DP_CASE(7) DP_CASE(8)
-#undef DP_CASE
-    }
-  } else {
-    switch (nv) {
-#define DP_CASE(K) case K: hipLaunchKernelGGL(k_dot_prod_multi_u<K>, g, b, 0, s, n, x, A, r->partials); break;
-      DP_CASE(1) DP_CASE(2) DP_CASE(3) DP_CASE(4) DP_CASE(5) DP_CASE(6) DP_CASE(7) DP_CASE(8)
-#undef DP_CASE
-    }
-  }
-  BDF_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, nv, g.x, 0, n, r->partials,
-                     finish_target(r, d, flags));
-  BDF_HIP_TRY(hipGetLastError());
+  BDF_HIP_TRY(launch_dot(nv, x, A, al, n, r->partials, finish_target(r, d, flags), s));
   return finish_reduction(r, nv, d, flags, s);
+}
+
+int nvec_dot_prod_multi_noalloc(int nv, const double* x, const double* const* Y, double* d,
+                                long n, void* stream) {
+  if (nv < 1 || nv > kRedK || n < 0 || !Y || !d || (n > 0 && !x))
+    return arg_error("nvec_dot_prod_multi_noalloc: bad argument (1 <= nv <= 8, device d)");
+  hipStream_t s = as_stream(stream);
+  if (n == 0) {
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, nv, d);
+    BDF_HIP_TRY(hipGetLastError());
+    return 0;
+  }
+  double* partials = nullptr;
+  int st = get_static_scratch(&partials);
+  if (st) return st;
+  DotArgs A;
+  memset(&A, 0, sizeof(A));
+  bool al = aligned16(x);
+  for (int j = 0; j < nv; ++j) {
+    if (!Y[j]) return arg_error("nvec_dot_prod_multi_noalloc: null vector");
+    A.Y[j] = Y[j];
+    al = al && aligned16(Y[j]);
+  }
+  if (dot_grid(n, al) > (unsigned int)kRedBlocks)
+    return arg_error("nvec_dot_prod_multi_noalloc: reduction grid exceeds the static scratch");
+  BDF_HIP_TRY(launch_dot(nv, x, A, al, n, partials, d, s));
+  return 0;
 }
 
 int nvec_wrms_norm(long n, const double* x, const double* w, double* out, int flags,
