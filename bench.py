@@ -26,14 +26,46 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 MAXCOR = 3
-# HBM bytes per launch of the fused Newton kernel at 2^20 cells and order 5,
-# from FETCH_SIZE/WRITE_SIZE counter runs scaled by a plain copy kernel
-# (profiles/); None when the kernel has changed since the counters were taken
-MEASURED_TRAFFIC_BYTES = 927.6e6
+HERE = os.path.dirname(os.path.abspath(__file__))
+# Sources that define the fused Newton kernel the roofline times.
+NEWTON_SOURCES = ("paper_2011_12984_amd/csrc/bdf_dev.hpp", "paper_2011_12984_amd/csrc/bdf_jit.hip",
+                  "paper_2011_12984_amd/csrc/common.hpp")
+# HBM bytes per launch of that kernel at 2^20 cells and order 5, from
+# FETCH_SIZE / WRITE_SIZE counter runs scaled by a plain copy kernel (the
+# traffic summary under profiles/), with the hash of NEWTON_SOURCES they
+# were taken at: reported only while the sources still hash to it.
+MEASURED_TRAFFIC = {"sha256_16": None, "bytes": None}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def sources_hash(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(HERE, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def host_cpu():
+    """Host CPU model and the number of logical CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return model, nproc
 
 
 def time_advance(b, t_end, steps, torch):
@@ -95,9 +127,10 @@ def fused_ops(G, W, torch, dev, n=1 << 26, warm=10, reps=50):
     return res
 
 
-def cpu_baseline(W, prob_full, ncells=1024, budget_s=12.0, max_steps=4000):
+def cpu_baseline(W, prob_full, ncells=1024, budget_s=12.0, max_steps=4000, robertson_reps=3):
     """The serial oracle on the first `ncells` cells of the same workload,
-    stepped from t = 0 until the time budget is spent."""
+    stepped from t = 0 until the time budget is spent; and the whole
+    1,000-cell Robertson BDF2 run to t = 10 (median of `robertson_reps`)."""
     import numpy as np
 
     import oracle
@@ -114,10 +147,27 @@ def cpu_baseline(W, prob_full, ncells=1024, budget_s=12.0, max_steps=4000):
             break
         steps += 1
     dt = time.perf_counter() - t0
-    return {"value": round(ncells * steps / dt, 1), "unit": "cell-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"first {ncells} cells of the same 2^20-cell workload, {steps} steps "
-                      f"from t=0 in {dt:.1f} s (serial C, FP64, FP64 LU)"}
+    model, nproc = host_cpu()
+    out = {"value": round(ncells * steps / dt, 1), "unit": "cell-steps/s", "cores": 1,
+           "kind": "oracle", "cpu_model": model, "host_logical_cpus": nproc,
+           "sample": f"first {ncells} cells of the same 2^20-cell workload, {steps} steps "
+                     f"from t=0 in {dt:.1f} s (serial C, FP64, FP64 LU, one thread)"}
+    if robertson_reps:
+        p = W.robertson_batch(1000)
+        times = []
+        for _ in range(robertson_reps):
+            ob = oracle.Bdf(p)
+            t0 = time.perf_counter()
+            rc = ob.integrate(p.t_end)
+            times.append(time.perf_counter() - t0)
+            if rc != 0:
+                break
+        ws = float(np.median(times))
+        st = ob.stats()["nsteps"]
+        out["robertson_1000"] = {"whole_run_s": round(ws, 4), "steps": int(st),
+                                 "value": round(1000 * st / ws, 1), "unit": "cell-steps/s",
+                                 "runs": len(times)}
+    return out
 
 def wrms(a, b, rtol, atol):
     import numpy as np
@@ -219,6 +269,52 @@ def learned_leg(G, W, torch, dev, cells, warmup, steps, epochs, nblocks):
     return out
 
 
+def robertson_leg(G, W, torch, dev, reps=3):
+    """1,000 Robertson-type cells (3 species), BDF2, whole run to t = 10:
+    far below the vector length where a GPU pays off, so launch and
+    synchronisation latency bound it.  Median of `reps` whole runs, each on
+    a fresh handle with its inputs already in HBM (creation not timed)."""
+    import numpy as np
+    p = W.robertson_batch(1000)
+    out = {}
+    for name, kw in (("stream", {"mode": G.MODE_STREAM}), ("graph", {"mode": G.MODE_GRAPH})):
+        times, steps = [], None
+        for _ in range(reps):
+            b = G.Bdf.from_problem(p, device=dev, attempts_per_sync=16, jit=True, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t = b.integrate(p.t_end)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            steps = b.stats()["nsteps"]
+            b.close()
+            assert t == p.t_end
+        ws = float(np.median(times))
+        out[name] = {"whole_run_s": round(ws, 4), "steps": int(steps),
+                     "value": round(1000 * steps / ws, 1), "unit": "cell-steps/s"}
+    return out
+
+
+def long_run_leg(G, W, torch, prob, dev, jit=True, max_steps=20000):
+    """The benchmark workload integrated from t = 0 for max_steps accepted
+    steps (or to t_end) on a fresh handle, creation and the starting step
+    not timed: the step mix of a long run (orders, retries, Newton
+    iterations) beside the short timed window of the headline."""
+    b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_STREAM, attempts_per_sync=16,
+                           linsol=G.LS_LU64, maxcor=MAXCOR, jit=jit)
+    b.advance(prob.t_end, 1)
+    s0 = b.stats()
+    dt, taken, t = time_advance(b, prob.t_end, max_steps, torch)
+    s1 = b.stats()
+    b.close()
+    return {"t_end": prob.t_end, "t_reached": t, "steps": taken + 1, "timed_steps": taken,
+            "wall_s": round(dt, 3), "value": round(prob.ncells * taken / dt, 1),
+            "unit": "cell-steps/s", "ms_per_step": round(1e3 * dt / max(taken, 1), 4),
+            "attempts_per_step": round((s1["nattempts"] - s0["nattempts"]) / max(taken, 1), 4),
+            "newton_iters_per_step": round((s1["nniters"] - s0["nniters"]) / max(taken, 1), 4),
+            "order_hist": [a - b_ for a, b_ in zip(s1["order_hist"], s0["order_hist"])]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +326,11 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-robertson", action="store_true")
+    ap.add_argument("--long-steps", type=int, default=20000,
+                    help="accepted steps of the long run from t = 0 (0 skips it)")
+    ap.add_argument("--profile-warmup", type=int, default=60,
+                    help="steps before the kernel-timing window (order 5 is reached by then)")
     ap.add_argument("--graph", action="store_true")
     ap.add_argument("--no-jit", action="store_true",
                     help="generic table-driven Newton kernels instead of network-specialised ones")
@@ -272,44 +373,62 @@ def main():
     attempts = s1["nattempts"] - s0["nattempts"]
     niters = s1["nniters"] - s0["nniters"]
 
+    t_after = b.stats()["t"]
+    hist_reads = s1["hist_reads"] - s0["hist_reads"]
+    b.close()
+
     log("profiling the dominant kernel")
-    pb = b
-    if args.graph:
-        # launches inside a captured graph cannot be bracketed with events:
-        # time the same kernels on a stream-mode handle of the same workload
-        pb = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_STREAM, attempts_per_sync=16,
-                                linsol=G.LS_LU64, maxcor=MAXCOR, jit=not args.no_jit)
-        pb.advance(prob.t_end, args.warmup)
+    # A stream-mode handle of the same workload that reads the controller
+    # after every attempt, so that every timed launch does work (with several
+    # attempts per status read, launches enqueued after the step limit return
+    # at once); advanced past the order ramp before the timing window.
+    pb = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_STREAM, attempts_per_sync=1,
+                            linsol=G.LS_LU64, maxcor=MAXCOR, jit=not args.no_jit)
+    pb.advance(prob.t_end, args.profile_warmup)
     pb.set_profiling(True)
     ps0 = pb.stats()
     pdt, ptaken, _ = time_advance(pb, prob.t_end, min(args.steps, 100), torch)
     ps1 = pb.stats()
     kt = pb.kernel_times()
     pb.set_profiling(False)
-    if pb is not b:
-        pb.close()
+    pb.close()
     p_ms, p_cnt = kt["newton"]
     p_att = ps1["nattempts"] - ps0["nattempts"]
+    if p_cnt != p_att:
+        raise RuntimeError(f"timed {p_cnt} Newton launches for {p_att} attempts")
     q1 = (ps1["hist_reads"] - ps0["hist_reads"]) / max(p_att, 1)   # mean q + 1
-    # fused predictor + Newton kernel, per cell: read q+1 history vectors
-    # and R rates, write the iterate of each of the maxcor iterations
-    bytes_per_launch = 8.0 * args.cells * (q1 * n + R + MAXCOR * n)
-    avg_ms = p_ms / max(p_cnt, 1)
+    # The step's algorithmic bytes per cell are 8 (2 (q+1) n + R): the
+    # history read and written once and the rates read once.  The fused
+    # Newton kernel's share is the read half, 8 ((q+1) n + R); the history
+    # update's the write half.
+    bytes_per_launch = 8.0 * args.cells * (q1 * n + R)
+    avg_ms = p_ms / max(p_att, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    sha = sources_hash(NEWTON_SOURCES)
+    traffic = (MEASURED_TRAFFIC["bytes"]
+               if (sha == MEASURED_TRAFFIC["sha256_16"] and args.cells == 1 << 20
+                   and not args.no_jit) else None)
+    # whole step against the step's algorithmic bytes, over the headline run
+    q1_main = hist_reads / max(attempts, 1)
+    step_bytes = 8.0 * args.cells * (2 * q1_main * n + R)
+    step_gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
     roofline = {"bound": "hbm",
                 "kernel": ("k_tpc_newton<10,0>" if args.no_jit else
                            "bdf_newton_net_np10_ls0 (k_tpc_newton<10,0> specialised to the network)")
                           + " (predictor, J, LU, 3 Newton iterations)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": (MEASURED_TRAFFIC_BYTES if args.cells == 1 << 20 and not args.no_jit
-                            else None),
-                "avg_launch_ms": round(avg_ms, 4), "launches": p_cnt,
+                "traffic": traffic, "newton_sources_sha256_16": sha,
+                "avg_launch_ms": round(avg_ms, 4), "launches": p_cnt, "attempts": p_att,
                 "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                "algorithmic_bytes": "8 * cells * ((q+1) * n + R): history read + rates",
                 "mean_q_plus_1": round(q1, 3),
-                "group_ms": {k: [round(v[0], 3), v[1]] for k, v in kt.items()}}
-    t_after = b.stats()["t"]
-    b.close()
+                "group_ms": {k: [round(v[0], 3), v[1]] for k, v in kt.items()},
+                "step": {"algorithmic_bytes_per_step": int(step_bytes),
+                         "algorithmic_bytes": "8 * cells * (2 (q+1) n + R)",
+                         "mean_q_plus_1": round(q1_main, 3),
+                         "achieved": round(step_gbs, 1),
+                         "frac": round(step_gbs / HBM_PEAK_GBS, 4)}}
 
     out_fp32 = None
     if not args.no_fp32:
@@ -329,6 +448,17 @@ def main():
             G, W, torch, dev, lambda: W.random_network_batch(1 << 16, n=10, seed=W.BASE_SEED + 3),
             1e-3, linsol=G.LS_LU32REF)
         torch.cuda.empty_cache()
+
+    long_run = None
+    if args.long_steps > 0:
+        log(f"long run: {args.long_steps} steps from t = 0")
+        long_run = long_run_leg(G, W, torch, prob, dev, jit=not args.no_jit,
+                                max_steps=args.long_steps)
+
+    robertson = None
+    if not args.no_robertson:
+        log("1,000-cell Robertson BDF2 whole runs")
+        robertson = robertson_leg(G, W, torch, dev)
 
     fused = None
     if not args.no_fused:
@@ -367,6 +497,8 @@ def main():
                    "t_reached": t_after},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "long_run": long_run,
+        "robertson_1000_bdf2": robertson,
         "fp32_refined": out_fp32,
         "fused_ops": fused,
         "uneven": uneven,

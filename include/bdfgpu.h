@@ -39,14 +39,21 @@
 extern "C" {
 #endif
 
+/* Status codes.  > 0: the step could not be completed but a smaller step
+ * may succeed (the paper's recoverable-failure semantics for task-local
+ * nonlinear solves, Section 7); the integrator handle then keeps its last
+ * accepted state (bdf_get_y, bdf_get_state) and stops: continue from that
+ * state with bdf_set_state and a smaller h.  < 0: unrecoverable. */
 #define BDFGPU_SUCCESS 0
-#define BDFGPU_RECOVERABLE 1
+#define BDFGPU_RECOVERABLE 1      /* recoverable failure (unspecified) */
+#define BDFGPU_CONV_FAIL 2        /* Newton failed 10 times in one step */
+#define BDFGPU_TEST_FAIL 3        /* error test failed 7 times in one step */
 #define BDFGPU_ERR_ARG (-1)       /* bad argument */
 #define BDFGPU_ERR_HIP (-2)       /* HIP runtime error */
-#define BDFGPU_ERR_CONV (-4)      /* too many Newton failures in one step */
-#define BDFGPU_ERR_TEST (-5)      /* too many error-test failures in one step */
-#define BDFGPU_ERR_HMIN (-6)      /* step size fell below hmin */
-#define BDFGPU_ERR_MAXSTEPS (-7)  /* max_steps reached before t_end */
+#define BDFGPU_ERR_WORKSPACE (-3) /* caller workspace too small */
+#define BDFGPU_ERR_TOO_MUCH_WORK (-4) /* max_steps reached before t_end */
+#define BDFGPU_ERR_HMIN (-5)      /* step size fell below hmin (or below the
+                                     resolution of t) */
 
 #define BDFGPU_RESULT_DEVICE 1
 
@@ -93,6 +100,12 @@ int nvec_dot_prod_multi_noalloc(int nv, const double* x, const double* const* Y,
 /* out = sqrt(sum_i (x_i w_i)^2 / n).  out: host (sync) or device. */
 int nvec_wrms_norm(long n, const double* x, const double* w, double* out,
                    int flags, void* stream);
+/* nrm[j] = sqrt(sum_i (X[j]_i W[j]_i)^2 / n), 1 <= nv <= 8: the WRMS norms
+ * of several vectors in one pass (the vector-array form of the WRMS norm).
+ * X, W: host arrays of nv device vectors; when every W[j] is the same
+ * pointer that weight vector is read once.  nrm: host (sync) or device. */
+int nvec_wrms_norm_multi(int nv, const double* const* X, const double* const* W,
+                         double* nrm, long n, int flags, void* stream);
 /* out = max_i |x_i|.  out: host (sync) or device. */
 int nvec_max_norm(long n, const double* x, double* out, int flags, void* stream);
 /* w_i = 1 / (rtol |y_i| + atol)  (error weights of the WRMS norm). */
@@ -122,6 +135,27 @@ int batched_lu_factor_f32(int nb, int n, float* A, int* piv, int* info,
                           void* stream);
 int batched_lu_solve_f32(int nb, int n, const float* LU, const int* piv,
                          float* B, void* stream);
+/* Blocks of different sizes (block-diagonal matrices whose blocks are not
+ * all alike) in one launch.  sizes, moff, voff: DEVICE arrays of nb
+ * entries; block b is the sizes[b] x sizes[b] column-major block at
+ * A + moff[b] (usually moff[b] = sum_{b'<b} sizes[b']^2), its pivots at
+ * piv + voff[b] and its right-hand side / solution at B + voff[b]
+ * (usually voff[b] = sum_{b'<b} sizes[b']).  nmax (host) bounds every size
+ * and sets the lanes per block (the next power of two, <= 64); a block
+ * whose size is outside 0..nmax gets info[b] = -1 and is left untouched.
+ * Semantics per block as the uniform calls above. */
+int batched_lu_factor_f64_var(int nb, int nmax, const int* sizes, const long* moff,
+                              const long* voff, double* A, int* piv, int* info,
+                              void* stream);
+int batched_lu_solve_f64_var(int nb, int nmax, const int* sizes, const long* moff,
+                             const long* voff, const double* LU, const int* piv,
+                             double* B, void* stream);
+int batched_lu_factor_f32_var(int nb, int nmax, const int* sizes, const long* moff,
+                              const long* voff, float* A, int* piv, int* info,
+                              void* stream);
+int batched_lu_solve_f32_var(int nb, int nmax, const int* sizes, const long* moff,
+                             const long* voff, const float* LU, const int* piv,
+                             float* B, void* stream);
 /* FP32 LU (LU32/piv32, from batched_lu_factor_f32 of M rounded to FP32)
  * plus FP64 iterative refinement: x0 = FP32 solve of b; then corrections
  * from the FP64 residual b - M x until |r|_inf <= sqrt(n) eps64 |M|_inf

@@ -12,13 +12,15 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import BdfGpuError, BdfOptions, BdfProblem, BdfStats, check, dp, ip, lib, vp
+from ._lib import (BdfGpuError, BdfOptions, BdfProblem, BdfStats, check, check_status, dp, ip,
+                   lib, vp)
 
 __all__ = [
     "nvec_linear_sum", "nvec_linear_combination", "nvec_scale_add_multi",
-    "nvec_dot_prod_multi", "nvec_dot_prod_multi_noalloc", "nvec_wrms_norm", "nvec_max_norm", "nvec_ewt", "nvec_scale",
+    "nvec_dot_prod_multi", "nvec_dot_prod_multi_noalloc", "nvec_wrms_norm", "nvec_wrms_norm_multi", "nvec_max_norm", "nvec_ewt", "nvec_scale",
     "nvec_const", "batched_lu_factor_f64", "batched_lu_solve_f64", "batched_lu_factor_f32",
-    "batched_lu_solve_f32", "batched_lu_solve_refine", "Bdf", "BdfGpuError", "lib",
+    "batched_lu_solve_f32", "batched_lu_solve_refine", "batched_lu_factor_var",
+    "batched_lu_solve_var", "Bdf", "BdfGpuError", "lib",
     "LS_LU64", "LS_LU32REF", "LS_LEARNED", "MODE_STREAM", "MODE_GRAPH", "RESULT_DEVICE",
     "LAUNCH_PER_CLASS", "LAUNCH_FUSED", "LAUNCH_AUTO", "capture_training_set", "train_precond",
     "Precond",
@@ -139,6 +141,27 @@ def nvec_wrms_norm(x, w, out=None):
     return out
 
 
+def nvec_wrms_norm_multi(X, Wt, out=None):
+    """WRMS norms of the vectors X[j] with weights Wt[j] (Wt may repeat one
+    tensor): host list (synchronising), or into device tensor `out`."""
+    torch = _torch()
+    for t in list(X) + list(Wt):
+        _dev(t, torch.float64)
+    if len(X) != len(Wt):
+        raise ValueError("one weight vector per vector")
+    n = X[0].numel()
+    if out is None:
+        d = (C.c_double * len(X))()
+        check("nvec_wrms_norm_multi",
+              lib().nvec_wrms_norm_multi(len(X), _ptr_array(X), _ptr_array(Wt), C.cast(d, vp), n,
+                                         0, _stream()))
+        return list(d)
+    check("nvec_wrms_norm_multi",
+          lib().nvec_wrms_norm_multi(len(X), _ptr_array(X), _ptr_array(Wt), _p(out), n,
+                                     RESULT_DEVICE, _stream()))
+    return out
+
+
 def nvec_max_norm(x, out=None):
     torch = _torch()
     _dev(x, torch.float64)
@@ -201,6 +224,43 @@ def batched_lu_factor_f32(A, piv, info):
 def batched_lu_solve_f32(LU, piv, B):
     nb, n = _blocks(LU, _torch().float32)
     check("batched_lu_solve_f32", lib().batched_lu_solve_f32(nb, n, _p(LU), _p(piv), _p(B), _stream()))
+    return B
+
+
+def _var_layout(sizes, device):
+    """Device arrays (sizes int32, moff int64, voff int64) of packed blocks."""
+    torch = _torch()
+    sz = np.asarray(sizes, np.int64)
+    moff = np.concatenate([[0], np.cumsum(sz * sz)[:-1]]).astype(np.int64)
+    voff = np.concatenate([[0], np.cumsum(sz)[:-1]]).astype(np.int64)
+    return (torch.tensor(sz.astype(np.int32), device=device), torch.tensor(moff, device=device),
+            torch.tensor(voff, device=device))
+
+
+def batched_lu_factor_var(A, piv, info, sizes, layout=None, nmax=None):
+    """Blocks of uneven sizes packed in A (column-major, block after block);
+    float64 or float32.  layout: (sizes, moff, voff) device tensors, else
+    the packed layout of `sizes` (host ints)."""
+    torch = _torch()
+    f64 = A.dtype == torch.float64
+    _dev(A, torch.float64 if f64 else torch.float32)
+    sz, mo, vo = layout if layout is not None else _var_layout(sizes, A.device)
+    nmax = int(max(sizes)) if nmax is None else nmax
+    fn = "batched_lu_factor_f64_var" if f64 else "batched_lu_factor_f32_var"
+    check(fn, getattr(lib(), fn)(len(sizes), nmax, _p(sz), _p(mo), _p(vo), _p(A), _p(piv),
+                                 _p(info), _stream()))
+    return A, piv, info
+
+
+def batched_lu_solve_var(LU, piv, B, sizes, layout=None, nmax=None):
+    torch = _torch()
+    f64 = LU.dtype == torch.float64
+    _dev(LU, torch.float64 if f64 else torch.float32)
+    sz, mo, vo = layout if layout is not None else _var_layout(sizes, LU.device)
+    nmax = int(max(sizes)) if nmax is None else nmax
+    fn = "batched_lu_solve_f64_var" if f64 else "batched_lu_solve_f32_var"
+    check(fn, getattr(lib(), fn)(len(sizes), nmax, _p(sz), _p(mo), _p(vo), _p(LU), _p(piv),
+                                 _p(B), _stream()))
     return B
 
 
@@ -277,20 +337,20 @@ class Bdf:
 
     def step(self, t_end):
         t = C.c_double(0.0)
-        check("bdf_step", lib().bdf_step(self.h, t_end, C.byref(t)))
+        check_status("bdf_step", lib().bdf_step(self.h, t_end, C.byref(t)))
         return t.value
 
     def integrate(self, t_end):
         t = C.c_double(0.0)
-        code = lib().bdf_integrate(self.h, t_end, C.byref(t))
-        check("bdf_integrate", code)
+        check_status("bdf_integrate", lib().bdf_integrate(self.h, t_end, C.byref(t)))
         return t.value
 
     def advance(self, t_end, nsteps):
         """At most nsteps accepted steps towards t_end; returns (t, taken)."""
         t = C.c_double(0.0)
         taken = C.c_long(0)
-        check("bdf_advance", lib().bdf_advance(self.h, t_end, nsteps, C.byref(t), C.byref(taken)))
+        check_status("bdf_advance",
+                     lib().bdf_advance(self.h, t_end, nsteps, C.byref(t), C.byref(taken)))
         return t.value, taken.value
 
     def set_profiling(self, on=True):

@@ -60,6 +60,7 @@ SIGNATURES = {
     "nvec_dot_prod_multi": (C.c_int, [C.c_int, vp, C.POINTER(vp), vp, C.c_long, C.c_int, vp]),
     "nvec_dot_prod_multi_noalloc": (C.c_int, [C.c_int, vp, C.POINTER(vp), vp, C.c_long, vp]),
     "nvec_wrms_norm": (C.c_int, [C.c_long, vp, vp, vp, C.c_int, vp]),
+    "nvec_wrms_norm_multi": (C.c_int, [C.c_int, C.POINTER(vp), C.POINTER(vp), vp, C.c_long, C.c_int, vp]),
     "nvec_max_norm": (C.c_int, [C.c_long, vp, vp, C.c_int, vp]),
     "nvec_ewt": (C.c_int, [C.c_long, C.c_double, C.c_double, vp, vp, vp]),
     "nvec_scale": (C.c_int, [C.c_long, C.c_double, vp, vp, vp]),
@@ -68,6 +69,10 @@ SIGNATURES = {
     "batched_lu_solve_f64": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp]),
     "batched_lu_factor_f32": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp]),
     "batched_lu_solve_f32": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp]),
+    "batched_lu_factor_f64_var": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]),
+    "batched_lu_solve_f64_var": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]),
+    "batched_lu_factor_f32_var": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]),
+    "batched_lu_solve_f32_var": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]),
     "batched_lu_solve_refine": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]),
     "bdf_create": (C.c_int, [C.POINTER(BdfProblem), C.POINTER(BdfOptions), vp, C.POINTER(vp)]),
     "bdf_destroy": (C.c_int, [vp]),
@@ -126,5 +131,13 @@ class BdfGpuError(RuntimeError):
 
 def check(fn, code):
     if code < 0:
+        raise BdfGpuError(fn, code)
+    return code
+
+
+def check_status(fn, code):
+    """Integrator calls: a positive status is a recoverable failure of the
+    step (the handle stops at its last accepted state), also raised."""
+    if code != 0:
         raise BdfGpuError(fn, code)
     return code

@@ -794,7 +794,7 @@ int bdf_integrate(bdf_handle* h, double t_end, double* tret) {
   if (st) return st;
   if (h->hC->phase == PH_PAUSE && h->hC->t < t_end) {
     set_last_error("max_steps reached before t_end", __FILE__, __LINE__);
-    return BDFGPU_ERR_MAXSTEPS;
+    return BDFGPU_ERR_TOO_MUCH_WORK;
   }
   return 0;
 }

@@ -65,6 +65,17 @@ struct Ctrl {
   int q, qmax, qwait, maxcor, qu;
   int phase, m, ncf, netf, last, restart, status, pad;
   int learned, force_lu;      // learned preconditioner; retry of an attempt with exact LU
+  // Deferred history update (fuse = 1): an accepted attempt's update
+  // z_new[j] = z(0)[j] + l_j acor is applied by the next attempt's Newton
+  // kernel as it reads the history (or by the flush at the end of a drive),
+  // so the history crosses HBM once per step instead of three times.  The
+  // upd_* fields describe the accepted attempt: its iterate index, order,
+  // coefficients, pending history scale and whether it also writes
+  // z[q+1] = craise acor for a possible order raise.
+  int fuse, upd, upd_m, upd_q, upd_raise, pad2;
+  double upd_l[kQmaxAll + 2];
+  double upd_hs[kQmaxAll + 2];
+  double upd_craise;
   long step_limit;
   long nsteps, nattempts, nfevals, nsetups, nniters, nncfails, netfails;
   long nlinsolves, refine_sweeps, refine_fallbacks, nprojections;
@@ -145,7 +156,7 @@ __device__ inline void newton_failed(Ctrl* C) {
   C->force_lu = 0;
   C->ncf++;
   C->nncfails++;
-  if (C->ncf >= kMxNcf) return fail_error(C, BDFGPU_ERR_CONV);
+  if (C->ncf >= kMxNcf) return fail_error(C, BDFGPU_CONV_FAIL);
   if (C->h * kEtaCf < C->hmin) return fail_error(C, BDFGPU_ERR_HMIN);
   rescale(C, kEtaCf);
   C->h = C->h * kEtaCf;
@@ -157,7 +168,7 @@ __device__ inline void error_test_failed(Ctrl* C, double err) {
   C->force_lu = 0;
   C->netf++;
   C->netfails++;
-  if (C->netf >= kMxNef) return fail_error(C, BDFGPU_ERR_TEST);
+  if (C->netf >= kMxNef) return fail_error(C, BDFGPU_TEST_FAIL);
   if (C->netf >= 3) {
     const double hn = C->h * kEtaRestart;
     if (hn < C->hmin) return fail_error(C, BDFGPU_ERR_HMIN);
@@ -188,11 +199,14 @@ __device__ inline void error_test_failed(Ctrl* C, double err) {
 // would take it, and C->m records the iteration whose iterate is the
 // corrected solution.  Iterates past that point were computed but are
 // unused, so the outcome equals that of stopping there.
+__device__ inline void after_accept(Ctrl* C, const double* s);
+
 __device__ inline void after_newton_all(Ctrl* C, const double* s) {
   if (C->restart) {   // the predictor re-evaluated f(z[0])
     C->nfevals++;
     C->restart = 0;
   }
+  C->upd = 0;         // the Newton kernel applied any pending history update
   for (int m = 0; m < C->maxcor; ++m) {
     const double* t = s + kRedPerIter * m;
     C->nfevals++;
@@ -200,8 +214,10 @@ __device__ inline void after_newton_all(Ctrl* C, const double* s) {
     C->nlinsolves++;
     C->refine_sweeps += (long)t[3];
     C->refine_fallbacks += (long)t[4];
-    C->lp_cell_solves += (long)t[5];
-    C->lp_fallback_cells += (long)t[6];
+    if (C->learned) {
+      C->lp_cell_solves += (long)t[5];
+      C->lp_fallback_cells += (long)t[6];
+    }
     if (m == 0 && s[7] > 0.0) return newton_failed(C);   // singular block in the setup
     const double d = sqrt(t[0] / C->N);
     if (!(d == d) || d > 1e300) return newton_failed(C);
@@ -216,6 +232,21 @@ __device__ inline void after_newton_all(Ctrl* C, const double* s) {
       const double err = sqrt(t[1] / C->N) / C->l[0] * C->tq;
       C->err = err;
       if (err <= 1.0) {
+        if (C->fuse) {
+          // the next Newton kernel applies the history update; the order
+          // selection's sums came with this iteration's (slots 5 and 6)
+          C->upd = 1;
+          C->upd_m = m;
+          C->upd_q = C->q;
+          for (int j = 0; j < kQmaxAll + 2; ++j) {
+            C->upd_l[j] = C->l[j];
+            C->upd_hs[j] = C->hs[j];
+          }
+          C->upd_craise = C->craise;
+          C->upd_raise = (C->qwait == 1 && C->q < kQmaxAll && C->q < C->qmax) ? 1 : 0;
+          const double sacc[2] = {t[5], t[6]};
+          return after_accept(C, sacc);
+        }
         C->phase = PH_ACCEPT;
         return;
       }
@@ -228,7 +259,8 @@ __device__ inline void after_newton_all(Ctrl* C, const double* s) {
   newton_failed(C);
 }
 
-// After the history update: sums of (z_new[q] w)^2 and ((acor - acor_prev) w)^2.
+// After the history update (or, with the deferred update, after the Newton
+// kernel): sums of (z_new[q] w)^2 and ((acor - acor_prev) w)^2.
 __device__ inline void after_accept(Ctrl* C, const double* s) {
   const int q = C->q;
   C->t = C->last ? C->tend : C->t + C->h;

@@ -135,6 +135,61 @@ __global__ void __launch_bounds__(kLuThreads) k_lu_refine(int nb, int n, const d
   }
 }
 
+// Blocks of different sizes in one launch: block b is sizes[b] x sizes[b]
+// (<= nmax <= SEG) at A + moff[b], its pivots and right-hand side at
+// voff[b].  A block whose size is outside 0..nmax gets info = -1 and is
+// left untouched.
+template <int SEG, typename T>
+__global__ void __launch_bounds__(kLuThreads) k_lu_factor_var(int nb, int nmax, const int* sizes,
+                                                              const long* moff, const long* voff,
+                                                              T* A, int* piv, int* info) {
+  __shared__ T s_prow[kLuThreads];
+  __shared__ int s_wl[kLuThreads];
+  const int lane = threadIdx.x & 63;
+  const int r = lane & (SEG - 1);
+  const int sbase = threadIdx.x & ~(SEG - 1);
+  const long b = ((long)blockIdx.x * blockDim.x + threadIdx.x) / SEG;
+  const int nraw = b < nb ? sizes[b] : 0;
+  const bool bad = nraw < 0 || nraw > nmax;
+  const int n = bad ? 0 : nraw;
+  const long base = n > 0 ? moff[b] : 0;
+  const long vb = n > 0 ? voff[b] : 0;
+  T row[SEG];
+#pragma unroll
+  for (int j = 0; j < SEG; ++j)
+    row[j] = (r < n && j < n) ? A[base + r + (long)j * n] : (r == j ? T(1) : T(0));
+  int pos, pv;
+  const int inf = SpcLU<SEG, T>::factor(row, r, n, pos, pv, s_prow + sbase, s_wl + sbase);
+  if (r < n && pos < n) {
+#pragma unroll
+    for (int j = 0; j < SEG; ++j)
+      if (j < n) A[base + pos + (long)j * n] = row[j];
+    piv[vb + r] = pv;
+  }
+  if (b < nb && r == 0) info[b] = bad ? -1 : inf;
+}
+
+template <int SEG, typename T>
+__global__ void __launch_bounds__(kLuThreads) k_lu_solve_var(int nb, int nmax, const int* sizes,
+                                                             const long* moff, const long* voff,
+                                                             const T* LU, const int* piv, T* B) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & (SEG - 1);
+  const int seg_base = lane & ~(SEG - 1);
+  const long b = ((long)blockIdx.x * blockDim.x + threadIdx.x) / SEG;
+  const int nraw = b < nb ? sizes[b] : 0;
+  const int n = (nraw < 0 || nraw > nmax) ? 0 : nraw;
+  const long base = n > 0 ? moff[b] : 0;
+  const long vb = n > 0 ? voff[b] : 0;
+  T row[SEG];
+#pragma unroll
+  for (int j = 0; j < SEG; ++j)
+    row[j] = (r < n && j < n) ? LU[base + r + (long)j * n] : (r == j ? T(1) : T(0));
+  T val = r < n ? B[vb + r] : T(0);
+  const T x = SpcLU<SEG, T>::solve_stored(row, r, seg_base, piv + vb, n, val);
+  if (r < n) B[vb + r] = x;
+}
+
 static int seg_for(int n) {
   return n <= 2 ? 2 : n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 0;
 }
@@ -142,6 +197,50 @@ static int seg_for(int n) {
 static unsigned int lu_blocks(long nb, int seg) {
   const long cpb = kLuThreads / seg;
   return (unsigned int)((nb + cpb - 1) / cpb);
+}
+
+template <typename T>
+static int lu_factor_var(const char* name, int nb, int nmax, const int* sizes, const long* moff,
+                         const long* voff, T* A, int* piv, int* info, void* stream) {
+  if (nb < 0 || nmax < 0 || nmax > 64 ||
+      (nb > 0 && nmax > 0 && (!sizes || !moff || !voff || !A || !piv || !info)))
+    return arg_error(name);
+  if (nb == 0) return 0;
+  const int seg = nmax == 0 ? 2 : seg_for(nmax);
+  hipStream_t s = as_stream(stream);
+  dim3 g(lu_blocks(nb, seg)), blk(kLuThreads);
+  switch (seg) {
+    case 2: hipLaunchKernelGGL((k_lu_factor_var<2, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, A, piv, info); break;
+    case 4: hipLaunchKernelGGL((k_lu_factor_var<4, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, A, piv, info); break;
+    case 8: hipLaunchKernelGGL((k_lu_factor_var<8, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, A, piv, info); break;
+    case 16: hipLaunchKernelGGL((k_lu_factor_var<16, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, A, piv, info); break;
+    case 32: hipLaunchKernelGGL((k_lu_factor_var<32, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, A, piv, info); break;
+    default: hipLaunchKernelGGL((k_lu_factor_var<64, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, A, piv, info); break;
+  }
+  BDF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+template <typename T>
+static int lu_solve_var(const char* name, int nb, int nmax, const int* sizes, const long* moff,
+                        const long* voff, const T* LU, const int* piv, T* B, void* stream) {
+  if (nb < 0 || nmax < 0 || nmax > 64 ||
+      (nb > 0 && nmax > 0 && (!sizes || !moff || !voff || !LU || !piv || !B)))
+    return arg_error(name);
+  if (nb == 0 || nmax == 0) return 0;
+  const int seg = seg_for(nmax);
+  hipStream_t s = as_stream(stream);
+  dim3 g(lu_blocks(nb, seg)), blk(kLuThreads);
+  switch (seg) {
+    case 2: hipLaunchKernelGGL((k_lu_solve_var<2, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, LU, piv, B); break;
+    case 4: hipLaunchKernelGGL((k_lu_solve_var<4, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, LU, piv, B); break;
+    case 8: hipLaunchKernelGGL((k_lu_solve_var<8, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, LU, piv, B); break;
+    case 16: hipLaunchKernelGGL((k_lu_solve_var<16, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, LU, piv, B); break;
+    case 32: hipLaunchKernelGGL((k_lu_solve_var<32, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, LU, piv, B); break;
+    default: hipLaunchKernelGGL((k_lu_solve_var<64, T>), g, blk, 0, s, nb, nmax, sizes, moff, voff, LU, piv, B); break;
+  }
+  BDF_HIP_TRY(hipGetLastError());
+  return 0;
 }
 
 }  // namespace bdfgpu
@@ -248,6 +347,32 @@ int batched_lu_solve_refine(int nb, int n, const double* M, const float* LU32, c
   }
   BDF_HIP_TRY(hipGetLastError());
   return 0;
+}
+
+int batched_lu_factor_f64_var(int nb, int nmax, const int* sizes, const long* moff,
+                              const long* voff, double* A, int* piv, int* info, void* stream) {
+  return lu_factor_var<double>("batched_lu_factor_f64_var: bad argument (nmax <= 64)", nb, nmax,
+                               sizes, moff, voff, A, piv, info, stream);
+}
+
+int batched_lu_factor_f32_var(int nb, int nmax, const int* sizes, const long* moff,
+                              const long* voff, float* A, int* piv, int* info, void* stream) {
+  return lu_factor_var<float>("batched_lu_factor_f32_var: bad argument (nmax <= 64)", nb, nmax,
+                              sizes, moff, voff, A, piv, info, stream);
+}
+
+int batched_lu_solve_f64_var(int nb, int nmax, const int* sizes, const long* moff,
+                             const long* voff, const double* LU, const int* piv, double* B,
+                             void* stream) {
+  return lu_solve_var<double>("batched_lu_solve_f64_var: bad argument (nmax <= 64)", nb, nmax,
+                              sizes, moff, voff, LU, piv, B, stream);
+}
+
+int batched_lu_solve_f32_var(int nb, int nmax, const int* sizes, const long* moff,
+                             const long* voff, const float* LU, const int* piv, float* B,
+                             void* stream) {
+  return lu_solve_var<float>("batched_lu_solve_f32_var: bad argument (nmax <= 64)", nb, nmax,
+                             sizes, moff, voff, LU, piv, B, stream);
 }
 
 }  // extern "C"

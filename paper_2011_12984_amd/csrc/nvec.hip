@@ -414,6 +414,85 @@ __global__ void __launch_bounds__(256) k_wrms(long n, const double* __restrict__
   store_block_partials<1>(acc, sh, partials);
 }
 
+// WRMS norms of nv vectors, each with its weight vector (SHW: one weight
+// vector shared by all, read once): sums of (x_ji w_ji)^2 per vector.
+struct WrmsArgs {
+  const double* X[8];
+  const double* W[8];
+};
+
+template <int NV, bool SHW>
+__global__ void __launch_bounds__(256) k_wrms_multi(long n, WrmsArgs A, double* partials) {
+  __shared__ double sh[4 * NV];
+  double acc[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+  constexpr int NW = SHW ? 1 : NV;
+  const long n2 = n >> 1;
+  const long nt = (n2 + kTile - 1) / kTile;
+  for (long t = blockIdx.x; t < nt; t += gridDim.x) {
+    const long i0 = tile_base(t);
+    if (i0 + (kU - 1) * 64 < n2) {
+      dbl2 xv[kU][NV], wv[kU][NW];
+#pragma unroll
+      for (int j = 0; j < NW; ++j)
+#pragma unroll
+        for (int u = 0; u < kU; ++u) wv[u][j] = ntload(A.W[j], i0 + u * 64);
+#pragma unroll
+      for (int j = 0; j < NV; ++j)
+#pragma unroll
+        for (int u = 0; u < kU; ++u) xv[u][j] = ntload(A.X[j], i0 + u * 64);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          const dbl2 w = wv[u][SHW ? 0 : j];
+          const double a = xv[u][j].x * w.x, b = xv[u][j].y * w.y;
+          acc[j] = fma(a, a, acc[j]);
+          acc[j] = fma(b, b, acc[j]);
+        }
+    } else {
+      for (int u = 0; u < kU; ++u) {
+        const long i = i0 + u * 64;
+        if (i >= n2) break;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          const dbl2 xv = ntload(A.X[j], i), w = ntload(A.W[SHW ? 0 : j], i);
+          const double a = xv.x * w.x, b = xv.y * w.y;
+          acc[j] = fma(a, a, acc[j]);
+          acc[j] = fma(b, b, acc[j]);
+        }
+      }
+    }
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const double a = A.X[j][n - 1] * A.W[SHW ? 0 : j][n - 1];
+      acc[j] = fma(a, a, acc[j]);
+    }
+  }
+  store_block_partials<NV>(acc, sh, partials);
+}
+
+template <int NV>
+__global__ void __launch_bounds__(256) k_wrms_multi_u(long n, WrmsArgs A, double* partials) {
+  __shared__ double sh[4 * NV];
+  double acc[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const double a = A.X[j][i] * A.W[j][i];
+      acc[j] = fma(a, a, acc[j]);
+    }
+  }
+  store_block_partials<NV>(acc, sh, partials);
+}
+
 // scalar-load variants for vectors that are not 16-byte aligned
 template <int NV>
 __global__ void __launch_bounds__(256) k_dot_prod_multi_u(long n, const double* x, DotArgs A,
@@ -733,6 +812,60 @@ int nvec_wrms_norm(long n, const double* x, const double* w, double* out, int fl
                      finish_target(r, out, flags));
   BDF_HIP_TRY(hipGetLastError());
   return finish_reduction(r, 1, out, flags, s);
+}
+
+int nvec_wrms_norm_multi(int nv, const double* const* X, const double* const* Wt, double* nrm,
+                         long n, int flags, void* stream) {
+  if (nv < 1 || nv > 8 || n < 0 || !X || !Wt || !nrm)
+    return arg_error("nvec_wrms_norm_multi: bad argument (1 <= nv <= 8)");
+  hipStream_t s = as_stream(stream);
+  if (n == 0) {
+    if (flags & BDFGPU_RESULT_DEVICE) {
+      hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, nv, nrm);
+      BDF_HIP_TRY(hipGetLastError());
+    } else {
+      for (int j = 0; j < nv; ++j) nrm[j] = 0.0;
+    }
+    return 0;
+  }
+  RedScratch* r = nullptr;
+  int st = get_red_scratch(&r);
+  if (st) return st;
+  WrmsArgs A;
+  memset(&A, 0, sizeof(A));
+  bool al = true, shw = true;
+  for (int j = 0; j < nv; ++j) {
+    if (!X[j] || !Wt[j]) return arg_error("nvec_wrms_norm_multi: null vector");
+    A.X[j] = X[j];
+    A.W[j] = Wt[j];
+    al = al && aligned16(X[j]) && aligned16(Wt[j]);
+    shw = shw && Wt[j] == Wt[0];
+  }
+  dim3 g(al ? red_blocks(n >> 1) : red_blocks(n, true)), b(256);
+  if (al && shw) {
+    switch (nv) {
+#define WM_CASE(K) case K: hipLaunchKernelGGL((k_wrms_multi<K, true>), g, b, 0, s, n, A, r->partials); break;
+      WM_CASE(1) WM_CASE(2) WM_CASE(3) WM_CASE(4) WM_CASE(5) WM_CASE(6) WM_CASE(7) WM_CASE(8)
+#undef WM_CASE
+    }
+  } else if (al) {
+    switch (nv) {
+#define WM_CASE(K) case K: hipLaunchKernelGGL((k_wrms_multi<K, false>), g, b, 0, s, n, A, r->partials); break;
+      WM_CASE(1) WM_CASE(2) WM_CASE(3) WM_CASE(4) WM_CASE(5) WM_CASE(6) WM_CASE(7) WM_CASE(8)
+#undef WM_CASE
+    }
+  } else {
+    switch (nv) {
+#define WM_CASE(K) case K: hipLaunchKernelGGL(k_wrms_multi_u<K>, g, b, 0, s, n, A, r->partials); break;
+      WM_CASE(1) WM_CASE(2) WM_CASE(3) WM_CASE(4) WM_CASE(5) WM_CASE(6) WM_CASE(7) WM_CASE(8)
+#undef WM_CASE
+    }
+  }
+  BDF_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, nv, g.x, 1, n, r->partials,
+                     finish_target(r, nrm, flags));
+  BDF_HIP_TRY(hipGetLastError());
+  return finish_reduction(r, nv, nrm, flags, s);
 }
 
 int nvec_max_norm(long n, const double* x, double* out, int flags, void* stream) {

@@ -4,10 +4,15 @@ Grouped Newton with block-diagonal solves and whole-step retry (Section 7);
 the BDF method itself is the fixed-coefficient Nordsieck reading.  Bars:
 mass-action f and J within 1e-13 of the oracle (relative to the term
 scale); one step from an identical state makes the same decisions and
-lands within 1e-6 in WRMS units; whole trajectories take the same number
-of steps and end within 1e-3 WRMS (if a decision flips near a threshold the
-step counts may differ and the bar becomes 1 WRMS, the tolerance itself);
-graph capture reproduces stream execution bit for bit.
+lands within 1e-6 in WRMS units; trajectories are compared in lockstep
+(parity_util.compare_trajectory): while every decision (attempts, Newton
+iterations, order) agrees the states at common times agree within
+1e-3 + 2e-5 per step WRMS (the rounding of the unconverged Newton iterates,
+derived and measured in parity_util) and the step-size drift is printed; a
+decision taken differently at a threshold is printed with the oracle's
+threshold quantities, and the runs must then end equally accurate against a
+tight-tolerance oracle run (the GPU's error within 3x the oracle's); graph
+capture reproduces stream execution bit for bit.
 """
 import numpy as np
 import pytest
@@ -18,13 +23,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def wrms_diff(a, b, rtol, atol):
-    w = 1.0 / (rtol * np.abs(b) + atol)
-    return float(np.sqrt(np.mean(((a - b) * w) ** 2)))
-
-
-def gpu_bdf(G, prob, dev, **kw):
-    return G.Bdf.from_problem(prob, device=dev, **kw)
+from parity_util import compare_trajectory, gpu_bdf, wrms_diff
 
 
 def jac_entries(prob):
@@ -83,41 +82,6 @@ def test_single_step_from_identical_state(orc, dev, G):
     assert st["h"] == pytest.approx(sc1["h"], rel=1e-12)
     z1, _ = ob.history()
     assert wrms_diff(st["z"][0].cpu().numpy(), z1[0], p.rtol, p.atol) <= 1e-6
-
-
-def compare_trajectory(orc, dev, G, p, **kw):
-    """Whole-trajectory parity.  Step-size and order decisions are
-    discontinuous in the rounding of the norms, so:
-    * identical decision sequences (steps, attempts, orders): the end states
-      agree within 0.1 WRMS, the Newton tolerance that defines each step's
-      result (rounding of near-zero components, weighted by 1/atol, is what
-      remains);
-    * a flipped decision: both runs must be equally accurate against a
-      tight-tolerance oracle run, and take a comparable number of steps."""
-    lin = kw.pop("linsol", 0)
-    rmi = kw.get("refine_max_it", 5)
-    ob = orc.Bdf(p, linsol=lin, refine_max_it=rmi)
-    assert ob.integrate(p.t_end) == 0
-    gb = gpu_bdf(G, p, dev, linsol=lin, **kw)
-    t = gb.integrate(p.t_end)
-    assert t == p.t_end
-    so, sg = ob.stats(), gb.stats()
-    yg, yo = gb.y().cpu().numpy(), ob.y()
-    d = wrms_diff(yg, yo, p.rtol, p.atol)
-    print(f"{p.label}: steps oracle {so['nsteps']} gpu {sg['nsteps']}, attempts "
-          f"{so['nattempts']}/{sg['nattempts']}, wrms diff {d:.3e}")
-    if so["nsteps"] == sg["nsteps"] and so["nattempts"] == sg["nattempts"]:
-        assert so["order_hist"] == sg["order_hist"]
-        assert d <= 0.1
-    else:
-        ref = orc.Bdf(p, rtol=p.rtol * 1e-3, atol=p.atol * 1e-3)
-        assert ref.integrate(p.t_end) == 0
-        yr = ref.y()
-        eg, eo = wrms_diff(yg, yr, p.rtol, p.atol), wrms_diff(yo, yr, p.rtol, p.atol)
-        print(f"  decisions differ: error vs reference gpu {eg:.3e} oracle {eo:.3e}")
-        assert eg <= max(3.0 * eo, 1.0)
-        assert abs(so["nsteps"] - sg["nsteps"]) <= 0.15 * so["nsteps"]
-    return ob, gb
 
 
 def test_trajectory_robertson_bdf2(orc, dev, G):
@@ -232,7 +196,7 @@ def test_max_steps_error(dev, G):
     b = gpu_bdf(G, p, dev, max_steps=4)
     with pytest.raises(G.BdfGpuError) as e:
         b.integrate(10.0)
-    assert e.value.code == -7
+    assert e.value.code == -4          # too much work
 
 
 def test_conservation_without_projection(dev, G):
@@ -245,13 +209,39 @@ def test_conservation_without_projection(dev, G):
     assert np.abs(y.sum(1) - p.y0.reshape(-1, 10).sum(1)).max() <= 1e-12
 
 
-def test_projection_large_batch(dev, G):
-    p = W.random_network_batch(4096, n=10, seed=8)
-    b = gpu_bdf(G, p, dev)
-    assert b.integrate(p.t_end) == p.t_end
-    y = b.y().cpu().numpy().reshape(-1, 10)
+def test_projection_matches_oracle(orc, dev, G):
+    """y >= 0 projection on a 1,024-cell batch that triggers it thousands of
+    times: lockstep parity with the oracle's projected run, every component
+    non-negative, and each cell's total mass equal to the oracle's within
+    1e3 atol.  (The projection adds the clipped negative parts to a cell's
+    mass; their total is a property of the trajectory, 1.2e-7 in the
+    worst cell of this batch for the oracle itself, so the GPU's mass is
+    held to the oracle's rather than to a fixed drift bound.)"""
+    p = W.random_network_batch(1024, n=10, seed=8)
+    ob, gb = compare_trajectory(orc, dev, G, p)
+    y = gb.y().cpu().numpy().reshape(-1, 10)
+    yo = ob.y().reshape(-1, 10)
     assert y.min() >= 0.0
-    # each projection adds at most the clipped negative parts (absolute-
-    # tolerance level); over thousands of steps the total stays below rtol
-    assert np.abs(y.sum(1) - p.y0.reshape(-1, 10).sum(1)).max() <= 10 * p.rtol
-    assert b.stats()["nprojections"] > 0
+    assert gb.stats()["nprojections"] > 0 and ob.stats()["nprojections"] > 0
+    m0 = p.y0.reshape(-1, 10).sum(1)
+    print(f"mass drift: gpu max {np.abs(y.sum(1) - m0).max():.3e}, "
+          f"oracle max {np.abs(yo.sum(1) - m0).max():.3e}")
+    assert np.abs(y.sum(1) - yo.sum(1)).max() <= 1e3 * p.atol
+
+
+def test_bench_kernel_parity_two_reduction_groups(orc, dev, G):
+    """The network-specialised Newton kernel the benchmark times, on 20,000
+    cells of the benchmark's network (313 one-wave blocks: two first-level
+    reduction groups, the last one ragged), 150 steps in lockstep with the
+    oracle."""
+    p = W.random_network_batch(20000, n=10, seed=W.BASE_SEED + 3)
+    compare_trajectory(orc, dev, G, p, max_steps=150, jit=True)
+
+
+def test_uneven_parity_2p16_unknowns(orc, dev, G):
+    """Uneven batch at 2^16 unknowns (about 2,300 cells of 4..64 species,
+    several blocks per class and reduction group), FP32-refined LU, graph
+    mode and the autotuned launch, 40 steps in lockstep with the oracle."""
+    p = W.uneven_batch(1 << 16, seed=W.BASE_SEED + 4)
+    compare_trajectory(orc, dev, G, p, max_steps=40, linsol=1, launch=G.LAUNCH_AUTO,
+                       mode=G.MODE_GRAPH, jit=True)

@@ -116,3 +116,50 @@ def test_refinement(orc, dev, G, nb, n):
     for b in range(nb):
         kap = np.linalg.cond(A[b], np.inf)
         assert np.abs(Xg[b] - X64[b]).max() <= 50 * n * U * kap * np.abs(X64[b]).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_uneven_block_sizes_var(orc, dev, G, dtype):
+    """Blocks of sizes 1..64 (the uneven batch's classes plus odd sizes) packed
+    one after the other, factored and solved in one launch each: per block
+    the pivots and info of the oracle, factors and solutions to the bars of
+    the uniform calls; an out-of-range size gets info = -1 and is untouched."""
+    rng = W.rng_for(77)
+    sizes = [int(s) for s in rng.choice([1, 3, 4, 8, 13, 16, 24, 32, 48, 64], size=90)]
+    sizes[5] = 65                               # outside 0..nmax: rejected per block
+    nmax = 64
+    f64 = dtype == "f64"
+    tdt, ndt = (torch.float64, np.float64) if f64 else (torch.float32, np.float32)
+    u = U if f64 else 2.0 ** -24
+    blocks = [W.random_blocks(1, n, seed=5000 + i, diag_shift=0.0 if f64 else 2.0)[0].astype(ndt)
+              for i, n in enumerate(sizes)]
+    packed = np.concatenate([b.ravel(order="F") for b in blocks])
+    rhs = [rng.uniform(-1, 1, n).astype(ndt) for n in sizes]
+    Ad = torch.tensor(packed, dtype=tdt, device=dev)
+    Bd = torch.tensor(np.concatenate(rhs), dtype=tdt, device=dev)
+    piv = torch.full((sum(sizes),), -7, dtype=torch.int32, device=dev)
+    info = torch.empty(len(sizes), dtype=torch.int32, device=dev)
+    G.batched_lu_factor_var(Ad, piv, info, sizes, nmax=nmax)
+    G.batched_lu_solve_var(Ad, piv, Bd, sizes, nmax=nmax)
+    LUg, pg, ig, xg = Ad.cpu().numpy(), piv.cpu().numpy(), info.cpu().numpy(), Bd.cpu().numpy()
+    mo = vo = 0
+    for i, n in enumerate(sizes):
+        A = blocks[i]
+        if n > nmax:
+            assert ig[i] == -1
+            assert np.array_equal(LUg[mo:mo + n * n], packed[mo:mo + n * n])
+            assert np.all(pg[vo:vo + n] == -7)
+        else:
+            fac = orc.lu_factor if f64 else orc.lu_factor_f32
+            sol = orc.lu_solve if f64 else orc.lu_solve_f32
+            LU, pv, inf = fac(A[None])
+            assert ig[i] == inf[0]
+            assert np.array_equal(pg[vo:vo + n], pv[0])
+            L = LUg[mo:mo + n * n].reshape(n, n, order="F")
+            scale = max(np.abs(A).max(), np.abs(LU).max())
+            assert np.all(np.abs(L - LU[0]) <= 200 * n * u * scale * (1 + np.abs(LU[0])))
+            X = sol(LU, pv, rhs[i][None])[0]
+            kap = np.linalg.cond(A.astype(np.float64), np.inf)
+            assert np.abs(xg[vo:vo + n] - X).max() <= 50 * n * u * kap * np.abs(X).max()
+        mo += n * n
+        vo += n

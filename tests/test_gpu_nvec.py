@@ -149,3 +149,37 @@ def test_full_size_microbench_parity(orc, dev, G):
     w = W.torch_uniform_device(n, seed=77, device=dev, lo=1e2, hi=1e8)
     v = G.nvec_wrms_norm(X[2], w)
     assert v == pytest.approx(orc.wrms_norm(X[2].cpu().numpy(), w.cpu().numpy()), rel=1e-12)
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("shared", [True, False])
+def test_wrms_norm_multi(orc, dev, G, n, shared):
+    """WRMS norms of 5 vectors in one pass, with one shared weight vector or
+    one per vector; each within 1e-12 relative of the oracle's WRMS norm of
+    that vector (host and device results)."""
+    nv = 5
+    X = W.uniform_vectors(nv, n, seed=600 + n)
+    Wv = [W.weight_vector(n, seed=700 + (0 if shared else j) + n) for j in range(nv)]
+    Xd = [T(x, dev) for x in X]
+    Wd = [T(w, dev) for w in Wv]
+    if shared:
+        Wd = [Wd[0]] * nv
+    got = G.nvec_wrms_norm_multi(Xd, Wd)
+    out = torch.empty(nv, dtype=torch.float64, device=dev)
+    G.nvec_wrms_norm_multi(Xd, Wd, out=out)
+    assert np.array_equal(np.array(got), out.cpu().numpy())
+    for j in range(nv):
+        ref = orc.wrms_norm(X[j], Wv[0] if shared else Wv[j]) if n else 0.0
+        assert abs(got[j] - ref) <= 1e-12 * abs(ref)
+
+
+def test_wrms_norm_multi_misaligned(orc, dev, G):
+    n = 10001
+    X = W.uniform_vectors(3, n + 1, seed=610)
+    w = W.weight_vector(n + 1, seed=611)
+    Xd = [T(x, dev)[1:] for x in X]
+    wd = T(w, dev)[1:]
+    got = G.nvec_wrms_norm_multi(Xd, [wd] * 3)
+    for j in range(3):
+        ref = orc.wrms_norm(X[j][1:], w[1:])
+        assert abs(got[j] - ref) <= 1e-12 * ref

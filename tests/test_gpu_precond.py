@@ -18,6 +18,7 @@ import pytest
 import torch
 
 import workloads as W
+from parity_util import compare_trajectory
 
 pytestmark = pytest.mark.gpu
 
@@ -136,37 +137,30 @@ def test_fit_normalization(dev, G):
 
 
 def test_learned_mode_trajectory_matches_oracle(orc, dev, G):
-    """Learned mode with one fixed (untrained) network: per-cell X r,
-    switches to LU, and attempt-level LU retries, against the oracle's
-    learned mode with the same weights.  X differs by the FP32-vs-FP64
-    accumulation of the MLP, so decisions may flip; then both runs must be
-    equally accurate against a tight plain-LU reference."""
+    """Learned mode with one fixed (untrained) network, in lockstep with the
+    oracle's learned mode with the same weights (per-cell X r, switches to
+    LU, attempt-level LU retries).  X differs by the FP32-vs-FP64
+    accumulation of the MLP, so a per-cell switch or a convergence test
+    can go the other way; the lockstep comparison prints the first such
+    step, holds the states before it to 1e-3 WRMS and the GPU's end-state
+    error against a tight FP64 reference to 3x the oracle's, with the
+    per-cell median and maximum differences printed."""
     p = W.learned_batch(48, t_end=3e-3)
     params = W.mlp_init(N21, seed=W.BASE_SEED + 6, out_scale=0.02)
     Xs = np.hstack([p.y0.reshape(-1, N21), np.full((48, 1), -8.0)])
     mean, std = norm_of(Xs)
     std[:] = np.maximum(std, 0.1)
-    ob = orc.Bdf(p, linsol=orc.LS_LEARNED, mlp=oracle_mlp(orc, params, mean, std))
-    assert ob.integrate(p.t_end) == 0
     pc = G.Precond(N21, batch_cap=128)
     pc.set_params(params)
     pc.set_normalization(mean, std)
-    gb = G.Bdf.from_problem(p, device=dev, linsol=G.LS_LEARNED, precond=pc)
-    assert gb.integrate(p.t_end) == p.t_end
+    ob, gb = compare_trajectory(orc, dev, G, p, okw={"mlp": oracle_mlp(orc, params, mean, std)},
+                                linsol=G.LS_LEARNED, precond=pc)
     so, sg = ob.stats(), gb.stats()
-    print("oracle", {k: so[k] for k in ("nsteps", "nattempts", "nniters", "lp_cell_solves",
-                                        "lp_fallback_cells", "lp_step_fallbacks")})
-    print("gpu   ", {k: sg[k] for k in ("nsteps", "nattempts", "nniters", "lp_cell_solves",
-                                        "lp_fallback_cells", "lp_step_fallbacks")})
-    assert sg["lp_cell_solves"] > 0
-    yg, yo = gb.y().cpu().numpy(), ob.y()
-    ref = orc.Bdf(p, rtol=p.rtol * 1e-3, atol=p.atol * 1e-3)
-    assert ref.integrate(p.t_end) == 0
-    yr = ref.y()
-    w = lambda a: float(np.sqrt(np.mean(((a - yr) / (p.rtol * np.abs(yr) + p.atol)) ** 2)))
-    print(f"error vs reference: gpu {w(yg):.3e} oracle {w(yo):.3e}")
-    assert w(yg) <= max(3.0 * w(yo), 1.0)
-    assert abs(so["nsteps"] - sg["nsteps"]) <= max(3, 0.15 * so["nsteps"])
+    keys = ("nsteps", "nattempts", "nniters", "lp_cell_solves", "lp_fallback_cells",
+            "lp_step_fallbacks")
+    print("oracle", {k: so[k] for k in keys})
+    print("gpu   ", {k: sg[k] for k in keys})
+    assert sg["lp_cell_solves"] > 0 and so["lp_cell_solves"] > 0
     gb.close()
     pc.close()
 
