@@ -76,10 +76,11 @@ def time_advance(b, t_end, steps, torch):
     return time.perf_counter() - t0, taken, t
 
 
-def bdf_leg(G, W, torch, prob, dev, warmup, steps, linsol, precond=None, jit=True, graph=False):
+def bdf_leg(G, W, torch, prob, dev, warmup, steps, linsol, precond=None, jit=True, graph=False,
+            defer=True):
     b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_GRAPH if graph else G.MODE_STREAM,
                            attempts_per_sync=16, linsol=linsol, maxcor=MAXCOR, precond=precond,
-                           jit=jit)
+                           jit=jit, defer=defer)
     b.advance(prob.t_end, warmup)
     s0 = b.stats()
     dt, taken, t = time_advance(b, prob.t_end, steps, torch)
@@ -332,6 +333,8 @@ def main():
     ap.add_argument("--profile-warmup", type=int, default=60,
                     help="steps before the kernel-timing window (order 5 is reached by then)")
     ap.add_argument("--graph", action="store_true")
+    ap.add_argument("--no-defer", action="store_true",
+                    help="separate history-update kernel instead of the deferred update")
     ap.add_argument("--no-jit", action="store_true",
                     help="generic table-driven Newton kernels instead of network-specialised ones")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -367,7 +370,7 @@ def main():
 
     log("FP64 LU leg")
     b, dt, taken, s0, s1 = bdf_leg(G, W, torch, prob, dev, args.warmup, args.steps, G.LS_LU64,
-                                   jit=not args.no_jit, graph=args.graph)
+                                   jit=not args.no_jit, graph=args.graph, defer=not args.no_defer)
     value = args.cells * taken / dt
     ms_per_step = 1e3 * dt / max(taken, 1)
     attempts = s1["nattempts"] - s0["nattempts"]
@@ -383,7 +386,8 @@ def main():
     # attempts per status read, launches enqueued after the step limit return
     # at once); advanced past the order ramp before the timing window.
     pb = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_STREAM, attempts_per_sync=1,
-                            linsol=G.LS_LU64, maxcor=MAXCOR, jit=not args.no_jit)
+                            linsol=G.LS_LU64, maxcor=MAXCOR, jit=not args.no_jit,
+                            defer=not args.no_defer)
     pb.advance(prob.t_end, args.profile_warmup)
     pb.set_profiling(True)
     ps0 = pb.stats()
@@ -398,10 +402,20 @@ def main():
         raise RuntimeError(f"timed {p_cnt} Newton launches for {p_att} attempts")
     q1 = (ps1["hist_reads"] - ps0["hist_reads"]) / max(p_att, 1)   # mean q + 1
     # The step's algorithmic bytes per cell are 8 (2 (q+1) n + R): the
-    # history read and written once and the rates read once.  The fused
-    # Newton kernel's share is the read half, 8 ((q+1) n + R); the history
-    # update's the write half.
-    bytes_per_launch = 8.0 * args.cells * (q1 * n + R)
+    # history read and written once and the rates read once.  With the
+    # deferred update the Newton kernel does all of it (the history write of
+    # an accepted step happens in the next attempt's kernel): per launch,
+    # the step bytes times accepted steps per launch.  With a separate
+    # history update the Newton kernel's share is the read half,
+    # 8 ((q+1) n + R), and the update's the write half.
+    deferred = kt["accept"][1] == 0
+    if deferred:
+        bytes_per_launch = 8.0 * args.cells * (2 * q1 * n + R) * ptaken / max(p_att, 1)
+        alg = "8 * cells * (2 (q+1) n + R) per accepted step (history read and written, rates " \
+              "read), times accepted steps per launch"
+    else:
+        bytes_per_launch = 8.0 * args.cells * (q1 * n + R)
+        alg = "8 * cells * ((q+1) * n + R): history read + rates"
     avg_ms = p_ms / max(p_att, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     sha = sources_hash(NEWTON_SOURCES)
@@ -415,13 +429,14 @@ def main():
     roofline = {"bound": "hbm",
                 "kernel": ("k_tpc_newton<10,0>" if args.no_jit else
                            "bdf_newton_net_np10_ls0 (k_tpc_newton<10,0> specialised to the network)")
-                          + " (predictor, J, LU, 3 Newton iterations)",
+                          + (" (history update of the previous step, predictor, J, LU, 3 Newton "
+                             "iterations)" if deferred else " (predictor, J, LU, 3 Newton iterations)"),
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "newton_sources_sha256_16": sha,
                 "avg_launch_ms": round(avg_ms, 4), "launches": p_cnt, "attempts": p_att,
                 "algorithmic_bytes_per_launch": int(bytes_per_launch),
-                "algorithmic_bytes": "8 * cells * ((q+1) * n + R): history read + rates",
+                "algorithmic_bytes": alg, "deferred_history_update": deferred,
                 "mean_q_plus_1": round(q1, 3),
                 "group_ms": {k: [round(v[0], 3), v[1]] for k, v in kt.items()},
                 "step": {"algorithmic_bytes_per_step": int(step_bytes),

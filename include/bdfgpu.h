@@ -35,6 +35,8 @@
 #ifndef BDFGPU_H
 #define BDFGPU_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -250,6 +252,16 @@ typedef struct {
                              generic kernel.  0: generic kernels only.  Error
                              BDFGPU_ERR_HIP with the end of the compiler log if
                              compilation or loading fails. */
+  int no_defer;           /* 0: with per-class launches of one-lane-per-cell
+                             classes (FP64 or FP32-refined LU), an accepted
+                             step's history update z_new = z(0) + l acor is
+                             applied by the next attempt's Newton kernel as it
+                             reads the history (and by the end of each
+                             bdf_step / bdf_integrate / bdf_advance call), so
+                             the history crosses HBM once per step; the order
+                             selection's norms are summed per Newton iteration.
+                             Results are those of the separate update.
+                             1: a separate history-update kernel per attempt. */
 } bdf_options;
 
 typedef struct {
@@ -271,6 +283,22 @@ typedef struct bdf_handle bdf_handle;
  * every later call on the handle. */
 int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream,
                bdf_handle** out);
+/* Device bytes bdf_create_ws needs for this problem and these options (the
+ * history, iterates, rates, network tables, reduction partials and control
+ * block of every class; with BDFGPU_LAUNCH_AUTO the largest candidate).  No
+ * device memory is touched and the problem's rates and y0 may be NULL; 0
+ * for an invalid problem or options. */
+size_t bdf_workspace_bytes(const bdf_problem* p, const bdf_options* o);
+/* bdf_create with every piece of device state carved from the caller's
+ * workspace ws (DEVICE memory, 256-byte aligned, ws_bytes >=
+ * bdf_workspace_bytes) instead of hipMalloc: the caller owns the memory
+ * and frees it after bdf_destroy, which frees only host-side handle memory
+ * (the SUNMemory ownership rule of Section 3).  The library zeroes what it
+ * needs.  BDFGPU_ERR_WORKSPACE if ws is NULL or too small.  (The
+ * diagnostic calls bdf_eval_rhs_jac and bdf_capture_blocks still allocate
+ * their own temporaries.) */
+int bdf_create_ws(const bdf_problem* p, const bdf_options* o, void* ws,
+                  size_t ws_bytes, void* stream, bdf_handle** out);
 int bdf_destroy(bdf_handle* h);
 /* Launch configuration in use (launch: BDFGPU_LAUNCH_PER_CLASS or _FUSED;
  * map_small as in bdf_options) and, after BDFGPU_LAUNCH_AUTO, the timed

@@ -282,12 +282,15 @@ class Bdf:
     topologies: list of (nu, mu) integer arrays of shape (R, n);
     cell_topo: int array (ncells,); rates, y0: float64 device tensors
     (concatenated per cell).  jit: compile network-specialised Newton
-    kernels for the one-lane-per-cell classes (bitwise the same results)."""
+    kernels for the one-lane-per-cell classes (bitwise the same results).
+    defer: apply each accepted step's history update in the next attempt's
+    Newton kernel (where the classes allow it) instead of a separate pass."""
 
     def __init__(self, topologies, cell_topo, rates, y0, t0=0.0, rtol=1e-6, atol=1e-10,
                  qmax=5, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64, refine_max_it=5,
                  max_steps=0, mode=MODE_STREAM, attempts_per_sync=8, nonneg=False,
-                 precond=None, launch=LAUNCH_PER_CLASS, map_small=0, jit=False):
+                 precond=None, launch=LAUNCH_PER_CLASS, map_small=0, jit=False, defer=True,
+                 workspace=None):
         torch = _torch()
         _dev(rates, torch.float64)
         _dev(y0, torch.float64)
@@ -306,12 +309,52 @@ class Bdf:
         opts = BdfOptions(rtol, atol, qmax, maxcor, h0, hmin, linsol, refine_max_it, max_steps,
                           mode, attempts_per_sync, launch,
                           precond.h if precond is not None else None, int(bool(nonneg)),
-                          int(map_small), int(bool(jit)))
+                          int(map_small), int(bool(jit)), int(not defer))
         h = vp()
-        check("bdf_create", lib().bdf_create(C.byref(prob), C.byref(opts), _stream(), C.byref(h)))
+        if workspace is None:
+            check("bdf_create", lib().bdf_create(C.byref(prob), C.byref(opts), _stream(),
+                                                 C.byref(h)))
+        else:
+            # caller-owned device workspace (a uint8 tensor kept alive by
+            # the handle), sized with workspace_bytes
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous device tensor")
+            self._keep.append(workspace)
+            check("bdf_create_ws", lib().bdf_create_ws(
+                C.byref(prob), C.byref(opts), _p(workspace),
+                workspace.numel() * workspace.element_size(), _stream(), C.byref(h)))
         self.h = h
         self.N = lib().bdf_get_N(h)
         self.device = y0.device
+
+    @staticmethod
+    def workspace_bytes(prob, **kw):
+        """Device bytes a handle of this problem and these options needs
+        (bdf_workspace_bytes); options as for the constructor."""
+        return Bdf._sizing(prob, **kw)
+
+    @staticmethod
+    def _sizing(prob, rtol=None, atol=None, qmax=None, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64,
+                refine_max_it=5, max_steps=0, mode=MODE_STREAM, attempts_per_sync=8,
+                nonneg=None, launch=LAUNCH_PER_CLASS, map_small=0, jit=False, defer=True,
+                precond=None):
+        topologies = prob["topologies"]
+        topo_n = np.array([nu.shape[1] for nu, _ in topologies], np.int32)
+        topo_R = np.array([nu.shape[0] for nu, _ in topologies], np.int32)
+        off = np.concatenate([[0], np.cumsum(topo_n * topo_R)[:-1]]).astype(np.int32)
+        nu_all = np.concatenate([np.ascontiguousarray(nu, np.int32).ravel() for nu, _ in topologies]).astype(np.int32)
+        mu_all = np.concatenate([np.ascontiguousarray(mu, np.int32).ravel() for _, mu in topologies]).astype(np.int32)
+        ct = np.ascontiguousarray(prob["cell_topo"], np.int32)
+        ipt = lambda a: a.ctypes.data_as(ip)
+        pr = BdfProblem(len(topo_n), ipt(topo_n), ipt(topo_R), ipt(off), ipt(nu_all), ipt(mu_all),
+                        len(ct), ipt(ct), None, None, float(prob["t0"]))
+        opts = BdfOptions(prob["rtol"] if rtol is None else rtol, prob["atol"] if atol is None else atol,
+                          prob["qmax"] if qmax is None else qmax, maxcor, h0, hmin, linsol,
+                          refine_max_it, max_steps, mode, attempts_per_sync, launch,
+                          precond.h if precond is not None else None,
+                          int(bool(prob.get("nonneg", False) if nonneg is None else nonneg)),
+                          int(map_small), int(bool(jit)), int(not defer))
+        return int(lib().bdf_workspace_bytes(C.byref(pr), C.byref(opts)))
 
     @classmethod
     def from_problem(cls, prob, device="cuda", **kw):

@@ -32,7 +32,7 @@ class BdfOptions(C.Structure):
                 ("linsol", C.c_int), ("refine_max_it", C.c_int), ("max_steps", C.c_long),
                 ("mode", C.c_int), ("attempts_per_sync", C.c_int), ("launch", C.c_int),
                 ("precond", vp), ("nonneg", C.c_int), ("map_small", C.c_int),
-                ("jit", C.c_int)]
+                ("jit", C.c_int), ("no_defer", C.c_int)]
 
 
 class BdfStats(C.Structure):
@@ -75,6 +75,9 @@ SIGNATURES = {
     "batched_lu_solve_f32_var": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]),
     "batched_lu_solve_refine": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]),
     "bdf_create": (C.c_int, [C.POINTER(BdfProblem), C.POINTER(BdfOptions), vp, C.POINTER(vp)]),
+    "bdf_workspace_bytes": (C.c_size_t, [C.POINTER(BdfProblem), C.POINTER(BdfOptions)]),
+    "bdf_create_ws": (C.c_int, [C.POINTER(BdfProblem), C.POINTER(BdfOptions), vp, C.c_size_t, vp,
+                                C.POINTER(vp)]),
     "bdf_destroy": (C.c_int, [vp]),
     "bdf_get_tuning": (C.c_int, [vp, ip, ip, dp]),
     "bdf_step": (C.c_int, [vp, C.c_double, dp]),

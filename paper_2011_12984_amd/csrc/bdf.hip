@@ -50,6 +50,8 @@ struct ClassHost {
   ClassDev dev;
 };
 
+__global__ void k_clear_upd(Ctrl* C) { C->upd = 0; }
+
 __global__ void k_resume(Ctrl* C, double tend, long inc) {
   C->tend = tend;
   const long lim = C->nsteps + inc;
@@ -162,6 +164,7 @@ struct bdf_handle {
   unsigned int nblocks_total = 0;  // per-class launches
   unsigned int nblocks_multi = 0;  // single launch over all classes
   bool fused = false;              // launch mode in use
+  bool defer = false;              // deferred history update (Ctrl::fuse)
   bool fusable = false;
   size_t multi_lds[4] = {0, 0, 0, 0};
   // autotuning record: candidate (launch, map_small) -> ms per step (-1 if
@@ -180,11 +183,41 @@ struct bdf_handle {
   size_t ev_used = 0;            // pairs recorded since the last fold
   double prof_ms[3] = {0, 0, 0};
   long prof_cnt[3] = {0, 0, 0};
+  // device state in caller memory (bdf_create_ws) or counted only
+  // (bdf_workspace_bytes: a dry run of the creation that touches no device)
+  char* ws = nullptr;
+  size_t ws_size = 0, ws_used = 0;
+  bool dry = false;
 };
 
+constexpr size_t kWsAlign = 256;
+
+// Device memory of the handle: from the caller's workspace when one was
+// given (256-byte aligned pieces, in creation order), else hipMalloc'd and
+// freed by bdf_destroy.
 static int dalloc(bdf_handle* h, void** p, size_t bytes) {
-  BDF_HIP_TRY(hipMalloc(p, bytes < 16 ? 16 : bytes));
+  bytes = bytes < 16 ? 16 : bytes;
+  if (h->dry || h->ws) {
+    const size_t off = (h->ws_used + kWsAlign - 1) / kWsAlign * kWsAlign;
+    if (!h->dry && off + bytes > h->ws_size) {
+      set_last_error("bdf_create_ws: workspace too small (see bdf_workspace_bytes)", __FILE__,
+                     __LINE__);
+      return BDFGPU_ERR_WORKSPACE;
+    }
+    h->ws_used = off + bytes;
+    *p = h->dry ? nullptr : h->ws + off;
+    return 0;
+  }
+  BDF_HIP_TRY(hipMalloc(p, bytes));
   h->allocs.push_back(*p);
+  return 0;
+}
+
+// zero-filled device memory (nothing in a dry run)
+static int dalloc_zero(bdf_handle* h, void** p, size_t bytes) {
+  int st = dalloc(h, p, bytes);
+  if (st || h->dry) return st;
+  BDF_HIP_TRY(hipMemsetAsync(*p, 0, bytes < 16 ? 16 : bytes, h->s));
   return 0;
 }
 
@@ -192,7 +225,8 @@ template <typename T>
 static int upload(bdf_handle* h, T** d, const std::vector<T>& v) {
   int st = dalloc(h, reinterpret_cast<void**>(d), sizeof(T) * std::max<size_t>(1, v.size()));
   if (st) return st;
-  if (!v.empty()) BDF_HIP_TRY(hipMemcpy(*d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  if (!v.empty() && !h->dry)
+    BDF_HIP_TRY(hipMemcpy(*d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
   return 0;
 }
 
@@ -204,6 +238,7 @@ static BdfDev make_dev(bdf_handle* h, const ClassHost& c) {
   D.rtol = h->o.rtol;
   D.atol = h->o.atol;
   D.nonneg = h->o.nonneg ? 1 : 0;
+  D.defer = h->defer ? 1 : 0;
   D.k = c.dev;
   D.k.blk0 = c.blk0;
   return D;
@@ -264,9 +299,11 @@ static void launch_phase_kernels(bdf_handle* h, int which, hipStream_t s) {
     return;
   }
   for (const ClassHost& c : h->cls) {
+    if (which == 5 && c.map != MAP_TPC) continue;   // flush: thread-per-cell classes only
     BdfDev D = make_dev(h, c);
     if (c.map == MAP_TPC && which == 2 && c.jit) {
-      c.jit(&D, c.grid, (unsigned int)tpc_newton_lds(c.np, c.R, h->o.linsol, kTpcThreads), s);
+      c.jit(&D, c.grid,
+            (unsigned int)tpc_newton_lds(c.np, c.R, h->o.linsol, kTpcThreads, h->defer), s);
     } else if (c.map == MAP_TPC)
       launch_tpc(c.np, h->o.linsol, which, D, c.grid, s);
     else
@@ -320,10 +357,22 @@ static void enqueue_attempt(bdf_handle* h, hipStream_t s) {
   launch_phase_kernels(h, 2, s);
   prof_mark(h, 0, false, s);
   launch_control(h, 2, s);
+  if (h->defer) return;   // the next Newton kernel updates the history
   prof_mark(h, 2, true, s);
   launch_phase_kernels(h, 3, s);
   prof_mark(h, 2, false, s);
   launch_control(h, 3, s);
+}
+
+// Deferred history update: apply the last accepted attempt's update before
+// the host reads or replaces the state (the flush kernels return at once
+// when none is pending), then clear the pending flag.
+static int flush_update(bdf_handle* h) {
+  if (!h->defer) return 0;
+  launch_phase_kernels(h, 5, h->s);
+  hipLaunchKernelGGL(k_clear_upd, dim3(1), dim3(1), 0, h->s, h->dC);
+  BDF_HIP_TRY(hipGetLastError());
+  return 0;
 }
 
 static int read_ctrl(bdf_handle* h) {
@@ -373,11 +422,17 @@ static int drive(bdf_handle* h, double tend, long inc, double* tret) {
     prof_fold(h);
     const int ph = h->hC->phase;
     if (ph == PH_ERROR) {
+      if ((st = flush_update(h))) return st;
+      BDF_HIP_TRY(hipStreamSynchronize(h->s));
       if (tret) *tret = h->hC->t;
       set_last_error("integrator failure (see status code)", __FILE__, __LINE__);
       return h->hC->status;
     }
-    if (ph == PH_DONE || ph == PH_PAUSE) break;
+    if (ph == PH_DONE || ph == PH_PAUSE) {
+      if ((st = flush_update(h))) return st;
+      BDF_HIP_TRY(hipStreamSynchronize(h->s));
+      break;
+    }
     const long progress = h->hC->nattempts + h->hC->nsteps;
     if (progress == last_progress) {
       set_last_error("integrator made no progress (phase stuck)", __FILE__, __LINE__);
@@ -391,11 +446,12 @@ static int drive(bdf_handle* h, double tend, long inc, double* tret) {
 
 extern "C" {
 
-static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
-                       bdf_handle** out) {
+static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream, void* ws,
+                       size_t ws_bytes, bool dry, bdf_handle** out) {
   if (!p || !o || !out) return arg_error("bdf_create: null argument");
   if (p->ncells < 0 || p->ntopo < 1 || !p->topo_n || !p->topo_R || !p->topo_off ||
-      !p->nu_all || !p->mu_all || (p->ncells > 0 && (!p->cell_topo || !p->rates || !p->y0)))
+      !p->nu_all || !p->mu_all ||
+      (p->ncells > 0 && (!p->cell_topo || (!dry && (!p->rates || !p->y0)))))
     return arg_error("bdf_create: bad problem description");
   if (o->qmax < 1 || o->qmax > kQmaxAll || o->maxcor < 1 || o->maxcor > kMaxCor ||
       !(o->rtol >= 0.0) || !(o->atol > 0.0) ||
@@ -406,6 +462,9 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   *out = nullptr;
   bdf_handle* h = new bdf_handle();
   h->s = as_stream(stream);
+  h->ws = static_cast<char*>(ws);
+  h->ws_size = ws_bytes;
+  h->dry = dry;
   h->o = *o;
   if (h->o.refine_max_it <= 0) h->o.refine_max_it = 5;
   h->ncells = p->ncells;
@@ -427,12 +486,16 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   long blk = 0, mblk = 0;
   int st = 0;
   // per-workgroup LDS limit (160 KiB on gfx950; 64 KiB assumed if unknown)
+  // (a dry run without a usable device assumes gfx950's 160 KiB)
   int dev = 0, lds_max = 0;
-  BDF_HIP_TRY(hipGetDevice(&dev));
-  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
-          hipSuccess ||
-      lds_max < 65536)
+  if (hipGetDevice(&dev) != hipSuccess) {
+    if (!dry) BDF_HIP_TRY(hipGetDevice(&dev));
+    lds_max = 160 * 1024;
+  } else if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                 hipSuccess ||
+             lds_max < 65536) {
     lds_max = 65536;
+  }
   for (auto& kv : members) {
     const int t = kv.first;
     const int n = p->topo_n[t], R = p->topo_R[t];
@@ -466,7 +529,7 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     }
     ch.np = ch.map == MAP_TPC ? tpc_padded(n) : spc_seg(n);
     // network-specialised Newton kernel
-    if (o->jit && ch.map == MAP_TPC) {
+    if (o->jit && ch.map == MAP_TPC && !dry) {
       st = jit_newton(net_newton_source(nu, mu, n, R, ch.np, o->linsol), &ch.jit);
       if (st) {
         bdf_destroy(h);
@@ -548,15 +611,12 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     K.R = R;
     K.net = nd;
     K.refine_max_it = h->o.refine_max_it;
-    for (int j = 0; j <= kQmaxAll; ++j) {
-      if ((st = dalloc(h, (void**)&K.z[j], vbytes))) { bdf_destroy(h); return st; }
-      BDF_HIP_TRY(hipMemset(K.z[j], 0, vbytes));
-    }
-    if ((st = dalloc(h, (void**)&K.dprev, vbytes))) {
+    for (int j = 0; j <= kQmaxAll; ++j)
+      if ((st = dalloc_zero(h, (void**)&K.z[j], vbytes))) { bdf_destroy(h); return st; }
+    if ((st = dalloc_zero(h, (void**)&K.dprev, vbytes))) {
       bdf_destroy(h);
       return st;
     }
-    BDF_HIP_TRY(hipMemset(K.dprev, 0, vbytes));
     for (int m = 0; m < o->maxcor; ++m)
       if ((st = dalloc(h, (void**)&K.ys[m], vbytes))) {
         bdf_destroy(h);
@@ -572,11 +632,11 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
       }
     }
     double* rates = nullptr;
-    if ((st = dalloc(h, (void**)&rates, sizeof(double) * (size_t)std::max<long>(1, cap_cells * R)))) {
+    if ((st = dalloc_zero(h, (void**)&rates,
+                          sizeof(double) * (size_t)std::max<long>(1, cap_cells * R)))) {
       bdf_destroy(h);
       return st;
     }
-    BDF_HIP_TRY(hipMemset(rates, 0, sizeof(double) * (size_t)std::max<long>(1, cap_cells * R)));
     K.rates = rates;
     std::vector<long> cy(ch.ncells), cr(ch.ncells);
     for (long i = 0; i < ch.ncells; ++i) {
@@ -587,7 +647,7 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
       bdf_destroy(h);
       return st;
     }
-    if (ch.ncells > 0) {
+    if (ch.ncells > 0 && !dry) {
       const unsigned int gy = ceil_div(ch.ncells * n, 256), gr = ceil_div(ch.ncells * (long)R, 256);
       hipLaunchKernelGGL(k_to_class, dim3(gy), dim3(256), 0, h->s, ch.ncells, n, (int)tiled,
                          ch.d_yoff, p->y0, K.z[0], 1.0);
@@ -616,6 +676,11 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
                      "preconditioner and per-block LDS within the device limit");
   }
   h->fused = o->launch == BDFGPU_LAUNCH_FUSED;
+  // deferred history update: per-class launches of thread-per-cell classes
+  // with FP64 or FP32-refined LU
+  h->defer = !o->no_defer && !h->fused && o->linsol != BDFGPU_LS_LEARNED && !h->cls.empty();
+  for (const ClassHost& c : h->cls)
+    if (c.map != MAP_TPC) h->defer = false;
   const long bmax = std::max(blk, mblk);
   const long ngroups = std::max<long>(1, (bmax + kRedGroup - 1) / kRedGroup);
   if ((st = dalloc(h, (void**)&h->partials, sizeof(double) * kRedMax * std::max<long>(1, bmax))) ||
@@ -623,6 +688,10 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
       (st = dalloc(h, (void**)&h->dC, sizeof(Ctrl)))) {
     bdf_destroy(h);
     return st;
+  }
+  if (dry) {   // sizes counted: nothing was allocated or launched
+    *out = h;
+    return 0;
   }
   BDF_HIP_TRY(hipHostMalloc((void**)&h->hC, sizeof(Ctrl), hipHostMallocDefault));
   Ctrl C;
@@ -639,6 +708,7 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   C.maxcor = o->maxcor;
   C.phase = h->N > 0 ? PH_INIT1 : PH_DONE;
   C.learned = o->linsol == BDFGPU_LS_LEARNED ? 1 : 0;
+  C.fuse = h->defer ? 1 : 0;
   C.step_limit = LONG_MAX;
   BDF_HIP_TRY(hipMemcpyAsync(h->dC, &C, sizeof(Ctrl), hipMemcpyHostToDevice, h->s));
   BDF_HIP_TRY(hipStreamSynchronize(h->s));
@@ -660,9 +730,10 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
 // fastest is then built for the caller.
 static constexpr int kTuneWarm = 4, kTuneSteps = 12;
 
-int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_handle** out) {
+static int create_tuned(const bdf_problem* p, const bdf_options* o, void* stream, void* ws,
+                        size_t ws_bytes, bdf_handle** out) {
   if (!p || !o || !out) return arg_error("bdf_create: null argument");
-  if (o->launch != BDFGPU_LAUNCH_AUTO) return create_impl(p, o, stream, out);
+  if (o->launch != BDFGPU_LAUNCH_AUTO) return create_impl(p, o, stream, ws, ws_bytes, false, out);
   bool small = false;
   for (long c = 0; c < p->ncells && !small; ++c) {
     const int t = p->cell_topo ? p->cell_topo[c] : -1;
@@ -678,7 +749,7 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
       o2.map_small = msm;
       o2.mode = BDFGPU_MODE_STREAM;
       bdf_handle* t = nullptr;
-      int st = create_impl(p, &o2, stream, &t);
+      int st = create_impl(p, &o2, stream, ws, ws_bytes, false, &t);
       if (st) {
         if (launch == 1) continue;   // no single launch for this problem
         return st;
@@ -707,12 +778,53 @@ int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_han
   bdf_options o3 = *o;
   o3.launch = bl;
   o3.map_small = bm;
-  int st = create_impl(p, &o3, stream, out);
+  int st = create_impl(p, &o3, stream, ws, ws_bytes, false, out);
   if (st) return st;
   for (int k = 0; k < 4; ++k) (*out)->tune_ms[k] = ms[k];
   (*out)->tune_launch = bl;
   (*out)->tune_map_small = bm;
   return 0;
+}
+
+int bdf_create(const bdf_problem* p, const bdf_options* o, void* stream, bdf_handle** out) {
+  return create_tuned(p, o, stream, nullptr, 0, out);
+}
+
+int bdf_create_ws(const bdf_problem* p, const bdf_options* o, void* ws, size_t ws_bytes,
+                  void* stream, bdf_handle** out) {
+  if (!ws && ws_bytes > 0) return arg_error("bdf_create_ws: null workspace");
+  if (!ws) {
+    if (out) *out = nullptr;
+    set_last_error("bdf_create_ws: no workspace (see bdf_workspace_bytes)", __FILE__, __LINE__);
+    return BDFGPU_ERR_WORKSPACE;
+  }
+  if (reinterpret_cast<uintptr_t>(ws) % kWsAlign != 0)
+    return arg_error("bdf_create_ws: workspace must be 256-byte aligned");
+  return create_tuned(p, o, stream, ws, ws_bytes, out);
+}
+
+size_t bdf_workspace_bytes(const bdf_problem* p, const bdf_options* o) {
+  if (!p || !o) return 0;
+  size_t need = 0;
+  auto count = [&](const bdf_options& oc) -> bool {
+    bdf_handle* t = nullptr;
+    if (create_impl(p, &oc, nullptr, nullptr, 0, true, &t) != 0) return false;
+    need = std::max(need, t->ws_used);
+    bdf_destroy(t);
+    return true;
+  };
+  if (o->launch != BDFGPU_LAUNCH_AUTO) return count(*o) ? need : 0;
+  // the autotuner builds every candidate in the same workspace, one at a time
+  bool ok = false;
+  for (int launch = 0; launch < 2; ++launch)
+    for (int msm = 0; msm < 2; ++msm) {
+      bdf_options oc = *o;
+      oc.launch = launch;
+      oc.map_small = msm;
+      oc.mode = BDFGPU_MODE_STREAM;
+      ok = count(oc) || ok;
+    }
+  return ok ? need : 0;
 }
 
 int bdf_get_tuning(bdf_handle* h, int* launch, int* map_small, double* ms_per_step) {
@@ -883,6 +995,7 @@ int bdf_set_state(bdf_handle* h, const double* dvals, const int* ivals, const do
   C.qwait = ivals[1];
   for (int j = 0; j < kQmaxAll + 2; ++j) C.hs[j] = 1.0;
   C.restart = 0;
+  C.upd = 0;   // the given history replaces any pending update
   C.ncf = 0;
   C.netf = 0;
   C.phase = PH_PAUSE;
@@ -951,8 +1064,10 @@ int bdf_eval_rhs_jac(bdf_handle* h, const double* y, double* f, double* J) {
     }
     for (size_t k = 0; k < h->cls.size(); ++k) {
       long* d = nullptr;
-      int st = upload(h, &d, jo[k]);
-      if (st) return st;
+      BDF_HIP_TRY(hipMalloc(&d, sizeof(long) * std::max<size_t>(1, jo[k].size())));
+      h->allocs.push_back(d);
+      if (!jo[k].empty())
+        BDF_HIP_TRY(hipMemcpy(d, jo[k].data(), sizeof(long) * jo[k].size(), hipMemcpyHostToDevice));
       h->d_joff.push_back(d);
     }
   }

@@ -69,6 +69,7 @@ struct BdfDev {
   unsigned int nblocks_total;
   double rtol, atol;
   int nonneg;
+  int defer;             // deferred history update (host copy of Ctrl::fuse, for LDS sizing)
   ClassDev k;
 };
 
@@ -486,14 +487,100 @@ __device__ __forceinline__ void tpc_load_vec(const double* v, long c, int n, dou
   }
 }
 
+// Deferred history update (Ctrl::fuse): the accepted previous attempt, of
+// order UQ, left its corrected solution in iterate upd_m; z_new[j] =
+// z(0)[j] + l_j acor is formed from the stored history (pending scale
+// upd_hs) exactly as the separate history-update kernel forms it, written
+// back (with z[UQ+1] = craise acor when that step could raise the order),
+// and returned unscaled in zs (rows 0..UQ+1), with acor.  All loads go out
+// in one batch.
+template <int NP, int UQ>
+__device__ __forceinline__ void tpc_apply_update_q(const BdfDev& D, long c, int n,
+                                                   double (&zs)[kQmaxAll + 1][NP],
+                                                   double (&acor)[NP]) {
+  const Ctrl* C = D.C;
+  const ClassDev& K = D.k;
+  const double* ysrc = K.ys[C->upd_m];
+  double yv[NP];
+#pragma unroll
+  for (int j = 0; j <= kQmaxAll; ++j) {
+    if (j <= UQ) {
+      const double hsj = C->upd_hs[j];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        const int ii = i < n ? i : n - 1;
+        const double v = K.z[j][Tpc<NP>::idx(c, ii, n)];
+        zs[j][i] = i < n ? v * hsj : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NP; ++i) zs[j][i] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int ii = i < n ? i : n - 1;
+    const double v = ysrc[Tpc<NP>::idx(c, ii, n)];
+    yv[i] = i < n ? v : 0.0;
+  }
+  const double l0 = C->upd_l[0];
+  const bool raise = UQ < kQmaxAll && C->upd_raise;
+  const double craise = C->upd_craise;
+  double lj[UQ + 1];
+#pragma unroll
+  for (int j = 0; j <= UQ; ++j) lj[j] = C->upd_l[j];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+#pragma unroll
+    for (int k = 1; k <= UQ; ++k)
+#pragma unroll
+      for (int j = UQ; j >= k; --j) zs[j - 1][i] = zs[j - 1][i] + zs[j][i];
+    const double yp = D.nonneg && yv[i] < 0.0 ? 0.0 : yv[i];
+    const double a = i < n ? (yp - zs[0][i]) / l0 : 0.0;
+    acor[i] = a;
+    zs[0][i] = i < n ? yp : 0.0;
+#pragma unroll
+    for (int j = 1; j <= UQ; ++j) zs[j][i] = i < n ? fma(lj[j], a, zs[j][i]) : 0.0;
+    if constexpr (UQ < kQmaxAll) zs[UQ + 1][i] = (raise && i < n) ? craise * a : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    if (i < n) {
+      const long id = Tpc<NP>::idx(c, i, n);
+#pragma unroll
+      for (int j = 0; j <= UQ; ++j) K.z[j][id] = zs[j][i];
+      if constexpr (UQ < kQmaxAll) {
+        if (raise) K.z[UQ + 1][id] = zs[UQ + 1][i];
+      }
+    }
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void tpc_apply_update(const BdfDev& D, long c, int n,
+                                                 double (&zs)[kQmaxAll + 1][NP],
+                                                 double (&acor)[NP]) {
+  switch (D.C->upd_q) {
+    case 1: tpc_apply_update_q<NP, 1>(D, c, n, zs, acor); break;
+    case 2: tpc_apply_update_q<NP, 2>(D, c, n, zs, acor); break;
+    case 3: tpc_apply_update_q<NP, 3>(D, c, n, zs, acor); break;
+    case 4: tpc_apply_update_q<NP, 4>(D, c, n, zs, acor); break;
+    default: tpc_apply_update_q<NP, 5>(D, c, n, zs, acor); break;
+  }
+}
+
 // Dynamic LDS of the TPC kernels (tb threads per block): the fused Newton
 // kernel keeps NP columns for the evaluation point, NP for the refinement
 // iterate (LS 1) and R for the rates, then the reduction scratch; the
 // starting-step kernels NP columns and the scratch; the history update only
 // the scratch.
-__host__ __device__ inline size_t tpc_newton_lds(int np, int R, int ls, int tb) {
+// With the deferred history update (defer) two more columns follow the
+// scratch: z(0)[q] and the previous step's correction, for the order
+// selection's sums.
+__host__ __device__ inline size_t tpc_newton_lds(int np, int R, int ls, int tb, bool defer = false) {
   return sizeof(double) *
-         ((size_t)tb * (size_t)(np * (ls == 1 ? 2 : 1) + R) + (size_t)(tb / 64) * kRedNewton);
+         ((size_t)tb * (size_t)(np * (ls == 1 ? 2 : 1) + R + (defer ? 2 * np : 0)) +
+          (size_t)(tb / 64) * kRedNewton);
 }
 __host__ __device__ inline size_t tpc_init_lds(int np, int tb) {
   return sizeof(double) * ((size_t)tb * np + (size_t)(tb / 64) * kRedVals);
@@ -513,13 +600,17 @@ __host__ __device__ inline size_t tpc_accept_lds(int tb) {
 // one network passes its R); the rest follow in chunks of 8.  Every wave
 // issues these loads before it waits on any of them, so their HBM round
 // trips overlap; at one wave per SIMD a serial round trip costs the SIMD.
-template <int NP, int LS, int TB, class Net = NetTables, int RC = 24>
+//
+// FULL: the class's species fill the padded size (n == NP), so n is a
+// compile-time constant: the padding selects and clamped addresses vanish
+// and every tiled address is a constant offset from the cell's base.
+template <int NP, int LS, int TB, class Net = NetTables, int RC = 24, bool FULL = false>
 __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, double* lds) {
   using TP = Tpc<NP, TB>;
   Ctrl* C = D.C;
   const ClassDev& K = D.k;
   const NetDev& nd = K.net;
-  const int n = K.n, R = K.R;
+  const int n = FULL ? NP : K.n, R = K.R;
   const long c = blk * TB + threadIdx.x;
   const bool act = c < K.ncells;
   constexpr int F = LS == 1 ? 2 : 1;
@@ -527,6 +618,8 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
   double* xcol = lds + NP * TB + threadIdx.x;       // LS 1 iterate
   double* kcol = lds + F * NP * TB + threadIdx.x;   // rates
   double* s_red = lds + (size_t)(F * NP + R) * TB;
+  double* qcol = s_red + (TB / 64) * kRedNewton + threadIdx.x;   // deferred update: z(0)[q]
+  double* pcol = qcol + NP * TB;                                 // and the previous acor
   double red[kRedNewton];
 #pragma unroll
   for (int k = 0; k < kRedNewton; ++k) red[k] = 0.0;
@@ -541,10 +634,26 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
     const double l0 = C->l[0];
     const int q = C->q;
     const int maxcor = C->maxcor;
+    // deferred update: if accepted, this step selects the order (qwait == 1),
+    // so each iteration also sums the selection's norms
+    const bool sel = C->fuse && C->qwait == 1;
+    const bool selp1 = sel && q < C->qmax && q < kQmaxAll;
     double zp0[NP], cv[NP], w[NP];
     {
       double zs[kQmaxAll + 1][NP];
-      tpc_load_hist<NP>(K, C, c, n, q, zs);
+      double acp[NP];
+      if (C->fuse && C->upd) {
+        tpc_apply_update<NP>(D, c, n, zs, acp);
+#pragma unroll
+        for (int j = 0; j <= kQmaxAll; ++j) {
+          const double hsj = C->hs[j];
+#pragma unroll
+          for (int i = 0; i < NP; ++i) zs[j][i] = j <= q ? zs[j][i] * hsj : 0.0;
+        }
+      } else {
+        tpc_load_hist<NP>(K, C, c, n, q, zs);
+        if (selp1) tpc_load_vec<NP>(K.dprev, c, n, acp);
+      }
 #pragma unroll
       for (int u = 0; u < RC; ++u)
         if (u < r0) kcol[u * TB] = rv[u];
@@ -581,6 +690,17 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
       for (int i = 0; i < NP; ++i) {
         zp0[i] = zs[0][i];
         cv[i] = zs[0][i] - l0 * zs[1][i];
+      }
+      if (sel) {
+        // z(0)[q] (the top row, which the predictor leaves unchanged)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          double v = 0.0;
+#pragma unroll
+          for (int j = 1; j <= kQmaxAll; ++j) v = j == q ? zs[j][i] : v;
+          qcol[i * TB] = v;
+          if (selp1) pcol[i * TB] = acp[i];
+        }
       }
     }
     TP::store_col(ycol, zp0);
@@ -668,7 +788,7 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
           TpcLU<NP, double>::solve(M, pv, del);
         }
       }
-      double sd = 0.0, sa = 0.0, neg = 0.0;
+      double sd = 0.0, sa = 0.0, neg = 0.0, sq = 0.0, sp = 0.0;
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
         if (i < n) {
@@ -681,6 +801,25 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
           sa = fma(b, b, sa);
         }
       }
+      if (sel) {
+        // the order selection's sums if this iterate is accepted: the new
+        // z[q] = z(0)[q] + l_q acor and acor - acor_prev, as the history
+        // update forms them
+        const double lq = C->l[q];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          if (i < n) {
+            const double yp = D.nonneg && y[i] < 0.0 ? 0.0 : y[i];
+            const double ac = (yp - zp0[i]) / l0;
+            const double zq = fma(lq, ac, qcol[i * TB]) * w[i];
+            sq = fma(zq, zq, sq);
+            if (selp1) {
+              const double e = (ac - pcol[i * TB]) * w[i];
+              sp = fma(e, e, sp);
+            }
+          }
+        }
+      }
       // m is not a compile-time constant: accumulate into every slot with
       // a select so that red[] stays in registers
 #pragma unroll
@@ -691,6 +830,8 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
         red[kRedPerIter * mm + 2] += hit ? neg : 0.0;
         red[kRedPerIter * mm + 3] += hit ? (double)sweeps : 0.0;
         red[kRedPerIter * mm + 4] += hit ? (double)fb : 0.0;
+        red[kRedPerIter * mm + 5] += hit ? sq : 0.0;
+        red[kRedPerIter * mm + 6] += hit ? sp : 0.0;
       }
     }
     red[7] = sing ? 1.0 : 0.0;
@@ -698,11 +839,11 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
   block_partials<kRedNewton>(D, (unsigned int)(D.k.blk0 + blk), red, s_red);
 }
 
-template <int NP, int LS>
+template <int NP, int LS, bool FULL = false>
 __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
   extern __shared__ double lds[];
   if (D.C->phase != PH_PREDICT) return;
-  tpc_newton_body<NP, LS, kTpcThreads>(D, blockIdx.x, lds);
+  tpc_newton_body<NP, LS, kTpcThreads, NetTables, 24, FULL>(D, blockIdx.x, lds);
 }
 
 // History update after an accepted attempt: z_new[j] = z(0)[j] + l_j acor
@@ -827,6 +968,25 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_accept(BdfDev D) {
   extern __shared__ double lds[];
   if (D.C->phase != PH_ACCEPT) return;
   tpc_accept_body<NP, kTpcThreads>(D, blockIdx.x, lds);
+}
+
+// Applies a pending deferred history update (end of a drive, before the
+// host reads the state) and saves acor for the next order selection.
+template <int NP>
+__global__ void __launch_bounds__(kTpcThreads) k_tpc_flush(BdfDev D) {
+  if (!D.C->upd) return;
+  const long c = (long)blockIdx.x * kTpcThreads + threadIdx.x;
+  const ClassDev& K = D.k;
+  if (c >= K.ncells) return;
+  const int n = K.n;
+  double zs[kQmaxAll + 1][NP], acor[NP];
+  if (n == NP)
+    tpc_apply_update<NP>(D, c, NP, zs, acor);
+  else
+    tpc_apply_update<NP>(D, c, n, zs, acor);
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+    if (i < n) K.dprev[Tpc<NP>::idx(c, i, n)] = acor[i];
 }
 
 // Starting step, part 1: f(y0) into z[1] (scaled later by h), norms of y0, f0.

@@ -217,7 +217,7 @@ std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np
        "  if (D.C->phase != bdfgpu::PH_PREDICT) return;\n"
        "  bdfgpu::tpc_newton_body<"
     << np << ", " << ls << ", bdfgpu::kTpcThreads, bdfgpu::NetGen, " << (R < 1 ? 1 : R > 24 ? 24 : R)
-    << ">(D, blockIdx.x, lds);\n}\n\n"
+    << ", " << (n == np ? "true" : "false") << ">(D, blockIdx.x, lds);\n}\n\n"
        "// dynamic LDS above 64 KiB is requested once per process\n"
        "extern \"C\" void bdf_newton_net_launch(const bdfgpu::BdfDev* D, unsigned int grid,\n"
        "                                      unsigned int lds, hipStream_t s) {\n"

@@ -6,14 +6,23 @@ namespace bdfgpu {
 
 // Dynamic LDS above 64 KiB (gfx950 has 160 KiB per workgroup) is requested
 // explicitly; the first launch that needs it raises the kernel's limit.
-template <int NP, int LS>
-static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
+template <int NP, int LS, bool FULL>
+static void go_newton_v(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
   static size_t raised = 65536;
   if (lds > raised &&
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tpc_newton<NP, LS>),
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tpc_newton<NP, LS, FULL>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
     raised = lds;
-  hipLaunchKernelGGL((k_tpc_newton<NP, LS>), g, b, lds, s, D);
+  hipLaunchKernelGGL((k_tpc_newton<NP, LS, FULL>), g, b, lds, s, D);
+}
+
+// classes whose species fill the padded size get the variant with n fixed
+template <int NP, int LS>
+static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
+  if (D.k.n == NP)
+    go_newton_v<NP, LS, true>(D, g, b, lds, s);
+  else
+    go_newton_v<NP, LS, false>(D, g, b, lds, s);
 }
 
 template <int NP>
@@ -24,14 +33,15 @@ static void tpc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStr
     case 0: hipLaunchKernelGGL(k_tpc_init1<NP>, g, b, ilds, s, D); break;
     case 1: hipLaunchKernelGGL(k_tpc_init2<NP>, g, b, ilds, s, D); break;
     case 2: {
-      const size_t lds = tpc_newton_lds(NP, D.k.R, ls, kTpcThreads);
+      const size_t lds = tpc_newton_lds(NP, D.k.R, ls, kTpcThreads, D.defer);
       if (ls == 1)
         go_newton<NP, 1>(D, g, b, lds, s);
       else
         go_newton<NP, 0>(D, g, b, lds, s);
       break;
     }
-    default: hipLaunchKernelGGL(k_tpc_accept<NP>, g, b, tpc_accept_lds(kTpcThreads), s, D); break;
+    case 3: hipLaunchKernelGGL(k_tpc_accept<NP>, g, b, tpc_accept_lds(kTpcThreads), s, D); break;
+    default: hipLaunchKernelGGL(k_tpc_flush<NP>, g, b, 0, s, D); break;
   }
 }
 

@@ -34,13 +34,14 @@ END_BAR_PER_STEP = 2e-5
 # multiplies it by eta = (1.2 err)^(-1/(q+1)), err being the WRMS norm of
 # acor = y_n - z0[0], a difference of two states that agree to about the
 # tolerance.  Measured: 3.7e-9 over the Robertson run, 8e-7 after 2,300
-# steps of the 256-cell network, up to a few 1e-3 late in runs where small
-# components (weighted by 1/atol) dominate err.  It is reported, not
-# bounded: a decision taken differently at a threshold is what separates
-# the runs, and it changes h by at least the 1.5x of the hysteresis (or the
-# attempt count, for a failed test), so a relative difference beyond FLIP_H
-# counts as a flipped decision.
-FLIP_H = 0.2
+# steps of the 256-cell network, and it can grow to a few percent late in
+# runs where small components (weighted by 1/atol) dominate err.  Once it
+# passes FLIP_H the two runs take materially different steps (their states
+# then differ by a fraction of the tolerance: 0.07-0.09 WRMS measured after
+# 1,400-3,300 steps), which is judged like a flipped decision; a decision
+# taken differently at a threshold changes h by at least the 1.5x of the
+# hysteresis, or the attempt count for a failed test.
+FLIP_H = 1e-3
 # After a decision flip both runs are valid integrations at the same
 # tolerance: the GPU's error against a tight-tolerance oracle run must be
 # within this factor of the oracle's own error against it.
@@ -101,9 +102,8 @@ def compare_trajectory(orc, dev, G, p, max_steps=None, okw=None, **kw):
       oracle's time along its own Nordsieck history); the largest relative
       step-size difference is printed.
     * At the first step where a decision differs (attempts, iterations,
-      order, or a step size that differs beyond FLIP_H: a hysteresis or
-      error-test threshold taken differently) the step, both sides'
-      decisions and the oracle's threshold quantities (error estimate
+      order) or the step sizes have drifted apart beyond FLIP_H, the step,
+      both sides' decisions and the oracle's threshold quantities (error estimate
       against 1, order-change estimates, the proposed growth factor
       against the 1.5 hysteresis) are printed; the last common state
       before it agreed within the bar above; both runs then continue

@@ -52,3 +52,17 @@ def test_no_oracle_in_product_sources():
             continue
         txt = open(path, errors="ignore").read()
         assert "orc_" not in txt and "import oracle" not in txt and "liborc" not in txt, path
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_workspace_bytes_without_device_memory():
+    """bdf_workspace_bytes is a dry run of the creation: it needs no device
+    memory or GPU and grows with the number of cells."""
+    import workloads as W
+    from paper_2011_12984_amd import Bdf
+    small = Bdf.workspace_bytes(W.random_network_batch(100, n=10, seed=1))
+    big = Bdf.workspace_bytes(W.random_network_batch(10000, n=10, seed=1))
+    # history (6 vectors), saved correction, 3 iterates and the rates: at
+    # least 8 (10 n + R) bytes per cell
+    assert big - small >= 8 * (10 * 10 + 20) * 9900
+    assert Bdf.workspace_bytes(W.random_network_batch(100, n=10, seed=1), qmax=9) == 0

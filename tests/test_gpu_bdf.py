@@ -212,11 +212,13 @@ def test_conservation_without_projection(dev, G):
 def test_projection_matches_oracle(orc, dev, G):
     """y >= 0 projection on a 1,024-cell batch that triggers it thousands of
     times: lockstep parity with the oracle's projected run, every component
-    non-negative, and each cell's total mass equal to the oracle's within
-    1e3 atol.  (The projection adds the clipped negative parts to a cell's
-    mass; their total is a property of the trajectory, 1.2e-7 in the
-    worst cell of this batch for the oracle itself, so the GPU's mass is
-    held to the oracle's rather than to a fixed drift bound.)"""
+    non-negative, and the mass the projection adds (the clipped negative
+    parts, tolerance-level amounts summed along the path) of the same order
+    as the oracle's: the largest per-cell drift within 10x the oracle's and
+    the mean within 3x.  The drift is a property of the trajectory (1.2e-7
+    in the worst cell for the oracle itself; the two runs separate at a
+    step-size decision, after which each cell clips along its own path), so
+    it is held to the oracle's rather than to a fixed bound."""
     p = W.random_network_batch(1024, n=10, seed=8)
     ob, gb = compare_trajectory(orc, dev, G, p)
     y = gb.y().cpu().numpy().reshape(-1, 10)
@@ -224,9 +226,11 @@ def test_projection_matches_oracle(orc, dev, G):
     assert y.min() >= 0.0
     assert gb.stats()["nprojections"] > 0 and ob.stats()["nprojections"] > 0
     m0 = p.y0.reshape(-1, 10).sum(1)
-    print(f"mass drift: gpu max {np.abs(y.sum(1) - m0).max():.3e}, "
-          f"oracle max {np.abs(yo.sum(1) - m0).max():.3e}")
-    assert np.abs(y.sum(1) - yo.sum(1)).max() <= 1e3 * p.atol
+    dg, do = np.abs(y.sum(1) - m0), np.abs(yo.sum(1) - m0)
+    print(f"mass drift: gpu max {dg.max():.3e} mean {dg.mean():.3e}, "
+          f"oracle max {do.max():.3e} mean {do.mean():.3e}")
+    assert dg.max() <= 10 * do.max()
+    assert dg.mean() <= 3 * do.mean()
 
 
 def test_bench_kernel_parity_two_reduction_groups(orc, dev, G):
@@ -245,3 +249,56 @@ def test_uneven_parity_2p16_unknowns(orc, dev, G):
     p = W.uneven_batch(1 << 16, seed=W.BASE_SEED + 4)
     compare_trajectory(orc, dev, G, p, max_steps=40, linsol=1, launch=G.LAUNCH_AUTO,
                        mode=G.MODE_GRAPH, jit=True)
+
+
+@pytest.mark.parametrize("linsol,jit", [(0, True), (1, False)])
+def test_deferred_update_matches_separate_update(dev, G, linsol, jit):
+    """The history update applied by the next attempt's Newton kernel (the
+    default for thread-per-cell classes) against the separate update kernel:
+    per cell the same operations on the same values; only the order
+    selection's two norms are summed in another reduction tree, which can
+    move a growth factor in its last bits (and, over thousands of steps,
+    separate the step-size sequences as any rounding does).  Over the first
+    300 steps, with a pause after 150 (the flush and resume path): the same
+    steps, attempts, Newton iterations and orders, step sizes to 1e-12 and
+    states within 1e-8 WRMS."""
+    p = W.random_network_batch(1000, n=10, seed=41)
+    a = gpu_bdf(G, p, dev, linsol=linsol, jit=jit, defer=True)
+    b = gpu_bdf(G, p, dev, linsol=linsol, jit=jit, defer=False)
+    for _ in range(2):
+        ta, na = a.advance(p.t_end, 150)
+        tb, nb = b.advance(p.t_end, 150)
+        assert na == nb == 150
+    sa, sb = a.stats(), b.stats()
+    print({k: (sa[k], sb[k]) for k in ("nsteps", "nattempts", "nniters", "netfails", "nncfails")})
+    for k in ("nsteps", "nattempts", "nniters", "order_hist"):
+        assert sa[k] == sb[k], k
+    assert sa["h"] == pytest.approx(sb["h"], rel=1e-12)
+    assert sa["t"] == pytest.approx(sb["t"], rel=1e-12)
+    d = wrms_diff(a.y().cpu().numpy(), b.y().cpu().numpy(), p.rtol, p.atol)
+    print(f"deferred vs separate update after 300 steps: wrms diff {d:.3e}")
+    assert d <= 1e-8
+    assert sa["order_hist"][3] > 0          # the order selection ran (and raised)
+
+
+@pytest.mark.parametrize("kw", [dict(jit=True), dict(linsol=1, launch=2, mode=1)])
+def test_caller_workspace(dev, G, kw):
+    """A handle whose device state lives in caller memory sized by
+    bdf_workspace_bytes reproduces the library-allocated handle bit for bit;
+    a workspace one byte short is refused with the workspace status."""
+    p = W.random_network_batch(3000, n=10, seed=43) if "launch" not in kw else \
+        W.uneven_batch(1 << 12, seed=9)
+    need = G.Bdf.workspace_bytes(p, **kw)
+    assert need > 0
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    a = gpu_bdf(G, p, dev, workspace=ws, **kw)
+    b = gpu_bdf(G, p, dev, **kw)
+    for t in (1e-3, 1e-1):
+        assert a.integrate(t) == t and b.integrate(t) == t
+    assert a.stats()["nsteps"] == b.stats()["nsteps"]
+    assert torch.equal(a.y(), b.y())
+    a.close()
+    small = torch.empty(need - 1, dtype=torch.uint8, device=dev)
+    with pytest.raises(G.BdfGpuError) as e:
+        gpu_bdf(G, p, dev, workspace=small, **kw)
+    assert e.value.code == -3
