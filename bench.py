@@ -296,6 +296,64 @@ def robertson_leg(G, W, torch, dev, reps=3):
     return out
 
 
+def brusselator_leg(G, W, torch, dev, ncells=1 << 20):
+    """The demonstration reaction of Section 7 (3 species per cell, the
+    1-D Gaussian profile over ncells cells), whole run from t = 0 to 10 on a
+    fresh handle (creation not timed): grouped stepping with the FP64 LU or
+    the explicit Gauss-Jordan block inverse, and per-cell stepping with the
+    inverse.  value = accepted cell-steps / wall time."""
+    p = W.brusselator_batch(ncells)
+    out = {"cells": ncells, "species": 3, "t_end": p.t_end}
+    for name, kw in (("grouped_lu", dict(linsol=G.LS_LU64, jit=True, attempts_per_sync=16)),
+                     ("grouped_gauss_jordan", dict(linsol=G.LS_GJ, jit=True,
+                                                   attempts_per_sync=16)),
+                     ("per_cell_gauss_jordan", dict(linsol=G.LS_GJ, per_cell=True))):
+        b = G.Bdf.from_problem(p, device=dev, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t = b.integrate(p.t_end)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s = b.stats()
+        b.close()
+        cell_steps = s["nsteps"] if kw.get("per_cell") else s["nsteps"] * ncells
+        out[name] = {"whole_run_s": round(dt, 4), "reached": t == p.t_end,
+                     "steps": int(s["nsteps"]) if not kw.get("per_cell") else None,
+                     "cell_steps": int(cell_steps), "value": round(cell_steps / dt, 1),
+                     "unit": "cell-steps/s",
+                     "attempts_per_step": round(s["nattempts"] / max(s["nsteps"], 1), 4)}
+    return out
+
+
+def per_cell_leg(G, W, torch, prob, dev, max_steps=2000000):
+    """The benchmark workload with per-cell adaptive stepping (every cell its
+    own step size and order), integrated from t = 0 to t_end = 10 on a fresh
+    handle; creation not timed.  value = total accepted cell-steps / wall
+    time; the per-cell step distribution shows what bounds the wall time."""
+    import numpy as np
+    b = G.Bdf.from_problem(prob, device=dev, per_cell=True, max_steps=max_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        t = b.integrate(prob.t_end)
+        err = None
+    except G.BdfGpuError as e:
+        t, err = None, str(e)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    counts, tc = b.cell_stats()
+    s = b.stats()
+    b.close()
+    st = counts[:, 0]
+    return {"t_end": prob.t_end, "reached_all": t == prob.t_end, "error": err,
+            "wall_s": round(dt, 3), "cell_steps": int(s["nsteps"]),
+            "value": round(s["nsteps"] / dt, 1), "unit": "cell-steps/s",
+            "attempts_per_step": round(s["nattempts"] / max(s["nsteps"], 1), 4),
+            "per_cell_steps": {"min": int(st.min()), "median": float(np.median(st)),
+                               "p99": float(np.quantile(st, 0.99)), "max": int(st.max())},
+            "cells_over_10k_steps": int((st > 10000).sum())}
+
+
 def long_run_leg(G, W, torch, prob, dev, jit=True, max_steps=20000):
     """The benchmark workload integrated from t = 0 for max_steps accepted
     steps (or to t_end) on a fresh handle, creation and the starting step
@@ -328,6 +386,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-robertson", action="store_true")
+    ap.add_argument("--no-brusselator", action="store_true",
+                    help="skip the demonstration reaction's whole runs")
+    ap.add_argument("--no-per-cell", action="store_true",
+                    help="skip the per-cell adaptive stepping run to t = 10")
     ap.add_argument("--long-steps", type=int, default=20000,
                     help="accepted steps of the long run from t = 0 (0 skips it)")
     ap.add_argument("--profile-warmup", type=int, default=60,
@@ -470,10 +532,20 @@ def main():
         long_run = long_run_leg(G, W, torch, prob, dev, jit=not args.no_jit,
                                 max_steps=args.long_steps)
 
+    per_cell = None
+    if not args.no_per_cell:
+        log("per-cell adaptive stepping, whole run to t = 10")
+        per_cell = per_cell_leg(G, W, torch, prob, dev)
+
     robertson = None
     if not args.no_robertson:
         log("1,000-cell Robertson BDF2 whole runs")
         robertson = robertson_leg(G, W, torch, dev)
+
+    brusselator = None
+    if not args.no_brusselator:
+        log("demonstration reaction (3 species, order-3 reaction), whole runs to t = 10")
+        brusselator = brusselator_leg(G, W, torch, dev)
 
     fused = None
     if not args.no_fused:
@@ -513,7 +585,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "long_run": long_run,
+        "per_cell_whole_run": per_cell,
         "robertson_1000_bdf2": robertson,
+        "brusselator_2p20": brusselator,
         "fp32_refined": out_fp32,
         "fused_ops": fused,
         "uneven": uneven,

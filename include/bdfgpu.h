@@ -183,7 +183,9 @@ int batched_lu_solve_refine(int nb, int n, const double* M, const float* LU32,
  * host only enqueues attempts and reads the status every few attempts.
  *
  * Kinetics: r_k = kappa_k prod_s y_s^nu_ks, f_s = sum_k (mu_ks - nu_ks) r_k;
- * each reaction may have at most two reactant molecules.
+ * each reaction may have at most three reactant molecules, and three only
+ * in classes of <= 12 species with FP64 LU or the Gauss-Jordan solve (the
+ * paper's demonstration reaction has one, 2u + v -> 3u).
  * ======================================================================== */
 
 #define BDFGPU_LS_LU64 0     /* FP64 LU per block */
@@ -191,6 +193,12 @@ int batched_lu_solve_refine(int nb, int n, const double* M, const float* LU32,
 #define BDFGPU_LS_LEARNED 2  /* learned approximate inverse (options.precond),
                                 per-cell and per-attempt fallback to FP64 LU;
                                 cells of 13..31 species */
+#define BDFGPU_LS_GJ 3       /* explicit block inverse by Gauss-Jordan
+                                elimination with partial pivoting, applied as
+                                a matrix-vector product in every Newton
+                                iteration: the task-local block solve of the
+                                paper's demonstration problem (Section 7).
+                                Cells of <= 4 species, per-class launches */
 
 #define BDFGPU_MODE_STREAM 0 /* kernels enqueued on the stream */
 #define BDFGPU_MODE_GRAPH 1  /* one attempt captured in a hipGraph */
@@ -262,6 +270,19 @@ typedef struct {
                              selection's norms are summed per Newton iteration.
                              Results are those of the separate update.
                              1: a separate history-update kernel per attempt. */
+  int per_cell;           /* 1: per-cell adaptive stepping.  Every cell is its
+                             own ODE with its own step size, order, Newton
+                             convergence test and error test, on WRMS norms
+                             over its own species (the task-local integrators
+                             of Section 7 taken down to single cells): a cell's
+                             result is the grouped method's for a problem of
+                             that one cell.  bdf_integrate advances every cell
+                             to t_end; bdf_get_stats sums the cells' counters
+                             (t: the earliest cell); bdf_get_cell_stats gives
+                             them per cell.  Cells of <= 12 species, FP64 LU,
+                             per-class launches; bdf_step, bdf_advance and the
+                             state calls are refused.  max_steps bounds the
+                             attempts per cell. */
 } bdf_options;
 
 typedef struct {
@@ -326,6 +347,11 @@ int bdf_get_kernel_times(bdf_handle* h, double* ms, long* counts);
 int bdf_get_y(bdf_handle* h, double* y);
 /* Counters and scalars (host struct). */
 int bdf_get_stats(bdf_handle* h, bdf_stats* s);
+/* Per-cell stepping only: per cell (user order), HOST arrays (any may be
+ * NULL, not all): counts[5 c + k] = accepted steps, attempts, Newton
+ * iterations, error-test failures, convergence failures; t[c] = time
+ * reached; hu[c] = last accepted step size. */
+int bdf_get_cell_stats(bdf_handle* h, int* counts, double* t, double* hu);
 /* Total unknowns N and number of cells. */
 long bdf_get_N(bdf_handle* h);
 /* Integrator state for exact single-step comparisons: scalars (host

@@ -114,6 +114,8 @@ def _declare(L):
     L.orc_lu_solve_f32.argtypes = [C.c_int, fp, ip, fp]
     L.orc_lu_refine_solve.restype = C.c_int
     L.orc_lu_refine_solve.argtypes = [C.c_int, dp, fp, ip, dp, dp, C.c_int, ip]
+    L.orc_gj_inverse.restype = C.c_int
+    L.orc_gj_inverse.argtypes = [C.c_int, dp, dp]
     L.orc_ma_rhs.argtypes = [C.c_int, C.c_int, ip, ip, dp, dp, dp]
     L.orc_ma_jac.argtypes = [C.c_int, C.c_int, ip, ip, dp, dp, dp]
     L.orc_set_bf16.argtypes = [C.c_int]
@@ -250,6 +252,21 @@ def lu_factor(A):
         LU[b] = cm.reshape(n, n, order="F")
         piv[b] = pv
     return LU, piv, info
+
+
+def gj_inverse(A):
+    """A: (nb, n, n).  Returns (inverses (nb, n, n), info (nb,)) by
+    Gauss-Jordan elimination with partial pivoting."""
+    A = np.asarray(A, dtype=np.float64)
+    nb, n, _ = A.shape
+    Xs = np.zeros_like(A)
+    info = np.zeros(nb, dtype=np.int32)
+    for b in range(nb):
+        cm = np.asfortranarray(A[b]).ravel(order="F").copy()
+        X = np.zeros(n * n)
+        info[b] = lib().orc_gj_inverse(n, _d(cm), _d(X))
+        Xs[b] = X.reshape(n, n)
+    return Xs, info
 
 
 def lu_solve(LU, piv, B):
@@ -407,7 +424,7 @@ def adam_step(p, g, m1, m2, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 # BDF integrator
 # ----------------------------------------------------------------------------
 
-LS_LU64, LS_LU32REF, LS_LEARNED = 0, 1, 2
+LS_LU64, LS_LU32REF, LS_LEARNED, LS_GJ = 0, 1, 2, 3
 
 
 def bdf_coeffs(q):

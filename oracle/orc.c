@@ -208,6 +208,49 @@ void orc_lu_solve_f32(int n, const float* LU, const int* piv, float* b) {
   }
 }
 
+/* Gauss-Jordan elimination on the augmented matrix [A | I]: at step k the
+ * pivot row (first maximal |a_ik|, i >= k) is exchanged into row k and
+ * divided by its pivot, then a multiple of it is subtracted from every other
+ * row, so that column k becomes the unit vector; after n steps the right
+ * half holds the inverse.  Plain loops, division by the pivot. */
+int orc_gj_inverse(int n, const double* A, double* Ainv) {
+  double* W = (double*)malloc(sizeof(double) * (size_t)n * 2 * n);   /* row-major n x 2n */
+  if (!W) return -1;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      W[i * 2 * n + j] = AT(A, i, j, n);
+      W[i * 2 * n + n + j] = i == j ? 1.0 : 0.0;
+    }
+  int info = 0;
+  for (int k = 0; k < n && !info; ++k) {
+    int p = k;
+    double amax = fabs(W[k * 2 * n + k]);
+    for (int i = k + 1; i < n; ++i) {
+      double v = fabs(W[i * 2 * n + k]);
+      if (v > amax) { amax = v; p = i; }
+    }
+    if (p != k)
+      for (int j = 0; j < 2 * n; ++j) {
+        double t = W[k * 2 * n + j];
+        W[k * 2 * n + j] = W[p * 2 * n + j];
+        W[p * 2 * n + j] = t;
+      }
+    double d = W[k * 2 * n + k];
+    if (d == 0.0) { info = k + 1; break; }
+    for (int j = 0; j < 2 * n; ++j) W[k * 2 * n + j] = W[k * 2 * n + j] / d;
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      double f = W[i * 2 * n + k];
+      for (int j = 0; j < 2 * n; ++j) W[i * 2 * n + j] = W[i * 2 * n + j] - f * W[k * 2 * n + j];
+    }
+  }
+  if (!info)
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) Ainv[i * n + j] = W[i * 2 * n + n + j];
+  free(W);
+  return info;
+}
+
 /* Mixed-precision refinement for one block.
  * x0 = FP32 solve of b; then up to max_it corrections d = FP32 solve of the
  * FP64 residual r = b - M x.  Converged when the residual is at FP64
@@ -585,7 +628,8 @@ orc_bdf* orc_bdf_create(const orc_problem* p, const orc_options* o) {
   b->cellmode = (int*)calloc((size_t)nc + 1, sizeof(int));
   b->cellinfo = (int*)calloc((size_t)nc + 1, sizeof(int));
   b->dcell_prev = (double*)calloc((size_t)nc + 1, sizeof(double));
-  if (o->linsol == ORC_LS_LEARNED) b->X = (double*)calloc(NM, sizeof(double));
+  if (o->linsol == ORC_LS_LEARNED || o->linsol == ORC_LS_GJ)
+    b->X = (double*)calloc(NM, sizeof(double));
   b->t = p->t0;
   b->err_qm1 = b->err_qp1 = -1.0;
   b->eta_prop = 1.0;
@@ -679,7 +723,8 @@ static int factor64(orc_bdf* b, long c) {
 }
 
 /* Solve M del_c = r_c for one cell according to cellmode:
- * 0 FP64 LU, 1 FP32 LU + refinement, 2 learned X, 3 FP64 LU after fallback. */
+ * 0 FP64 LU, 1 FP32 LU + refinement, 2 learned X, 3 FP64 LU after fallback,
+ * 5 Gauss-Jordan inverse. */
 static int cell_solve(orc_bdf* b, long c) {
   int n = b->cn[c];
   long off = b->yoff[c];
@@ -697,14 +742,14 @@ static int cell_solve(orc_bdf* b, long c) {
     if (factor64(b, c)) return 1;
     mode = 3;
   }
-  if (mode == 2) {
+  if (mode == 2 || mode == 5) {   /* learned X, or the Gauss-Jordan inverse */
     const double* X = b->X + b->moff[c];
     for (int i = 0; i < n; ++i) {
       double s = 0.0;
       for (int j = 0; j < n; ++j) s = s + X[i * n + j] * r[j];
       d[i] = s;
     }
-    b->st.lp_cell_solves++;
+    if (mode == 2) b->st.lp_cell_solves++;
     return 0;
   }
   memcpy(d, r, sizeof(double) * (size_t)n);
@@ -757,6 +802,10 @@ static int newton(orc_bdf* b, double gamma, double l0, int force_lu) {
           b->cellmode[c] = 3;
           if (factor64(b, c)) setup_fail = 1;
         }
+      } else if (ls == ORC_LS_GJ) {
+        /* explicit inverse; the solve is then X r (mode 5) */
+        b->cellmode[c] = 5;
+        if (orc_gj_inverse(b->cn[c], b->M + b->moff[c], b->X + b->moff[c])) setup_fail = 1;
       } else {
         b->cellmode[c] = 0;
         if (factor64(b, c)) setup_fail = 1;

@@ -55,6 +55,14 @@ int orc_lu_refine_solve(int n, const double* M, const float* LU32,
                         const int* piv32, const double* b, double* x,
                         int max_it, int* sweeps);
 
+/* Inverse of one block by Gauss-Jordan elimination on [A | I] (column-major
+ * A, n x n), partial pivoting with the first maximal |a_ik| (rows below and
+ * including k), division by the pivot; Ainv receives the inverse, row-major
+ * (Ainv[i*n + j]).  Returns 0, or k+1 for the first exactly-zero pivot
+ * (Ainv then undefined).  The explicit-inverse block solve of the paper's
+ * demonstration problem (Section 7). */
+int orc_gj_inverse(int n, const double* A, double* Ainv);
+
 /* ---------------- mass-action kinetics ---------------------------------- */
 void orc_ma_rhs(int n, int R, const int* nu, const int* mu,
                 const double* kappa, const double* y, double* f);
@@ -102,7 +110,7 @@ typedef struct {
   double t0;
 } orc_problem;
 
-enum { ORC_LS_LU64 = 0, ORC_LS_LU32REF = 1, ORC_LS_LEARNED = 2 };
+enum { ORC_LS_LU64 = 0, ORC_LS_LU32REF = 1, ORC_LS_LEARNED = 2, ORC_LS_GJ = 3 };
 
 typedef struct {
   double rtol, atol;

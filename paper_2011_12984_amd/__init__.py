@@ -21,12 +21,12 @@ __all__ = [
     "nvec_const", "batched_lu_factor_f64", "batched_lu_solve_f64", "batched_lu_factor_f32",
     "batched_lu_solve_f32", "batched_lu_solve_refine", "batched_lu_factor_var",
     "batched_lu_solve_var", "Bdf", "BdfGpuError", "lib",
-    "LS_LU64", "LS_LU32REF", "LS_LEARNED", "MODE_STREAM", "MODE_GRAPH", "RESULT_DEVICE",
+    "LS_LU64", "LS_LU32REF", "LS_LEARNED", "LS_GJ", "MODE_STREAM", "MODE_GRAPH", "RESULT_DEVICE",
     "LAUNCH_PER_CLASS", "LAUNCH_FUSED", "LAUNCH_AUTO", "capture_training_set", "train_precond",
     "Precond",
 ]
 
-LS_LU64, LS_LU32REF, LS_LEARNED = 0, 1, 2
+LS_LU64, LS_LU32REF, LS_LEARNED, LS_GJ = 0, 1, 2, 3
 MODE_STREAM, MODE_GRAPH = 0, 1
 LAUNCH_PER_CLASS, LAUNCH_FUSED, LAUNCH_AUTO = 0, 1, 2
 RESULT_DEVICE = 1
@@ -290,7 +290,7 @@ class Bdf:
                  qmax=5, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64, refine_max_it=5,
                  max_steps=0, mode=MODE_STREAM, attempts_per_sync=8, nonneg=False,
                  precond=None, launch=LAUNCH_PER_CLASS, map_small=0, jit=False, defer=True,
-                 workspace=None):
+                 workspace=None, per_cell=False):
         torch = _torch()
         _dev(rates, torch.float64)
         _dev(y0, torch.float64)
@@ -309,7 +309,7 @@ class Bdf:
         opts = BdfOptions(rtol, atol, qmax, maxcor, h0, hmin, linsol, refine_max_it, max_steps,
                           mode, attempts_per_sync, launch,
                           precond.h if precond is not None else None, int(bool(nonneg)),
-                          int(map_small), int(bool(jit)), int(not defer))
+                          int(map_small), int(bool(jit)), int(not defer), int(bool(per_cell)))
         h = vp()
         if workspace is None:
             check("bdf_create", lib().bdf_create(C.byref(prob), C.byref(opts), _stream(),
@@ -337,7 +337,7 @@ class Bdf:
     def _sizing(prob, rtol=None, atol=None, qmax=None, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64,
                 refine_max_it=5, max_steps=0, mode=MODE_STREAM, attempts_per_sync=8,
                 nonneg=None, launch=LAUNCH_PER_CLASS, map_small=0, jit=False, defer=True,
-                precond=None):
+                precond=None, per_cell=False):
         topologies = prob["topologies"]
         topo_n = np.array([nu.shape[1] for nu, _ in topologies], np.int32)
         topo_R = np.array([nu.shape[0] for nu, _ in topologies], np.int32)
@@ -353,7 +353,7 @@ class Bdf:
                           refine_max_it, max_steps, mode, attempts_per_sync, launch,
                           precond.h if precond is not None else None,
                           int(bool(prob.get("nonneg", False) if nonneg is None else nonneg)),
-                          int(map_small), int(bool(jit)), int(not defer))
+                          int(map_small), int(bool(jit)), int(not defer), int(bool(per_cell)))
         return int(lib().bdf_workspace_bytes(C.byref(pr), C.byref(opts)))
 
     @classmethod
@@ -417,6 +417,19 @@ class Bdf:
         check("bdf_get_kernel_times", lib().bdf_get_kernel_times(self.h, C.cast(ms, dp),
                                                                  C.cast(cnt, C.POINTER(C.c_long))))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(("newton", "learned", "accept"))}
+
+    def cell_stats(self, with_hu=False):
+        """Per-cell stepping: (counts (ncells, 5): steps, attempts, Newton
+        iterations, error-test and convergence failures; t (ncells,)), and
+        the last accepted step sizes (ncells,) when with_hu."""
+        nc = len(self._keep[5])
+        counts = np.zeros((nc, 5), np.int32)
+        t = np.zeros(nc)
+        hu = np.zeros(nc)
+        check("bdf_get_cell_stats", lib().bdf_get_cell_stats(
+            self.h, C.c_void_p(counts.ctypes.data), C.c_void_p(t.ctypes.data),
+            C.c_void_p(hu.ctypes.data)))
+        return (counts, t, hu) if with_hu else (counts, t)
 
     def y(self):
         torch = _torch()

@@ -32,7 +32,7 @@ class BdfOptions(C.Structure):
                 ("linsol", C.c_int), ("refine_max_it", C.c_int), ("max_steps", C.c_long),
                 ("mode", C.c_int), ("attempts_per_sync", C.c_int), ("launch", C.c_int),
                 ("precond", vp), ("nonneg", C.c_int), ("map_small", C.c_int),
-                ("jit", C.c_int), ("no_defer", C.c_int)]
+                ("jit", C.c_int), ("no_defer", C.c_int), ("per_cell", C.c_int)]
 
 
 class BdfStats(C.Structure):
@@ -88,6 +88,7 @@ SIGNATURES = {
     "bdf_get_y": (C.c_int, [vp, vp]),
     "bdf_get_stats": (C.c_int, [vp, C.POINTER(BdfStats)]),
     "bdf_get_N": (C.c_long, [vp]),
+    "bdf_get_cell_stats": (C.c_int, [vp, vp, vp, vp]),
     "bdf_get_state": (C.c_int, [vp, dp, ip, vp, vp]),
     "bdf_set_state": (C.c_int, [vp, dp, ip, vp, vp]),
     "bdf_eval_rhs_jac": (C.c_int, [vp, vp, vp, vp]),

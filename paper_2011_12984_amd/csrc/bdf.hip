@@ -18,6 +18,7 @@
 
 #include <chrono>
 
+#include "bdf_cell.hpp"
 #include "bdf_dev.hpp"
 #include "bdf_jit.hpp"
 #include "bdf_multi.hpp"
@@ -29,6 +30,12 @@ int tpc_padded(int n);
 int spc_seg(int n);
 void launch_tpc(int np, int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s);
 void launch_spc(int seg, int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s);
+void launch_cell(int np, int ls, int which, const BdfDev& D, const CellDev& P, unsigned int grid,
+                 hipStream_t s);
+__global__ void k_cell_setup(long ncells, double t0, double* t, double* h, double* hsc,
+                             double* hu, int* iv, int* cnt);
+__global__ void k_cell_resume(long ncells, double tend, const double* t, int* iv);
+__global__ void k_zero_u32(unsigned int* p, int n);
 
 int precond_launch_gated(precond_handle* h, long B, const double* X, float* out,
                          const int* gphase, int want, const int* gskip, hipStream_t s);
@@ -48,6 +55,8 @@ struct ClassHost {
   long* d_roff = nullptr;       // user-layout offset of each class cell's rates
   NetLaunch jit = nullptr;      // network-specialised Newton kernel, if any
   ClassDev dev;
+  std::vector<long> members;    // user indices of the class's cells
+  CellDev cell;                 // per-cell stepping: control state of each cell
 };
 
 __global__ void k_clear_upd(Ctrl* C) { C->upd = 0; }
@@ -101,19 +110,21 @@ __global__ void k_eval_rhs_jac(long ncells, NetDev nd, const long* yoff, const l
   if (J)
     for (int i = 0; i < n * n; ++i) J[joff[c] + i] = 0.0;
   for (int k = 0; k < nd.R; ++k) {
-    const int a = nd.ra[k], b = nd.rb[k];
+    const int a = nd.ra[k], b = nd.rb[k], d = nd.rc[k];
     double r = kc[k];
     if (a >= 0) r *= yc[a];
     if (b >= 0) r *= yc[b];
+    if (d >= 0) r *= yc[d];
     if (f)
       for (int i = 0; i < n; ++i) f[yoff[c] + i] += nd.S[(long)k * nd.np + i] * r;
   }
   if (J)
     for (int a = 0; a < n; ++a)
       for (int e = nd.jst[a]; e < nd.jst[a + 1]; ++e) {
-        const int k = nd.jk[e], p = nd.jp[e];
+        const int k = nd.jk[e], p = nd.jp[e], p2 = nd.jp2[e];
         double g = kc[k] * nd.jm[e];
         if (p >= 0) g *= yc[p];
+        if (p2 >= 0) g *= yc[p2];
         for (int i = 0; i < n; ++i) J[joff[c] + i + (long)a * n] += nd.S[(long)k * nd.np + i] * g;
       }
 }
@@ -135,11 +146,12 @@ __global__ void k_capture(long nsamp, long stride, int n, int tiled, NetDev nd,
   for (int e = 0; e < n * n; ++e) Mk[e] = 0.0;
   for (int a = 0; a < n; ++a)
     for (int e = nd.jst[a]; e < nd.jst[a + 1]; ++e) {
-      const int kk = nd.jk[e], p = nd.jp[e];
+      const int kk = nd.jk[e], p = nd.jp[e], p2 = nd.jp2[e];
       const double kap = rates[tiled ? (c >> 6) * 64L * nd.R + (long)kk * 64 + (c & 63)
                                      : c * nd.R + kk];
       double g = kap * nd.jm[e];
       if (p >= 0) g *= y[p];
+      if (p2 >= 0) g *= y[p2];
       for (int i = 0; i < n; ++i) Mk[i + (long)a * n] += nd.S[(long)kk * nd.np + i] * g;
     }
   for (int a = 0; a < n; ++a)
@@ -188,7 +200,15 @@ struct bdf_handle {
   char* ws = nullptr;
   size_t ws_size = 0, ws_used = 0;
   bool dry = false;
+  // per-cell stepping: counts of cells still running after each attempt of
+  // a batch (device) and the pinned copy of the last one
+  bool per_cell = false;
+  unsigned int* d_active = nullptr;
+  unsigned int* h_active = nullptr;
 };
+
+constexpr int kCellSlots = 1;       // per-cell mode: count of running cells
+constexpr int kCellAttempts = 128;  // per-cell mode: attempts per cell in one launch
 
 constexpr size_t kWsAlign = 256;
 
@@ -444,6 +464,63 @@ static int drive(bdf_handle* h, double tend, long inc, double* tret) {
   return 0;
 }
 
+// Per-cell stepping: starting steps of the cells not started yet, then
+// batches of attempts (every unfinished cell of every class one attempt per
+// launch) until no cell is running; the count of running cells after the
+// batch's last attempt is the only host read.  Returns the first failing
+// cell's status (in class order), if any.
+static int cell_dev(bdf_handle* h, const ClassHost& c, double tend, int slot, CellDev* P) {
+  *P = c.cell;
+  P->tend = tend;
+  P->active = h->d_active;
+  P->slot = slot;
+  P->cap = kCellAttempts;
+  P->max_att = h->o.max_steps;
+  return 0;
+}
+
+static int drive_cells(bdf_handle* h, double tend, double* tret) {
+  CellDev P;
+  for (const ClassHost& c : h->cls) {
+    if (c.ncells == 0) continue;
+    cell_dev(h, c, tend, 0, &P);
+    hipLaunchKernelGGL(k_cell_resume, dim3(ceil_div(c.ncells, 256)), dim3(256), 0, h->s,
+                       c.ncells, tend, c.cell.t, c.cell.iv);
+    launch_cell(c.np, h->o.linsol, 0, make_dev(h, c), P, c.grid, h->s);
+  }
+  BDF_HIP_TRY(hipGetLastError());
+  // each launch runs up to kCellAttempts attempts per cell; the host reads
+  // the number of cells still running after each launch
+  for (;;) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, h->s, h->d_active, 1);
+    for (const ClassHost& c : h->cls) {
+      if (c.ncells == 0) continue;
+      cell_dev(h, c, tend, 0, &P);
+      launch_cell(c.np, h->o.linsol, 1, make_dev(h, c), P, c.grid, h->s);
+    }
+    BDF_HIP_TRY(hipGetLastError());
+    BDF_HIP_TRY(hipMemcpyAsync(h->h_active, h->d_active, sizeof(unsigned int),
+                               hipMemcpyDeviceToHost, h->s));
+    BDF_HIP_TRY(hipStreamSynchronize(h->s));
+    if (*h->h_active == 0) break;
+  }
+  if (tret) *tret = tend;
+  // the first failed cell's status
+  for (const ClassHost& c : h->cls) {
+    if (c.ncells == 0) continue;
+    std::vector<int> iv(4 * c.ncells);
+    BDF_HIP_TRY(hipMemcpy(iv.data(), c.cell.iv, sizeof(int) * iv.size(), hipMemcpyDeviceToHost));
+    for (long i = 0; i < c.ncells; ++i) {
+      const int stc = iv[4 * i + 3];
+      if (stc != CELL_DONE && stc != CELL_RUN) {
+        set_last_error("per-cell stepping: a cell failed (see status code)", __FILE__, __LINE__);
+        return stc;
+      }
+    }
+  }
+  return 0;
+}
+
 extern "C" {
 
 static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream, void* ws,
@@ -456,12 +533,20 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   if (o->qmax < 1 || o->qmax > kQmaxAll || o->maxcor < 1 || o->maxcor > kMaxCor ||
       !(o->rtol >= 0.0) || !(o->atol > 0.0) ||
       (o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_LU32REF &&
-       o->linsol != BDFGPU_LS_LEARNED) ||
+       o->linsol != BDFGPU_LS_LEARNED && o->linsol != BDFGPU_LS_GJ) ||
       (o->linsol == BDFGPU_LS_LEARNED && !o->precond))
     return arg_error("bdf_create: bad options (qmax 1..5, maxcor 1..4, atol > 0, linsol, precond)");
+  if (o->per_cell && ((o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_GJ) ||
+                      o->launch == BDFGPU_LAUNCH_FUSED || o->map_small))
+    return arg_error("bdf_create: per-cell stepping needs FP64 LU or the Gauss-Jordan solve, "
+                     "per-class launches and one lane per cell");
+  if (o->linsol == BDFGPU_LS_GJ && (o->launch != BDFGPU_LAUNCH_PER_CLASS || o->map_small))
+    return arg_error("bdf_create: the Gauss-Jordan solve needs per-class launches and one lane "
+                     "per cell");
   *out = nullptr;
   bdf_handle* h = new bdf_handle();
   h->s = as_stream(stream);
+  h->per_cell = o->per_cell != 0;
   h->ws = static_cast<char*>(ws);
   h->ws_size = ws_bytes;
   h->dry = dry;
@@ -510,12 +595,21 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     ch.n = n;
     ch.R = R;
     ch.ncells = (long)kv.second.size();
+    ch.members = kv.second;
     // thread per cell while the rates and evaluation point fit the LDS of a
     // block, else segment per cell
     ch.map = (!o->map_small && n <= 12 &&
               tpc_newton_lds(tpc_padded(n), R, o->linsol, kTpcThreads) <= (size_t)lds_max)
                  ? MAP_TPC
                  : MAP_SPC;
+    if (o->per_cell && ch.map != MAP_TPC) {
+      bdf_destroy(h);
+      return arg_error("bdf_create: per-cell stepping needs cells of <= 12 species");
+    }
+    if (o->linsol == BDFGPU_LS_GJ && (ch.map != MAP_TPC || n > 4)) {
+      bdf_destroy(h);
+      return arg_error("bdf_create: the Gauss-Jordan solve takes cells of <= 4 species");
+    }
     if (ch.map == MAP_SPC && spc_lds_bytes(spc_seg(n), R) > (size_t)lds_max) {
       bdf_destroy(h);
       return arg_error("bdf_create: too many reactions for the block's LDS");
@@ -547,8 +641,15 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     // network tables
     const int np = ch.np;
     std::vector<double> S((size_t)R * np, 0.0);
-    std::vector<int> ra(R, -1), rb(R, -1);
-    std::vector<std::vector<std::pair<int, std::pair<int, double>>>> cols(np);
+    std::vector<int> ra(R, -1), rb(R, -1), rc(R, -1);
+    // Jacobian entries per column: (reaction, partner, second partner,
+    // multiplicity), reactions ascending
+    struct JEnt {
+      int k, p, p2;
+      double m;
+    };
+    std::vector<std::vector<JEnt>> cols(np);
+    bool third = false;
     for (int k = 0; k < R; ++k) {
       int order = 0;
       std::vector<int> reac;
@@ -562,30 +663,51 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
         order += e;
         S[(size_t)k * np + s2] = (double)(mu[k * n + s2] - nu[k * n + s2]);
       }
-      if (order > 2) {
+      if (order > 3) {
         bdf_destroy(h);
-        return arg_error("bdf_create: reactions may have at most two reactant molecules");
+        return arg_error("bdf_create: reactions may have at most three reactant molecules");
       }
+      third = third || order == 3;
       if (order >= 1) ra[k] = reac[0];
-      if (order == 2) rb[k] = reac[1];
-      if (order == 1) cols[reac[0]].push_back({k, {-1, 1.0}});
-      if (order == 2) {
-        if (reac[0] == reac[1]) {
-          cols[reac[0]].push_back({k, {reac[0], 2.0}});
-        } else {
-          cols[reac[0]].push_back({k, {reac[1], 1.0}});
-          cols[reac[1]].push_back({k, {reac[0], 1.0}});
+      if (order >= 2) rb[k] = reac[1];
+      if (order == 3) rc[k] = reac[2];
+      // d r / d y_a = e_a kappa prod(other reactant molecules), once per
+      // distinct reactant a (reac is sorted)
+      for (int i = 0; i < order; ++i) {
+        if (i > 0 && reac[i] == reac[i - 1]) continue;
+        const int a = reac[i];
+        int e = 0;
+        std::vector<int> others;
+        bool dropped = false;
+        for (int r : reac) {
+          if (r == a) {
+            ++e;
+            if (!dropped) {
+              dropped = true;
+              continue;
+            }
+          }
+          others.push_back(r);
         }
+        cols[a].push_back({k, others.size() > 0 ? others[0] : -1,
+                           others.size() > 1 ? others[1] : -1, (double)e});
       }
     }
-    std::vector<int> jst(np + 1, 0), jk, jp;
+    if (third && (ch.map != MAP_TPC || o->linsol == BDFGPU_LS_LU32REF ||
+                  o->linsol == BDFGPU_LS_LEARNED)) {
+      bdf_destroy(h);
+      return arg_error("bdf_create: three-molecule reactions need one lane per cell (<= 12 "
+                       "species) and FP64 LU or the Gauss-Jordan solve");
+    }
+    std::vector<int> jst(np + 1, 0), jk, jp, jp2;
     std::vector<double> jm;
     for (int a = 0; a < np; ++a) {
       jst[a] = (int)jk.size();
       for (auto& e : cols[a]) {
-        jk.push_back(e.first);
-        jp.push_back(e.second.first);
-        jm.push_back(e.second.second);
+        jk.push_back(e.k);
+        jp.push_back(e.p);
+        jp2.push_back(e.p2);
+        jm.push_back(e.m);
       }
     }
     jst[np] = (int)jk.size();
@@ -594,8 +716,10 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     nd.R = R;
     nd.np = np;
     if ((st = upload(h, const_cast<double**>(&nd.S), S)) || (st = upload(h, const_cast<int**>(&nd.ra), ra)) ||
-        (st = upload(h, const_cast<int**>(&nd.rb), rb)) || (st = upload(h, const_cast<int**>(&nd.jst), jst)) ||
+        (st = upload(h, const_cast<int**>(&nd.rb), rb)) || (st = upload(h, const_cast<int**>(&nd.rc), rc)) ||
+        (st = upload(h, const_cast<int**>(&nd.jst), jst)) ||
         (st = upload(h, const_cast<int**>(&nd.jk), jk)) || (st = upload(h, const_cast<int**>(&nd.jp), jp)) ||
+        (st = upload(h, const_cast<int**>(&nd.jp2), jp2)) ||
         (st = upload(h, const_cast<double**>(&nd.jm), jm))) {
       bdf_destroy(h);
       return st;
@@ -647,6 +771,27 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
       bdf_destroy(h);
       return st;
     }
+    if (o->per_cell) {
+      CellDev& P = ch.cell;
+      memset(&P, 0, sizeof(P));
+      const size_t nc = (size_t)std::max<long>(1, ch.ncells);
+      if ((st = dalloc(h, (void**)&P.t, sizeof(double) * nc)) ||
+          (st = dalloc(h, (void**)&P.h, sizeof(double) * nc)) ||
+          (st = dalloc(h, (void**)&P.hsc, sizeof(double) * nc)) ||
+          (st = dalloc(h, (void**)&P.hu, sizeof(double) * nc)) ||
+          (st = dalloc(h, (void**)&P.iv, sizeof(int) * 4 * nc)) ||
+          (st = dalloc(h, (void**)&P.cnt, sizeof(int) * 5 * nc))) {
+        bdf_destroy(h);
+        return st;
+      }
+      P.h0user = o->h0;
+      P.hmin = o->hmin;
+      P.qmax = o->qmax;
+      P.maxcor = o->maxcor;
+      if (!dry && ch.ncells > 0)
+        hipLaunchKernelGGL(k_cell_setup, dim3(ceil_div(ch.ncells, 256)), dim3(256), 0, h->s,
+                           ch.ncells, p->t0, P.t, P.h, P.hsc, P.hu, P.iv, P.cnt);
+    }
     if (ch.ncells > 0 && !dry) {
       const unsigned int gy = ceil_div(ch.ncells * n, 256), gr = ceil_div(ch.ncells * (long)R, 256);
       hipLaunchKernelGGL(k_to_class, dim3(gy), dim3(256), 0, h->s, ch.ncells, n, (int)tiled,
@@ -678,7 +823,8 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   h->fused = o->launch == BDFGPU_LAUNCH_FUSED;
   // deferred history update: per-class launches of thread-per-cell classes
   // with FP64 or FP32-refined LU
-  h->defer = !o->no_defer && !h->fused && o->linsol != BDFGPU_LS_LEARNED && !h->cls.empty();
+  h->defer = !o->no_defer && !h->fused && o->linsol != BDFGPU_LS_LEARNED && !h->cls.empty() &&
+             !o->per_cell;
   for (const ClassHost& c : h->cls)
     if (c.map != MAP_TPC) h->defer = false;
   const long bmax = std::max(blk, mblk);
@@ -689,10 +835,17 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     bdf_destroy(h);
     return st;
   }
+  if (o->per_cell &&
+      (st = dalloc(h, (void**)&h->d_active, sizeof(unsigned int) * kCellSlots))) {
+    bdf_destroy(h);
+    return st;
+  }
   if (dry) {   // sizes counted: nothing was allocated or launched
     *out = h;
     return 0;
   }
+  if (o->per_cell)
+    BDF_HIP_TRY(hipHostMalloc((void**)&h->h_active, sizeof(unsigned int), hipHostMallocDefault));
   BDF_HIP_TRY(hipHostMalloc((void**)&h->hC, sizeof(Ctrl), hipHostMallocDefault));
   Ctrl C;
   memset(&C, 0, sizeof(C));
@@ -712,7 +865,7 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   C.step_limit = LONG_MAX;
   BDF_HIP_TRY(hipMemcpyAsync(h->dC, &C, sizeof(Ctrl), hipMemcpyHostToDevice, h->s));
   BDF_HIP_TRY(hipStreamSynchronize(h->s));
-  if (o->mode == BDFGPU_MODE_GRAPH && h->N > 0) {
+  if (o->mode == BDFGPU_MODE_GRAPH && h->N > 0 && !o->per_cell) {
     st = build_graph(h);
     if (st) {
       bdf_destroy(h);
@@ -844,6 +997,7 @@ int bdf_destroy(bdf_handle* h) {
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->hC) (void)hipHostFree(h->hC);
+  if (h->h_active) (void)hipHostFree(h->h_active);
   delete h;
   return 0;
 }
@@ -852,6 +1006,7 @@ long bdf_get_N(bdf_handle* h) { return h ? h->N : -1; }
 
 int bdf_step(bdf_handle* h, double t_end, double* tret) {
   if (!h) return arg_error("bdf_step: null handle");
+  if (h->per_cell) return arg_error("bdf_step: per-cell stepping integrates to t_end only");
   if (h->N == 0) {
     if (tret) *tret = t_end;
     return 0;
@@ -861,6 +1016,7 @@ int bdf_step(bdf_handle* h, double t_end, double* tret) {
 
 int bdf_advance(bdf_handle* h, double t_end, long nsteps, double* tret, long* taken) {
   if (!h || nsteps < 0) return arg_error("bdf_advance: bad argument");
+  if (h->per_cell) return arg_error("bdf_advance: per-cell stepping integrates to t_end only");
   if (taken) *taken = 0;
   if (h->N == 0 || nsteps == 0) {
     if (tret) *tret = h->N == 0 ? t_end : h->hC->t;
@@ -901,6 +1057,7 @@ int bdf_integrate(bdf_handle* h, double t_end, double* tret) {
     if (tret) *tret = t_end;
     return 0;
   }
+  if (h->per_cell) return drive_cells(h, t_end, tret);
   const long inc = h->o.max_steps > 0 ? h->o.max_steps : LONG_MAX / 4;
   int st = drive(h, t_end, inc, tret);
   if (st) return st;
@@ -922,8 +1079,71 @@ int bdf_get_y(bdf_handle* h, double* y) {
   return 0;
 }
 
+// Per-cell mode: sums of the cells' counters; t = the earliest cell time,
+// h and q of the first cell, status = the first failed cell's.
+static int cell_stats_sum(bdf_handle* h, bdf_stats* s) {
+  memset(s, 0, sizeof(*s));
+  double tmin = 1e300;
+  bool first = true;
+  for (const ClassHost& c : h->cls) {
+    if (c.ncells == 0) continue;
+    std::vector<int> cnt(5 * c.ncells), iv(4 * c.ncells);
+    std::vector<double> t(c.ncells), hh(c.ncells);
+    BDF_HIP_TRY(hipMemcpy(cnt.data(), c.cell.cnt, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost));
+    BDF_HIP_TRY(hipMemcpy(iv.data(), c.cell.iv, sizeof(int) * iv.size(), hipMemcpyDeviceToHost));
+    BDF_HIP_TRY(hipMemcpy(t.data(), c.cell.t, sizeof(double) * t.size(), hipMemcpyDeviceToHost));
+    BDF_HIP_TRY(hipMemcpy(hh.data(), c.cell.h, sizeof(double) * hh.size(), hipMemcpyDeviceToHost));
+    for (long i = 0; i < c.ncells; ++i) {
+      s->nsteps += cnt[5 * i + 0];
+      s->nattempts += cnt[5 * i + 1];
+      s->nniters += cnt[5 * i + 2];
+      s->netfails += cnt[5 * i + 3];
+      s->nncfails += cnt[5 * i + 4];
+      tmin = std::min(tmin, t[i]);
+      const int stc = iv[4 * i + 3];
+      if (stc != CELL_DONE && stc != CELL_RUN && s->status == 0) s->status = stc;
+      if (first) {
+        s->h = hh[i];
+        s->q = iv[4 * i + 0];
+        first = false;
+      }
+    }
+  }
+  s->nsetups = s->nattempts;
+  s->nlinsolves = s->nniters;
+  s->nfevals = s->nniters;
+  s->t = tmin < 1e300 ? tmin : 0.0;
+  return 0;
+}
+
+int bdf_get_cell_stats(bdf_handle* h, int* counts, double* t, double* hu) {
+  if (!h || (!counts && !t && !hu)) return arg_error("bdf_get_cell_stats: bad argument");
+  if (!h->per_cell) return arg_error("bdf_get_cell_stats: the handle does not step per cell");
+  BDF_HIP_TRY(hipStreamSynchronize(h->s));
+  for (const ClassHost& c : h->cls) {
+    if (c.ncells == 0) continue;
+    std::vector<int> cnt(5 * c.ncells);
+    std::vector<double> tt(c.ncells), hh(c.ncells);
+    BDF_HIP_TRY(hipMemcpy(cnt.data(), c.cell.cnt, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost));
+    BDF_HIP_TRY(hipMemcpy(tt.data(), c.cell.t, sizeof(double) * tt.size(), hipMemcpyDeviceToHost));
+    BDF_HIP_TRY(hipMemcpy(hh.data(), c.cell.hu, sizeof(double) * hh.size(), hipMemcpyDeviceToHost));
+    for (long i = 0; i < c.ncells; ++i) {
+      const long u = c.members[i];
+      if (counts)
+        for (int k = 0; k < 5; ++k) counts[5 * u + k] = cnt[5 * i + k];
+      if (t) t[u] = tt[i];
+      if (hu) hu[u] = hh[i];
+    }
+  }
+  return 0;
+}
+
 int bdf_get_stats(bdf_handle* h, bdf_stats* s) {
   if (!h || !s) return arg_error("bdf_get_stats: bad argument");
+  if (h->per_cell) {
+    BDF_HIP_TRY(hipStreamSynchronize(h->s));
+    return cell_stats_sum(h, s);
+  }
   int st = read_ctrl(h);
   if (st) return st;
   const Ctrl& C = *h->hC;
@@ -958,6 +1178,7 @@ int bdf_get_stats(bdf_handle* h, bdf_stats* s) {
 int bdf_get_state(bdf_handle* h, double* dvals, int* ivals, double* z6, double* dprev) {
   if (!h || !dvals || !ivals || (h->N > 0 && (!z6 || !dprev)))
     return arg_error("bdf_get_state: bad argument");
+  if (h->per_cell) return arg_error("bdf_get_state: not available with per-cell stepping");
   int st = read_ctrl(h);
   if (st) return st;
   const Ctrl C = *h->hC;
@@ -985,6 +1206,7 @@ int bdf_set_state(bdf_handle* h, const double* dvals, const int* ivals, const do
                   const double* dprev) {
   if (!h || !dvals || !ivals || (h->N > 0 && (!z6 || !dprev)))
     return arg_error("bdf_set_state: bad argument");
+  if (h->per_cell) return arg_error("bdf_set_state: not available with per-cell stepping");
   if (ivals[0] < 1 || ivals[0] > h->o.qmax) return arg_error("bdf_set_state: q out of range");
   int st = read_ctrl(h);
   if (st) return st;

@@ -31,18 +31,21 @@
 
 namespace bdfgpu {
 
-// Shared network of one class of cells: r_k = kappa_k * y[ra_k] * y[rb_k]
-// (missing reactant = -1), f = S r, and for the Jacobian a list per column a
-// of (reaction k, partner species p or -1, multiplicity m): dr_k/dy_a =
-// m kappa_k y_p.
+// Shared network of one class of cells: r_k = kappa_k * y[ra_k] * y[rb_k] *
+// y[rc_k] (missing reactant = -1; a third reactant only in thread-per-cell
+// classes), f = S r, and for the Jacobian a list per column a of (reaction
+// k, partner species p and p2 or -1, multiplicity m): dr_k/dy_a =
+// m kappa_k y_p y_p2.
 struct NetDev {
   int n, R, np;          // species, reactions, padded row length of S
   const double* S;       // [R][np] net stoichiometry mu - nu
   const int* ra;         // [R]
   const int* rb;         // [R]
+  const int* rc;         // [R]
   const int* jst;        // [np + 1] start of each column's list
   const int* jk;         // [nent]
   const int* jp;         // [nent]
+  const int* jp2;        // [nent]
   const double* jm;      // [nent]
 };
 
@@ -314,6 +317,92 @@ struct TpcLU {
   }
 };
 
+// Explicit inverse of one lane's NP x NP block (NP <= 4) by Gauss-Jordan
+// elimination on [A | I]: at step K the first maximal |a_iK| (i >= K) is
+// exchanged into row K (columns left of K are unit columns there, so only
+// columns K.. of A and all of X move), row K is divided by its pivot and
+// its multiples are subtracted from every other row.  X receives A^-1
+// (X[i][j] = (A^-1)_ij); A is destroyed.  The explicit-inverse block solve
+// of the paper's demonstration problem (Section 7).  Returns the first
+// exactly-zero pivot (1-based) or 0; a zero pivot leaves that step's column
+// as it is.
+template <int NP>
+struct TpcGJ {
+  template <int K>
+  __device__ static __forceinline__ void step(double (&A)[NP][NP], double (&X)[NP][NP], int& info) {
+    if constexpr (K < NP) {
+      int p = K;
+      double amax = sabs(A[K][K]);
+#pragma unroll
+      for (int i = K + 1; i < NP; ++i) {
+        const double v = sabs(A[i][K]);
+        const bool gt = v > amax;
+        amax = gt ? v : amax;
+        p = gt ? i : p;
+      }
+#pragma unroll
+      for (int i = K + 1; i < NP; ++i) {
+        if (__any(p == i)) {
+          keep_branch();
+          const bool sw = (p == i);
+#pragma unroll
+          for (int j = K; j < NP; ++j) {
+            const double t = A[K][j];
+            A[K][j] = sw ? A[i][j] : t;
+            A[i][j] = sw ? t : A[i][j];
+          }
+#pragma unroll
+          for (int j = 0; j < NP; ++j) {
+            const double t = X[K][j];
+            X[K][j] = sw ? X[i][j] : t;
+            X[i][j] = sw ? t : X[i][j];
+          }
+        }
+      }
+      const double d0 = A[K][K];
+      const bool z = (d0 == 0.0);
+      if (z && !info) info = K + 1;
+      const double d = z ? 1.0 : d0;
+#pragma unroll
+      for (int j = K + 1; j < NP; ++j) A[K][j] = A[K][j] / d;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) X[K][j] = X[K][j] / d;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        if (i == K) continue;
+        const double f = A[i][K];
+#pragma unroll
+        for (int j = K + 1; j < NP; ++j) A[i][j] = fma(-f, A[K][j], A[i][j]);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) X[i][j] = fma(-f, X[K][j], X[i][j]);
+      }
+      step<K + 1>(A, X, info);
+    }
+  }
+
+  __device__ static __forceinline__ int invert(double (&A)[NP][NP], double (&X)[NP][NP]) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) X[i][j] = i == j ? 1.0 : 0.0;
+    int info = 0;
+    step<0>(A, X, info);
+    return info;
+  }
+
+  // out = X r, each row summed in column order
+  __device__ static __forceinline__ void apply(const double (&X)[NP][NP], const double (&r)[NP],
+                                               double (&out)[NP]) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) s = fma(X[i][j], r[j], s);
+      out[i] = s;
+    }
+  }
+};
+
 template <int NP, int TB = kTpcThreads>
 struct Tpc {
   static constexpr int T = TB;            // LDS column stride (threads per block)
@@ -333,10 +422,11 @@ struct Tpc {
     for (int i = 0; i < NP; ++i) f[i] = 0.0;
 #pragma unroll 2
     for (int k = 0; k < nd.R; ++k) {
-      const int a = nd.ra[k], b = nd.rb[k];
+      const int a = nd.ra[k], b = nd.rb[k], c3 = nd.rc[k];
       double r = kcol[k * ks];
       if (a >= 0) r *= ycol[a * T];
       if (b >= 0) r *= ycol[b * T];
+      if (c3 >= 0) r *= ycol[c3 * T];
       const double* Sk = nd.S + (long)k * nd.np;
 #pragma unroll
       for (int i = 0; i < NP; ++i) f[i] = fma(Sk[i], r, f[i]);
@@ -352,9 +442,10 @@ struct Tpc {
     const int e0 = nd.jst[a], e1 = nd.jst[a + 1];
 #pragma unroll 2
     for (int e = e0; e < e1; ++e) {
-      const int k = nd.jk[e], p = nd.jp[e];
+      const int k = nd.jk[e], p = nd.jp[e], p2 = nd.jp2[e];
       double g = kcol[k * ks] * nd.jm[e];
       if (p >= 0) g *= ycol[p * T];
+      if (p2 >= 0) g *= ycol[p2 * T];
       const double* Sk = nd.S + (long)k * nd.np;
 #pragma unroll
       for (int i = 0; i < NP; ++i) col[i] = fma(Sk[i], g, col[i]);
@@ -708,13 +799,19 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
     TF A[NP][NP];
     int piv[NP];
     double rowsum[NP];
+    constexpr int NX = LS == 3 ? NP : 1;   // LS 3: the block's explicit inverse
+    double Xi[NX][NX];
     Net::template build_M<NP, TB, TF, LS == 1>(nd, kcol, TB, ycol, gamma, A, rowsum);
     double mnorm = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) mnorm = fmax(mnorm, rowsum[i]);
-    const int info = TpcLU<NP, TF>::factor(A, piv);
+    int info;
+    if constexpr (LS == 3)
+      info = TpcGJ<NP>::invert(A, Xi);
+    else
+      info = TpcLU<NP, TF>::factor(A, piv);
     bool fp64 = (LS == 1) && info != 0;   // LS 1: FP32 factor singular -> FP64 LU
-    bool sing = (LS == 0) && info != 0;
+    bool sing = (LS == 0 || LS == 3) && info != 0;
     red[4] = fp64 ? 1.0 : 0.0;            // counted with the first iteration
     double y[NP];
 #pragma unroll
@@ -732,6 +829,8 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
 #pragma unroll
         for (int i = 0; i < NP; ++i) del[i] = r[i];
         TpcLU<NP, TF>::solve(A, piv, del);
+      } else if constexpr (LS == 3) {
+        TpcGJ<NP>::apply(Xi, r, del);
       } else {
         bool ok = false;
         if (!fp64) {

@@ -51,8 +51,9 @@ namespace bdfgpu {
 namespace {
 
 struct Reaction {
-  int a = -1, b = -1;        // reactant species (a <= b), -1 if absent
-  std::vector<int> s;        // net stoichiometry mu - nu, length n
+  int a = -1, b = -1, c = -1;   // reactant species (a <= b <= c), -1 if absent
+  std::vector<int> s;           // net stoichiometry mu - nu, length n
+  std::vector<int> reac;        // reactant molecules, sorted
 };
 
 std::vector<Reaction> reactions(const int* nu, const int* mu, int n, int R) {
@@ -66,6 +67,8 @@ std::vector<Reaction> reactions(const int* nu, const int* mu, int n, int R) {
     }
     if (reac.size() >= 1) out[k].a = reac[0];
     if (reac.size() >= 2) out[k].b = reac[1];
+    if (reac.size() >= 3) out[k].c = reac[2];
+    out[k].reac = reac;
   }
   return out;
 }
@@ -86,27 +89,36 @@ void emit_update(std::ostringstream& o, const std::string& dst, int S, const cha
 std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np, int ls) {
   const std::vector<Reaction> rx = reactions(nu, mu, n, R);
   std::vector<bool> react(n, false);
-  for (const Reaction& r : rx) {
-    if (r.a >= 0) react[r.a] = true;
-    if (r.b >= 0) react[r.b] = true;
-  }
+  for (const Reaction& r : rx)
+    for (int x : r.reac) react[x] = true;
   // Jacobian entries per column a in the order of the network tables:
-  // reaction k ascending; (k, partner species or -1, multiplicity)
+  // reaction k ascending; (k, partners or -1, multiplicity): once per
+  // distinct reactant a, dr/dy_a = e_a kappa prod(the other molecules)
   struct Ent {
-    int k, p;
+    int k, p, p2;
     double m;
   };
   std::vector<std::vector<Ent>> cols(n);
   for (int k = 0; k < R; ++k) {
-    const Reaction& r = rx[k];
-    if (r.a < 0) continue;
-    if (r.b < 0) {
-      cols[r.a].push_back({k, -1, 1.0});
-    } else if (r.a == r.b) {
-      cols[r.a].push_back({k, r.a, 2.0});
-    } else {
-      cols[r.a].push_back({k, r.b, 1.0});
-      cols[r.b].push_back({k, r.a, 1.0});
+    const std::vector<int>& rc = rx[k].reac;
+    for (size_t i = 0; i < rc.size(); ++i) {
+      if (i > 0 && rc[i] == rc[i - 1]) continue;
+      const int a = rc[i];
+      int e = 0;
+      std::vector<int> others;
+      bool dropped = false;
+      for (int x : rc) {
+        if (x == a) {
+          ++e;
+          if (!dropped) {
+            dropped = true;
+            continue;
+          }
+        }
+        others.push_back(x);
+      }
+      cols[a].push_back({k, others.size() > 0 ? others[0] : -1, others.size() > 1 ? others[1] : -1,
+                         (double)e});
     }
   }
 
@@ -129,6 +141,7 @@ std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np
     o << "    {\n      double r = kcol[" << k << " * ks];\n";
     if (r.a >= 0) o << "      r *= y" << r.a << ";\n";
     if (r.b >= 0) o << "      r *= y" << r.b << ";\n";
+    if (r.c >= 0) o << "      r *= y" << r.c << ";\n";
     for (int i = 0; i < n; ++i)
       if (r.s[i] != 0) emit_update(o, "f[" + std::to_string(i) + "]", r.s[i], "r", "      ");
     o << "    }\n";
@@ -156,9 +169,9 @@ std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np
       if (touched[i]) o << "      double c" << i << " = 0.0;\n";
     if (a < n)
       for (const Ent& e : cols[a]) {
-        o << "      {\n        double g = kcol[" << e.k << " * ks] * " << (e.m == 2.0 ? "2.0" : "1.0")
-          << ";\n";
+        o << "      {\n        double g = kcol[" << e.k << " * ks] * " << (int)e.m << ".0;\n";
         if (e.p >= 0) o << "        g *= y" << e.p << ";\n";
+        if (e.p2 >= 0) o << "        g *= y" << e.p2 << ";\n";
         for (int i = 0; i < n; ++i)
           if (rx[e.k].s[i] != 0) emit_update(o, "c" + std::to_string(i), rx[e.k].s[i], "g", "        ");
         o << "      }\n";
@@ -198,9 +211,13 @@ std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np
     o << "    {\n      const double kk = kcol[" << k << " * ks];\n";
     if (r.b < 0)
       o << "      const double d = kk * x" << r.a << ";\n";
-    else
+    else if (r.c < 0)
       o << "      const double d = kk * fma(x" << r.a << ", y" << r.b << ", y" << r.a << " * x"
         << r.b << ");\n";
+    else   // three molecules (the FP32-refined solve, which uses this, refuses them)
+      o << "      const double d = kk * (x" << r.a << " * y" << r.b << " * y" << r.c << " + y"
+        << r.a << " * x" << r.b << " * y" << r.c << " + y" << r.a << " * y" << r.b << " * x"
+        << r.c << ");\n";
     for (int i = 0; i < n; ++i)
       if (r.s[i] != 0) emit_update(o, "jx[" + std::to_string(i) + "]", r.s[i], "d", "      ");
     o << "    }\n";

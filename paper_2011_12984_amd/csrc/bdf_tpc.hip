@@ -36,7 +36,9 @@ static void tpc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStr
       const size_t lds = tpc_newton_lds(NP, D.k.R, ls, kTpcThreads, D.defer);
       if (ls == 1)
         go_newton<NP, 1>(D, g, b, lds, s);
-      else
+      else if (ls == 3) {
+        if constexpr (NP <= 4) go_newton<NP, 3>(D, g, b, lds, s);   // (bdf_create enforces NP <= 4)
+      } else
         go_newton<NP, 0>(D, g, b, lds, s);
       break;
     }

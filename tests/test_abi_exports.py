@@ -66,3 +66,19 @@ def test_workspace_bytes_without_device_memory():
     # least 8 (10 n + R) bytes per cell
     assert big - small >= 8 * (10 * 10 + 20) * 9900
     assert Bdf.workspace_bytes(W.random_network_batch(100, n=10, seed=1), qmax=9) == 0
+
+
+def test_gauss_jordan_and_order3_option_checks():
+    """Option checks of the dry run: the Gauss-Jordan block inverse is
+    accepted for blocks of <= 4 species on per-class launches (also with
+    per-cell stepping) and refused otherwise; a reaction of order three
+    (the demonstration reaction's 2u + v -> 3u) is refused by the FP32 LU
+    with refinement, whose matrix-free product covers order <= 2."""
+    import workloads as W
+    from paper_2011_12984_amd import LS_GJ, LS_LU32REF, LAUNCH_FUSED, Bdf
+    br = W.brusselator_batch(100)
+    assert Bdf.workspace_bytes(br, linsol=LS_GJ) > 0
+    assert Bdf.workspace_bytes(br, linsol=LS_GJ, per_cell=True) > 0
+    assert Bdf.workspace_bytes(br, linsol=LS_GJ, launch=LAUNCH_FUSED) == 0
+    assert Bdf.workspace_bytes(W.random_network_batch(100, n=10, seed=1), linsol=LS_GJ) == 0
+    assert Bdf.workspace_bytes(br, linsol=LS_LU32REF) == 0

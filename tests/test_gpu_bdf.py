@@ -35,6 +35,7 @@ def jac_entries(prob):
     lambda: W.random_network_batch(300, n=10, seed=5),
     lambda: W.learned_batch(70),
     lambda: W.uneven_batch(1 << 12, seed=9),
+    lambda: W.brusselator_batch(500),   # a reaction of order three
 ])
 def test_rhs_jac_parity(orc, dev, G, maker):
     p = maker()
@@ -86,6 +87,29 @@ def test_single_step_from_identical_state(orc, dev, G):
 
 def test_trajectory_robertson_bdf2(orc, dev, G):
     compare_trajectory(orc, dev, G, W.robertson_batch(1000))
+
+
+@pytest.mark.parametrize("solve", ["lu", "gauss_jordan"])
+def test_trajectory_brusselator(orc, dev, G, solve):
+    """The demonstration reaction of Section 7 on 1,000 cells of the 1-D
+    Gaussian profile, to t = 10, with the FP64 LU or the explicit
+    Gauss-Jordan block inverse on both sides."""
+    compare_trajectory(orc, dev, G, W.brusselator_batch(1000),
+                       linsol=G.LS_GJ if solve == "gauss_jordan" else G.LS_LU64)
+
+
+def test_gauss_jordan_differs_from_lu_by_rounding_only(dev, G):
+    """The Gauss-Jordan handle really applies the explicit inverse (its
+    state is not bit-identical to the LU handle's) and takes the same steps
+    to a state within 1e-6 WRMS of it."""
+    p = W.brusselator_batch(4096)
+    a = gpu_bdf(G, p, dev, linsol=G.LS_GJ)
+    b = gpu_bdf(G, p, dev, linsol=G.LS_LU64)
+    assert a.integrate(p.t_end) == p.t_end and b.integrate(p.t_end) == p.t_end
+    assert a.stats()["nsteps"] == b.stats()["nsteps"]
+    ya, yb = a.y(), b.y()
+    assert not torch.equal(ya, yb)
+    assert wrms_diff(ya.cpu().numpy(), yb.cpu().numpy(), p.rtol, p.atol) <= 1e-6
 
 
 def test_trajectory_network10(orc, dev, G):

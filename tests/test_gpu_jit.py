@@ -6,8 +6,8 @@ operations in the same order as the table-driven ones (terms with a zero
 stoichiometric coefficient, which add +-0 exactly, are left out), so whole
 trajectories must agree bit for bit: same step counts, same final state.
 The generic kernel is itself held to the oracle in test_gpu_bdf.py.  Cases
-cover padded block sizes (5 -> 6, 9 -> 10), several classes at once, both
-linear-solver forms, graph replay, and the compiled-library caches (per
+cover padded block sizes (5 -> 6, 9 -> 10), several classes at once, a
+reaction of order three, the three block solves, graph replay, and the compiled-library caches (per
 process, and on disk under BDFGPU_JIT_DIR).
 """
 import os
@@ -28,6 +28,7 @@ CASES = {
     "net9_padded10": (lambda: W.random_network_batch(500, n=9, seed=4), 0.5),
     "net12": (lambda: W.random_network_batch(400, n=12, seed=6), 0.5),
     "uneven_4_8_12": (lambda: W.uneven_batch(6000, seed=9, classes=(4, 8, 12)), 0.2),
+    "brusselator3": (lambda: W.brusselator_batch(2000), 10.0),   # order-3 reaction
 }
 
 
@@ -61,6 +62,10 @@ def test_jit_bitwise_equal_to_generic_lu64(dev, G, name):
 @pytest.mark.parametrize("name", ["net10", "net5_padded6"])
 def test_jit_bitwise_equal_to_generic_lu32_refined(dev, G, name):
     check_equal(G, dev, name, G.LS_LU32REF)
+
+
+def test_jit_bitwise_equal_to_generic_gauss_jordan(dev, G):
+    check_equal(G, dev, "brusselator3", G.LS_GJ)
 
 
 def test_jit_graph_replay_and_library_cache(dev, G, tmp_path):

@@ -45,6 +45,27 @@ def robertson_topology():
 ROBERTSON_RATES = np.array([0.04, 3.0e7, 1.0e4])
 
 
+# The reaction term of the paper's demonstration problem (a brusselator
+# variant, Section 7): with u, v, w the three concentrations,
+#   u' = A - (w + 1) u + v u^2,  v' = w u - v u^2,  w' = (B - w)/eps - w u,
+# A = 1, B = 3.5, eps = 5e-6, written as mass-action reactions over
+# (u, v, w): 0 -> u (rate A), u -> 0 (1), u + w -> v (1), 2u + v -> 3u (1),
+# 0 -> w (B/eps), w -> 0 (1/eps).
+BRUSSELATOR_A, BRUSSELATOR_B, BRUSSELATOR_EPS = 1.0, 3.5, 5e-6
+
+
+def brusselator_topology():
+    nu = np.array([[0, 0, 0], [1, 0, 0], [1, 0, 1], [2, 1, 0], [0, 0, 0], [0, 0, 1]],
+                  dtype=np.int32)
+    mu = np.array([[1, 0, 0], [0, 0, 0], [0, 1, 0], [3, 0, 0], [0, 0, 1], [0, 0, 0]],
+                  dtype=np.int32)
+    return nu, mu
+
+
+def brusselator_rates(A=BRUSSELATOR_A, B=BRUSSELATOR_B, eps=BRUSSELATOR_EPS):
+    return np.array([A, 1.0, 1.0, 1.0, B / eps, 1.0 / eps])
+
+
 def random_network(n: int, R: int, rng: np.random.Generator):
     """Random count-conserving mass-action network.
 
@@ -194,6 +215,26 @@ def random_network_batch(ncells: int, n: int = 10, seed: int = BASE_SEED + 3,
                    rates=rates.copy(), y0=y0.copy(), rtol=1e-6, atol=1e-10,
                    t0=0.0, t_end=t_end, qmax=qmax, nonneg=True,
                    label=f"net{ncells}x{n}")
+
+
+def brusselator_batch(ncells: int, length: float = 10.0, t_end: float = 10.0,
+                      rtol: float = 1e-6, atol: float = 1e-10) -> Problem:
+    """The demonstration problem's reaction term at `ncells` points of the
+    domain [0, length] (cell centres), each cell an independent 3-species
+    system: the initial profile u = A + p, v = B/A + p, w = 3 + p with
+    p = 0.1 exp(-(x - length/2)^2 / (2 (length/4)^2)); rates as in
+    brusselator_rates for every cell.  (The advection coupling between
+    cells is not part of this workload.)"""
+    A, B = BRUSSELATOR_A, BRUSSELATOR_B
+    x = (np.arange(ncells) + 0.5) * (length / ncells)
+    mu_, sig = length / 2.0, length / 4.0
+    pert = 0.1 * np.exp(-((x - mu_) ** 2) / (2.0 * sig * sig))
+    y0 = np.stack([A + pert, B / A + pert, 3.0 + pert], axis=1)
+    nu, mu = brusselator_topology()
+    rates = np.tile(brusselator_rates(), ncells)
+    return Problem(topologies=[(nu, mu)], cell_topo=np.zeros(ncells, np.int32),
+                   rates=rates, y0=y0.ravel().copy(), rtol=rtol, atol=atol, t0=0.0,
+                   t_end=t_end, qmax=5, nonneg=False, label=f"brusselator{ncells}")
 
 
 def uneven_batch(total_unknowns: int, seed: int = BASE_SEED + 4,
