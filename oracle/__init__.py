@@ -70,7 +70,7 @@ class OrcOptions(C.Structure):
                 ("maxcor", C.c_int), ("h0", C.c_double), ("linsol", C.c_int),
                 ("refine_max_it", C.c_int), ("max_steps", C.c_long),
                 ("hmin", C.c_double), ("mlp", C.POINTER(OrcMLP)), ("nonneg", C.c_int),
-                ("fixed_step", C.c_int)]
+                ("fixed_step", C.c_int), ("vc", C.c_int), ("lazy", C.c_int)]
 
 
 class OrcStats(C.Structure):
@@ -78,7 +78,7 @@ class OrcStats(C.Structure):
         "nsteps", "nattempts", "nfevals", "nsetups", "nniters", "nncfails",
         "netfails", "nlinsolves", "refine_sweeps", "refine_fallbacks",
         "lp_cell_solves", "lp_fallback_cells", "lp_step_fallbacks")] + [
-        ("order_hist", C.c_long * 6), ("nprojections", C.c_long)]
+        ("order_hist", C.c_long * 6), ("nprojections", C.c_long), ("nstale_retries", C.c_long)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "order_hist"}
@@ -143,6 +143,10 @@ def _declare(L):
     L.orc_bdf_get_history.argtypes = [C.c_void_p, dp, dp]
     L.orc_bdf_set_history.argtypes = [C.c_void_p, dp, dp]
     L.orc_bdf_coeffs.argtypes = [C.c_int, dp, dp]
+    L.orc_bdf_set_past_steps.argtypes = [C.c_void_p, C.c_int, dp, C.c_double, C.c_double]
+    L.orc_bdf_get_past_steps.restype = C.c_int
+    L.orc_bdf_get_past_steps.argtypes = [C.c_void_p, dp, dp, dp]
+    L.orc_bdf_get_lazy.argtypes = [C.c_void_p, dp, C.POINTER(C.c_long), dp]
 
 
 def _d(a):
@@ -439,7 +443,8 @@ class Bdf:
 
     def __init__(self, prob, rtol=None, atol=None, qmax=None, maxcor=3, h0=0.0,
                  linsol=LS_LU64, refine_max_it=5, max_steps=0, hmin=0.0,
-                 mlp: MLP | None = None, nonneg=None, fixed_step=False):
+                 mlp: MLP | None = None, nonneg=None, fixed_step=False, vc=False,
+                 lazy=False):
         self._keep = []
         topo_n = np.array([nu.shape[1] for nu, _ in prob.topologies], np.int32)
         topo_R = np.array([nu.shape[0] for nu, _ in prob.topologies], np.int32)
@@ -463,8 +468,10 @@ class Bdf:
                                linsol, refine_max_it, max_steps, hmin,
                                C.pointer(mlp.s) if mlp is not None else None,
                                int(prob.get("nonneg", False) if nonneg is None else nonneg),
-                               int(bool(fixed_step)))
+                               int(bool(fixed_step)), int(bool(vc)), int(bool(lazy)))
         self.h = lib().orc_bdf_create(C.byref(self.prob), C.byref(self.opts))
+        if not self.h:
+            raise ValueError("orc_bdf_create refused the options (lazy needs LU64 or GJ)")
         self.N = lib().orc_bdf_N(self.h)
 
     def __del__(self):
@@ -509,6 +516,25 @@ class Bdf:
         dp_ = np.empty(self.N)
         lib().orc_bdf_get_history(self.h, _d(z), _d(dp_))
         return z.reshape(6, self.N), dp_
+
+    def past_steps(self):
+        """(accepted step sizes, most recent first; scale and step of the
+        saved correction) of the variable-coefficient form."""
+        tau = np.zeros(6)
+        c, h = C.c_double(), C.c_double()
+        k = lib().orc_bdf_get_past_steps(self.h, _d(tau), C.byref(c), C.byref(h))
+        return tau[:k].copy(), c.value, h.value
+
+    def set_past_steps(self, tau, dprev_c=1.0, dprev_h=1.0):
+        tau = _c64(tau)
+        lib().orc_bdf_set_past_steps(self.h, len(tau), _d(tau) if len(tau) else None,
+                                     dprev_c, dprev_h)
+
+    def lazy_state(self):
+        g, c = C.c_double(), C.c_double()
+        n = C.c_long()
+        lib().orc_bdf_get_lazy(self.h, C.byref(g), C.byref(n), C.byref(c))
+        return {"gamma_s": g.value, "nst_s": n.value, "crate": c.value}
 
     def set_history(self, z, dprev):
         z = _c64(z).reshape(-1)

@@ -533,6 +533,9 @@ void orc_adam_step(long np, float* p, const double* g, double* m1, double* m2,
 #define BIAS_QP1 1.4
 #define ADDON 1e-6
 #define LP_CELL_RATIO 0.9
+#define MSBP 20       /* lazy setup: accepted steps between fresh Newton matrices */
+#define DGMAX 0.3     /* lazy setup: largest |gamma / gamma_setup - 1| kept */
+#define NTAU (QMAX_ALL + 1)
 
 struct orc_bdf {
   orc_problem p;
@@ -552,6 +555,16 @@ struct orc_bdf {
   int q, qwait, qu, initialized;
   double err_qm1, err_qp1, eta_prop;
   int q_prop;
+  /* variable coefficients: accepted step sizes, most recent first, and the
+   * scale c of the previous correction (D = c acor, see vc_order_terms) */
+  double tau[NTAU];
+  int ntau;
+  double dprev_c, dprev_h;
+  /* lazy Newton matrix: stored factors valid, forced refresh, gamma and
+   * step count of the last setup, convergence-rate estimate carried over */
+  int m_valid, force_setup;
+  long nst_s;
+  double gamma_s, crate_keep;
   orc_stats st;
 };
 
@@ -582,7 +595,58 @@ void orc_bdf_coeffs(int q, double* l, double* tq) {
   if (tq) *tq = 1.0 / ((double)(q + 1) * H * harmonic(q + 1));
 }
 
+/* ---- variable-coefficient BDF (option vc) --------------------------------
+ * Past accepted points t_{n-i} of an attempt of size h that reaches t_n sit
+ * at s = -xi_i in units of h: xi_1 = 1 and xi_{i+1} = xi_i + tau_{i-1} / h
+ * (tau_0 the last accepted step); points older than the known history are
+ * taken one h apart, which is the start of an integration or a restart.
+ * xi[1..k] are filled (xi[0] = 0). */
+static void vc_xi(const orc_bdf* b, double h, int k, double* xi) {
+  xi[0] = 0.0;
+  xi[1] = 1.0;
+  for (int i = 2; i <= k; ++i)
+    xi[i] = xi[i - 1] + (i - 2 < b->ntau ? b->tau[i - 2] / h : 1.0);
+}
+
+/* c[j] = [s^j] prod_{i=1..k} (1 + s/xi_i) (degree k). */
+static void poly_unit(const double* xi, int k, double* c) {
+  for (int j = 0; j <= QMAX_ALL + 2; ++j) c[j] = 0.0;
+  c[0] = 1.0;
+  for (int i = 1; i <= k; ++i)
+    for (int j = i; j >= 1; --j) c[j] = c[j] + c[j - 1] / xi[i];
+}
+
+/* c[j] = [s^j] s prod_{i=1..k} (s + xi_i) (degree k + 1, c[0] = 0). */
+static void poly_through(const double* xi, int k, double* c) {
+  for (int j = 0; j <= QMAX_ALL + 2; ++j) c[j] = 0.0;
+  c[1] = 1.0;
+  for (int i = 1; i <= k; ++i)
+    for (int j = i + 1; j >= 1; --j) c[j] = c[j - 1] + xi[i] * c[j];
+}
+
+/* Variable-coefficient corrector of order q (reading: the step is the BDF
+ * formula on the actual past grid).  The correction polynomial
+ * prod_{i=1..q} (1 + s/xi_i) vanishes at the q previous accepted points,
+ * so the corrected history keeps interpolating the last q + 1 accepted
+ * values; normalised to slope 1 at s = 0: l_j = [s^j] prod / S_q with
+ * S_k = sum_{i<=k} 1/xi_i.  With the history the interpolant of exact
+ * values, the step's local error is the correction times
+ * l_0 (1/xi_{q+1}) / S_{q+1} (the error polynomial of a degree-(q+1)
+ * solution is a multiple of prod_{i=1..q+1} (s + xi_i)), so
+ * tq = (1/xi_{q+1}) / (S_q S_{q+1}).  Constant steps (xi_i = i) give the
+ * fixed coefficients. */
+static void vc_coeffs(int q, const double* xi, double* l, double* tq) {
+  double c[QMAX_ALL + 3];
+  poly_unit(xi, q, c);
+  double Sq = 0.0;
+  for (int i = 1; i <= q; ++i) Sq = Sq + 1.0 / xi[i];
+  for (int j = 0; j <= q; ++j) l[j] = c[j] / Sq;
+  const double Sq1 = Sq + 1.0 / xi[q + 1];
+  *tq = (1.0 / xi[q + 1]) / (Sq * Sq1);
+}
+
 orc_bdf* orc_bdf_create(const orc_problem* p, const orc_options* o) {
+  if (o->lazy && o->linsol != ORC_LS_LU64 && o->linsol != ORC_LS_GJ) return NULL;
   orc_bdf* b = (orc_bdf*)calloc(1, sizeof(orc_bdf));
   b->p = *p;
   b->o = *o;
@@ -702,6 +766,8 @@ static void initialize(orc_bdf* b, double t_end) {
   b->h = h;
   b->q = 1;
   b->qwait = 2;
+  b->ntau = 0;
+  b->m_valid = 0;
   b->initialized = 1;
 }
 
@@ -768,13 +834,19 @@ static int finite_cell(const orc_bdf* b, long c, const double* x) {
 }
 
 /* Newton iteration on all cells at once (grouped; one global norm).
+ * setup: fresh J, M = I - gamma J and its factors (else the stored factors
+ * of an earlier gamma are reused and every correction is scaled by dscale);
+ * *crate: the convergence-rate estimate, carried in and out.
  * Returns 0 converged, 1 failed (caller retries the step). */
-static int newton(orc_bdf* b, double gamma, double l0, int force_lu) {
+static int newton(orc_bdf* b, double gamma, double l0, int force_lu, int setup, double dscale,
+                  double* crate_io) {
   long N = b->N, nc = b->p.ncells;
   int ls = b->o.linsol;
   int setup_fail = 0;
-  b->st.nsetups++;
-  if (ls == ORC_LS_LEARNED && !force_lu) {
+  if (setup) b->st.nsetups++;
+  if (!setup) {
+    /* lazy reuse: cellmode (0 LU, 5 inverse) and the factors stay */
+  } else if (ls == ORC_LS_LEARNED && !force_lu) {
     double xin[64];
     double lg = log(gamma);
     for (long c = 0; c < nc; ++c) {
@@ -814,7 +886,8 @@ static int newton(orc_bdf* b, double gamma, double l0, int force_lu) {
   }
   if (setup_fail) return 1;
   memcpy(b->y, b->zp[0], sizeof(double) * (size_t)N);
-  double crate = 1.0, dold = 0.0;
+  double crate = *crate_io, dold = 0.0;
+  int rc = 1;
   for (int m = 0; m < b->o.maxcor; ++m) {
     rhs_all(b, b->y, b->f);
     for (long i = 0; i < N; ++i)
@@ -839,6 +912,8 @@ static int newton(orc_bdf* b, double gamma, double l0, int force_lu) {
       }
     }
     b->st.nlinsolves++;
+    if (dscale != 1.0)
+      for (long i = 0; i < N; ++i) b->del[i] = dscale * b->del[i];
     if (ls == ORC_LS_LEARNED && !force_lu) {
       for (long c = 0; c < nc; ++c) {
         double dc = cell_wrms(b, c, b->del);
@@ -850,18 +925,22 @@ static int newton(orc_bdf* b, double gamma, double l0, int force_lu) {
     for (long i = 0; i < N; ++i) b->y[i] = b->y[i] + b->del[i];
     double d = wrms(b, b->del);
     b->st.nniters++;
-    if (!isfinite(d)) return 1;
+    if (!isfinite(d)) break;
     if (m > 0) {
       double ratio = d / dold;
       crate = CRDOWN * crate > ratio ? CRDOWN * crate : ratio;
     }
     double dcon = d * (crate < 1.0 ? crate : 1.0);
-    if (dcon <= NLS_COEF) return 0;
-    if (m + 1 == b->o.maxcor) return 1;
-    if (m >= 1 && d > RDIV * dold) return 1;
+    if (dcon <= NLS_COEF) {
+      rc = 0;
+      break;
+    }
+    if (m + 1 == b->o.maxcor) break;
+    if (m >= 1 && d > RDIV * dold) break;
     dold = d;
   }
-  return 1;
+  *crate_io = crate;
+  return rc;
 }
 
 int orc_bdf_step(orc_bdf* b, double t_end) {
@@ -879,8 +958,13 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
     }
     if (b->h <= 4.0 * 2.220446049250313e-16 * fabs(b->t)) return -5;  /* t + h == t */
     int last = (b->t + b->h >= t_end);
-    double l[QMAX_ALL + 1], tq;
-    orc_bdf_coeffs(q, l, &tq);
+    double l[QMAX_ALL + 1], tq, xi[QMAX_ALL + 3];
+    if (b->o.vc) {
+      vc_xi(b, b->h, q + 1, xi);
+      vc_coeffs(q, xi, l, &tq);
+    } else {
+      orc_bdf_coeffs(q, l, &tq);
+    }
     orc_nv_ewt(N, b->o.rtol, b->o.atol, b->z[0], b->w);
     for (int j = 0; j <= q; ++j) memcpy(b->zp[j], b->z[j], sizeof(double) * (size_t)N);
     for (int k = 1; k <= q; ++k)
@@ -888,12 +972,42 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
         for (long i = 0; i < N; ++i) b->zp[j - 1][i] = b->zp[j - 1][i] + b->zp[j][i];
     double gamma = b->h * l[0];
     b->st.nattempts++;
-    int nst = newton(b, gamma, l[0], force_lu);
+    /* lazy Newton matrix (reading): a fresh J and M at the first attempt,
+     * after any Newton failure, every MSBP accepted steps and when gamma has
+     * moved more than DGMAX from the gamma of the stored factors; otherwise
+     * the stored factors of gamma_s are reused and each correction is
+     * scaled by 2 / (1 + gamma / gamma_s), and the convergence-rate estimate
+     * carries over from the previous attempt (it restarts at 1 after a
+     * setup) */
+    int setup = 1;
+    double dscale = 1.0, crate = 1.0;
+    if (b->o.lazy) {
+      setup = !b->m_valid || b->force_setup || b->st.nsteps - b->nst_s >= MSBP ||
+              fabs(gamma / b->gamma_s - 1.0) > DGMAX;
+      if (setup) {
+        b->gamma_s = gamma;
+        b->nst_s = b->st.nsteps;
+        b->m_valid = 1;
+        b->force_setup = 0;
+      } else {
+        dscale = 2.0 / (1.0 + gamma / b->gamma_s);
+        crate = b->crate_keep;
+      }
+    }
+    int nst = newton(b, gamma, l[0], force_lu, setup, dscale, &crate);
+    b->crate_keep = crate;
     if (nst) {
       if (b->o.linsol == ORC_LS_LEARNED && !force_lu) {
         force_lu = 1;
         b->st.lp_step_fallbacks++;
         continue;
+      }
+      if (b->o.lazy) {
+        b->force_setup = 1;
+        if (!setup) {   /* stale factors: redo the attempt with fresh ones */
+          b->st.nstale_retries++;
+          continue;
+        }
       }
       force_lu = 0;
       ncf++;
@@ -932,6 +1046,7 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
         if (hn < b->o.hmin) return -5;
         b->h = hn;
         b->q = 1;
+        b->ntau = 0;   /* the new history knows no past points */
         rhs_all(b, b->z[0], b->f);
         for (long i = 0; i < N; ++i) b->z[1][i] = b->h * b->f[i];
         b->qwait = 2;
@@ -953,6 +1068,19 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
     b->t = last ? t_end : b->t + b->h;
     b->hu = b->h;
     b->qu = q;
+    for (int k = NTAU - 1; k > 0; --k) b->tau[k] = b->tau[k - 1];
+    b->tau[0] = b->h;
+    if (b->ntau < NTAU) b->ntau++;
+    /* scale of this correction for the next order-(q+1) estimate:
+     * acor c_n = h^{q+1} y^{(q+1)} / (q+1)! for a degree-(q+1) solution */
+    double Sq1 = 0.0, pxi = 1.0;
+    if (b->o.vc) {
+      for (int i = 1; i <= q + 1; ++i) {
+        Sq1 = Sq1 + 1.0 / xi[i];
+        pxi = pxi * xi[i];
+      }
+    }
+    const double cn = b->o.vc ? 1.0 / (pxi * Sq1) : 1.0;
     b->st.nsteps++;
     b->st.order_hist[q]++;
     b->qwait--;
@@ -964,6 +1092,8 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
     b->err_qp1 = -1.0;
     if (b->o.fixed_step) {
       memcpy(b->dprev, b->acor, sizeof(double) * (size_t)N);
+      b->dprev_c = cn;
+      b->dprev_h = b->h;
       b->eta_prop = 1.0;
       b->q_prop = q;
       return 0;
@@ -972,13 +1102,35 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
       b->qwait = 2;
       double etaqm1 = 0.0, etaqp1 = 0.0;
       if (q > 1) {
-        double e = wrms(b, b->z[q]) * factorial(q - 1) / harmonic(q - 1);
+        /* error of an order-(q-1) step: z[q] times prod_{i<q} xi_i / S_{q-1}
+         * (constant steps: (q-1)! / H_{q-1}) */
+        double pr = factorial(q - 1), S = harmonic(q - 1);
+        if (b->o.vc) {
+          pr = 1.0;
+          S = 0.0;
+          for (int i = 1; i <= q - 1; ++i) {
+            pr = pr * xi[i];
+            S = S + 1.0 / xi[i];
+          }
+        }
+        double e = wrms(b, b->z[q]) * pr / S;
         b->err_qm1 = e;
         etaqm1 = 1.0 / (pow(BIAS_QM1 * e, 1.0 / (double)q) + ADDON);
       }
       if (q < b->o.qmax) {
-        for (long i = 0; i < N; ++i) b->tmp[i] = b->acor[i] - b->dprev[i];
-        double e = wrms(b, b->tmp) / ((double)(q + 2) * harmonic(q + 1) * harmonic(q + 1));
+        /* error of an order-(q+1) step from the change of D = c acor
+         * between the previous step and this one, the previous brought to
+         * this h: (D_n - (h/h_prev)^{q+1} D_{n-1}) / (q+2) estimates
+         * h^{q+2} y^{(q+2)} / (q+2)!; the order-(q+1) error is that times
+         * prod_{i<=q+1} xi_i / S_{q+1}, i.e. |acor - kap acor_prev| /
+         * ((q+2) S_{q+1}^2) (constant steps: kap = 1, S = H_{q+1}) */
+        double kap = 1.0, S1 = harmonic(q + 1);
+        if (b->o.vc) {
+          kap = pow(b->h / b->dprev_h, (double)(q + 1)) * b->dprev_c / cn;
+          S1 = Sq1;
+        }
+        for (long i = 0; i < N; ++i) b->tmp[i] = b->acor[i] - kap * b->dprev[i];
+        double e = wrms(b, b->tmp) / ((double)(q + 2) * S1 * S1);
         b->err_qp1 = e;
         etaqp1 = 1.0 / (pow(BIAS_QP1 * e, 1.0 / (double)(q + 2)) + ADDON);
       }
@@ -994,9 +1146,35 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
     b->q_prop = qnew;
     if (eta >= THRESH) {
       if (eta > ETA_MAX) eta = ETA_MAX;
-      if (qnew == q + 1) {
+      if (qnew == q + 1 && b->o.vc) {
+        /* raise keeping the interpolation of the past values: add
+         * C s prod_{i<=q} (s + xi_i), which leaves the last q + 1 points,
+         * with C such that the history also passes through y_{n-q-1}; the
+         * previous history passed through it and differs from the new one
+         * by acor Lambda(s), so C = acor Lambda(-xi_{q+1}) /
+         * (xi_{q+1} prod_{i<=q} (xi_i - xi_{q+1})) */
+        double lam = 0.0, pw = 1.0, den = xi[q + 1], e[QMAX_ALL + 3];
+        for (int j = 0; j <= q; ++j) {
+          lam = lam + l[j] * pw;
+          pw = pw * -xi[q + 1];
+        }
+        for (int i = 1; i <= q; ++i) den = den * (xi[i] - xi[q + 1]);
+        const double cr = lam / den;
+        poly_through(xi, q, e);
+        for (int j = 1; j <= q; ++j)
+          for (long i = 0; i < N; ++i) b->z[j][i] = b->z[j][i] + (cr * e[j]) * b->acor[i];
+        for (long i = 0; i < N; ++i) b->z[q + 1][i] = cr * b->acor[i];
+      } else if (qnew == q + 1) {
         double c = 1.0 / (factorial(q + 1) * harmonic(q + 1));
         for (long i = 0; i < N; ++i) b->z[q + 1][i] = c * b->acor[i];
+      } else if (qnew == q - 1 && b->o.vc) {
+        /* lower the order keeping the interpolation: subtract
+         * z[q] s prod_{i<q} (s + xi_i), which removes the s^q term and leaves
+         * the last q points */
+        double d[QMAX_ALL + 3];
+        poly_through(xi, q - 1, d);
+        for (int j = 1; j <= q - 1; ++j)
+          for (long i = 0; i < N; ++i) b->z[j][i] = b->z[j][i] - d[j] * b->z[q][i];
       }
       b->q = qnew;
       rescale(b, eta);
@@ -1004,6 +1182,8 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
       b->qwait = b->q + 1;
     }
     memcpy(b->dprev, b->acor, sizeof(double) * (size_t)N);
+    b->dprev_c = cn;
+    b->dprev_h = b->hu;
     return 0;
   }
 }
@@ -1053,4 +1233,26 @@ void orc_bdf_set_history(orc_bdf* b, const double* z6, const double* dprev) {
   for (int j = 0; j <= QMAX_ALL; ++j)
     memcpy(b->z[j], z6 + (long)j * b->N, sizeof(double) * (size_t)b->N);
   memcpy(b->dprev, dprev, sizeof(double) * (size_t)b->N);
+  b->m_valid = 0;
+}
+
+void orc_bdf_set_past_steps(orc_bdf* b, int k, const double* tau, double dprev_c,
+                            double dprev_h) {
+  b->ntau = k < 0 ? 0 : (k > NTAU ? NTAU : k);
+  for (int i = 0; i < b->ntau; ++i) b->tau[i] = tau[i];
+  b->dprev_c = dprev_c;
+  b->dprev_h = dprev_h;
+}
+
+int orc_bdf_get_past_steps(const orc_bdf* b, double* tau, double* dprev_c, double* dprev_h) {
+  for (int i = 0; i < b->ntau; ++i) tau[i] = b->tau[i];
+  *dprev_c = b->dprev_c;
+  *dprev_h = b->dprev_h;
+  return b->ntau;
+}
+
+void orc_bdf_get_lazy(const orc_bdf* b, double* gamma_s, long* nst_s, double* crate) {
+  *gamma_s = b->gamma_s;
+  *nst_s = b->nst_s;
+  *crate = b->crate_keep;
 }

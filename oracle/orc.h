@@ -125,6 +125,9 @@ typedef struct {
   int nonneg;        /* 1: corrected solutions projected onto y >= 0 */
   int fixed_step;    /* 1: accepted steps keep h and q (no step-size or order
                         selection); used only by the convergence-order pins */
+  int vc;            /* 1: variable-coefficient BDF (coefficients from the past
+                        step sizes; order changes keep the interpolation) */
+  int lazy;          /* 1: Newton matrix kept over steps (LU64 or GJ only) */
 } orc_options;
 
 typedef struct {
@@ -133,6 +136,7 @@ typedef struct {
   long lp_cell_solves, lp_fallback_cells, lp_step_fallbacks;
   long order_hist[6];
   long nprojections;
+  long nstale_retries;   /* attempts redone with fresh factors (lazy) */
 } orc_stats;
 
 typedef struct orc_bdf orc_bdf;
@@ -169,6 +173,14 @@ void orc_bdf_set_history(orc_bdf* b, const double* z6, const double* dprev);
 /* the BDF coefficient vector for order q (q+1 values) and the error
  * constant 1/((q+1) H_q H_{q+1}); exposed for the exactness pins */
 void orc_bdf_coeffs(int q, double* l, double* tq);
+/* variable coefficients: past accepted step sizes (most recent first, at
+ * most 6) and the scale and step of the saved correction; for the pins */
+void orc_bdf_set_past_steps(orc_bdf* b, int k, const double* tau, double dprev_c,
+                            double dprev_h);
+int orc_bdf_get_past_steps(const orc_bdf* b, double* tau, double* dprev_c, double* dprev_h);
+/* lazy Newton matrix: gamma and step count of the last setup, carried
+ * convergence-rate estimate */
+void orc_bdf_get_lazy(const orc_bdf* b, double* gamma_s, long* nst_s, double* crate);
 
 #ifdef __cplusplus
 }
