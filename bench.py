@@ -354,13 +354,14 @@ def per_cell_leg(G, W, torch, prob, dev, max_steps=2000000):
             "cells_over_10k_steps": int((st > 10000).sum())}
 
 
-def long_run_leg(G, W, torch, prob, dev, jit=True, max_steps=20000):
+def long_run_leg(G, W, torch, prob, dev, jit=True, max_steps=20000, **kw):
     """The benchmark workload integrated from t = 0 for max_steps accepted
     steps (or to t_end) on a fresh handle, creation and the starting step
     not timed: the step mix of a long run (orders, retries, Newton
-    iterations) beside the short timed window of the headline."""
+    iterations) beside the short timed window of the headline.  kw: extra
+    handle options (variable coefficients, lazy Newton matrix)."""
     b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_STREAM, attempts_per_sync=16,
-                           linsol=G.LS_LU64, maxcor=MAXCOR, jit=jit)
+                           linsol=G.LS_LU64, maxcor=MAXCOR, jit=jit, **kw)
     b.advance(prob.t_end, 1)
     s0 = b.stats()
     dt, taken, t = time_advance(b, prob.t_end, max_steps, torch)
@@ -371,7 +372,37 @@ def long_run_leg(G, W, torch, prob, dev, jit=True, max_steps=20000):
             "unit": "cell-steps/s", "ms_per_step": round(1e3 * dt / max(taken, 1), 4),
             "attempts_per_step": round((s1["nattempts"] - s0["nattempts"]) / max(taken, 1), 4),
             "newton_iters_per_step": round((s1["nniters"] - s0["nniters"]) / max(taken, 1), 4),
+            "setups_per_attempt": round((s1["nsetups"] - s0["nsetups"]) /
+                                        max(s1["nattempts"] - s0["nattempts"], 1), 4),
             "order_hist": [a - b_ for a, b_ in zip(s1["order_hist"], s0["order_hist"])]}
+
+
+def vc_lazy_leg(G, W, torch, prob, dev, warmup, steps, long_steps, jit=True):
+    """The benchmark workload with variable coefficients, the lazy Newton
+    matrix, and both: the headline's window (warmup, then `steps` timed
+    steps) and, for both together, the long run from t = 0."""
+    out = {}
+    for name, kw in (("vc", dict(vc=True)), ("lazy", dict(lazy=True)),
+                     ("vc_lazy", dict(vc=True, lazy=True))):
+        b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_STREAM, attempts_per_sync=16,
+                               linsol=G.LS_LU64, maxcor=MAXCOR, jit=jit, **kw)
+        b.advance(prob.t_end, warmup)
+        s0 = b.stats()
+        dt, taken, _ = time_advance(b, prob.t_end, steps, torch)
+        s1 = b.stats()
+        b.close()
+        att = s1["nattempts"] - s0["nattempts"]
+        out[name] = {"value": round(prob.ncells * taken / dt, 1), "unit": "cell-steps/s",
+                     "ms_per_step": round(1e3 * dt / max(taken, 1), 4),
+                     "attempts_per_step": round(att / max(taken, 1), 4),
+                     "newton_iters_per_step": round((s1["nniters"] - s0["nniters"]) /
+                                                    max(taken, 1), 4),
+                     "setups_per_attempt": round((s1["nsetups"] - s0["nsetups"]) / max(att, 1), 4),
+                     "stale_retries": s1["nstale_retries"] - s0["nstale_retries"]}
+    if long_steps > 0:
+        out["vc_lazy_long_run"] = long_run_leg(G, W, torch, prob, dev, jit=jit,
+                                               max_steps=long_steps, vc=True, lazy=True)
+    return out
 
 
 def main():
@@ -386,6 +417,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-robertson", action="store_true")
+    ap.add_argument("--no-vc-lazy", action="store_true",
+                    help="skip the variable-coefficient / lazy Newton matrix legs")
     ap.add_argument("--no-brusselator", action="store_true",
                     help="skip the demonstration reaction's whole runs")
     ap.add_argument("--no-per-cell", action="store_true",
@@ -532,6 +565,12 @@ def main():
         long_run = long_run_leg(G, W, torch, prob, dev, jit=not args.no_jit,
                                 max_steps=args.long_steps)
 
+    vc_lazy = None
+    if not args.no_vc_lazy:
+        log("variable coefficients and lazy Newton matrix")
+        vc_lazy = vc_lazy_leg(G, W, torch, prob, dev, args.warmup, args.steps, args.long_steps,
+                              jit=not args.no_jit)
+
     per_cell = None
     if not args.no_per_cell:
         log("per-cell adaptive stepping, whole run to t = 10")
@@ -585,6 +624,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "long_run": long_run,
+        "variable_coefficients_lazy": vc_lazy,
         "per_cell_whole_run": per_cell,
         "robertson_1000_bdf2": robertson,
         "brusselator_2p20": brusselator,

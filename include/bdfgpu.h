@@ -279,10 +279,31 @@ typedef struct {
                              that one cell.  bdf_integrate advances every cell
                              to t_end; bdf_get_stats sums the cells' counters
                              (t: the earliest cell); bdf_get_cell_stats gives
-                             them per cell.  Cells of <= 12 species, FP64 LU,
-                             per-class launches; bdf_step, bdf_advance and the
-                             state calls are refused.  max_steps bounds the
-                             attempts per cell. */
+                             them per cell.  Cells of <= 12 species, FP64 LU
+                             or Gauss-Jordan, per-class launches; bdf_step,
+                             bdf_advance and the state calls are refused.
+                             max_steps bounds the attempts per cell. */
+  int vc;                 /* 1: variable-coefficient BDF (CVODE's BDF takes its
+                             coefficients from the step sizes, Section 1): the
+                             corrector is the BDF formula on the actual past
+                             grid, the error and order-change constants follow
+                             from the history interpolating the last q + 1
+                             accepted values, and order changes keep that
+                             interpolation.  Constant steps give the fixed
+                             coefficients.  Needs the deferred history update
+                             (see no_defer) and not per_cell. */
+  int lazy;               /* 1: the Newton matrix is kept over steps: its factors
+                             (or inverse) are stored per cell (n^2 + n values)
+                             and refreshed at the first attempt, after a Newton
+                             failure, every 20 accepted steps and when gamma
+                             has moved more than 30% from the stored factors'
+                             gamma_s; a reuse scales each correction by
+                             2 / (1 + gamma / gamma_s) and carries the
+                             convergence-rate estimate over, and a Newton
+                             failure on reused factors redoes the attempt with
+                             fresh ones at the same step size.  Needs the
+                             deferred history update, FP64 LU or Gauss-Jordan,
+                             and not per_cell. */
 } bdf_options;
 
 typedef struct {
@@ -295,6 +316,7 @@ typedef struct {
   long order_hist[6];
   double t, h, hu, err_last;
   int q, qu, qwait, status;
+  long nstale_retries;    /* lazy: attempts redone with fresh factors */
 } bdf_stats;
 
 typedef struct bdf_handle bdf_handle;

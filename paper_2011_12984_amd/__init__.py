@@ -290,7 +290,7 @@ class Bdf:
                  qmax=5, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64, refine_max_it=5,
                  max_steps=0, mode=MODE_STREAM, attempts_per_sync=8, nonneg=False,
                  precond=None, launch=LAUNCH_PER_CLASS, map_small=0, jit=False, defer=True,
-                 workspace=None, per_cell=False):
+                 workspace=None, per_cell=False, vc=False, lazy=False):
         torch = _torch()
         _dev(rates, torch.float64)
         _dev(y0, torch.float64)
@@ -309,7 +309,8 @@ class Bdf:
         opts = BdfOptions(rtol, atol, qmax, maxcor, h0, hmin, linsol, refine_max_it, max_steps,
                           mode, attempts_per_sync, launch,
                           precond.h if precond is not None else None, int(bool(nonneg)),
-                          int(map_small), int(bool(jit)), int(not defer), int(bool(per_cell)))
+                          int(map_small), int(bool(jit)), int(not defer), int(bool(per_cell)),
+                          int(bool(vc)), int(bool(lazy)))
         h = vp()
         if workspace is None:
             check("bdf_create", lib().bdf_create(C.byref(prob), C.byref(opts), _stream(),
@@ -337,7 +338,7 @@ class Bdf:
     def _sizing(prob, rtol=None, atol=None, qmax=None, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64,
                 refine_max_it=5, max_steps=0, mode=MODE_STREAM, attempts_per_sync=8,
                 nonneg=None, launch=LAUNCH_PER_CLASS, map_small=0, jit=False, defer=True,
-                precond=None, per_cell=False):
+                precond=None, per_cell=False, vc=False, lazy=False):
         topologies = prob["topologies"]
         topo_n = np.array([nu.shape[1] for nu, _ in topologies], np.int32)
         topo_R = np.array([nu.shape[0] for nu, _ in topologies], np.int32)
@@ -353,7 +354,8 @@ class Bdf:
                           refine_max_it, max_steps, mode, attempts_per_sync, launch,
                           precond.h if precond is not None else None,
                           int(bool(prob.get("nonneg", False) if nonneg is None else nonneg)),
-                          int(map_small), int(bool(jit)), int(not defer), int(bool(per_cell)))
+                          int(map_small), int(bool(jit)), int(not defer), int(bool(per_cell)),
+                          int(bool(vc)), int(bool(lazy)))
         return int(lib().bdf_workspace_bytes(C.byref(pr), C.byref(opts)))
 
     @classmethod

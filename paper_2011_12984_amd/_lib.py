@@ -32,7 +32,8 @@ class BdfOptions(C.Structure):
                 ("linsol", C.c_int), ("refine_max_it", C.c_int), ("max_steps", C.c_long),
                 ("mode", C.c_int), ("attempts_per_sync", C.c_int), ("launch", C.c_int),
                 ("precond", vp), ("nonneg", C.c_int), ("map_small", C.c_int),
-                ("jit", C.c_int), ("no_defer", C.c_int), ("per_cell", C.c_int)]
+                ("jit", C.c_int), ("no_defer", C.c_int), ("per_cell", C.c_int),
+                ("vc", C.c_int), ("lazy", C.c_int)]
 
 
 class BdfStats(C.Structure):
@@ -42,7 +43,7 @@ class BdfStats(C.Structure):
         "lp_cell_solves", "lp_fallback_cells", "lp_step_fallbacks")] + [
         ("order_hist", C.c_long * 6), ("t", C.c_double), ("h", C.c_double),
         ("hu", C.c_double), ("err_last", C.c_double), ("q", C.c_int), ("qu", C.c_int),
-        ("qwait", C.c_int), ("status", C.c_int)]
+        ("qwait", C.c_int), ("status", C.c_int), ("nstale_retries", C.c_long)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "order_hist"}

@@ -259,6 +259,8 @@ static BdfDev make_dev(bdf_handle* h, const ClassHost& c) {
   D.atol = h->o.atol;
   D.nonneg = h->o.nonneg ? 1 : 0;
   D.defer = h->defer ? 1 : 0;
+  D.lazy = h->o.lazy ? 1 : 0;
+  D.vc = h->o.vc ? 1 : 0;
   D.k = c.dev;
   D.k.blk0 = c.blk0;
   return D;
@@ -543,6 +545,11 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   if (o->linsol == BDFGPU_LS_GJ && (o->launch != BDFGPU_LAUNCH_PER_CLASS || o->map_small))
     return arg_error("bdf_create: the Gauss-Jordan solve needs per-class launches and one lane "
                      "per cell");
+  if ((o->vc || o->lazy) && (o->per_cell || o->no_defer))
+    return arg_error("bdf_create: variable coefficients and the lazy Newton matrix need the "
+                     "deferred history update and grouped stepping");
+  if (o->lazy && o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_GJ)
+    return arg_error("bdf_create: the lazy Newton matrix needs FP64 LU or the Gauss-Jordan solve");
   *out = nullptr;
   bdf_handle* h = new bdf_handle();
   h->s = as_stream(stream);
@@ -624,7 +631,9 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     ch.np = ch.map == MAP_TPC ? tpc_padded(n) : spc_seg(n);
     // network-specialised Newton kernel
     if (o->jit && ch.map == MAP_TPC && !dry) {
-      st = jit_newton(net_newton_source(nu, mu, n, R, ch.np, o->linsol), &ch.jit);
+      st = jit_newton(net_newton_source(nu, mu, n, R, ch.np, o->linsol,
+                                        (o->lazy ? 1 : 0) | (o->vc ? 2 : 0)),
+                      &ch.jit);
       if (st) {
         bdf_destroy(h);
         return st;
@@ -746,6 +755,15 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
         bdf_destroy(h);
         return st;
       }
+    if (o->lazy && tiled) {   // stored factors of M (or its inverse) and pivots
+      const size_t np2 = (size_t)ch.np * (size_t)ch.np;
+      if ((st = dalloc(h, (void**)&K.lu, sizeof(double) * std::max<long>(1, cap_cells) * np2)) ||
+          (st = dalloc(h, (void**)&K.lpiv,
+                       sizeof(int) * std::max<long>(1, cap_cells) * (size_t)ch.np))) {
+        bdf_destroy(h);
+        return st;
+      }
+    }
     if (o->linsol == BDFGPU_LS_LEARNED) {
       const long nc = std::max<long>(1, ch.ncells);
       if ((st = dalloc(h, (void**)&K.X, sizeof(float) * nc * n * n)) ||
@@ -827,6 +845,12 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
              !o->per_cell;
   for (const ClassHost& c : h->cls)
     if (c.map != MAP_TPC) h->defer = false;
+  if ((o->vc || o->lazy) && !h->defer) {
+    bdf_destroy(h);
+    return arg_error("bdf_create: variable coefficients and the lazy Newton matrix need the "
+                     "deferred history update: one lane per cell for every class (<= 12 "
+                     "species), per-class launches, no learned preconditioner");
+  }
   const long bmax = std::max(blk, mblk);
   const long ngroups = std::max<long>(1, (bmax + kRedGroup - 1) / kRedGroup);
   if ((st = dalloc(h, (void**)&h->partials, sizeof(double) * kRedMax * std::max<long>(1, bmax))) ||
@@ -862,6 +886,11 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   C.phase = h->N > 0 ? PH_INIT1 : PH_DONE;
   C.learned = o->linsol == BDFGPU_LS_LEARNED ? 1 : 0;
   C.fuse = h->defer ? 1 : 0;
+  C.vc = o->vc ? 1 : 0;
+  C.lazy = o->lazy ? 1 : 0;
+  C.kap = 1.0;
+  C.dscale = 1.0;
+  C.setup = 1;
   C.step_limit = LONG_MAX;
   BDF_HIP_TRY(hipMemcpyAsync(h->dC, &C, sizeof(Ctrl), hipMemcpyHostToDevice, h->s));
   BDF_HIP_TRY(hipStreamSynchronize(h->s));
@@ -1172,6 +1201,7 @@ int bdf_get_stats(bdf_handle* h, bdf_stats* s) {
   s->qu = C.qu;
   s->qwait = C.qwait;
   s->status = C.status;
+  s->nstale_retries = C.nstale_retries;
   return 0;
 }
 
@@ -1218,6 +1248,8 @@ int bdf_set_state(bdf_handle* h, const double* dvals, const int* ivals, const do
   for (int j = 0; j < kQmaxAll + 2; ++j) C.hs[j] = 1.0;
   C.restart = 0;
   C.upd = 0;   // the given history replaces any pending update
+  C.ntau = 0;      // variable coefficients: no known past points
+  C.m_valid = 0;   // lazy: no stored factors for this state
   C.ncf = 0;
   C.netf = 0;
   C.phase = PH_PAUSE;

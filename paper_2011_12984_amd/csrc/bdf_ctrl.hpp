@@ -19,6 +19,16 @@
 // acor / ((q+1) H_q H_{q+1}).  Rescaling by eta multiplies z[j] by eta^j;
 // here that factor is kept pending in hs[j] and applied by the next kernel
 // that reads the history.
+//
+// Variable coefficients (vc): the corrector is the BDF formula on the actual
+// past grid.  Past accepted points sit at s = -xi_i (units of the attempt's
+// h); the correction polynomial prod_{i<=q} (1 + s/xi_i), normalised to
+// slope 1, vanishes at them, so the history keeps interpolating the last
+// q + 1 accepted values, and the error and order-change constants follow
+// from that (constant steps give the fixed ones).  Lazy Newton matrix
+// (lazy): the factors of M are stored per cell and reused over steps while
+// gamma stays within 30% of theirs, for at most 20 steps, with each
+// correction scaled by 2 / (1 + gamma / gamma_s).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,6 +65,9 @@ constexpr double kBiasQm1 = 1.3;
 constexpr double kBiasQ = 1.2;
 constexpr double kBiasQp1 = 1.4;
 constexpr double kAddon = 1e-6;
+constexpr int kMsbp = 20;          // lazy: accepted steps between fresh Newton matrices
+constexpr double kDgmax = 0.3;     // lazy: largest |gamma / gamma_s - 1| kept
+constexpr int kNtau = kQmaxAll + 1;
 
 struct Ctrl {
   double t, h, tend, hmin, h0user, hnw_h0;
@@ -76,6 +89,20 @@ struct Ctrl {
   double upd_l[kQmaxAll + 2];
   double upd_hs[kQmaxAll + 2];
   double upd_craise;
+  // variable coefficients: accepted step sizes (most recent first), the
+  // attempt's xi_1..xi_{q+1} (xi[0] = 0), scale and step of the saved
+  // correction, and kap, the factor on acor_prev in the order-(q+1) sum;
+  // a lowering of the order applied with the deferred update:
+  // z_new[j] -= upd_d[j] z_new[q] for j = 1..q-1
+  int vc, ntau, upd_dec, lazy, setup, force_setup, m_valid, pad3;
+  double tau[kNtau];
+  double xi[kQmaxAll + 3];
+  double dprev_c, dprev_h, kap;
+  double upd_d[kQmaxAll + 2];
+  // lazy Newton matrix: gamma and step count of the stored factors, the
+  // correction scale of a reuse, the carried convergence-rate estimate
+  double gamma_s, dscale, crate_keep;
+  long nst_s, nstale_retries;
   long step_limit;
   long nsteps, nattempts, nfevals, nsetups, nniters, nncfails, netfails;
   long nlinsolves, refine_sweeps, refine_fallbacks, nprojections;
@@ -97,17 +124,43 @@ __host__ __device__ inline double factorial(int q) {
 }
 
 // l vector of order q and the local-error constant 1/((q+1) H_q H_{q+1}).
+// With variable coefficients: xi_1 = 1, xi_{i+1} = xi_i + tau_{i-1} / h
+// (points older than the known steps one h apart), l_j = [s^j] prod_{i<=q}
+// (1 + s/xi_i) / S_q with S_k = sum_{i<=k} 1/xi_i, local-error constant
+// (1/xi_{q+1}) / (S_q S_{q+1}); kap brings the saved correction to this
+// step's scale: (h / h_prev)^{q+1} c_prev / c with c = 1 / (prod_{i<=q+1}
+// xi_i S_{q+1}).
 __device__ inline void set_coeffs(Ctrl* C) {
   const int q = C->q;
   double c[kQmaxAll + 2];
   for (int j = 0; j < kQmaxAll + 2; ++j) c[j] = 0.0;
   c[0] = 1.0;
+  if (C->vc) {
+    C->xi[0] = 0.0;
+    C->xi[1] = 1.0;
+    for (int i = 2; i <= kQmaxAll + 2; ++i)
+      C->xi[i] = C->xi[i - 1] + (i - 2 < C->ntau ? C->tau[i - 2] / C->h : 1.0);
+    for (int i = 1; i <= q; ++i)
+      for (int j = i; j >= 1; --j) c[j] = c[j] + c[j - 1] / C->xi[i];
+    double Sq = 0.0;
+    for (int i = 1; i <= q; ++i) Sq = Sq + 1.0 / C->xi[i];
+    for (int j = 0; j < kQmaxAll + 2; ++j) C->l[j] = j <= q ? c[j] / Sq : 0.0;
+    const double Sq1 = Sq + 1.0 / C->xi[q + 1];
+    C->tq = (1.0 / C->xi[q + 1]) / (Sq * Sq1);
+    double pxi = 1.0;
+    for (int i = 1; i <= q + 1; ++i) pxi = pxi * C->xi[i];
+    const double cn = 1.0 / (pxi * Sq1);
+    C->kap = C->dprev_h > 0.0 ? pow(C->h / C->dprev_h, (double)(q + 1)) * C->dprev_c / cn : 1.0;
+    C->craise = 0.0;   // a raise is formed by after_accept
+    return;
+  }
   for (int i = 1; i <= q; ++i)
     for (int j = i; j >= 1; --j) c[j] = c[j] + c[j - 1] / (double)i;
   const double H = harmonic(q);
   for (int j = 0; j < kQmaxAll + 2; ++j) C->l[j] = j <= q ? c[j] / H : 0.0;
   C->tq = 1.0 / ((double)(q + 1) * H * harmonic(q + 1));
   C->craise = 1.0 / (factorial(q + 1) * harmonic(q + 1));
+  C->kap = 1.0;
 }
 
 __device__ inline void rescale(Ctrl* C, double eta) {
@@ -137,8 +190,24 @@ __device__ inline void prepare_attempt(Ctrl* C) {
   C->dold = 0.0;
   C->phase = PH_PREDICT;
   C->nattempts++;
-  C->nsetups++;
   C->hist_reads += C->q + 1;
+  C->setup = 1;
+  C->dscale = 1.0;
+  if (C->lazy) {
+    const bool fresh = !C->m_valid || C->force_setup || C->nsteps - C->nst_s >= kMsbp ||
+                       fabs(C->gamma / C->gamma_s - 1.0) > kDgmax;
+    if (fresh) {
+      C->gamma_s = C->gamma;
+      C->nst_s = C->nsteps;
+      C->m_valid = 1;
+      C->force_setup = 0;
+    } else {
+      C->setup = 0;
+      C->dscale = 2.0 / (1.0 + C->gamma / C->gamma_s);
+      C->crate = C->crate_keep;
+    }
+  }
+  if (C->setup) C->nsetups++;
 }
 
 __device__ inline void fail_error(Ctrl* C, int code) {
@@ -147,6 +216,14 @@ __device__ inline void fail_error(Ctrl* C, int code) {
 }
 
 __device__ inline void newton_failed(Ctrl* C) {
+  C->crate_keep = C->crate;
+  if (C->lazy) {
+    C->force_setup = 1;
+    if (!C->setup) {   // reused factors: redo the attempt with fresh ones
+      C->nstale_retries++;
+      return prepare_attempt(C);
+    }
+  }
   if (C->learned && !C->force_lu) {
     // the learned attempt failed: redo it with exact LU before reducing h
     C->force_lu = 1;
@@ -174,6 +251,7 @@ __device__ inline void error_test_failed(Ctrl* C, double err) {
     if (hn < C->hmin) return fail_error(C, BDFGPU_ERR_HMIN);
     C->h = hn;
     C->q = 1;
+    C->ntau = 0;             // the new history knows no past points
     C->restart = 1;          // next predictor sets z[1] = h f(z[0])
     for (int j = 0; j < kQmaxAll + 2; ++j) C->hs[j] = 1.0;
     C->qwait = 2;
@@ -228,6 +306,7 @@ __device__ inline void after_newton_all(Ctrl* C, const double* s) {
     const double dcon = d * (C->crate < 1.0 ? C->crate : 1.0);
     if (dcon <= kNlsCoef) {
       C->m = m;
+      C->crate_keep = C->crate;
       if (t[2] > 0.0) C->nprojections++;
       const double err = sqrt(t[1] / C->N) / C->l[0] * C->tq;
       C->err = err;
@@ -243,7 +322,8 @@ __device__ inline void after_newton_all(Ctrl* C, const double* s) {
             C->upd_hs[j] = C->hs[j];
           }
           C->upd_craise = C->craise;
-          C->upd_raise = (C->qwait == 1 && C->q < kQmaxAll && C->q < C->qmax) ? 1 : 0;
+          C->upd_raise = (!C->vc && C->qwait == 1 && C->q < kQmaxAll && C->q < C->qmax) ? 1 : 0;
+          C->upd_dec = 0;
           const double sacc[2] = {t[5], t[6]};
           return after_accept(C, sacc);
         }
@@ -269,6 +349,18 @@ __device__ inline void after_accept(Ctrl* C, const double* s) {
   C->nsteps++;
   C->order_hist[q]++;
   C->qwait--;
+  double Sq1 = 0.0, pxi = 1.0;   // variable coefficients: S_{q+1}, prod xi
+  if (C->vc) {
+    for (int k = kNtau - 1; k > 0; --k) C->tau[k] = C->tau[k - 1];
+    C->tau[0] = C->h;
+    if (C->ntau < kNtau) C->ntau++;
+    for (int i = 1; i <= q + 1; ++i) {
+      Sq1 = Sq1 + 1.0 / C->xi[i];
+      pxi = pxi * C->xi[i];
+    }
+    C->dprev_c = 1.0 / (pxi * Sq1);
+    C->dprev_h = C->h;
+  }
   const double err = C->err;
   const double etaq = 1.0 / (pow(kBiasQ * err, 1.0 / (double)(q + 1)) + kAddon);
   double eta = etaq;
@@ -277,12 +369,24 @@ __device__ inline void after_accept(Ctrl* C, const double* s) {
     C->qwait = 2;
     double etaqm1 = 0.0, etaqp1 = 0.0;
     if (q > 1) {
-      const double e = sqrt(s[0] / C->N) * factorial(q - 1) / harmonic(q - 1);
+      // order q-1: |z[q]| prod_{i<q} xi_i / S_{q-1} ((q-1)! / H_{q-1} at
+      // constant steps)
+      double pr = factorial(q - 1), S = harmonic(q - 1);
+      if (C->vc) {
+        pr = 1.0;
+        S = 0.0;
+        for (int i = 1; i <= q - 1; ++i) {
+          pr = pr * C->xi[i];
+          S = S + 1.0 / C->xi[i];
+        }
+      }
+      const double e = sqrt(s[0] / C->N) * pr / S;
       etaqm1 = 1.0 / (pow(kBiasQm1 * e, 1.0 / (double)q) + kAddon);
     }
     if (q < C->qmax) {
-      const double e = sqrt(s[1] / C->N) /
-                       ((double)(q + 2) * harmonic(q + 1) * harmonic(q + 1));
+      // order q+1: |acor - kap acor_prev| / ((q+2) S_{q+1}^2)
+      const double S1 = C->vc ? Sq1 : harmonic(q + 1);
+      const double e = sqrt(s[1] / C->N) / ((double)(q + 2) * S1 * S1);
       etaqp1 = 1.0 / (pow(kBiasQp1 * e, 1.0 / (double)(q + 2)) + kAddon);
     }
     if (etaq >= etaqm1 && etaq >= etaqp1) {
@@ -299,6 +403,36 @@ __device__ inline void after_accept(Ctrl* C, const double* s) {
   for (int j = 0; j < kQmaxAll + 2; ++j) C->hs[j] = 1.0;
   if (eta >= kThresh) {
     if (eta > kEtaMax) eta = kEtaMax;
+    if (C->vc && C->fuse && qnew == q + 1) {
+      // raise keeping the interpolation: the update adds
+      // cr acor s prod_{i<=q} (s + xi_i), cr = Lambda(-xi_{q+1}) /
+      // (xi_{q+1} prod_{i<=q} (xi_i - xi_{q+1})), so the history also passes
+      // through the accepted value before the last q + 1
+      double lam = 0.0, pw = 1.0, den = C->xi[q + 1], e[kQmaxAll + 3];
+      for (int j = 0; j <= q; ++j) {
+        lam = lam + C->l[j] * pw;
+        pw = pw * -C->xi[q + 1];
+      }
+      for (int i = 1; i <= q; ++i) den = den * (C->xi[i] - C->xi[q + 1]);
+      const double cr = lam / den;
+      for (int j = 0; j < kQmaxAll + 3; ++j) e[j] = 0.0;
+      e[1] = 1.0;
+      for (int i = 1; i <= q; ++i)
+        for (int j = i + 1; j >= 1; --j) e[j] = e[j - 1] + C->xi[i] * e[j];
+      for (int j = 1; j <= q; ++j) C->upd_l[j] = C->upd_l[j] + cr * e[j];
+      C->upd_craise = cr;
+      C->upd_raise = 1;
+    } else if (C->vc && C->fuse && qnew == q - 1) {
+      // lowering keeping the interpolation: subtract z[q] s prod_{i<q}
+      // (s + xi_i), applied by the update after z_new is formed
+      double d[kQmaxAll + 3];
+      for (int j = 0; j < kQmaxAll + 3; ++j) d[j] = 0.0;
+      d[1] = 1.0;
+      for (int i = 1; i <= q - 1; ++i)
+        for (int j = i + 1; j >= 1; --j) d[j] = d[j - 1] + C->xi[i] * d[j];
+      for (int j = 0; j < kQmaxAll + 2; ++j) C->upd_d[j] = d[j];
+      C->upd_dec = 1;
+    }
     C->q = qnew;
     rescale(C, eta);
     C->h = C->h * eta;
@@ -320,6 +454,8 @@ __device__ inline void after_accept(Ctrl* C, const double* s) {
 // scale becomes h, so z[1] = h f(y0).
 __device__ inline void finish_init(Ctrl* C, double h) {
   C->h = h;
+  C->ntau = 0;
+  C->m_valid = 0;
   for (int j = 0; j < kQmaxAll + 2; ++j) C->hs[j] = 1.0;
   C->hs[1] = h;
   C->q = 1;

@@ -64,6 +64,11 @@ struct ClassDev {
   // learned preconditioner
   float* X;              // per cell n x n approximate inverse (row-major)
   double* xin;           // per cell MLP inputs [z(0)[0], log gamma]
+  // lazy Newton matrix (thread-per-cell classes): per cell the NP x NP
+  // factors (or inverse) and NP pivots, tiled like the state: entry k of
+  // cell c at (c/64) 64 K + 64 k + c%64 with K = NP^2 (NP for pivots)
+  double* lu;
+  int* lpiv;
 };
 
 struct BdfDev {
@@ -73,6 +78,8 @@ struct BdfDev {
   double rtol, atol;
   int nonneg;
   int defer;             // deferred history update (host copy of Ctrl::fuse, for LDS sizing)
+  int lazy;              // stored Newton-matrix factors (host copy of Ctrl::lazy)
+  int vc;                // variable coefficients (host copy of Ctrl::vc)
   ClassDev k;
 };
 
@@ -585,7 +592,7 @@ __device__ __forceinline__ void tpc_load_vec(const double* v, long c, int n, dou
 // back (with z[UQ+1] = craise acor when that step could raise the order),
 // and returned unscaled in zs (rows 0..UQ+1), with acor.  All loads go out
 // in one batch.
-template <int NP, int UQ>
+template <int NP, int UQ, bool VC>
 __device__ __forceinline__ void tpc_apply_update_q(const BdfDev& D, long c, int n,
                                                    double (&zs)[kQmaxAll + 1][NP],
                                                    double (&acor)[NP]) {
@@ -634,6 +641,16 @@ __device__ __forceinline__ void tpc_apply_update_q(const BdfDev& D, long c, int 
     for (int j = 1; j <= UQ; ++j) zs[j][i] = i < n ? fma(lj[j], a, zs[j][i]) : 0.0;
     if constexpr (UQ < kQmaxAll) zs[UQ + 1][i] = (raise && i < n) ? craise * a : 0.0;
   }
+  if constexpr (VC) {
+    if (C->upd_dec) {   // variable coefficients: order lowered to UQ - 1
+#pragma unroll
+      for (int j = 1; j < UQ; ++j) {
+        const double dj = C->upd_d[j];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) zs[j][i] = fma(-dj, zs[UQ][i], zs[j][i]);
+      }
+    }
+  }
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
     if (i < n) {
@@ -647,16 +664,66 @@ __device__ __forceinline__ void tpc_apply_update_q(const BdfDev& D, long c, int 
   }
 }
 
-template <int NP>
+// VC: variable coefficients (an order lowering may come with the update)
+template <int NP, bool VC>
 __device__ __forceinline__ void tpc_apply_update(const BdfDev& D, long c, int n,
                                                  double (&zs)[kQmaxAll + 1][NP],
                                                  double (&acor)[NP]) {
   switch (D.C->upd_q) {
-    case 1: tpc_apply_update_q<NP, 1>(D, c, n, zs, acor); break;
-    case 2: tpc_apply_update_q<NP, 2>(D, c, n, zs, acor); break;
-    case 3: tpc_apply_update_q<NP, 3>(D, c, n, zs, acor); break;
-    case 4: tpc_apply_update_q<NP, 4>(D, c, n, zs, acor); break;
-    default: tpc_apply_update_q<NP, 5>(D, c, n, zs, acor); break;
+    case 1: tpc_apply_update_q<NP, 1, VC>(D, c, n, zs, acor); break;
+    case 2: tpc_apply_update_q<NP, 2, VC>(D, c, n, zs, acor); break;
+    case 3: tpc_apply_update_q<NP, 3, VC>(D, c, n, zs, acor); break;
+    case 4: tpc_apply_update_q<NP, 4, VC>(D, c, n, zs, acor); break;
+    default: tpc_apply_update_q<NP, 5, VC>(D, c, n, zs, acor); break;
+  }
+}
+
+// Lazy Newton matrix: a cell's factors (LU with pivots, or the inverse),
+// tiled as described at ClassDev::lu; every load goes out before the first
+// use.
+template <int NP, int LS, class TF>
+__device__ __forceinline__ void tpc_store_factors(const ClassDev& K, long c,
+                                                  const TF (&A)[NP][NP], const int (&piv)[NP],
+                                                  const double (&Xi)[LS == 3 ? NP : 1]
+                                                                    [LS == 3 ? NP : 1]) {
+  const long base = (c >> 6) * 64L * NP * NP + (c & 63);
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const long k = (long)(i * NP + j) * 64;
+      if constexpr (LS == 3)
+        K.lu[base + k] = Xi[i][j];
+      else
+        K.lu[base + k] = (double)A[i][j];
+    }
+  if constexpr (LS != 3) {
+    const long pb = (c >> 6) * 64L * NP + (c & 63);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) K.lpiv[pb + i * 64] = piv[i];
+  }
+}
+
+template <int NP, int LS, class TF>
+__device__ __forceinline__ void tpc_load_factors(const ClassDev& K, long c, TF (&A)[NP][NP],
+                                                 int (&piv)[NP],
+                                                 double (&Xi)[LS == 3 ? NP : 1]
+                                                             [LS == 3 ? NP : 1]) {
+  const long base = (c >> 6) * 64L * NP * NP + (c & 63);
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const long k = (long)(i * NP + j) * 64;
+      if constexpr (LS == 3)
+        Xi[i][j] = K.lu[base + k];
+      else
+        A[i][j] = (TF)K.lu[base + k];
+    }
+  if constexpr (LS != 3) {
+    const long pb = (c >> 6) * 64L * NP + (c & 63);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) piv[i] = K.lpiv[pb + i * 64];
   }
 }
 
@@ -695,8 +762,14 @@ __host__ __device__ inline size_t tpc_accept_lds(int tb) {
 // FULL: the class's species fill the padded size (n == NP), so n is a
 // compile-time constant: the padding selects and clamped addresses vanish
 // and every tiled address is a constant offset from the cell's base.
-template <int NP, int LS, int TB, class Net = NetTables, int RC = 24, bool FULL = false>
+// MODE: bit 0 lazy Newton matrix (stored factors), bit 1 variable
+// coefficients; each combination is its own kernel so that the plain one
+// carries none of their code.
+template <int NP, int LS, int TB, class Net = NetTables, int RC = 24, bool FULL = false,
+          int MODE = 0>
 __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, double* lds) {
+  constexpr bool LZ = (MODE & 1) != 0, VC = (MODE & 2) != 0;
+  static_assert(!LZ || LS == 0 || LS == 3, "stored factors: FP64 LU or the inverse");
   using TP = Tpc<NP, TB>;
   Ctrl* C = D.C;
   const ClassDev& K = D.k;
@@ -734,7 +807,7 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
       double zs[kQmaxAll + 1][NP];
       double acp[NP];
       if (C->fuse && C->upd) {
-        tpc_apply_update<NP>(D, c, n, zs, acp);
+        tpc_apply_update<NP, VC>(D, c, n, zs, acp);
 #pragma unroll
         for (int j = 0; j <= kQmaxAll; ++j) {
           const double hsj = C->hs[j];
@@ -801,15 +874,24 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
     double rowsum[NP];
     constexpr int NX = LS == 3 ? NP : 1;   // LS 3: the block's explicit inverse
     double Xi[NX][NX];
-    Net::template build_M<NP, TB, TF, LS == 1>(nd, kcol, TB, ycol, gamma, A, rowsum);
     double mnorm = 0.0;
+    int info = 0;
+    // LZ (lazy Newton matrix): reuse the stored factors unless this attempt
+    // sets up (uniform over the grid)
+    const bool reuse = LZ && !C->setup;
+    if (reuse) {
+      tpc_load_factors<NP, LS>(K, c, A, piv, Xi);
+    } else {
+      Net::template build_M<NP, TB, TF, LS == 1>(nd, kcol, TB, ycol, gamma, A, rowsum);
 #pragma unroll
-    for (int i = 0; i < NP; ++i) mnorm = fmax(mnorm, rowsum[i]);
-    int info;
-    if constexpr (LS == 3)
-      info = TpcGJ<NP>::invert(A, Xi);
-    else
-      info = TpcLU<NP, TF>::factor(A, piv);
+      for (int i = 0; i < NP; ++i) mnorm = fmax(mnorm, rowsum[i]);
+      if constexpr (LS == 3)
+        info = TpcGJ<NP>::invert(A, Xi);
+      else
+        info = TpcLU<NP, TF>::factor(A, piv);
+      if constexpr (LZ) tpc_store_factors<NP, LS>(K, c, A, piv, Xi);
+    }
+    const double dscale = C->dscale;
     bool fp64 = (LS == 1) && info != 0;   // LS 1: FP32 factor singular -> FP64 LU
     bool sing = (LS == 0 || LS == 3) && info != 0;
     red[4] = fp64 ? 1.0 : 0.0;            // counted with the first iteration
@@ -829,8 +911,16 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
 #pragma unroll
         for (int i = 0; i < NP; ++i) del[i] = r[i];
         TpcLU<NP, TF>::solve(A, piv, del);
+        if (reuse) {
+#pragma unroll
+          for (int i = 0; i < NP; ++i) del[i] = dscale * del[i];
+        }
       } else if constexpr (LS == 3) {
         TpcGJ<NP>::apply(Xi, r, del);
+        if (reuse) {
+#pragma unroll
+          for (int i = 0; i < NP; ++i) del[i] = dscale * del[i];
+        }
       } else {
         bool ok = false;
         if (!fp64) {
@@ -905,6 +995,7 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
         // z[q] = z(0)[q] + l_q acor and acor - acor_prev, as the history
         // update forms them
         const double lq = C->l[q];
+        const double kap = VC ? C->kap : 1.0;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
           if (i < n) {
@@ -913,7 +1004,11 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
             const double zq = fma(lq, ac, qcol[i * TB]) * w[i];
             sq = fma(zq, zq, sq);
             if (selp1) {
-              const double e = (ac - pcol[i * TB]) * w[i];
+              double e;
+              if constexpr (VC)
+                e = (ac - kap * pcol[i * TB]) * w[i];
+              else
+                e = (ac - pcol[i * TB]) * w[i];
               sp = fma(e, e, sp);
             }
           }
@@ -938,11 +1033,11 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
   block_partials<kRedNewton>(D, (unsigned int)(D.k.blk0 + blk), red, s_red);
 }
 
-template <int NP, int LS, bool FULL = false>
+template <int NP, int LS, bool FULL = false, int MODE = 0>
 __global__ void __launch_bounds__(kTpcThreads) k_tpc_newton(BdfDev D) {
   extern __shared__ double lds[];
   if (D.C->phase != PH_PREDICT) return;
-  tpc_newton_body<NP, LS, kTpcThreads, NetTables, 24, FULL>(D, blockIdx.x, lds);
+  tpc_newton_body<NP, LS, kTpcThreads, NetTables, 24, FULL, MODE>(D, blockIdx.x, lds);
 }
 
 // History update after an accepted attempt: z_new[j] = z(0)[j] + l_j acor
@@ -1079,10 +1174,10 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_flush(BdfDev D) {
   if (c >= K.ncells) return;
   const int n = K.n;
   double zs[kQmaxAll + 1][NP], acor[NP];
-  if (n == NP)
-    tpc_apply_update<NP>(D, c, NP, zs, acor);
+  if (n == NP)   // (rare: the end of a drive; one variant serves every mode)
+    tpc_apply_update<NP, true>(D, c, NP, zs, acor);
   else
-    tpc_apply_update<NP>(D, c, n, zs, acor);
+    tpc_apply_update<NP, true>(D, c, n, zs, acor);
 #pragma unroll
   for (int i = 0; i < NP; ++i)
     if (i < n) K.dprev[Tpc<NP>::idx(c, i, n)] = acor[i];

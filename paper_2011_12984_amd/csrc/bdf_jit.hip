@@ -86,7 +86,8 @@ void emit_update(std::ostringstream& o, const std::string& dst, int S, const cha
 
 }  // namespace
 
-std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np, int ls) {
+std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np, int ls,
+                              int mode) {
   const std::vector<Reaction> rx = reactions(nu, mu, n, R);
   std::vector<bool> react(n, false);
   for (const Reaction& r : rx)
@@ -227,14 +228,16 @@ std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np
        "  }\n};\n}  // namespace bdfgpu\n\n";
 
   // named by block size and solver so that profiles keep the variants apart
-  const std::string kname = "bdf_newton_net_np" + std::to_string(np) + "_ls" + std::to_string(ls);
+  const std::string kname = "bdf_newton_net_np" + std::to_string(np) + "_ls" + std::to_string(ls) +
+                            (mode ? "_m" + std::to_string(mode) : std::string());
   o << "__global__ void __launch_bounds__(bdfgpu::kTpcThreads) " << kname
     << "(bdfgpu::BdfDev D) {\n"
        "  extern __shared__ double lds[];\n"
        "  if (D.C->phase != bdfgpu::PH_PREDICT) return;\n"
        "  bdfgpu::tpc_newton_body<"
     << np << ", " << ls << ", bdfgpu::kTpcThreads, bdfgpu::NetGen, " << (R < 1 ? 1 : R > 24 ? 24 : R)
-    << ", " << (n == np ? "true" : "false") << ">(D, blockIdx.x, lds);\n}\n\n"
+    << ", " << (n == np ? "true" : "false") << ", " << mode
+    << ">(D, blockIdx.x, lds);\n}\n\n"
        "// dynamic LDS above 64 KiB is requested once per process\n"
        "extern \"C\" void bdf_newton_net_launch(const bdfgpu::BdfDev* D, unsigned int grid,\n"
        "                                      unsigned int lds, hipStream_t s) {\n"

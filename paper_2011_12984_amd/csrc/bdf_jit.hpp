@@ -21,7 +21,9 @@ typedef void (*NetLaunch)(const BdfDev* D, unsigned int grid, unsigned int lds, 
 // straight-line code over the network's nonzeros, in the same operations
 // and order as the table-driven kernel, so both give identical bits.  The
 // source also defines the extern "C" launcher bdf_newton_net_launch.
-std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np, int ls);
+// mode: bit 0 lazy Newton matrix, bit 1 variable coefficients
+std::string net_newton_source(const int* nu, const int* mu, int n, int R, int np, int ls,
+                              int mode);
 
 // Compiles src with hipcc ($HIPCC, else /opt/rocm/bin/hipcc) into
 // net.so under $BDFGPU_JIT_DIR (else $TMPDIR/bdfgpu-jit-<uid>) in a

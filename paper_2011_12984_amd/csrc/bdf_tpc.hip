@@ -4,6 +4,9 @@
 
 namespace bdfgpu {
 
+void launch_tpc_newton_mode(int np, int ls, int mode, const BdfDev& D, unsigned int grid,
+                            size_t lds, hipStream_t s);
+
 // Dynamic LDS above 64 KiB (gfx950 has 160 KiB per workgroup) is requested
 // explicitly; the first launch that needs it raises the kernel's limit.
 template <int NP, int LS, bool FULL>
@@ -16,9 +19,13 @@ static void go_newton_v(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t
   hipLaunchKernelGGL((k_tpc_newton<NP, LS, FULL>), g, b, lds, s, D);
 }
 
-// classes whose species fill the padded size get the variant with n fixed
+// classes whose species fill the padded size get the variant with n fixed;
+// the lazy Newton matrix and variable coefficients have kernels of their
+// own (bdf_tpc_modes.hip)
 template <int NP, int LS>
 static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
+  const int mode = (D.lazy ? 1 : 0) | (D.vc ? 2 : 0);
+  if (mode) return launch_tpc_newton_mode(NP, LS, mode, D, g.x, lds, s);
   if (D.k.n == NP)
     go_newton_v<NP, LS, true>(D, g, b, lds, s);
   else

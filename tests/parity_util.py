@@ -30,6 +30,13 @@ def gpu_bdf(G, prob, dev, **kw):
 # END_BAR0 + END_BAR_PER_STEP * (steps taken).
 END_BAR0 = 1e-3
 END_BAR_PER_STEP = 2e-5
+# With the lazy Newton matrix the convergence-rate estimate carries over
+# between attempts, so the grouped test (WRMS over all cells) accepts a
+# first correction of up to 0.1 / crate: single cells may stop well short
+# of convergence, and the rounding of their unconverged states then shows
+# at up to ~4e-5 WRMS per step over the 256-cell network (measured: 0.079
+# after 1,984 steps; 0.049 after 2,176 with variable coefficients).
+END_BAR_PER_STEP_LAZY = 1e-4
 # The step sizes drift apart through the same rounding: each change of h
 # multiplies it by eta = (1.2 err)^(-1/(q+1)), err being the WRMS norm of
 # acor = y_n - z0[0], a difference of two states that agree to about the
@@ -51,8 +58,10 @@ _REF_CACHE = {}
 
 
 def _decisions(sg, so):
-    """(attempts, Newton iterations, order) of both sides after a step."""
-    return ((sg["nattempts"], sg["nniters"], sg["q"]), (so["nattempts"], so["nniters"], so["q"]))
+    """(attempts, Newton iterations, order, Newton-matrix setups, attempts
+    redone with fresh factors) of both sides after a step."""
+    keys = ("nattempts", "nniters", "q", "nsetups", "nstale_retries")
+    return tuple(sg[k] for k in keys), tuple(so[k] for k in keys)
 
 
 def gpu_y_at(gb, t):
@@ -89,7 +98,8 @@ def _report(label, yg, yo, p):
     return d, f"wrms diff {d:.3e}"
 
 
-def compare_trajectory(orc, dev, G, p, max_steps=None, okw=None, **kw):
+def compare_trajectory(orc, dev, G, p, max_steps=None, okw=None, bar_per_step=END_BAR_PER_STEP,
+                       **kw):
     """Lockstep parity of one trajectory (to p.t_end, or over its first
     max_steps accepted steps).  The oracle and the GPU integrator take one
     accepted step at a time; after every step the attempt and
@@ -102,7 +112,8 @@ def compare_trajectory(orc, dev, G, p, max_steps=None, okw=None, **kw):
       oracle's time along its own Nordsieck history); the largest relative
       step-size difference is printed.
     * At the first step where a decision differs (attempts, iterations,
-      order) or the step sizes have drifted apart beyond FLIP_H, the step,
+      order, Newton-matrix setups) or the step sizes have drifted apart
+      beyond FLIP_H, the step,
       both sides' decisions and the oracle's threshold quantities (error estimate
       against 1, order-change estimates, the proposed growth factor
       against the 1.5 hysteresis) are printed; the last common state
@@ -113,7 +124,9 @@ def compare_trajectory(orc, dev, G, p, max_steps=None, okw=None, **kw):
       counts within 15%.
 
     okw: extra oracle options (e.g. the learned mode's network); kw: GPU
-    handle options (linsol and refine_max_it go to both sides)."""
+    handle options (linsol and refine_max_it go to both sides); bar_per_step
+    replaces END_BAR_PER_STEP (END_BAR_PER_STEP_LAZY for the lazy Newton
+    matrix)."""
     lin = kw.pop("linsol", 0)
     rmi = kw.get("refine_max_it", 5)
     ob = orc.Bdf(p, linsol=lin, refine_max_it=rmi, **(okw or {}))
@@ -141,7 +154,7 @@ def compare_trajectory(orc, dev, G, p, max_steps=None, okw=None, **kw):
         if k % 32 == 0:
             yg = gpu_y_at(gb, sc["t"])
             dsnap, _ = _report(p.label, yg, ob.y(), p)
-            assert dsnap <= END_BAR0 + END_BAR_PER_STEP * k, (k, sc["t"], dsnap)
+            assert dsnap <= END_BAR0 + bar_per_step * k, (k, sc["t"], dsnap)
             snap = (k, sc["t"], yg, ob.y())
     if flip is None:
         sof, sgf = ob.stats(), gb.stats()
@@ -150,7 +163,7 @@ def compare_trajectory(orc, dev, G, p, max_steps=None, okw=None, **kw):
         d, msg = _report(p.label, yg, ob.y(), p)
         print(f"{p.label}: {k} steps to t = {sc['t']:.6e}, identical decisions; max rel "
               f"step-size difference {hdev:.2e}; state {msg}")
-        assert d <= END_BAR0 + END_BAR_PER_STEP * k
+        assert d <= END_BAR0 + bar_per_step * k
         return ob, gb
     print(f"{p.label}: decision flip {flip}; max rel step-size difference before it {hdev:.2e}")
     if snap is not None:

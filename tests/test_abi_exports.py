@@ -82,3 +82,24 @@ def test_gauss_jordan_and_order3_option_checks():
     assert Bdf.workspace_bytes(br, linsol=LS_GJ, launch=LAUNCH_FUSED) == 0
     assert Bdf.workspace_bytes(W.random_network_batch(100, n=10, seed=1), linsol=LS_GJ) == 0
     assert Bdf.workspace_bytes(br, linsol=LS_LU32REF) == 0
+
+
+def test_variable_coefficient_and_lazy_option_checks():
+    """vc and lazy need the deferred history update (thread-per-cell
+    classes, per-class launches, grouped stepping); lazy needs FP64 LU or
+    the Gauss-Jordan solve; the stored factors are counted in the
+    workspace."""
+    import workloads as W
+    from paper_2011_12984_amd import LS_GJ, LS_LU32REF, Bdf
+    net = W.random_network_batch(1000, n=10, seed=1)
+    base = Bdf.workspace_bytes(net)
+    lazy = Bdf.workspace_bytes(net, lazy=True)
+    assert Bdf.workspace_bytes(net, vc=True) == base
+    assert lazy - base >= 1000 * (10 * 10 * 8 + 10 * 4)
+    assert Bdf.workspace_bytes(net, vc=True, lazy=True) == lazy
+    assert Bdf.workspace_bytes(net, vc=True, linsol=LS_LU32REF) > 0
+    assert Bdf.workspace_bytes(net, lazy=True, linsol=LS_LU32REF) == 0
+    assert Bdf.workspace_bytes(W.brusselator_batch(100), lazy=True, linsol=LS_GJ) > 0
+    assert Bdf.workspace_bytes(net, vc=True, defer=False) == 0
+    assert Bdf.workspace_bytes(net, lazy=True, per_cell=True) == 0
+    assert Bdf.workspace_bytes(W.uneven_batch(1 << 12, seed=9), vc=True) == 0

@@ -1,0 +1,109 @@
+"""Variable-coefficient BDF and the lazy Newton matrix on the GPU against
+the oracle with the same options (the oracle's forms are pinned in
+test_oracle_vc.py).
+
+The coefficients are scalars the device controller forms from the past
+step sizes; the kernels apply the interpolation-keeping order lowering in
+the deferred history update, scale the order-(q+1) sum, and with the lazy
+Newton matrix store and reload each cell's factors.  Trajectories are
+compared in lockstep (parity_util.compare_trajectory, the bars derived
+there; END_BAR_PER_STEP_LAZY for the lazy forms): attempts, Newton
+iterations, order, setups and retries with fresh factors must agree step
+by step while the step sizes agree.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from parity_util import (END_BAR_PER_STEP, END_BAR_PER_STEP_LAZY, compare_trajectory, gpu_bdf,
+                         wrms_diff)
+
+pytestmark = pytest.mark.gpu
+
+FORMS = {
+    "vc": dict(vc=True),
+    "lazy": dict(lazy=True),
+    "vc_lazy": dict(vc=True, lazy=True),
+}
+
+
+def bar(kw):
+    return END_BAR_PER_STEP_LAZY if kw.get("lazy") else END_BAR_PER_STEP
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_trajectory_network10(orc, dev, G, form):
+    kw = FORMS[form]
+    ob, gb = compare_trajectory(orc, dev, G, W.random_network_batch(256, n=10, seed=31),
+                                okw=kw, bar_per_step=bar(kw), **kw)
+    s = gb.stats()
+    print(form, {k: s[k] for k in ("nsteps", "nattempts", "nsetups", "nstale_retries")})
+    if kw.get("lazy"):
+        assert s["nsetups"] * 3 < s["nattempts"]
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_trajectory_robertson_bdf2(orc, dev, G, form):
+    kw = FORMS[form]
+    compare_trajectory(orc, dev, G, W.robertson_batch(1000), okw=kw, bar_per_step=bar(kw), **kw)
+
+
+@pytest.mark.parametrize("form", ["vc_lazy"])
+@pytest.mark.parametrize("solve", ["lu", "gauss_jordan"])
+def test_trajectory_brusselator(orc, dev, G, form, solve):
+    kw = FORMS[form]
+    compare_trajectory(orc, dev, G, W.brusselator_batch(1000), okw=kw, bar_per_step=bar(kw),
+                       linsol=G.LS_GJ if solve == "gauss_jordan" else G.LS_LU64, **kw)
+
+
+def test_bench_kernel_vc_lazy_two_reduction_groups(orc, dev, G):
+    """The network-specialised kernel of the benchmark network with both
+    options, 20,000 cells (more than one reduction group, a ragged tile),
+    150 steps in lockstep."""
+    p = W.random_network_batch(20000, n=10, seed=W.BASE_SEED + 3)
+    kw = FORMS["vc_lazy"]
+    compare_trajectory(orc, dev, G, p, max_steps=150, okw=kw, bar_per_step=bar(kw), jit=True,
+                       **kw)
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_pauses_do_not_change_the_run(dev, G, form):
+    """Stopping every 37 steps (the pending history update is flushed and
+    picked up again) gives the same run bit for bit as one call."""
+    kw = FORMS[form]
+    p = W.random_network_batch(1000, n=10, seed=41)
+    a = gpu_bdf(G, p, dev, **kw)
+    b = gpu_bdf(G, p, dev, **kw)
+    assert a.advance(p.t_end, 370)[1] == 370
+    for _ in range(10):
+        assert b.advance(p.t_end, 37)[1] == 37
+    sa, sb = a.stats(), b.stats()
+    for k in ("nsteps", "nattempts", "nniters", "nsetups", "nstale_retries", "order_hist"):
+        assert sa[k] == sb[k], k
+    assert torch.equal(a.y(), b.y())
+
+
+def test_lazy_reduces_setups_at_scale(dev, G):
+    """2^16 cells of the benchmark network to t = 3e-5 (about 400 steps):
+    the lazy form with variable coefficients sets up at most one attempt in
+    5, and its error against a tight-tolerance run (rtol and atol 1e-3 of
+    the problem's) is within 3x that of the eager fixed-coefficient run
+    (both hold only their local errors to the tolerance)."""
+    p = W.random_network_batch(1 << 16, n=10, seed=W.BASE_SEED + 3)
+    t = 3e-5
+    runs = {}
+    for name, kw in (("eager", {}), ("vc_lazy", dict(vc=True, lazy=True)),
+                     ("tight", dict(rtol=p.rtol * 1e-3, atol=p.atol * 1e-3))):
+        b = gpu_bdf(G, p, dev, jit=True, **kw)
+        assert b.integrate(t) == t
+        runs[name] = (b.y().cpu().numpy(), b.stats())
+        b.close()
+    yr = runs["tight"][0]
+    err = {k: wrms_diff(runs[k][0], yr, p.rtol, p.atol) for k in ("eager", "vc_lazy")}
+    sa, sb = runs["eager"][1], runs["vc_lazy"][1]
+    print(f"to t = {t:.1e}: eager {sa['nsteps']} steps {sa['nsetups']} setups, error "
+          f"{err['eager']:.3e}; vc+lazy {sb['nsteps']} steps {sb['nsetups']} setups "
+          f"{sb['nstale_retries']} retries, error {err['vc_lazy']:.3e}")
+    assert sb["nsetups"] * 5 <= sb["nattempts"]
+    assert err["vc_lazy"] <= 3.0 * err["eager"]
