@@ -78,7 +78,8 @@ class OrcStats(C.Structure):
         "nsteps", "nattempts", "nfevals", "nsetups", "nniters", "nncfails",
         "netfails", "nlinsolves", "refine_sweeps", "refine_fallbacks",
         "lp_cell_solves", "lp_fallback_cells", "lp_step_fallbacks")] + [
-        ("order_hist", C.c_long * 6), ("nprojections", C.c_long), ("nstale_retries", C.c_long)]
+        ("order_hist", C.c_long * 6), ("nprojections", C.c_long), ("nstale_retries", C.c_long),
+        ("nliters", C.c_long)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "order_hist"}
@@ -147,6 +148,8 @@ def _declare(L):
     L.orc_bdf_get_past_steps.restype = C.c_int
     L.orc_bdf_get_past_steps.argtypes = [C.c_void_p, dp, dp, dp]
     L.orc_bdf_get_lazy.argtypes = [C.c_void_p, dp, C.POINTER(C.c_long), dp]
+    L.orc_gmres_solve.restype = C.c_int
+    L.orc_gmres_solve.argtypes = [C.c_long, ip, dp, dp, ip, dp, dp, C.c_double, dp]
 
 
 def _d(a):
@@ -428,7 +431,25 @@ def adam_step(p, g, m1, m2, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 # BDF integrator
 # ----------------------------------------------------------------------------
 
-LS_LU64, LS_LU32REF, LS_LEARNED, LS_GJ = 0, 1, 2, 3
+LS_LU64, LS_LU32REF, LS_LEARNED, LS_GJ, LS_GMRES = 0, 1, 2, 3, 4
+
+
+def gmres_solve(Ms, Ps, w, r, tol):
+    """The Newton-Krylov GMRES on blocks Ms (list of n x n) preconditioned
+    by the LU factors of the blocks Ps; returns (del, iterations)."""
+    ns = np.array([m.shape[0] for m in Ms], np.int32)
+    M = np.concatenate([np.asarray(m, float).T.ravel() for m in Ms])
+    LUs, pivs = [], []
+    for P in Ps:
+        lu, pv, _ = lu_factor(np.asarray(P, float)[None])
+        LUs.append(lu[0].T.ravel())
+        pivs.append(pv[0])
+    LU = np.concatenate(LUs)
+    piv = np.concatenate(pivs).astype(np.int32)
+    w, r = _c64(w), _c64(r)
+    d = np.zeros_like(r)
+    it = lib().orc_gmres_solve(len(ns), _i(ns), _d(M), _d(LU), _i(piv), _d(w), _d(r), tol, _d(d))
+    return d, it
 
 
 def bdf_coeffs(q):
@@ -471,7 +492,7 @@ class Bdf:
                                int(bool(fixed_step)), int(bool(vc)), int(bool(lazy)))
         self.h = lib().orc_bdf_create(C.byref(self.prob), C.byref(self.opts))
         if not self.h:
-            raise ValueError("orc_bdf_create refused the options (lazy needs LU64 or GJ)")
+            raise ValueError("orc_bdf_create refused the options (lazy needs LU64, GJ or GMRES)")
         self.N = lib().orc_bdf_N(self.h)
 
     def __del__(self):

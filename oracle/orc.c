@@ -84,6 +84,13 @@ void orc_nv_dot_prod_multi(int nv, const double* x, const double* const* Y,
   }
 }
 
+static double orc_nv_dot_prod_multi_1(long n, const double* x, const double* y) {
+  const double* Y[1] = {y};
+  double d;
+  orc_nv_dot_prod_multi(1, x, Y, &d, n);
+  return d;
+}
+
 double orc_nv_wrms_norm(long n, const double* x, const double* w) {
   if (n <= 0) return 0.0;
   nsum s = {0.0, 0.0};
@@ -536,6 +543,8 @@ void orc_adam_step(long np, float* p, const double* g, double* m1, double* m2,
 #define MSBP 20       /* lazy setup: accepted steps between fresh Newton matrices */
 #define DGMAX 0.3     /* lazy setup: largest |gamma / gamma_setup - 1| kept */
 #define NTAU (QMAX_ALL + 1)
+#define KRY_MAXL 5         /* GMRES: Krylov dimension, no restarts */
+#define KRY_EPLIN 0.05     /* GMRES: tolerance factor on the Newton tolerance */
 
 struct orc_bdf {
   orc_problem p;
@@ -565,6 +574,7 @@ struct orc_bdf {
   int m_valid, force_setup;
   long nst_s;
   double gamma_s, crate_keep;
+  double* V;   /* GMRES: Krylov basis, KRY_MAXL + 1 vectors of N */
   orc_stats st;
 };
 
@@ -646,7 +656,8 @@ static void vc_coeffs(int q, const double* xi, double* l, double* tq) {
 }
 
 orc_bdf* orc_bdf_create(const orc_problem* p, const orc_options* o) {
-  if (o->lazy && o->linsol != ORC_LS_LU64 && o->linsol != ORC_LS_GJ) return NULL;
+  if (o->lazy && o->linsol != ORC_LS_LU64 && o->linsol != ORC_LS_GJ && o->linsol != ORC_LS_GMRES)
+    return NULL;
   orc_bdf* b = (orc_bdf*)calloc(1, sizeof(orc_bdf));
   b->p = *p;
   b->o = *o;
@@ -694,6 +705,7 @@ orc_bdf* orc_bdf_create(const orc_problem* p, const orc_options* o) {
   b->dcell_prev = (double*)calloc((size_t)nc + 1, sizeof(double));
   if (o->linsol == ORC_LS_LEARNED || o->linsol == ORC_LS_GJ)
     b->X = (double*)calloc(NM, sizeof(double));
+  if (o->linsol == ORC_LS_GMRES) b->V = (double*)calloc((KRY_MAXL + 1) * N, sizeof(double));
   b->t = p->t0;
   b->err_qm1 = b->err_qp1 = -1.0;
   b->eta_prop = 1.0;
@@ -709,7 +721,7 @@ void orc_bdf_destroy(orc_bdf* b) {
   free(b->dprev); free(b->acor); free(b->y); free(b->w); free(b->f);
   free(b->r); free(b->del); free(b->tmp); free(b->M); free(b->LU);
   free(b->LU32); free(b->piv); free(b->piv32); free(b->cellmode);
-  free(b->cellinfo); free(b->dcell_prev); free(b->X);
+  free(b->cellinfo); free(b->dcell_prev); free(b->X); free(b->V);
   free(b);
 }
 
@@ -833,6 +845,140 @@ static int finite_cell(const orc_bdf* b, long c, const double* x) {
   return 1;
 }
 
+/* ---- Newton-Krylov (linsol GMRES) --------------------------------------
+ * The Newton system M del = r is solved over all N unknowns at once by
+ * GMRES (Saad & Schultz 1986) with right preconditioning and the error
+ * weights as scaling (Brown & Hindmarsh 1989): with W = diag(w) it is
+ * GMRES on W M P^{-1} W^{-1} for W r, and del = P^{-1} W^{-1} x.  P is
+ * the block-Jacobi preconditioner: the LU factors of the cells' blocks of
+ * M at the last setup (every attempt without lazy, so that P = M and one
+ * iteration solves it).  The operator applies the current M = I - gamma J
+ * with J at the predicted state.  Classical Gram-Schmidt (all inner
+ * products of a new vector with the basis, then one update); Givens
+ * rotations; at most KRY_MAXL iterations, no restart, stop when the scaled
+ * residual's 2-norm is at most KRY_EPLIN * NLS_COEF * sqrt(N) (WRMS
+ * KRY_EPLIN times the Newton tolerance).  Returns the iterations taken. */
+typedef struct {
+  long N, ncells;
+  const int* cn;
+  const long *yoff, *moff;
+  const double* M;     /* current Newton matrix blocks (column-major) */
+  const double* LU;    /* preconditioner: LU factors of the blocks */
+  const int* piv;
+  const double* w;     /* error weights (scaling) */
+  double *V, *tmp;     /* (KRY_MAXL + 1) N and N doubles of workspace */
+} kry_sys;
+
+static void prec_solve(const kry_sys* k, double* x) {   /* x <- P^{-1} x, per cell */
+  for (long c = 0; c < k->ncells; ++c)
+    orc_lu_solve(k->cn[c], k->LU + k->moff[c], k->piv + k->yoff[c], x + k->yoff[c]);
+}
+
+static void apply_M(const kry_sys* k, const double* x, double* out) {   /* out = M x */
+  for (long c = 0; c < k->ncells; ++c) {
+    int n = k->cn[c];
+    const double* M = k->M + k->moff[c];
+    const double* xc = x + k->yoff[c];
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) s = s + AT(M, i, j, n) * xc[j];
+      out[k->yoff[c] + i] = s;
+    }
+  }
+}
+
+/* del <- solution of M del = r to the scaled-residual tolerance tol (2-norm
+ * of W (r - M del)); returns the iterations taken. */
+static int gmres(const kry_sys* ks, const double* r, double tol, double* del) {
+  const long N = ks->N;
+  const double* w = ks->w;
+  double* V = ks->V;
+  double H[KRY_MAXL + 1][KRY_MAXL], cs[KRY_MAXL], sn[KRY_MAXL], g[KRY_MAXL + 1];
+  for (long i = 0; i < N; ++i) V[i] = w[i] * r[i];
+  double beta = sqrt(orc_nv_dot_prod_multi_1(N, V, V));
+  memset(del, 0, sizeof(double) * (size_t)N);
+  if (!(beta > tol)) return 0;
+  for (long i = 0; i < N; ++i) V[i] = V[i] / beta;
+  for (int j = 0; j <= KRY_MAXL; ++j) g[j] = 0.0;
+  g[0] = beta;
+  int k = 0, iters = 0;
+  for (k = 0; k < KRY_MAXL; ++k) {
+    double* vk = V + (long)k * N;
+    double* wv = V + (long)(k + 1) * N;
+    for (long i = 0; i < N; ++i) ks->tmp[i] = vk[i] / w[i];
+    prec_solve(ks, ks->tmp);
+    apply_M(ks, ks->tmp, wv);
+    for (long i = 0; i < N; ++i) wv[i] = w[i] * wv[i];
+    /* classical Gram-Schmidt: all inner products first, then one update */
+    const double* Y[KRY_MAXL];
+    for (int j = 0; j <= k; ++j) Y[j] = V + (long)j * N;
+    double hk[KRY_MAXL + 1];
+    orc_nv_dot_prod_multi(k + 1, wv, Y, hk, N);
+    for (int j = 0; j <= k; ++j)
+      for (long i = 0; i < N; ++i) wv[i] = wv[i] - hk[j] * Y[j][i];
+    hk[k + 1] = sqrt(orc_nv_dot_prod_multi_1(N, wv, wv));
+    iters++;
+    const int breakdown = !(hk[k + 1] > 0.0);
+    if (!breakdown)
+      for (long i = 0; i < N; ++i) wv[i] = wv[i] / hk[k + 1];
+    /* previous rotations on the new column, then one that zeroes h_{k+1,k} */
+    for (int j = 0; j < k; ++j) {
+      const double a = hk[j], c2 = hk[j + 1];
+      hk[j] = cs[j] * a + sn[j] * c2;
+      hk[j + 1] = -sn[j] * a + cs[j] * c2;
+    }
+    const double rr = sqrt(hk[k] * hk[k] + hk[k + 1] * hk[k + 1]);
+    cs[k] = hk[k] / rr;
+    sn[k] = hk[k + 1] / rr;
+    hk[k] = rr;
+    hk[k + 1] = 0.0;
+    g[k + 1] = -sn[k] * g[k];
+    g[k] = cs[k] * g[k];
+    for (int j = 0; j <= k; ++j) H[j][k] = hk[j];
+    if (breakdown || fabs(g[k + 1]) <= tol) {
+      k++;
+      break;
+    }
+  }
+  /* y = R^{-1} g, x = sum y_j v_j, del = P^{-1} W^{-1} x */
+  double y[KRY_MAXL];
+  for (int i = k - 1; i >= 0; --i) {
+    double s2 = g[i];
+    for (int j = i + 1; j < k; ++j) s2 = s2 - H[i][j] * y[j];
+    y[i] = s2 / H[i][i];
+  }
+  for (int j = 0; j < k; ++j)
+    for (long i = 0; i < N; ++i) del[i] = del[i] + y[j] * V[(long)j * N + i];
+  for (long i = 0; i < N; ++i) del[i] = del[i] / w[i];
+  prec_solve(ks, del);
+  return iters;
+}
+
+static int newton_gmres(orc_bdf* b) {
+  kry_sys ks = {b->N, b->p.ncells, b->cn, b->yoff, b->moff, b->M, b->LU, b->piv, b->w,
+                b->V, b->tmp};
+  const int it = gmres(&ks, b->r, KRY_EPLIN * NLS_COEF * sqrt((double)b->N), b->del);
+  b->st.nliters += it;
+  return it;
+}
+
+int orc_gmres_solve(long ncells, const int* n, const double* M, const double* LU,
+                    const int* piv, const double* w, const double* r, double tol, double* del) {
+  long* yoff = (long*)calloc((size_t)ncells + 1, sizeof(long));
+  long* moff = (long*)calloc((size_t)ncells + 1, sizeof(long));
+  for (long c = 0; c < ncells; ++c) {
+    yoff[c + 1] = yoff[c] + n[c];
+    moff[c + 1] = moff[c] + (long)n[c] * n[c];
+  }
+  const long N = yoff[ncells];
+  double* V = (double*)calloc((size_t)(KRY_MAXL + 1) * (size_t)(N > 0 ? N : 1), sizeof(double));
+  double* tmp = (double*)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
+  kry_sys ks = {N, ncells, n, yoff, moff, M, LU, piv, w, V, tmp};
+  const int it = gmres(&ks, r, tol, del);
+  free(V); free(tmp); free(yoff); free(moff);
+  return it;
+}
+
 /* Newton iteration on all cells at once (grouped; one global norm).
  * setup: fresh J, M = I - gamma J and its factors (else the stored factors
  * of an earlier gamma are reused and every correction is scaled by dscale);
@@ -844,7 +990,15 @@ static int newton(orc_bdf* b, double gamma, double l0, int force_lu, int setup, 
   int ls = b->o.linsol;
   int setup_fail = 0;
   if (setup) b->st.nsetups++;
-  if (!setup) {
+  if (ls == ORC_LS_GMRES) {
+    /* the operator's M at every attempt; the preconditioner's factors at a
+     * setup only */
+    for (long c = 0; c < nc; ++c) {
+      build_M(b, c, gamma);
+      b->cellmode[c] = 0;
+      if (setup && factor64(b, c)) setup_fail = 1;
+    }
+  } else if (!setup) {
     /* lazy reuse: cellmode (0 LU, 5 inverse) and the factors stay */
   } else if (ls == ORC_LS_LEARNED && !force_lu) {
     double xin[64];
@@ -892,7 +1046,8 @@ static int newton(orc_bdf* b, double gamma, double l0, int force_lu, int setup, 
     rhs_all(b, b->y, b->f);
     for (long i = 0; i < N; ++i)
       b->r[i] = gamma * b->f[i] - l0 * b->zp[1][i] - (b->y[i] - b->zp[0][i]);
-    for (long c = 0; c < nc; ++c) {
+    if (ls == ORC_LS_GMRES) newton_gmres(b);
+    for (long c = 0; c < nc && ls != ORC_LS_GMRES; ++c) {
       if (b->cellmode[c] == 2) {
         cell_solve(b, c);
         if (!finite_cell(b, c, b->del)) b->cellmode[c] = 4;  /* switch now */
@@ -990,7 +1145,8 @@ int orc_bdf_step(orc_bdf* b, double t_end) {
         b->m_valid = 1;
         b->force_setup = 0;
       } else {
-        dscale = 2.0 / (1.0 + gamma / b->gamma_s);
+        /* (the direct solve's correction scale; GMRES solves the current M) */
+        dscale = b->o.linsol == ORC_LS_GMRES ? 1.0 : 2.0 / (1.0 + gamma / b->gamma_s);
         crate = b->crate_keep;
       }
     }

@@ -110,7 +110,7 @@ typedef struct {
   double t0;
 } orc_problem;
 
-enum { ORC_LS_LU64 = 0, ORC_LS_LU32REF = 1, ORC_LS_LEARNED = 2, ORC_LS_GJ = 3 };
+enum { ORC_LS_LU64 = 0, ORC_LS_LU32REF = 1, ORC_LS_LEARNED = 2, ORC_LS_GJ = 3, ORC_LS_GMRES = 4 };
 
 typedef struct {
   double rtol, atol;
@@ -127,7 +127,8 @@ typedef struct {
                         selection); used only by the convergence-order pins */
   int vc;            /* 1: variable-coefficient BDF (coefficients from the past
                         step sizes; order changes keep the interpolation) */
-  int lazy;          /* 1: Newton matrix kept over steps (LU64 or GJ only) */
+  int lazy;          /* 1: Newton matrix kept over steps (LU64, GJ; with GMRES the
+                        block-Jacobi preconditioner) */
 } orc_options;
 
 typedef struct {
@@ -137,6 +138,7 @@ typedef struct {
   long order_hist[6];
   long nprojections;
   long nstale_retries;   /* attempts redone with fresh factors (lazy) */
+  long nliters;          /* GMRES iterations */
 } orc_stats;
 
 typedef struct orc_bdf orc_bdf;
@@ -181,6 +183,12 @@ int orc_bdf_get_past_steps(const orc_bdf* b, double* tau, double* dprev_c, doubl
 /* lazy Newton matrix: gamma and step count of the last setup, carried
  * convergence-rate estimate */
 void orc_bdf_get_lazy(const orc_bdf* b, double* gamma_s, long* nst_s, double* crate);
+/* GMRES of the Newton-Krylov path on a block-diagonal system (blocks of
+ * n[c], column-major M; block-Jacobi preconditioner from the LU factors LU,
+ * piv): del with |W (r - M del)|_2 <= tol, W = diag(w); returns the
+ * iterations taken (at most 5). */
+int orc_gmres_solve(long ncells, const int* n, const double* M, const double* LU,
+                    const int* piv, const double* w, const double* r, double tol, double* del);
 
 #ifdef __cplusplus
 }
