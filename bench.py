@@ -296,6 +296,33 @@ def robertson_leg(G, W, torch, dev, reps=3):
     return out
 
 
+def krylov_leg(G, W, torch, prob, dev, warmup, steps):
+    """The benchmark workload with Newton-Krylov (GMRES over all cells,
+    block-Jacobi preconditioner from the batched LU): a fresh preconditioner
+    every attempt (one Krylov iteration per solve) and the lazy one (reused
+    over steps, several Krylov iterations).  The host drives the Krylov
+    iteration with one synchronising reduction per inner-product pass."""
+    out = {}
+    for name, kw in (("gmres_fresh_preconditioner", dict()),
+                     ("gmres_lazy_preconditioner", dict(lazy=True))):
+        b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_STREAM, linsol=G.LS_GMRES,
+                               maxcor=MAXCOR, **kw)
+        b.advance(prob.t_end, warmup)
+        s0 = b.stats()
+        dt, taken, _ = time_advance(b, prob.t_end, steps, torch)
+        s1 = b.stats()
+        b.close()
+        nit = s1["nniters"] - s0["nniters"]
+        out[name] = {"value": round(prob.ncells * taken / dt, 1), "unit": "cell-steps/s",
+                     "ms_per_step": round(1e3 * dt / max(taken, 1), 4),
+                     "newton_iters_per_step": round(nit / max(taken, 1), 4),
+                     "krylov_iters_per_newton_iter":
+                         round((s1["nliters"] - s0["nliters"]) / max(nit, 1), 4),
+                     "setups_per_attempt": round((s1["nsetups"] - s0["nsetups"]) /
+                                                 max(s1["nattempts"] - s0["nattempts"], 1), 4)}
+    return out
+
+
 def brusselator_leg(G, W, torch, dev, ncells=1 << 20):
     """The demonstration reaction of Section 7 (3 species per cell, the
     1-D Gaussian profile over ncells cells), whole run from t = 0 to 10 on a
@@ -417,6 +444,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-robertson", action="store_true")
+    ap.add_argument("--no-krylov", action="store_true",
+                    help="skip the Newton-Krylov (GMRES) legs")
     ap.add_argument("--no-vc-lazy", action="store_true",
                     help="skip the variable-coefficient / lazy Newton matrix legs")
     ap.add_argument("--no-brusselator", action="store_true",
@@ -571,6 +600,11 @@ def main():
         vc_lazy = vc_lazy_leg(G, W, torch, prob, dev, args.warmup, args.steps, args.long_steps,
                               jit=not args.no_jit)
 
+    krylov = None
+    if not args.no_krylov:
+        log("Newton-Krylov (GMRES, block-Jacobi preconditioner)")
+        krylov = krylov_leg(G, W, torch, prob, dev, args.warmup, min(args.steps, 100))
+
     per_cell = None
     if not args.no_per_cell:
         log("per-cell adaptive stepping, whole run to t = 10")
@@ -625,6 +659,7 @@ def main():
         "cpu_baseline": cpu,
         "long_run": long_run,
         "variable_coefficients_lazy": vc_lazy,
+        "newton_krylov": krylov,
         "per_cell_whole_run": per_cell,
         "robertson_1000_bdf2": robertson,
         "brusselator_2p20": brusselator,

@@ -193,6 +193,19 @@ int batched_lu_solve_refine(int nb, int n, const double* M, const float* LU32,
 #define BDFGPU_LS_LEARNED 2  /* learned approximate inverse (options.precond),
                                 per-cell and per-attempt fallback to FP64 LU;
                                 cells of 13..31 species */
+#define BDFGPU_LS_GMRES 4    /* Newton-Krylov: each Newton system solved over all
+                                cells at once by right-preconditioned GMRES
+                                scaled by the error weights (Krylov dimension 5,
+                                classical Gram-Schmidt, tolerance 0.05 of the
+                                Newton tolerance), with the cells' LU factors
+                                at the last setup as block-Jacobi
+                                preconditioner (refreshed every attempt, or per
+                                the lazy rules); the global Newton with GMRES
+                                of Section 7.  One lane per cell (<= 12
+                                species), per-class launches, stream mode; the
+                                host drives the Krylov iteration (one
+                                synchronising reduction per inner-product
+                                pass, as in Section 4.1) */
 #define BDFGPU_LS_GJ 3       /* explicit block inverse by Gauss-Jordan
                                 elimination with partial pivoting, applied as
                                 a matrix-vector product in every Newton
@@ -317,6 +330,7 @@ typedef struct {
   double t, h, hu, err_last;
   int q, qu, qwait, status;
   long nstale_retries;    /* lazy: attempts redone with fresh factors */
+  long nliters;           /* GMRES iterations */
 } bdf_stats;
 
 typedef struct bdf_handle bdf_handle;

@@ -26,7 +26,7 @@ __all__ = [
     "Precond",
 ]
 
-LS_LU64, LS_LU32REF, LS_LEARNED, LS_GJ = 0, 1, 2, 3
+LS_LU64, LS_LU32REF, LS_LEARNED, LS_GJ, LS_GMRES = 0, 1, 2, 3, 4
 MODE_STREAM, MODE_GRAPH = 0, 1
 LAUNCH_PER_CLASS, LAUNCH_FUSED, LAUNCH_AUTO = 0, 1, 2
 RESULT_DEVICE = 1

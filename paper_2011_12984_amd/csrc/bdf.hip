@@ -32,6 +32,10 @@ void launch_tpc(int np, int ls, int which, const BdfDev& D, unsigned int grid, h
 void launch_spc(int seg, int ls, int which, const BdfDev& D, unsigned int grid, hipStream_t s);
 void launch_cell(int np, int ls, int which, const BdfDev& D, const CellDev& P, unsigned int grid,
                  hipStream_t s);
+void launch_kry(int np, int which, const BdfDev& D, unsigned int grid, hipStream_t s, int k,
+                double a, const double* coef);
+void launch_kry_sum(const double* partials, unsigned int nb, double* out, hipStream_t s);
+void launch_kry_control(Ctrl* C, const double* sums, long liters, hipStream_t s);
 __global__ void k_cell_setup(long ncells, double t0, double* t, double* h, double* hsc,
                              double* hu, int* iv, int* cnt);
 __global__ void k_cell_resume(long ncells, double tend, const double* t, int* iv);
@@ -205,6 +209,12 @@ struct bdf_handle {
   bool per_cell = false;
   unsigned int* d_active = nullptr;
   unsigned int* h_active = nullptr;
+  // Newton-Krylov: host-driven GMRES; reduced sums (device, pinned host)
+  // and the per-iteration Newton sums handed to the controller
+  bool krylov = false;
+  double* d_kry = nullptr;
+  double* h_kry = nullptr;
+  double* d_ksums = nullptr;
 };
 
 constexpr int kCellSlots = 1;       // per-cell mode: count of running cells
@@ -417,6 +427,135 @@ static int build_graph(bdf_handle* h) {
   return 0;
 }
 
+// One pass of a Krylov kernel over every class, its block partials summed
+// on the device and read back (8 values).
+static int kry_phase(bdf_handle* h, int which, int k, double a, const double* coef, double* out) {
+  for (const ClassHost& c : h->cls) {
+    if (c.ncells == 0) continue;
+    launch_kry(c.np, which, make_dev(h, c), c.grid, h->s, k, a, coef);
+  }
+  launch_kry_sum(h->partials, h->nblocks_total, h->d_kry, h->s);
+  BDF_HIP_TRY(hipMemcpyAsync(h->h_kry, h->d_kry, sizeof(double) * 8, hipMemcpyDeviceToHost, h->s));
+  BDF_HIP_TRY(hipStreamSynchronize(h->s));
+  for (int j = 0; j < 8; ++j) out[j] = h->h_kry[j];
+  return 0;
+}
+
+// The Newton iterations of one attempt with GMRES (the controller's state
+// read just before, phase PH_PREDICT): predictor and preconditioner setup,
+// then per Newton iteration the residual, the Krylov iterations and the
+// update; the Newton sums go to the controller, which takes the decision.
+// The host stops at the iteration where the controller will decide (the
+// same test on the same sums); iterations not run get NaN sums, which the
+// controller would treat as a failure if it ever read them.
+static int kry_attempt(bdf_handle* h) {
+  const Ctrl C0 = *h->hC;
+  double o[8], sums[kRedNewton];
+  for (int j = 0; j < kRedNewton; ++j) sums[j] = 0.0;
+  int st = kry_phase(h, 0, 0, 0.0, nullptr, o);
+  if (st) return st;
+  sums[7] = o[0];   // singular blocks in the setup
+  const double N = C0.N;
+  const double tol = kKryEplin * kNlsCoef * sqrt(N);
+  long liters = 0;
+  double crate = C0.crate, dold = 0.0;
+  int mlast = 0;
+  for (int m = 0; m < C0.maxcor; ++m) {
+    mlast = m;
+    if (m == 0 && sums[7] > 0.0) break;
+    if ((st = kry_phase(h, 1, 0, 0.0, nullptr, o))) return st;
+    const double beta = sqrt(o[0]);
+    double g[kKryMaxl + 1], cs[kKryMaxl], sn[kKryMaxl], H[kKryMaxl][kKryMaxl], y[kKryMaxl + 1];
+    for (int j = 0; j <= kKryMaxl; ++j) g[j] = y[j] = 0.0;
+    int kend = 0;
+    if (beta > tol) {
+      g[0] = beta;
+      double inv = 1.0 / beta;
+      int k = 0;
+      for (k = 0; k < kKryMaxl; ++k) {
+        double hk[kKryMaxl + 1];
+        if ((st = kry_phase(h, 2, k, inv, nullptr, o))) return st;
+        for (int j = 0; j <= k; ++j) hk[j] = o[j];
+        if ((st = kry_phase(h, 3, k, 0.0, hk, o))) return st;
+        hk[k + 1] = sqrt(o[0]);
+        liters++;
+        const bool breakdown = !(hk[k + 1] > 0.0);
+        inv = breakdown ? 0.0 : 1.0 / hk[k + 1];
+        for (int j = 0; j < k; ++j) {
+          const double a = hk[j], c2 = hk[j + 1];
+          hk[j] = cs[j] * a + sn[j] * c2;
+          hk[j + 1] = -sn[j] * a + cs[j] * c2;
+        }
+        const double rr = sqrt(hk[k] * hk[k] + hk[k + 1] * hk[k + 1]);
+        cs[k] = hk[k] / rr;
+        sn[k] = hk[k + 1] / rr;
+        hk[k] = rr;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        for (int j = 0; j <= k; ++j) H[j][k] = hk[j];
+        if (breakdown || fabs(g[k + 1]) <= tol) {
+          k++;
+          break;
+        }
+      }
+      kend = k;
+      for (int i = kend - 1; i >= 0; --i) {
+        double s2 = g[i];
+        for (int j = i + 1; j < kend; ++j) s2 = s2 - H[i][j] * y[j];
+        y[i] = s2 / H[i][i];
+      }
+    }
+    if ((st = kry_phase(h, 4, m, (double)kend, y, o))) return st;
+    sums[kRedPerIter * m + 0] = o[0];
+    sums[kRedPerIter * m + 1] = o[1];
+    sums[kRedPerIter * m + 2] = o[2];
+    // the controller's test (after_newton_all), to know where it stops
+    const double d = sqrt(o[0] / N);
+    if (!(d == d) || d > 1e300) break;
+    if (m > 0) {
+      const double ratio = d / dold;
+      crate = kCrDown * crate > ratio ? kCrDown * crate : ratio;
+    }
+    if (d * (crate < 1.0 ? crate : 1.0) <= kNlsCoef) break;
+    if (m >= 1 && d > kRdiv * dold) break;
+    dold = d;
+  }
+  for (int m = mlast + 1; m < kMaxCor; ++m) sums[kRedPerIter * m] = NAN;
+  BDF_HIP_TRY(hipMemcpyAsync(h->d_ksums, sums, sizeof(sums), hipMemcpyHostToDevice, h->s));
+  launch_kry_control(h->dC, h->d_ksums, liters, h->s);
+  BDF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+// Newton-Krylov: one attempt at a time, the host driving the Krylov
+// iterations, then the history update and its controller step.
+static int drive_krylov(bdf_handle* h, double* tret) {
+  long last_progress = -1;
+  for (;;) {
+    int st = read_ctrl(h);
+    if (st) return st;
+    const int ph = h->hC->phase;
+    if (ph == PH_ERROR) {
+      if (tret) *tret = h->hC->t;
+      set_last_error("integrator failure (see status code)", __FILE__, __LINE__);
+      return h->hC->status;
+    }
+    if (ph == PH_DONE || ph == PH_PAUSE) break;
+    const long progress = h->hC->nattempts + h->hC->nsteps;
+    if (progress == last_progress) {
+      set_last_error("integrator made no progress (phase stuck)", __FILE__, __LINE__);
+      return BDFGPU_ERR_HIP;
+    }
+    last_progress = progress;
+    if (ph == PH_PREDICT && (st = kry_attempt(h))) return st;
+    launch_phase_kernels(h, 3, h->s);
+    launch_control(h, 3, h->s);
+    BDF_HIP_TRY(hipGetLastError());
+  }
+  if (tret) *tret = h->hC->t;
+  return 0;
+}
+
 // Run attempts until the controller leaves the active phases.
 static int drive(bdf_handle* h, double tend, long inc, double* tret) {
   if (h->o.linsol == BDFGPU_LS_LEARNED) {
@@ -428,6 +567,7 @@ static int drive(bdf_handle* h, double tend, long inc, double* tret) {
   launch_phase(h, 0, h->s);   // starting-step estimate (no-ops once done)
   launch_phase(h, 1, h->s);
   BDF_HIP_TRY(hipGetLastError());
+  if (h->krylov) return drive_krylov(h, tret);
   const int per = std::max(1, h->o.attempts_per_sync);
   long last_progress = -1;
   for (;;) {
@@ -535,7 +675,8 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   if (o->qmax < 1 || o->qmax > kQmaxAll || o->maxcor < 1 || o->maxcor > kMaxCor ||
       !(o->rtol >= 0.0) || !(o->atol > 0.0) ||
       (o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_LU32REF &&
-       o->linsol != BDFGPU_LS_LEARNED && o->linsol != BDFGPU_LS_GJ) ||
+       o->linsol != BDFGPU_LS_LEARNED && o->linsol != BDFGPU_LS_GJ &&
+       o->linsol != BDFGPU_LS_GMRES) ||
       (o->linsol == BDFGPU_LS_LEARNED && !o->precond))
     return arg_error("bdf_create: bad options (qmax 1..5, maxcor 1..4, atol > 0, linsol, precond)");
   if (o->per_cell && ((o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_GJ) ||
@@ -548,12 +689,20 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   if ((o->vc || o->lazy) && (o->per_cell || o->no_defer))
     return arg_error("bdf_create: variable coefficients and the lazy Newton matrix need the "
                      "deferred history update and grouped stepping");
-  if (o->lazy && o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_GJ)
-    return arg_error("bdf_create: the lazy Newton matrix needs FP64 LU or the Gauss-Jordan solve");
+  if (o->lazy && o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_GJ &&
+      o->linsol != BDFGPU_LS_GMRES)
+    return arg_error("bdf_create: the lazy Newton matrix needs FP64 LU, the Gauss-Jordan solve "
+                     "or GMRES");
+  if (o->linsol == BDFGPU_LS_GMRES &&
+      (o->per_cell || o->vc || o->map_small || o->launch == BDFGPU_LAUNCH_FUSED ||
+       o->launch == BDFGPU_LAUNCH_AUTO || o->mode == BDFGPU_MODE_GRAPH))
+    return arg_error("bdf_create: GMRES needs grouped stepping with fixed coefficients, one lane "
+                     "per cell, per-class launches and stream mode");
   *out = nullptr;
   bdf_handle* h = new bdf_handle();
   h->s = as_stream(stream);
   h->per_cell = o->per_cell != 0;
+  h->krylov = o->linsol == BDFGPU_LS_GMRES;
   h->ws = static_cast<char*>(ws);
   h->ws_size = ws_bytes;
   h->dry = dry;
@@ -630,7 +779,7 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     }
     ch.np = ch.map == MAP_TPC ? tpc_padded(n) : spc_seg(n);
     // network-specialised Newton kernel
-    if (o->jit && ch.map == MAP_TPC && !dry) {
+    if (o->jit && ch.map == MAP_TPC && !dry && o->linsol != BDFGPU_LS_GMRES) {
       st = jit_newton(net_newton_source(nu, mu, n, R, ch.np, o->linsol,
                                         (o->lazy ? 1 : 0) | (o->vc ? 2 : 0)),
                       &ch.jit);
@@ -755,7 +904,16 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
         bdf_destroy(h);
         return st;
       }
-    if (o->lazy && tiled) {   // stored factors of M (or its inverse) and pivots
+    if (h->krylov && tiled) {   // predicted state, weights, iterate, Krylov basis
+      K.vstride = cap_cells * n;
+      if ((st = dalloc(h, (void**)&K.zp0, vbytes)) || (st = dalloc(h, (void**)&K.cv, vbytes)) ||
+          (st = dalloc(h, (void**)&K.wt, vbytes)) || (st = dalloc(h, (void**)&K.yk, vbytes)) ||
+          (st = dalloc_zero(h, (void**)&K.V, vbytes * (kKryMaxl + 1)))) {
+        bdf_destroy(h);
+        return st;
+      }
+    }
+    if ((o->lazy || h->krylov) && tiled) {   // stored factors of M (or its inverse), pivots
       const size_t np2 = (size_t)ch.np * (size_t)ch.np;
       if ((st = dalloc(h, (void**)&K.lu, sizeof(double) * std::max<long>(1, cap_cells) * np2)) ||
           (st = dalloc(h, (void**)&K.lpiv,
@@ -845,7 +1003,20 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
              !o->per_cell;
   for (const ClassHost& c : h->cls)
     if (c.map != MAP_TPC) h->defer = false;
-  if ((o->vc || o->lazy) && !h->defer) {
+  if (h->krylov) {
+    h->defer = false;   // the separate history update follows the Krylov Newton iterations
+    for (const ClassHost& c : h->cls)
+      if (c.map != MAP_TPC) {
+        bdf_destroy(h);
+        return arg_error("bdf_create: GMRES needs one lane per cell (<= 12 species)");
+      }
+    if ((st = dalloc(h, (void**)&h->d_kry, sizeof(double) * 8)) ||
+        (st = dalloc(h, (void**)&h->d_ksums, sizeof(double) * kRedNewton))) {
+      bdf_destroy(h);
+      return st;
+    }
+  }
+  if ((o->vc || o->lazy) && !h->defer && !h->krylov) {
     bdf_destroy(h);
     return arg_error("bdf_create: variable coefficients and the lazy Newton matrix need the "
                      "deferred history update: one lane per cell for every class (<= 12 "
@@ -870,6 +1041,8 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   }
   if (o->per_cell)
     BDF_HIP_TRY(hipHostMalloc((void**)&h->h_active, sizeof(unsigned int), hipHostMallocDefault));
+  if (h->krylov)
+    BDF_HIP_TRY(hipHostMalloc((void**)&h->h_kry, sizeof(double) * 8, hipHostMallocDefault));
   BDF_HIP_TRY(hipHostMalloc((void**)&h->hC, sizeof(Ctrl), hipHostMallocDefault));
   Ctrl C;
   memset(&C, 0, sizeof(C));
@@ -888,6 +1061,7 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   C.fuse = h->defer ? 1 : 0;
   C.vc = o->vc ? 1 : 0;
   C.lazy = o->lazy ? 1 : 0;
+  C.krylov = h->krylov ? 1 : 0;
   C.kap = 1.0;
   C.dscale = 1.0;
   C.setup = 1;
@@ -1027,6 +1201,7 @@ int bdf_destroy(bdf_handle* h) {
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->hC) (void)hipHostFree(h->hC);
   if (h->h_active) (void)hipHostFree(h->h_active);
+  if (h->h_kry) (void)hipHostFree(h->h_kry);
   delete h;
   return 0;
 }
@@ -1202,6 +1377,7 @@ int bdf_get_stats(bdf_handle* h, bdf_stats* s) {
   s->qwait = C.qwait;
   s->status = C.status;
   s->nstale_retries = C.nstale_retries;
+  s->nliters = C.nliters;
   return 0;
 }
 

@@ -68,6 +68,8 @@ constexpr double kAddon = 1e-6;
 constexpr int kMsbp = 20;          // lazy: accepted steps between fresh Newton matrices
 constexpr double kDgmax = 0.3;     // lazy: largest |gamma / gamma_s - 1| kept
 constexpr int kNtau = kQmaxAll + 1;
+constexpr int kKryMaxl = 5;        // GMRES: Krylov dimension (no restarts)
+constexpr double kKryEplin = 0.05; // GMRES: tolerance factor on the Newton tolerance
 
 struct Ctrl {
   double t, h, tend, hmin, h0user, hnw_h0;
@@ -103,6 +105,8 @@ struct Ctrl {
   // correction scale of a reuse, the carried convergence-rate estimate
   double gamma_s, dscale, crate_keep;
   long nst_s, nstale_retries;
+  int krylov, pad4;          // Newton-Krylov: GMRES solves the current M (no scaling)
+  long nliters;              // GMRES iterations
   long step_limit;
   long nsteps, nattempts, nfevals, nsetups, nniters, nncfails, netfails;
   long nlinsolves, refine_sweeps, refine_fallbacks, nprojections;
@@ -203,7 +207,7 @@ __device__ inline void prepare_attempt(Ctrl* C) {
       C->force_setup = 0;
     } else {
       C->setup = 0;
-      C->dscale = 2.0 / (1.0 + C->gamma / C->gamma_s);
+      C->dscale = C->krylov ? 1.0 : 2.0 / (1.0 + C->gamma / C->gamma_s);
       C->crate = C->crate_keep;
     }
   }

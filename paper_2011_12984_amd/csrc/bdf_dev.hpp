@@ -69,6 +69,11 @@ struct ClassDev {
   // cell c at (c/64) 64 K + 64 k + c%64 with K = NP^2 (NP for pivots)
   double* lu;
   int* lpiv;
+  // Newton-Krylov: weights, current iterate, Krylov basis V[j] = V + j vstride
+  double* wt;
+  double* yk;
+  double* V;
+  long vstride;
 };
 
 struct BdfDev {

@@ -59,8 +59,9 @@ _REF_CACHE = {}
 
 def _decisions(sg, so):
     """(attempts, Newton iterations, order, Newton-matrix setups, attempts
-    redone with fresh factors) of both sides after a step."""
-    keys = ("nattempts", "nniters", "q", "nsetups", "nstale_retries")
+    redone with fresh factors, GMRES iterations) of both sides after a
+    step."""
+    keys = ("nattempts", "nniters", "q", "nsetups", "nstale_retries", "nliters")
     return tuple(sg[k] for k in keys), tuple(so[k] for k in keys)
 
 

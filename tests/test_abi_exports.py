@@ -103,3 +103,22 @@ def test_variable_coefficient_and_lazy_option_checks():
     assert Bdf.workspace_bytes(net, vc=True, defer=False) == 0
     assert Bdf.workspace_bytes(net, lazy=True, per_cell=True) == 0
     assert Bdf.workspace_bytes(W.uneven_batch(1 << 12, seed=9), vc=True) == 0
+
+
+def test_gmres_option_checks():
+    """GMRES: thread-per-cell classes, per-class launches, stream mode,
+    fixed coefficients; the Krylov basis (6 vectors), the predicted state,
+    weights, iterate and the preconditioner's factors are counted in the
+    workspace."""
+    import workloads as W
+    from paper_2011_12984_amd import LS_GMRES, MODE_GRAPH, Bdf
+    net = W.random_network_batch(1000, n=10, seed=1)
+    base = Bdf.workspace_bytes(net)
+    kry = Bdf.workspace_bytes(net, linsol=LS_GMRES)
+    assert kry - base >= 1024 * 10 * 8 * (6 + 4) + 1000 * (10 * 10 * 8)
+    assert Bdf.workspace_bytes(net, linsol=LS_GMRES, lazy=True) == kry
+    assert Bdf.workspace_bytes(net, linsol=LS_GMRES, vc=True) == 0
+    assert Bdf.workspace_bytes(net, linsol=LS_GMRES, mode=MODE_GRAPH) == 0
+    assert Bdf.workspace_bytes(net, linsol=LS_GMRES, per_cell=True) == 0
+    assert Bdf.workspace_bytes(W.uneven_batch(1 << 12, seed=9), linsol=LS_GMRES) == 0
+    assert Bdf.workspace_bytes(W.brusselator_batch(100), linsol=LS_GMRES) > 0
