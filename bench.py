@@ -34,7 +34,7 @@ NEWTON_SOURCES = ("paper_2011_12984_amd/csrc/bdf_dev.hpp", "paper_2011_12984_amd
 # FETCH_SIZE / WRITE_SIZE counter runs scaled by a plain copy kernel (the
 # traffic summary under profiles/), with the hash of NEWTON_SOURCES they
 # were taken at: reported only while the sources still hash to it.
-MEASURED_TRAFFIC = {"sha256_16": None, "bytes": None}
+MEASURED_TRAFFIC = {"sha256_16": "11783dd77b894ad1", "bytes": 1514891264}
 
 
 def log(*a):
@@ -464,6 +464,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run nvec_scale (a plain copy, 512 MiB in and out) 5 times: "
                          "the reference for HBM byte counters")
+    ap.add_argument("--profile-uneven", type=int, default=0, metavar="STEPS",
+                    help="only advance the uneven batch (per-class launches, FP32-refined LU, "
+                         "stream mode) STEPS steps: the workload of the segment-kernel profiles")
+    ap.add_argument("--profile-mlp", action="store_true",
+                    help="only run the learned preconditioner's MFMA forward pass on 2^20 random "
+                         "inputs (2 warm-up + 5 timed calls): the workload of the MLP profiles")
     ap.add_argument("--learned-epochs", type=int, default=30)
     ap.add_argument("--learned-blocks", type=int, default=1 << 18)
     args = ap.parse_args()
@@ -487,6 +493,33 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"kernel": "k_scale", "bytes_read": 8 << 26,
                                                "bytes_written": 8 << 26, "launches": 5}}))
+        return
+    if args.profile_uneven > 0:
+        p = W.uneven_batch(1 << 22)
+        b = G.Bdf.from_problem(p, device=dev, mode=G.MODE_STREAM, attempts_per_sync=1,
+                               linsol=G.LS_LU32REF, launch=G.LAUNCH_PER_CLASS, maxcor=MAXCOR,
+                               jit=True)
+        b.advance(p.t_end, args.profile_uneven)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_uneven": {"steps": b.stats()["nsteps"]}}))
+        return
+    if args.profile_mlp:
+        n, B = 21, 1 << 20
+        pc = G.Precond(n, batch_cap=1024)
+        pc.set_params(W.mlp_init(n, out_scale=0.02))
+        X = W.torch_uniform_device(B * (n + 1), seed=7, device=dev).view(B, n + 1)
+        pc.fit_normalization(X)
+        for _ in range(2):
+            pc.forward(X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            pc.forward(X)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / 5
+        flops = 2.0 * B * ((n + 1) * 256 + 256 * 256 + 256 * n * n)
+        print(json.dumps({"profile_mlp": {"samples": B, "ms": round(ms, 4),
+                                          "TFLOP_per_s": round(flops / ms / 1e9, 1)}}))
         return
     log("generating workload")
     prob = W.random_network_batch(args.cells, n=10, seed=W.BASE_SEED + 3)
