@@ -177,25 +177,39 @@ def wrms(a, b, rtol, atol):
 
 
 def accuracy_vs_fp64(G, W, torch, dev, make, t_end, **kw):
-    """End-state difference (WRMS, and its largest per-cell value) between
-    a run with the given linear solver and the FP64-LU run on the same
-    problem to the same t_end."""
+    """End-state difference (WRMS over all cells, and per cell: median and
+    largest) between a run with the given linear solver and the FP64-LU run
+    on the same problem to the same t_end; and each run's per-cell error
+    against a tight-tolerance FP64 run (rtol and atol 1e-3 of the
+    problem's), since two valid step sequences differ by their global
+    errors."""
     import numpy as np
     prob = make()
-    ref = G.Bdf.from_problem(prob, device=dev)
-    ref.integrate(t_end)
-    yr = ref.y().cpu().numpy()
-    sr = ref.stats()
-    ref.close()
-    b = G.Bdf.from_problem(prob, device=dev, **kw)
-    b.integrate(t_end)
-    y = b.y().cpu().numpy()
-    s = b.stats()
-    b.close()
+    out = {}
+    for name, k in (("fp64", {}), ("solver", kw),
+                    ("tight", dict(rtol=prob.rtol * 1e-3, atol=prob.atol * 1e-3))):
+        b = G.Bdf.from_problem(prob, device=dev, **k)
+        b.integrate(t_end)
+        out[name] = (b.y().cpu().numpy(), b.stats())
+        b.close()
+    yr, sr = out["fp64"]
+    y, s = out["solver"]
+    yt = out["tight"][0]
     n = prob.sizes[0]
-    per = np.sqrt(np.mean((((y - yr) / (prob.rtol * np.abs(yr) + prob.atol)) ** 2).reshape(-1, n), 1))
-    return {"cells": int(prob.ncells), "t_end": t_end, "wrms_diff": round(wrms(y, yr, prob.rtol, prob.atol), 6),
+
+    def per_cell(a, ref):
+        return np.sqrt(np.mean((((a - ref) / (prob.rtol * np.abs(ref) + prob.atol)) ** 2)
+                               .reshape(-1, n), 1))
+    per = per_cell(y, yr)
+    es, ef = per_cell(y, yt), per_cell(yr, yt)
+    return {"cells": int(prob.ncells), "t_end": t_end,
+            "wrms_diff": round(wrms(y, yr, prob.rtol, prob.atol), 6),
+            "median_cell_wrms_diff": round(float(np.median(per)), 6),
             "max_cell_wrms_diff": round(float(per.max()), 6),
+            "error_vs_tight_per_cell": {"solver": {"median": round(float(np.median(es)), 6),
+                                                   "max": round(float(es.max()), 6)},
+                                        "fp64_lu": {"median": round(float(np.median(ef)), 6),
+                                                    "max": round(float(ef.max()), 6)}},
             "steps": [int(s["nsteps"]), int(sr["nsteps"])]}
 
 

@@ -79,7 +79,7 @@ class OrcStats(C.Structure):
         "netfails", "nlinsolves", "refine_sweeps", "refine_fallbacks",
         "lp_cell_solves", "lp_fallback_cells", "lp_step_fallbacks")] + [
         ("order_hist", C.c_long * 6), ("nprojections", C.c_long), ("nstale_retries", C.c_long),
-        ("nliters", C.c_long)]
+        ("nliters", C.c_long), ("lp_unconverged", C.c_long)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "order_hist"}

@@ -1069,13 +1069,24 @@ static int newton(orc_bdf* b, double gamma, double l0, int force_lu, int setup, 
     b->st.nlinsolves++;
     if (dscale != 1.0)
       for (long i = 0; i < N; ++i) b->del[i] = dscale * b->del[i];
+    /* learned cells: a cell still solved with X that does not contract by
+     * LP_CELL_RATIO switches to exact LU from the next iteration, and the
+     * attempt cannot be accepted at that iteration; at the first iteration
+     * no cell has a contraction rate yet, so a learned attempt is never
+     * accepted there (reading: the grouped test alone would let a cell
+     * whose X is poor pass on a small first correction X r) */
+    long unconv = 0;
     if (ls == ORC_LS_LEARNED && !force_lu) {
       for (long c = 0; c < nc; ++c) {
         double dc = cell_wrms(b, c, b->del);
-        if (b->cellmode[c] == 2 && m >= 1 && dc > LP_CELL_RATIO * b->dcell_prev[c])
+        if (b->cellmode[c] == 2 && m >= 1 && !(dc <= LP_CELL_RATIO * b->dcell_prev[c])) {
           b->cellmode[c] = 4;     /* exact LU from the next iteration on */
+          unconv++;
+        }
         b->dcell_prev[c] = dc;
       }
+      if (m == 0) unconv = 1;
+      b->st.lp_unconverged += unconv;
     }
     for (long i = 0; i < N; ++i) b->y[i] = b->y[i] + b->del[i];
     double d = wrms(b, b->del);
@@ -1086,7 +1097,7 @@ static int newton(orc_bdf* b, double gamma, double l0, int force_lu, int setup, 
       crate = CRDOWN * crate > ratio ? CRDOWN * crate : ratio;
     }
     double dcon = d * (crate < 1.0 ? crate : 1.0);
-    if (dcon <= NLS_COEF) {
+    if (dcon <= NLS_COEF && unconv == 0) {
       rc = 0;
       break;
     }

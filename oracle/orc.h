@@ -139,6 +139,8 @@ typedef struct {
   long nprojections;
   long nstale_retries;   /* attempts redone with fresh factors (lazy) */
   long nliters;          /* GMRES iterations */
+  long lp_unconverged;   /* learned: cells (first iteration: attempts) that kept
+                            an iteration from being accepted */
 } orc_stats;
 
 typedef struct orc_bdf orc_bdf;

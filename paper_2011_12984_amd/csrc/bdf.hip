@@ -19,7 +19,7 @@
 #include <chrono>
 
 #include "bdf_cell.hpp"
-#include "bdf_dev.hpp"
+#include "bdf_spc_dev.hpp"
 #include "bdf_jit.hpp"
 #include "bdf_multi.hpp"
 #include "common.hpp"

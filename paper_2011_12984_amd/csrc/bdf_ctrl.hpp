@@ -308,7 +308,11 @@ __device__ inline void after_newton_all(Ctrl* C, const double* s) {
       C->crate = kCrDown * C->crate > ratio ? kCrDown * C->crate : ratio;
     }
     const double dcon = d * (C->crate < 1.0 ? C->crate : 1.0);
-    if (dcon <= kNlsCoef) {
+    // learned mode: no acceptance at the first iteration (no cell has a
+    // contraction rate yet), nor at an iteration where a cell on its
+    // approximate inverse did not contract (slot 7 of iterations >= 1)
+    const bool lp_open = C->learned && !C->force_lu && (m == 0 || t[7] > 0.0);
+    if (dcon <= kNlsCoef && !lp_open) {
       C->m = m;
       C->crate_keep = C->crate;
       if (t[2] > 0.0) C->nprojections++;

@@ -1272,569 +1272,4 @@ __global__ void __launch_bounds__(kTpcThreads) k_tpc_init2(BdfDev D) {
   tpc_init2_body<NP, kTpcThreads>(D, blockIdx.x, lds);
 }
 
-// ===========================================================================
-// Segment per cell
-// ===========================================================================
-template <int SEG>
-struct Spc {
-  static constexpr int CPB = kCellThreads / SEG;   // cells per block
-
-  // lane i: f_i at the segment's state in ys (LDS, SEG values); kap: the
-  // cell's rates, St: the stoichiometry staged in LDS as St[k * SEG + i]
-  // (FP32 holds the small integer entries exactly)
-  __device__ static __forceinline__ void rhs_row(const NetDev& nd, const double* kap,
-                                                 const float* St, const double* ys, int i,
-                                                 double& f) {
-    f = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < nd.R; ++k) {
-      const int a = nd.ra[k], b = nd.rb[k];
-      double r = kap[k];
-      if (a >= 0) r *= ys[a];
-      if (b >= 0) r *= ys[b];
-      f = fma((double)St[k * SEG + i], r, f);
-    }
-  }
-
-  template <int NC>
-  __device__ static __forceinline__ void jac_row(const NetDev& nd, const double* kap,
-                                                 const float* St, const double* ys, int i,
-                                                 double (&J)[NC]) {
-#pragma unroll
-    for (int a = 0; a < NC; ++a) {
-      double acc = 0.0;
-      if (a < nd.n) {
-        const int e0 = nd.jst[a], e1 = nd.jst[a + 1];
-#pragma unroll 2
-        for (int e = e0; e < e1; ++e) {
-          const int k = nd.jk[e], p = nd.jp[e];
-          double g = kap[k] * nd.jm[e];
-          if (p >= 0) g *= ys[p];
-          acc = fma((double)St[k * SEG + i], g, acc);
-        }
-      }
-      J[a] = acc;
-    }
-  }
-};
-
-struct SpcShared {
-  double ys[kCellThreads];
-  double prow[kCellThreads];
-  float prow32[kCellThreads];
-  int wl[kCellThreads];
-  int wl32[kCellThreads];
-  double red[(kCellThreads / 64) * kRedNewton];
-  double wsum[(kCellThreads / 64) * kRedNewton];   // per-wave Newton sums
-};
-
-// v summed over the wave (every lane gets the same bits) and added by lane 0
-// to *s; all 64 lanes must be active.
-__device__ __forceinline__ void wave_add(double v, double* s) {
-  v += lane_pair_t<0>(v);
-  v += lane_pair_t<1>(v);
-  v += lane_pair_t<2>(v);
-  v += lane_pair_t<3>(v);
-  v += lane_pair_t<4>(v);
-  v += lane_pair_t<5>(v);
-  if ((threadIdx.x & 63) == 0) *s += v;
-}
-
-// Dynamic LDS of the SPC kernels: the shared scratch, then the rates of the
-// block's cells (CPB x R, FP64), then the stoichiometry (R x SEG; its entries
-// are small integers, exact in FP32).
-__host__ __device__ inline size_t spc_lds_bytes(int seg, int R) {
-  const size_t r = (size_t)(R > 0 ? R : 1);
-  return sizeof(SpcShared) + sizeof(double) * (size_t)(kCellThreads / seg) * r +
-         sizeof(float) * r * seg;
-}
-
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Carve the dynamic LDS and stage the rates of the block's cells
-// (cell-major, contiguous) and the class stoichiometry.
-template <int SEG>
-__device__ __forceinline__ void spc_stage(const ClassDev& K, long blk, double* lds,
-                                          SpcShared*& sh, double*& lk, float*& St) {
-  sh = reinterpret_cast<SpcShared*>(lds);
-  lk = lds + sizeof(SpcShared) / sizeof(double);
-  const int R = K.R;
-  St = reinterpret_cast<float*>(lk + (size_t)Spc<SEG>::CPB * (R > 0 ? R : 1));
-  const long c0 = blk * Spc<SEG>::CPB;
-  const long cnt = (K.ncells - c0 < Spc<SEG>::CPB ? K.ncells - c0 : Spc<SEG>::CPB) * (long)R;
-  for (long t = threadIdx.x; t < cnt; t += blockDim.x) lk[t] = K.rates[c0 * R + t];
-  const int np = K.net.np;
-  for (int t = threadIdx.x; t < R * SEG; t += blockDim.x) {
-    const int k = t / SEG, i = t - k * SEG;
-    St[t] = i < np ? (float)K.net.S[(long)k * np + i] : 0.0f;
-  }
-  __syncthreads();
-}
-
-// History of one SPC lane: clamped index for padding lanes, compile-time
-// order (see the TPC history loads).
-template <int Q>
-__device__ __forceinline__ void spc_load_hist_q(const ClassDev& K, const Ctrl* C, long ids,
-                                                bool row, double (&zs)[kQmaxAll + 1]) {
-#pragma unroll
-  for (int j = 0; j <= kQmaxAll; ++j) {
-    if (j <= Q) {
-      const double v = K.z[j][ids];
-      zs[j] = row ? v * C->hs[j] : 0.0;
-    } else {
-      zs[j] = 0.0;
-    }
-  }
-}
-
-__device__ __forceinline__ void spc_load_hist(const ClassDev& K, const Ctrl* C, long ids, bool row,
-                                              int q, double (&zs)[kQmaxAll + 1]) {
-  switch (q) {
-    case 1: spc_load_hist_q<1>(K, C, ids, row, zs); break;
-    case 2: spc_load_hist_q<2>(K, C, ids, row, zs); break;
-    case 3: spc_load_hist_q<3>(K, C, ids, row, zs); break;
-    case 4: spc_load_hist_q<4>(K, C, ids, row, zs); break;
-    default: spc_load_hist_q<5>(K, C, ids, row, zs); break;
-  }
-}
-
-// Predictor for one segment-per-cell lane: z(0)[0] and z(0)[0] - l0 z(0)[1]
-// of row i (Pascal triangle on the pending-scaled history), and the error
-// weight from z[0].
-template <int SEG>
-__device__ __forceinline__ void spc_predict_row(const BdfDev& D, const Ctrl* C, SpcShared& sh,
-                                                int sb, int i, bool act, bool row, long id,
-                                                const double* kap, const float* St,
-                                                double& zp0, double& cv, double& w) {
-  const ClassDev& K = D.k;
-  const int q = C->q;
-  double zs[kQmaxAll + 1];
-  spc_load_hist(K, C, row ? id : 0, row, q, zs);
-  w = row ? 1.0 / (D.rtol * fabs(zs[0]) + D.atol) : 0.0;
-  if (C->restart) {
-    __builtin_amdgcn_wave_barrier();
-    sh.ys[threadIdx.x] = zs[0];
-    wave_sync_lds();
-    double f0 = 0.0;
-    if (act) Spc<SEG>::rhs_row(K.net, kap, St, sh.ys + sb, i, f0);
-    zs[1] = row ? C->h * f0 : 0.0;
-    if (row) K.z[1][id] = zs[1];
-  }
-#pragma unroll
-  for (int k = 1; k <= kQmaxAll; ++k)
-#pragma unroll
-    for (int j = kQmaxAll; j >= k; --j)
-      if (k <= q && j <= q) zs[j - 1] = zs[j - 1] + zs[j];
-  zp0 = zs[0];
-  cv = zs[0] - C->l[0] * zs[1];
-}
-
-// Learned mode: predictor only, plus the MLP inputs [z(0)[0], log gamma]
-// of every cell.
-template <int SEG>
-__device__ __forceinline__ void spc_predict_body(const BdfDev& D, long blk, double* lds) {
-  Ctrl* C = D.C;
-  const ClassDev& K = D.k;
-  const int n = K.n;
-  const int i = threadIdx.x & (SEG - 1);
-  const int sb = threadIdx.x & ~(SEG - 1);
-  const int cb = threadIdx.x / SEG;
-  const long c = blk * Spc<SEG>::CPB + cb;
-  const bool act = c < K.ncells;
-  const bool row = act && i < n;
-  const long id = c * n + i;
-  SpcShared* shp;
-  double* lk;
-  float* St;
-  spc_stage<SEG>(K, blk, lds, shp, lk, St);
-  const double* kap = lk + cb * K.R;
-  double zp0, cv, w;
-  spc_predict_row<SEG>(D, C, *shp, sb, i, act, row, id, kap, St, zp0, cv, w);
-  if (row) {
-    K.zp0[id] = zp0;
-    K.cv[id] = cv;
-    K.xin[c * (n + 1) + i] = zp0;
-  }
-  if (act && i == 0) K.xin[c * (n + 1) + n] = log(C->gamma);
-}
-
-template <int SEG>
-__global__ void __launch_bounds__(kCellThreads) k_spc_predict(BdfDev D) {
-  extern __shared__ double lds[];
-  if (D.C->phase != PH_PREDICT) return;
-  spc_predict_body<SEG>(D, blockIdx.x, lds);
-}
-
-// Fused Newton iterations, segment per cell.  LS 0: FP64 LU factored once.
-// LS 1: FP32 LU factored once, each solve refined with FP64 residuals from
-// the FP64 rows; a cell whose refinement fails factors its FP64 rows in
-// place and uses them from then on.  LS 2: correction X r with the cell's
-// learned approximate inverse (X from the MLP, computed after the predictor
-// kernel); a cell switches to FP64 LU for the rest of the attempt when X r
-// is not finite, or from the second iteration on when its correction norm
-// does not fall below 0.9 times the previous one.
-// NC: columns held per lane (n rounded up to a multiple of 8, at most SEG).
-template <int SEG, int LS, int NC = SEG>
-__device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, double* lds) {
-  Ctrl* C = D.C;
-  const ClassDev& K = D.k;
-  const NetDev& nd = K.net;
-  const int n = K.n;
-  const int lane = threadIdx.x & 63;
-  const int i = lane & (SEG - 1);
-  const int seg_base = lane & ~(SEG - 1);
-  const int sb = threadIdx.x & ~(SEG - 1);
-  const int cb = threadIdx.x / SEG;
-  const long c = blk * Spc<SEG>::CPB + cb;
-  const bool act = c < K.ncells;           // uniform over the segment
-  const bool row = act && i < n;
-  const long id = c * n + i;
-  SpcShared* shp;
-  double* lk;
-  float* St;
-  spc_stage<SEG>(K, blk, lds, shp, lk, St);
-  SpcShared& sh = *shp;
-  // Each iteration's norms: with the FP32 and learned solvers they are
-  // summed over the wave at once and kept in LDS (the iteration number is
-  // not a compile-time index, and per-lane accumulators for every iteration
-  // cost registers those kernels need to run two or three waves per SIMD);
-  // the FP64 kernel, which gains no wave from that, keeps per-lane sums.
-  constexpr bool kLdsSums = LS != 0;
-  double* wsum = sh.wsum + (threadIdx.x >> 6) * kRedNewton;
-  if (kLdsSums && lane < kRedNewton) wsum[lane] = 0.0;
-  double red[kRedNewton];
-#pragma unroll
-  for (int k = 0; k < kRedNewton; ++k) red[k] = 0.0;
-  const double* kap = lk + cb * K.R;
-  const double gamma = C->gamma;
-  const int maxcor = C->maxcor;
-  double zp0 = 0.0, cv = 0.0, w = 0.0;
-  if (LS != 2) {
-    spc_predict_row<SEG>(D, C, sh, sb, i, act, row, id, kap, St, zp0, cv, w);
-  } else if (row) {
-    zp0 = K.zp0[id];
-    cv = K.cv[id];
-    w = 1.0 / (D.rtol * fabs(K.z[0][id]) + D.atol);
-  }
-  // M = I - gamma J(z(0)[0]), row i in this lane (identity rows past n)
-  double Mrow[NC];
-  auto assemble = [&]() {
-    __builtin_amdgcn_wave_barrier();
-    sh.ys[threadIdx.x] = zp0;
-    wave_sync_lds();
-    if (act)
-      Spc<SEG>::template jac_row<NC>(nd, kap, St, sh.ys + sb, i, Mrow);
-    else
-#pragma unroll
-      for (int j = 0; j < NC; ++j) Mrow[j] = 0.0;
-#pragma unroll
-    for (int j = 0; j < NC; ++j) Mrow[j] = (i == j ? 1.0 : 0.0) - gamma * Mrow[j];
-    if (!row)
-#pragma unroll
-      for (int j = 0; j < NC; ++j) Mrow[j] = (i == j ? 1.0 : 0.0);
-  };
-  const int nn = act ? n : 0;
-  int pos = i, piv = i, info = 0;
-  // LS 1 state
-  float L[LS == 1 ? NC : 1];
-  int pos32 = i, piv32 = i;
-  bool fp64 = LS == 0;
-  double mnorm = 0.0;
-  // LS 2 state
-  int mode = 0;                           // 2 learned, 3 switching to LU, 4 LU
-  bool factored = false;
-  double dcprev = 0.0;
-  if constexpr (LS == 0) {
-    assemble();
-    info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
-    factored = true;
-  } else if constexpr (LS == 1) {
-    assemble();
-#pragma unroll
-    for (int j = 0; j < NC; ++j) L[j] = (float)Mrow[j];
-    const int inf32 =
-        SpcLU<SEG, float, NC>::factor(L, i, nn, pos32, piv32, sh.prow32 + sb, sh.wl32 + sb);
-    double rs = 0.0;
-#pragma unroll
-    for (int j = 0; j < NC; ++j) rs += fabs(Mrow[j]);
-    mnorm = seg_max<SEG>(rs);
-    if (inf32) {
-      fp64 = true;
-      info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
-    }
-  } else {
-    mode = (act && !C->force_lu) ? 2 : 4;
-    if (mode == 4) {
-      assemble();
-      info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
-      factored = true;
-    }
-  }
-  float Xrow[LS == 2 ? NC : 1];
-  if constexpr (LS == 2) {
-#pragma unroll
-    for (int j = 0; j < NC; ++j)
-      Xrow[j] = K.X[(row ? c * (long)n * n + (long)i * n : 0) + (j < n ? j : 0)];
-#pragma unroll
-    for (int j = 0; j < NC; ++j) Xrow[j] = (mode == 2 && row && j < n) ? Xrow[j] : 0.0f;
-  }
-  if (LS == 1 && fp64 && act && i == 0) wsum[4] = 1.0;   // FP32 factor singular at setup
-  double y = zp0;
-  for (int m = 0; m < maxcor; ++m) {
-    __builtin_amdgcn_wave_barrier();
-    sh.ys[threadIdx.x] = y;
-    wave_sync_lds();
-    double f = 0.0;
-    if (act) Spc<SEG>::rhs_row(nd, kap, St, sh.ys + sb, i, f);
-    const double r = row ? fma(gamma, f, cv - y) : 0.0;
-    double del = 0.0;
-    int sweeps = 0, fb = 0;
-    double lp_solves = 0.0, lp_fb = 0.0;
-    if constexpr (LS == 0) {
-      del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
-    } else if constexpr (LS == 1) {
-      bool ok = false;
-      if (!fp64) {
-        double x = (double)SpcLU<SEG, float, NC>::solve(L, i, seg_base, nn, pos32, sh.wl32 + sb,
-                                                    (float)r);
-        const double eps64 = 2.220446049250313e-16;
-        double dprv = 0.0;
-        for (int it = 0; it <= K.refine_max_it; ++it) {
-          double res = r;
-#pragma unroll
-          for (int j = 0; j < NC; ++j) res = fma(-Mrow[j], __shfl(x, seg_base + j, 64), res);
-          const double rn = seg_max<SEG>(fabs(res));
-          const double xn = seg_max<SEG>(fabs(x));
-          if (!(rn == rn) || !(xn == xn)) break;
-          if (rn <= sqrt((double)n) * eps64 * mnorm * xn) {
-            ok = true;
-            break;
-          }
-          if (it == K.refine_max_it) break;
-          const double d = (double)SpcLU<SEG, float, NC>::solve(L, i, seg_base, nn, pos32,
-                                                            sh.wl32 + sb, (float)res);
-          x += d;
-          const double dn = seg_max<SEG>(fabs(d));
-          sweeps = it + 1;
-          if (it >= 1 && dn > 0.5 * dprv) break;
-          dprv = dn;
-        }
-        del = x;
-        if (!ok) {
-          fb = 1;
-          fp64 = true;
-          info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
-        }
-      }
-      if (!ok) del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
-    } else {
-      if (mode == 2) {
-        // correction = X r with row i of the cell's approximate inverse
-        double sx = 0.0;
-#pragma unroll
-        for (int j = 0; j < NC; ++j) sx = fma((double)Xrow[j], __shfl(r, seg_base + j, 64), sx);
-        del = row ? sx : 0.0;
-        const double bad = seg_max<SEG>(row && !(fabs(del) <= 1.79e308) ? 1.0 : 0.0);
-        lp_solves = act ? 1.0 : 0.0;
-        if (bad > 0.0) mode = 3;
-      }
-      if (mode != 2) {
-        if (!factored) {
-          assemble();
-          info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
-          factored = true;
-        }
-        del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
-        if (mode == 3) {
-          lp_fb = 1.0;
-          mode = 4;
-        }
-      }
-      const double dc = sqrt(seg_sum<SEG>(row ? (del * w) * (del * w) : 0.0) / (double)n);
-      if (mode == 2 && m >= 1 && dc > 0.9 * dcprev) mode = 3;
-      dcprev = dc;
-    }
-    double sd = 0.0, sa = 0.0, neg = 0.0;
-    if (row) {
-      y += del;
-      K.ys[m][id] = y;
-      const bool ng = D.nonneg && y < 0.0;
-      const double a = del * w, b = ((ng ? 0.0 : y) - zp0) * w;
-      sd = a * a;
-      sa = b * b;
-      neg = ng ? 1.0 : 0.0;
-    }
-    const bool lead = act && i == 0;
-    if constexpr (kLdsSums) {
-      double* ws = wsum + kRedPerIter * m;
-      wave_add(sd, ws + 0);
-      wave_add(sa, ws + 1);
-      wave_add(neg, ws + 2);
-      if constexpr (LS == 1) {
-        wave_add(lead ? (double)sweeps : 0.0, ws + 3);
-        wave_add(lead ? (double)fb : 0.0, ws + 4);
-      }
-      if constexpr (LS == 2) {
-        wave_add(lead ? lp_solves : 0.0, ws + 5);
-        wave_add(lead ? lp_fb : 0.0, ws + 6);
-      }
-    } else {
-#pragma unroll
-      for (int mm = 0; mm < kMaxCor; ++mm) {
-        const bool hit = (mm == m);
-        red[kRedPerIter * mm + 0] += hit ? sd : 0.0;
-        red[kRedPerIter * mm + 1] += hit ? sa : 0.0;
-        red[kRedPerIter * mm + 2] += hit ? neg : 0.0;
-      }
-    }
-  }
-  if constexpr (kLdsSums) {
-#pragma unroll
-    for (int k = 0; k < kRedNewton; ++k) red[k] = lane == 0 ? wsum[k] : 0.0;
-  }
-  // a singular FP64 factorisation fails the attempt (LS 1: only the FP64
-  // fallback can be singular; the FP32 factor then falls back)
-  red[7] = (act && i == 0 && info) ? 1.0 : 0.0;
-  block_partials<kRedNewton>(D, (unsigned int)(K.blk0 + blk), red, sh.red);
-}
-
-template <int SEG, int LS, int NC = SEG>
-__global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
-  extern __shared__ double lds[];
-  if (D.C->phase != PH_PREDICT) return;
-  spc_newton_body<SEG, LS, NC>(D, blockIdx.x, lds);
-}
-
-// The same kernel asked to fit W waves per SIMD (512 / W registers), for
-// instantiations that need only a few registers more than that, or whose
-// excess belongs to a rarely taken path (the FP64 fallback of the
-// FP32-refined solver), around which the compiler places the spills.
-template <int SEG, int LS, int NC, int W>
-__global__ void __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(W)))
-k_spc_newton_w(BdfDev D) {
-  extern __shared__ double lds[];
-  if (D.C->phase != PH_PREDICT) return;
-  spc_newton_body<SEG, LS, NC>(D, blockIdx.x, lds);
-}
-
-__host__ __device__ inline size_t spc_accept_lds() {
-  return sizeof(double) * (size_t)(kCellThreads / 64) * kRedVals;
-}
-
-template <int SEG>
-__device__ __forceinline__ void spc_accept_body(const BdfDev& D, long blk, double* lds) {
-  double* s_red = lds;
-  Ctrl* C = D.C;
-  const ClassDev& K = D.k;
-  const int n = K.n;
-  const int i = threadIdx.x & (SEG - 1);
-  const long c = blk * Spc<SEG>::CPB + threadIdx.x / SEG;
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (c < K.ncells && i < n) {
-    const long id = c * n + i;
-    const int q = C->q;
-    const double l0 = C->l[0];
-    const bool select = C->qwait == 1;
-    const bool raise = select && q < C->qmax;
-    const bool keep = C->qwait == 2;
-    double zs[kQmaxAll + 1];
-    spc_load_hist(K, C, id, true, q, zs);
-    const double yv = K.ys[C->m][id];
-    const double dp = raise ? K.dprev[id] : 0.0;
-    const double w = 1.0 / (D.rtol * fabs(zs[0]) + D.atol);
-#pragma unroll
-    for (int k = 1; k <= kQmaxAll; ++k)
-#pragma unroll
-      for (int j = kQmaxAll; j >= k; --j)
-        if (k <= q && j <= q) zs[j - 1] = zs[j - 1] + zs[j];
-    const double yp = D.nonneg && yv < 0.0 ? 0.0 : yv;
-    const double acor = (yp - zs[0]) / l0;
-    double znq = yp;
-    K.z[0][id] = yp;   // z(0)[0] + l0 acor is the corrected solution itself
-#pragma unroll
-    for (int j = 1; j <= kQmaxAll; ++j) {
-      if (j <= q) {
-        const double zn = fma(C->l[j], acor, zs[j]);
-        K.z[j][id] = zn;
-        if (j == q) znq = zn;
-      }
-    }
-    if (raise) {
-      K.z[q + 1][id] = C->craise * acor;
-      const double b = (acor - dp) * w;
-      red[1] = b * b;
-    }
-    if (keep) K.dprev[id] = acor;
-    const double a = znq * w;
-    red[0] = a * a;
-  }
-  block_partials<kRedVals>(D, (unsigned int)(K.blk0 + blk), red, s_red);
-}
-
-template <int SEG>
-__global__ void __launch_bounds__(kCellThreads) k_spc_accept(BdfDev D) {
-  extern __shared__ double lds[];
-  if (D.C->phase != PH_ACCEPT) return;
-  spc_accept_body<SEG>(D, blockIdx.x, lds);
-}
-
-// Starting step, part 1 (f(y0) into z[1], norms of y0 and f0) and part 2
-// (norm of f(y0 + h0 f0) - f0).
-template <int SEG, int PART>
-__device__ __forceinline__ void spc_init_body(const BdfDev& D, long blk, double* lds) {
-  Ctrl* C = D.C;
-  const ClassDev& K = D.k;
-  const int n = K.n;
-  const int i = threadIdx.x & (SEG - 1);
-  const int sb = threadIdx.x & ~(SEG - 1);
-  const int cb = threadIdx.x / SEG;
-  const long c = blk * Spc<SEG>::CPB + cb;
-  const bool act = c < K.ncells;
-  const bool row = act && i < n;
-  const long id = c * n + i;
-  SpcShared* shp;
-  double* lk;
-  float* St;
-  spc_stage<SEG>(K, blk, lds, shp, lk, St);
-  SpcShared& sh = *shp;
-  const double* kap = lk + cb * K.R;
-  const double y0 = row ? K.z[0][id] : 0.0;
-  const double f0 = (PART == 2 && row) ? K.z[1][id] : 0.0;
-  sh.ys[threadIdx.x] = PART == 1 ? y0 : y0 + C->hnw_h0 * f0;
-  __syncthreads();
-  double f = 0.0;
-  if (act) Spc<SEG>::rhs_row(K.net, kap, St, sh.ys + sb, i, f);
-  double red[kRedVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (row) {
-    const double w = 1.0 / (D.rtol * fabs(y0) + D.atol);
-    if (PART == 1) {
-      K.z[1][id] = f;
-      red[0] = (y0 * w) * (y0 * w);
-      red[1] = (f * w) * (f * w);
-    } else {
-      const double d = (f - f0) * w;
-      red[0] = d * d;
-    }
-  }
-  block_partials<kRedVals>(D, (unsigned int)(K.blk0 + blk), red, sh.red);
-}
-
-template <int SEG>
-__global__ void __launch_bounds__(kCellThreads) k_spc_init1(BdfDev D) {
-  extern __shared__ double lds[];
-  if (D.C->phase != PH_INIT1) return;
-  spc_init_body<SEG, 1>(D, blockIdx.x, lds);
-}
-
-template <int SEG>
-__global__ void __launch_bounds__(kCellThreads) k_spc_init2(BdfDev D) {
-  extern __shared__ double lds[];
-  if (D.C->phase != PH_INIT2) return;
-  spc_init_body<SEG, 2>(D, blockIdx.x, lds);
-}
-
 }  // namespace bdfgpu

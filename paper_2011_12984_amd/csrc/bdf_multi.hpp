@@ -1,7 +1,7 @@
 // Descriptor of a single launch over every class of cells.
 #pragma once
 
-#include "bdf_dev.hpp"
+#include "bdf_spc_dev.hpp"
 
 namespace bdfgpu {
 

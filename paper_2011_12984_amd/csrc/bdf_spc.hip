@@ -1,7 +1,7 @@
 // Segment-per-cell instantiations of the BDF step kernels (blocks of 13 to
 // 64 species in segments of 16, 32 or 64 lanes; the Newton kernel also by
 // the row width each lane holds).
-#include "bdf_dev.hpp"
+#include "bdf_spc_dev.hpp"
 
 namespace bdfgpu {
 

@@ -208,6 +208,57 @@ def test_learned_identity_network_falls_back_to_lu(orc):
         assert np.sqrt(np.mean(((b.y() - ref) * w) ** 2)) <= 10.0
 
 
+def test_learned_underestimating_inverse_keeps_every_cell_accurate(orc):
+    """X = 0.2 I underestimates M^{-1} for the non-stiff species: its
+    corrections are small, so the grouped Newton test alone could accept
+    an attempt after one iteration with cells far from the Newton solution.
+    The guard (no acceptance at the first iteration; a cell that does not
+    contract by 0.9 moves to LU and blocks acceptance at that iteration)
+    keeps every cell within 3x (+1 WRMS) of the LU run's error against a
+    tight-tolerance run."""
+    n = 6
+    p = W.random_network_batch(16, n=n, seed=13, shared_rates=True, t_end=1e-3)
+    hid = 16
+    nin, nout = n + 1, n * n
+    z = np.zeros
+    b3 = z(nout)
+    b3[:: n + 1] = 0.2 - 1.0            # X = I + diag(b3) = 0.2 I
+    mlp = orc.MLP(z((hid, nin)), z(hid), z((hid, hid)), z(hid), z((nout, hid)), b3,
+                  z(nin), np.ones(nin))
+    bl = orc.Bdf(p, linsol=orc.LS_LEARNED, mlp=mlp, nonneg=False)
+    b64 = orc.Bdf(p, nonneg=False)
+    bref = orc.Bdf(p, rtol=p.rtol * 1e-3, atol=p.atol * 1e-3, nonneg=False)
+    for b in (bl, b64, bref):
+        assert b.integrate(p.t_end) == 0
+    st = bl.stats()
+    assert st["lp_unconverged"] > st["nattempts"] // 2
+    ref = bref.y()
+    w = 1.0 / (p.rtol * np.abs(ref) + p.atol)
+    cell = lambda y: np.sqrt(np.mean((((y - ref) * w) ** 2).reshape(-1, n), 1))
+    el, e64 = cell(bl.y()), cell(b64.y())
+    print(f"per-cell error vs tight run: learned max {el.max():.3e} median {np.median(el):.3e}; "
+          f"LU max {e64.max():.3e}; {st['lp_unconverged']} unconverged-cell events, "
+          f"{st['lp_fallback_cells']} LU switches, {st['lp_step_fallbacks']} LU retries")
+    assert el.max() <= 3.0 * e64.max() + 1.0
+    # one step from the same state: every cell's accepted value is the
+    # Newton solution the LU step reaches, to a fraction of the tolerance
+    b64 = orc.Bdf(p, nonneg=False)
+    for _ in range(25):
+        assert b64.step(p.t_end) == 0
+    sc = b64.scalars()
+    z6, dprev = b64.history()
+    bl = orc.Bdf(p, linsol=orc.LS_LEARNED, mlp=mlp, nonneg=False)
+    for b in (b64, bl):
+        b.set_history(z6, dprev)
+        b.set_scalars(sc)
+        assert b.step(p.t_end) == 0
+    assert bl.scalars()["t"] == b64.scalars()["t"]
+    w = 1.0 / (p.rtol * np.abs(z6[0]) + p.atol)
+    dc = np.sqrt(np.mean((((bl.y() - b64.y()) * w) ** 2).reshape(-1, n), 1))
+    print(f"one step: per-cell difference learned vs LU max {dc.max():.3e}")
+    assert dc.max() <= 0.5
+
+
 def test_tstop_and_max_steps(orc):
     p = W.robertson_batch(4)
     b = orc.Bdf(p, max_steps=5)
