@@ -207,5 +207,24 @@ def test_training_reduces_loss_and_helps_newton(dev, G):
           f"steps {st['nsteps']}, iters {st['nniters']}; untrained: fallback {frac(su):.3f}, "
           f"step retries {su['lp_step_fallbacks']}, steps {su['nsteps']}, iters {su['nniters']}")
     assert st["lp_cell_solves"] > 0 and frac(st) < 0.5
+    # the trained network's run, cell by cell, against a tight-tolerance
+    # FP64 run: no worse than 3x (+1 WRMS) the FP64 LU run's own per-cell
+    # error (two valid runs differ by their global errors, which for some
+    # cells of this network reach tens of WRMS units)
+    q = W.learned_batch(4096, t_end=0.1)
+    ys = {}
+    for name, kw in (("learned", dict(linsol=G.LS_LEARNED, precond=pc)), ("lu", {}),
+                     ("tight", dict(rtol=q.rtol * 1e-3, atol=q.atol * 1e-3))):
+        b = G.Bdf.from_problem(q, device=dev, **kw)
+        assert b.integrate(0.1) == 0.1
+        ys[name] = b.y().cpu().numpy()
+        b.close()
+    w = 1.0 / (q.rtol * np.abs(ys["tight"]) + q.atol)
+    cell = lambda y: np.sqrt(np.mean((((y - ys["tight"]) * w) ** 2).reshape(-1, N21), 1))
+    el, eu = cell(ys["learned"]), cell(ys["lu"])
+    print(f"per-cell error vs tight run: learned median {np.median(el):.3e} max {el.max():.3e}; "
+          f"LU median {np.median(eu):.3e} max {eu.max():.3e}")
+    assert el.max() <= 3.0 * eu.max() + 1.0
+    assert np.median(el) <= 3.0 * np.median(eu) + 0.1
     pc.close()
     pu.close()
