@@ -62,3 +62,14 @@ def test_krylov_at_scale_is_as_accurate(dev, G):
           f"{sg['nliters']} Krylov iterations")
     assert err["gmres"] <= 3.0 * err["lu"] + 0.1
     assert sg["nsetups"] < sg["nattempts"]
+
+
+@pytest.mark.parametrize("lazy", [False, True])
+def test_krylov_padded_sizes_and_classes(orc, dev, G, lazy):
+    """Three thread-per-cell classes (4, 8 and 12 species) in one Krylov
+    space, and a padded size (5 species in the 6-wide kernels)."""
+    for p in (W.uneven_batch(3000, seed=9, classes=(4, 8, 12), t_end=0.05),
+              W.random_network_batch(300, n=5, seed=3, t_end=0.2)):
+        compare_trajectory(orc, dev, G, p, linsol=G.LS_GMRES, okw=dict(lazy=lazy),
+                           bar_per_step=END_BAR_PER_STEP_LAZY if lazy else END_BAR_PER_STEP,
+                           lazy=lazy)

@@ -107,3 +107,13 @@ def test_lazy_reduces_setups_at_scale(dev, G):
           f"{sb['nstale_retries']} retries, error {err['vc_lazy']:.3e}")
     assert sb["nsetups"] * 5 <= sb["nattempts"]
     assert err["vc_lazy"] <= 3.0 * err["eager"]
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_padded_sizes_and_classes(orc, dev, G, form):
+    """Three thread-per-cell classes (4, 8 and 12 species) and a padded size
+    (5 species in the 6-wide kernels), with the generated kernels."""
+    kw = FORMS[form]
+    for p in (W.uneven_batch(3000, seed=9, classes=(4, 8, 12), t_end=0.05),
+              W.random_network_batch(300, n=5, seed=3, t_end=0.2)):
+        compare_trajectory(orc, dev, G, p, okw=kw, bar_per_step=bar(kw), jit=True, **kw)
