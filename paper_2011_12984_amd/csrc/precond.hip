@@ -387,14 +387,24 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_mfma(long B, int n, const doubl
     for (int t = 0; t < 8; ++t)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
+    // weight fragments of the next k step are loaded while this step's
+    // MFMAs run (each wave streams the weights from L2; without the overlap
+    // every MFMA waited for its own load)
+    const unsigned short* Wl = W + (long)row * K + 8 * kh;
+    bf16x8 bcur[8], bnext[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) bcur[t] = *reinterpret_cast<const bf16x8*>(&Wl[(long)t * 32 * K]);
     for (int k0 = 0; k0 < K; k0 += 16) {
       const bf16x8 a = *reinterpret_cast<const bf16x8*>(&A[row * kMlpRowPad + k0 + 8 * kh]);
+      const int kn = k0 + 16 < K ? k0 + 16 : k0;   // (the last step reloads its own)
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const bf16x8 bv =
-            *reinterpret_cast<const bf16x8*>(&W[(long)(t * 32 + row) * K + k0 + 8 * kh]);
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[t], 0, 0, 0);
-      }
+      for (int t = 0; t < 8; ++t)
+        bnext[t] = *reinterpret_cast<const bf16x8*>(&Wl[(long)t * 32 * K + kn]);
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bcur[t], acc[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) bcur[t] = bnext[t];
     }
     __syncthreads();   // every lane finished reading this layer's input
 #pragma unroll
@@ -410,24 +420,30 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_mfma(long B, int n, const doubl
     }
     __syncthreads();
   }
-  // ---- layer 3 (K = 256, nout_pad / 32 tiles, two at a time)
+  // ---- layer 3 (K = 256, nout_pad / 32 tiles, two at a time; the next
+  // k step's weight fragments load during this step's MFMAs)
   for (int t0 = 0; t0 < nout_pad / 32; t0 += 2) {
     f32x16 acc[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[u][v] = 0.f;
+    // a second tile past nout_pad reads the first tile's rows (in bounds);
+    // its MFMAs are skipped
+    const bool two = (t0 + 1) * 32 < nout_pad;
+    const unsigned short* W0 = w3b + (long)(t0 * 32 + row) * kMlpHid + 8 * kh;
+    const unsigned short* W1 = two ? W0 + 32L * kMlpHid : W0;
+    bf16x8 c0 = *reinterpret_cast<const bf16x8*>(W0);
+    bf16x8 c1 = *reinterpret_cast<const bf16x8*>(W1);
     for (int k0 = 0; k0 < kMlpHid; k0 += 16) {
       const bf16x8 a = *reinterpret_cast<const bf16x8*>(&A[row * kMlpRowPad + k0 + 8 * kh]);
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int t = t0 + u;
-        if (t * 32 < nout_pad) {
-          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(
-              &w3b[(long)(t * 32 + row) * kMlpHid + k0 + 8 * kh]);
-          acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[u], 0, 0, 0);
-        }
-      }
+      const int kn = k0 + 16 < kMlpHid ? k0 + 16 : k0;
+      const bf16x8 n0 = *reinterpret_cast<const bf16x8*>(W0 + kn);
+      const bf16x8 n1 = *reinterpret_cast<const bf16x8*>(W1 + kn);
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, c0, acc[0], 0, 0, 0);
+      if (two) acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, c1, acc[1], 0, 0, 0);
+      c0 = n0;
+      c1 = n1;
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
