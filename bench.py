@@ -213,14 +213,16 @@ def accuracy_vs_fp64(G, W, torch, dev, make, t_end, **kw):
             "steps": [int(s["nsteps"]), int(sr["nsteps"])]}
 
 
-def uneven_leg(G, W, torch, dev, warmup, steps, jit=True):
-    """Blocks of 4..64 species (2^22 unknowns), FP32 LU + refinement,
+def uneven_leg(G, W, torch, dev, warmup, steps, jit=True, linsol=None, lazy=False):
+    """Blocks of 4..64 species (2^22 unknowns), FP32 LU + refinement (or
+    another linsol, optionally with the lazy Newton matrix),
     hipGraph-captured attempts, launch mode and small-block mapping chosen
     by the library's autotuner."""
     prob = W.uneven_batch(1 << 22)
     t0 = time.perf_counter()
     b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_GRAPH, attempts_per_sync=16,
-                           linsol=G.LS_LU32REF, launch=G.LAUNCH_AUTO, maxcor=MAXCOR, jit=jit)
+                           linsol=G.LS_LU32REF if linsol is None else linsol,
+                           launch=G.LAUNCH_AUTO, maxcor=MAXCOR, jit=jit, lazy=lazy)
     torch.cuda.synchronize()
     t_tune = time.perf_counter() - t0
     tu = b.tuning()
@@ -237,6 +239,9 @@ def uneven_leg(G, W, torch, dev, warmup, steps, jit=True):
             "candidates_ms_per_step": {names[k]: round(v, 4) for k, v in tu["ms_per_step"].items()},
             "create_and_tune_s": round(t_tune, 2),
             "attempts_per_step": round((s1["nattempts"] - s0["nattempts"]) / max(taken, 1), 4),
+            "setups_per_attempt": round((s1["nsetups"] - s0["nsetups"]) /
+                                        max(s1["nattempts"] - s0["nattempts"], 1), 4),
+            "newton_iters_per_step": round((s1["nniters"] - s0["nniters"]) / max(taken, 1), 4),
             "refine_sweeps": s1["refine_sweeps"] - s0["refine_sweeps"],
             "refine_fallbacks": s1["refine_fallbacks"] - s0["refine_fallbacks"]}
 
@@ -481,6 +486,11 @@ def main():
     ap.add_argument("--profile-uneven", type=int, default=0, metavar="STEPS",
                     help="only advance the uneven batch (per-class launches, FP32-refined LU, "
                          "stream mode) STEPS steps: the workload of the segment-kernel profiles")
+    ap.add_argument("--profile-lazy", action="store_true",
+                    help="with --profile-uneven: FP64 LU with the lazy Newton matrix")
+    ap.add_argument("--only-uneven", action="store_true",
+                    help="only run the uneven-batch legs (FP32-refined, FP64, FP64 lazy) and "
+                         "print their results")
     ap.add_argument("--profile-mlp", action="store_true",
                     help="only run the learned preconditioner's MFMA forward pass on 2^20 random "
                          "inputs (2 warm-up + 5 timed calls): the workload of the MLP profiles")
@@ -511,11 +521,21 @@ def main():
     if args.profile_uneven > 0:
         p = W.uneven_batch(1 << 22)
         b = G.Bdf.from_problem(p, device=dev, mode=G.MODE_STREAM, attempts_per_sync=1,
-                               linsol=G.LS_LU32REF, launch=G.LAUNCH_PER_CLASS, maxcor=MAXCOR,
+                               linsol=G.LS_LU64 if args.profile_lazy else G.LS_LU32REF,
+                               lazy=args.profile_lazy, launch=G.LAUNCH_PER_CLASS, maxcor=MAXCOR,
                                jit=True)
         b.advance(p.t_end, args.profile_uneven)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_uneven": {"steps": b.stats()["nsteps"]}}))
+        s = b.stats()
+        print(json.dumps({"profile_uneven": {"steps": s["nsteps"], "attempts": s["nattempts"],
+                                             "setups": s["nsetups"]}}))
+        return
+    if args.only_uneven:
+        out = uneven_leg(G, W, torch, dev, args.warmup, min(args.steps, 200), jit=not args.no_jit)
+        for name, kw in (("fp64_lu", {}), ("fp64_lu_lazy", {"lazy": True})):
+            out[name] = uneven_leg(G, W, torch, dev, args.warmup, min(args.steps, 200),
+                                   jit=not args.no_jit, linsol=G.LS_LU64, **kw)
+        print(json.dumps({"uneven": out}))
         return
     if args.profile_mlp:
         n, B = 21, 1 << 20
@@ -676,6 +696,11 @@ def main():
     if not args.no_uneven:
         log("uneven batch leg (autotuned launch, hipGraph, FP32-refined LU)")
         uneven = uneven_leg(G, W, torch, dev, args.warmup, min(args.steps, 200), jit=not args.no_jit)
+        # the same batch with FP64 LU, factored every attempt and with the
+        # lazy Newton matrix (factors stored and reused over steps)
+        for name, kw in (("fp64_lu", {}), ("fp64_lu_lazy", {"lazy": True})):
+            uneven[name] = uneven_leg(G, W, torch, dev, args.warmup, min(args.steps, 200),
+                                      jit=not args.no_jit, linsol=G.LS_LU64, **kw)
 
     learned = None
     if not args.no_learned:

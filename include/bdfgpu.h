@@ -314,9 +314,10 @@ typedef struct {
                              2 / (1 + gamma / gamma_s) and carries the
                              convergence-rate estimate over, and a Newton
                              failure on reused factors redoes the attempt with
-                             fresh ones at the same step size.  Needs the
-                             deferred history update, FP64 LU or Gauss-Jordan,
-                             and not per_cell. */
+                             fresh ones at the same step size.  Any class
+                             size; needs FP64 LU, Gauss-Jordan or GMRES,
+                             per-class launches (not BDFGPU_LAUNCH_FUSED) and
+                             not per_cell. */
 } bdf_options;
 
 typedef struct {

@@ -686,9 +686,12 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   if (o->linsol == BDFGPU_LS_GJ && (o->launch != BDFGPU_LAUNCH_PER_CLASS || o->map_small))
     return arg_error("bdf_create: the Gauss-Jordan solve needs per-class launches and one lane "
                      "per cell");
-  if ((o->vc || o->lazy) && (o->per_cell || o->no_defer))
-    return arg_error("bdf_create: variable coefficients and the lazy Newton matrix need the "
-                     "deferred history update and grouped stepping");
+  if (o->vc && (o->per_cell || o->no_defer))
+    return arg_error("bdf_create: variable coefficients need the deferred history update and "
+                     "grouped stepping");
+  if (o->lazy && (o->per_cell || o->launch == BDFGPU_LAUNCH_FUSED))
+    return arg_error("bdf_create: the lazy Newton matrix needs grouped stepping and per-class "
+                     "launches");
   if (o->lazy && o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_GJ &&
       o->linsol != BDFGPU_LS_GMRES)
     return arg_error("bdf_create: the lazy Newton matrix needs FP64 LU, the Gauss-Jordan solve "
@@ -913,11 +916,12 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
         return st;
       }
     }
-    if ((o->lazy || h->krylov) && tiled) {   // stored factors of M (or its inverse), pivots
-      const size_t np2 = (size_t)ch.np * (size_t)ch.np;
-      if ((st = dalloc(h, (void**)&K.lu, sizeof(double) * std::max<long>(1, cap_cells) * np2)) ||
-          (st = dalloc(h, (void**)&K.lpiv,
-                       sizeof(int) * std::max<long>(1, cap_cells) * (size_t)ch.np))) {
+    if (o->lazy || (h->krylov && tiled)) {   // stored factors of M (or its inverse), pivots
+      // thread per cell: NP x NP tiled like the state; segment per cell:
+      // NC x NC per cell with NC = n rounded up to 8, the kernel's row width
+      const size_t w = tiled ? (size_t)ch.np : (size_t)((n + 7) / 8 * 8);
+      if ((st = dalloc(h, (void**)&K.lu, sizeof(double) * std::max<long>(1, cap_cells) * w * w)) ||
+          (st = dalloc(h, (void**)&K.lpiv, sizeof(int) * std::max<long>(1, cap_cells) * w))) {
         bdf_destroy(h);
         return st;
       }
@@ -1016,11 +1020,11 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
       return st;
     }
   }
-  if ((o->vc || o->lazy) && !h->defer && !h->krylov) {
+  if (o->vc && !h->defer && !h->krylov) {
     bdf_destroy(h);
-    return arg_error("bdf_create: variable coefficients and the lazy Newton matrix need the "
-                     "deferred history update: one lane per cell for every class (<= 12 "
-                     "species), per-class launches, no learned preconditioner");
+    return arg_error("bdf_create: variable coefficients need the deferred history update: one "
+                     "lane per cell for every class (<= 12 species), per-class launches, no "
+                     "learned preconditioner");
   }
   const long bmax = std::max(blk, mblk);
   const long ngroups = std::max<long>(1, (bmax + kRedGroup - 1) / kRedGroup);

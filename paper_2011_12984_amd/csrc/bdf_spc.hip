@@ -1,6 +1,7 @@
 // Segment-per-cell instantiations of the BDF step kernels (blocks of 13 to
 // 64 species in segments of 16, 32 or 64 lanes; the Newton kernel also by
-// the row width each lane holds).
+// the row width each lane holds, and with FP64 LU also with stored factors
+// for the lazy Newton matrix).
 #include "bdf_spc_dev.hpp"
 
 namespace bdfgpu {
@@ -34,6 +35,14 @@ template <int SEG, int LS, int NC>
 static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
   static size_t raised = 65536;
   constexpr int w = newton_waves<SEG, LS, NC>();
+  if constexpr (LS == 0) {
+    if (D.lazy) {   // stored factors (lazy Newton matrix)
+      static size_t raised_lz = 65536;
+      raise_lds(&k_spc_newton<SEG, 0, NC, true>, lds, raised_lz);
+      hipLaunchKernelGGL((k_spc_newton<SEG, 0, NC, true>), g, b, lds, s, D);
+      return;
+    }
+  }
   if constexpr (w > 0) {
     raise_lds(&k_spc_newton_w<SEG, LS, NC, w>, lds, raised);
     hipLaunchKernelGGL((k_spc_newton_w<SEG, LS, NC, w>), g, b, lds, s, D);

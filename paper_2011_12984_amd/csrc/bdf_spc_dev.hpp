@@ -205,6 +205,36 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_predict(BdfDev D) {
   spc_predict_body<SEG>(D, blockIdx.x, lds);
 }
 
+// Lazy Newton matrix on segment classes: the FP64 factors of cell c, lane i
+// holding row i of L\U in column order and its position in the permuted
+// matrix, at K.lu[c NC^2 + j NC + i] (column j of the lane-held rows
+// contiguous, so each column is one coalesced access per segment) and
+// K.lpiv[c NC + i].  Only the lanes holding rows (i < NC) store or load.
+template <int SEG, int NC>
+__device__ __forceinline__ void spc_store_factors(const ClassDev& K, long c, int i, bool act,
+                                                  const double (&Mrow)[NC], int pos) {
+  if (!act || i >= NC) return;
+  double* base = K.lu + c * (long)(NC * NC) + i;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) base[j * NC] = Mrow[j];
+  K.lpiv[c * NC + i] = pos;
+}
+
+// Reload what spc_store_factors stored and rebuild the position -> lane map
+// wl of the segment; lanes without a row keep the identity row (zeros).
+template <int SEG, int NC>
+__device__ __forceinline__ void spc_load_factors(const ClassDev& K, long c, int i, bool act,
+                                                 double (&Mrow)[NC], int& pos, int* wl) {
+  const bool has = act && i < NC;
+  const double* base = K.lu + (has ? c * (long)(NC * NC) + i : 0);
+#pragma unroll
+  for (int j = 0; j < NC; ++j) Mrow[j] = has ? base[j * NC] : (i == j ? 1.0 : 0.0);
+  pos = has ? K.lpiv[c * NC + i] : i;
+  __builtin_amdgcn_wave_barrier();
+  if (has) wl[pos] = i;
+  wave_sync_lds();
+}
+
 // Fused Newton iterations, segment per cell.  LS 0: FP64 LU factored once.
 // LS 1: FP32 LU factored once, each solve refined with FP64 residuals from
 // the FP64 rows; a cell whose refinement fails factors its FP64 rows in
@@ -214,8 +244,11 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_predict(BdfDev D) {
 // is not finite, or from the second iteration on when its correction norm
 // does not fall below 0.9 times the previous one.
 // NC: columns held per lane (n rounded up to a multiple of 8, at most SEG).
-template <int SEG, int LS, int NC = SEG>
+// LZ (LS 0 only): lazy Newton matrix, the factors stored at a setup attempt
+// and reloaded at the others, each correction then scaled by C->dscale.
+template <int SEG, int LS, int NC = SEG, bool LZ = false>
 __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, double* lds) {
+  static_assert(!LZ || LS == 0, "stored factors: FP64 LU");
   Ctrl* C = D.C;
   const ClassDev& K = D.k;
   const NetDev& nd = K.net;
@@ -284,9 +317,15 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   int mode = 0;                           // 2 learned, 3 switching to LU, 4 LU
   bool factored = false;
   double dcprev = 0.0;
+  const bool reuse = LZ && !C->setup;   // uniform over the grid
   if constexpr (LS == 0) {
-    assemble();
-    info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+    if (reuse) {
+      spc_load_factors<SEG, NC>(K, c, i, act, Mrow, pos, sh.wl + sb);
+    } else {
+      assemble();
+      info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+      if constexpr (LZ) spc_store_factors<SEG, NC>(K, c, i, act, Mrow, pos);
+    }
     factored = true;
   } else if constexpr (LS == 1) {
     assemble();
@@ -332,6 +371,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
     double lp_solves = 0.0, lp_fb = 0.0, lp_unconv = 0.0;
     if constexpr (LS == 0) {
       del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
+      if (reuse) del *= C->dscale;
     } else if constexpr (LS == 1) {
       bool ok = false;
       if (!fp64) {
@@ -445,11 +485,11 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   block_partials<kRedNewton>(D, (unsigned int)(K.blk0 + blk), red, sh.red);
 }
 
-template <int SEG, int LS, int NC = SEG>
+template <int SEG, int LS, int NC = SEG, bool LZ = false>
 __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
   extern __shared__ double lds[];
   if (D.C->phase != PH_PREDICT) return;
-  spc_newton_body<SEG, LS, NC>(D, blockIdx.x, lds);
+  spc_newton_body<SEG, LS, NC, LZ>(D, blockIdx.x, lds);
 }
 
 // The same kernel asked to fit W waves per SIMD (512 / W registers), for

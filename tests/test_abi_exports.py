@@ -85,12 +85,14 @@ def test_gauss_jordan_and_order3_option_checks():
 
 
 def test_variable_coefficient_and_lazy_option_checks():
-    """vc and lazy need the deferred history update (thread-per-cell
-    classes, per-class launches, grouped stepping); lazy needs FP64 LU or
-    the Gauss-Jordan solve; the stored factors are counted in the
-    workspace."""
+    """vc needs the deferred history update (thread-per-cell classes,
+    per-class launches, grouped stepping); lazy takes any class size with
+    per-class launches and grouped stepping, and needs FP64 LU or the
+    Gauss-Jordan solve; the stored factors are counted in the workspace
+    (segment classes: n rounded up to 8, squared, per cell)."""
+    import numpy as np
     import workloads as W
-    from paper_2011_12984_amd import LS_GJ, LS_LU32REF, Bdf
+    from paper_2011_12984_amd import LAUNCH_FUSED, LS_GJ, LS_LU32REF, Bdf
     net = W.random_network_batch(1000, n=10, seed=1)
     base = Bdf.workspace_bytes(net)
     lazy = Bdf.workspace_bytes(net, lazy=True)
@@ -102,7 +104,14 @@ def test_variable_coefficient_and_lazy_option_checks():
     assert Bdf.workspace_bytes(W.brusselator_batch(100), lazy=True, linsol=LS_GJ) > 0
     assert Bdf.workspace_bytes(net, vc=True, defer=False) == 0
     assert Bdf.workspace_bytes(net, lazy=True, per_cell=True) == 0
-    assert Bdf.workspace_bytes(W.uneven_batch(1 << 12, seed=9), vc=True) == 0
+    assert Bdf.workspace_bytes(net, lazy=True, launch=LAUNCH_FUSED) == 0
+    assert Bdf.workspace_bytes(net, lazy=True, defer=False) > 0
+    un = W.uneven_batch(1 << 12, seed=9)
+    assert Bdf.workspace_bytes(un, vc=True) == 0
+    sizes = np.array([un.topologies[t][0].shape[1] for t in un.cell_topo])
+    spc = sum(((n + 7) // 8 * 8) ** 2 * 8 + ((n + 7) // 8 * 8) * 4 for n in sizes if n > 12)
+    assert Bdf.workspace_bytes(un, lazy=True) - Bdf.workspace_bytes(un) >= spc
+    assert Bdf.workspace_bytes(un, lazy=True, launch=LAUNCH_FUSED) == 0
 
 
 def test_gmres_option_checks():

@@ -117,3 +117,30 @@ def test_padded_sizes_and_classes(orc, dev, G, form):
     for p in (W.uneven_batch(3000, seed=9, classes=(4, 8, 12), t_end=0.05),
               W.random_network_batch(300, n=5, seed=3, t_end=0.2)):
         compare_trajectory(orc, dev, G, p, okw=kw, bar_per_step=bar(kw), jit=True, **kw)
+
+
+@pytest.mark.parametrize("map_small", [False, True])
+def test_lazy_uneven_segment_classes(orc, dev, G, map_small):
+    """The lazy Newton matrix on the uneven batch (4..64 species): the
+    segment-per-cell classes (16..64 species; with map_small every class)
+    store their FP64 factors, one row per lane, and reload them, while the
+    thread-per-cell classes do so in their tiled layout, all with the
+    separate history update; lockstep against the oracle with the same
+    option, setups and retries compared step by step."""
+    kw = dict(lazy=True)
+    ob, gb = compare_trajectory(orc, dev, G, W.uneven_batch(1 << 12, seed=9), okw=kw,
+                                bar_per_step=END_BAR_PER_STEP_LAZY, map_small=map_small, **kw)
+    s = gb.stats()
+    print({k: s[k] for k in ("nsteps", "nattempts", "nsetups", "nstale_retries")})
+    assert s["nsetups"] * 3 < s["nattempts"]
+
+
+@pytest.mark.parametrize("classes,total", [((14, 42), 2800), ((20, 40, 60), 3000)])
+def test_lazy_segment_padded_rows(orc, dev, G, classes, total):
+    """Segment classes whose species count is not the row width: 14, 20,
+    42 and 60 species in rows of 16, 24, 48 and 64 columns (identity rows
+    and columns past n are stored and reloaded with the factors)."""
+    kw = dict(lazy=True)
+    p = W.uneven_batch(total, seed=23, classes=classes, t_end=0.05)
+    compare_trajectory(orc, dev, G, p, okw=kw, bar_per_step=END_BAR_PER_STEP_LAZY, **kw)
+
