@@ -246,6 +246,16 @@ def uneven_leg(G, W, torch, dev, warmup, steps, jit=True, linsol=None, lazy=Fals
             "refine_fallbacks": s1["refine_fallbacks"] - s0["refine_fallbacks"]}
 
 
+def uneven_variants(G):
+    """The uneven batch with other block solves: FP64 LU and the
+    Gauss-Jordan inverse, each factored every attempt and with the lazy
+    Newton matrix (factors or inverse stored and reused over steps)."""
+    return (("fp64_lu", {"linsol": G.LS_LU64}),
+            ("fp64_lu_lazy", {"linsol": G.LS_LU64, "lazy": True}),
+            ("gauss_jordan", {"linsol": G.LS_GJ}),
+            ("gauss_jordan_lazy", {"linsol": G.LS_GJ, "lazy": True}))
+
+
 def learned_leg(G, W, torch, dev, cells, warmup, steps, epochs, nblocks):
     """cfg: 2^20 cells x 21 species (one network and rate vector, cells differ
     in their state); MLP trained on `nblocks` blocks captured from the plain
@@ -487,7 +497,10 @@ def main():
                     help="only advance the uneven batch (per-class launches, FP32-refined LU, "
                          "stream mode) STEPS steps: the workload of the segment-kernel profiles")
     ap.add_argument("--profile-lazy", action="store_true",
-                    help="with --profile-uneven: FP64 LU with the lazy Newton matrix")
+                    help="with --profile-uneven: the lazy Newton matrix (FP64 LU, or the "
+                         "Gauss-Jordan inverse with --profile-gj)")
+    ap.add_argument("--profile-gj", action="store_true",
+                    help="with --profile-uneven: the Gauss-Jordan inverse")
     ap.add_argument("--only-uneven", action="store_true",
                     help="only run the uneven-batch legs (FP32-refined, FP64, FP64 lazy) and "
                          "print their results")
@@ -521,7 +534,8 @@ def main():
     if args.profile_uneven > 0:
         p = W.uneven_batch(1 << 22)
         b = G.Bdf.from_problem(p, device=dev, mode=G.MODE_STREAM, attempts_per_sync=1,
-                               linsol=G.LS_LU64 if args.profile_lazy else G.LS_LU32REF,
+                               linsol=(G.LS_GJ if args.profile_gj else
+                                       G.LS_LU64 if args.profile_lazy else G.LS_LU32REF),
                                lazy=args.profile_lazy, launch=G.LAUNCH_PER_CLASS, maxcor=MAXCOR,
                                jit=True)
         b.advance(p.t_end, args.profile_uneven)
@@ -532,9 +546,9 @@ def main():
         return
     if args.only_uneven:
         out = uneven_leg(G, W, torch, dev, args.warmup, min(args.steps, 200), jit=not args.no_jit)
-        for name, kw in (("fp64_lu", {}), ("fp64_lu_lazy", {"lazy": True})):
+        for name, kw in uneven_variants(G):
             out[name] = uneven_leg(G, W, torch, dev, args.warmup, min(args.steps, 200),
-                                   jit=not args.no_jit, linsol=G.LS_LU64, **kw)
+                                   jit=not args.no_jit, **kw)
         print(json.dumps({"uneven": out}))
         return
     if args.profile_mlp:
@@ -696,11 +710,9 @@ def main():
     if not args.no_uneven:
         log("uneven batch leg (autotuned launch, hipGraph, FP32-refined LU)")
         uneven = uneven_leg(G, W, torch, dev, args.warmup, min(args.steps, 200), jit=not args.no_jit)
-        # the same batch with FP64 LU, factored every attempt and with the
-        # lazy Newton matrix (factors stored and reused over steps)
-        for name, kw in (("fp64_lu", {}), ("fp64_lu_lazy", {"lazy": True})):
+        for name, kw in uneven_variants(G):
             uneven[name] = uneven_leg(G, W, torch, dev, args.warmup, min(args.steps, 200),
-                                      jit=not args.no_jit, linsol=G.LS_LU64, **kw)
+                                      jit=not args.no_jit, **kw)
 
     learned = None
     if not args.no_learned:

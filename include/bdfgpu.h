@@ -211,7 +211,10 @@ int batched_lu_solve_refine(int nb, int n, const double* M, const float* LU32,
                                 a matrix-vector product in every Newton
                                 iteration: the task-local block solve of the
                                 paper's demonstration problem (Section 7).
-                                Cells of <= 4 species, per-class launches */
+                                Cells of <= 4 species one lane per cell,
+                                larger cells (up to 64 species) one row per
+                                lane of a segment; per-class launches (not
+                                BDFGPU_LAUNCH_FUSED) */
 
 #define BDFGPU_MODE_STREAM 0 /* kernels enqueued on the stream */
 #define BDFGPU_MODE_GRAPH 1  /* one attempt captured in a hipGraph */

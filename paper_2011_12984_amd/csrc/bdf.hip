@@ -683,9 +683,8 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
                       o->launch == BDFGPU_LAUNCH_FUSED || o->map_small))
     return arg_error("bdf_create: per-cell stepping needs FP64 LU or the Gauss-Jordan solve, "
                      "per-class launches and one lane per cell");
-  if (o->linsol == BDFGPU_LS_GJ && (o->launch != BDFGPU_LAUNCH_PER_CLASS || o->map_small))
-    return arg_error("bdf_create: the Gauss-Jordan solve needs per-class launches and one lane "
-                     "per cell");
+  if (o->linsol == BDFGPU_LS_GJ && o->launch == BDFGPU_LAUNCH_FUSED)
+    return arg_error("bdf_create: the Gauss-Jordan solve needs per-class launches");
   if (o->vc && (o->per_cell || o->no_defer))
     return arg_error("bdf_create: variable coefficients need the deferred history update and "
                      "grouped stepping");
@@ -756,18 +755,16 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     ch.ncells = (long)kv.second.size();
     ch.members = kv.second;
     // thread per cell while the rates and evaluation point fit the LDS of a
-    // block, else segment per cell
-    ch.map = (!o->map_small && n <= 12 &&
+    // block (and, with the Gauss-Jordan inverse, for <= 4 species), else
+    // segment per cell
+    ch.map = (!o->map_small && n <= 12 && (o->linsol != BDFGPU_LS_GJ || n <= 4) &&
               tpc_newton_lds(tpc_padded(n), R, o->linsol, kTpcThreads) <= (size_t)lds_max)
                  ? MAP_TPC
                  : MAP_SPC;
     if (o->per_cell && ch.map != MAP_TPC) {
       bdf_destroy(h);
-      return arg_error("bdf_create: per-cell stepping needs cells of <= 12 species");
-    }
-    if (o->linsol == BDFGPU_LS_GJ && (ch.map != MAP_TPC || n > 4)) {
-      bdf_destroy(h);
-      return arg_error("bdf_create: the Gauss-Jordan solve takes cells of <= 4 species");
+      return arg_error("bdf_create: per-cell stepping needs cells of <= 12 species (<= 4 with "
+                       "the Gauss-Jordan solve)");
     }
     if (ch.map == MAP_SPC && spc_lds_bytes(spc_seg(n), R) > (size_t)lds_max) {
       bdf_destroy(h);

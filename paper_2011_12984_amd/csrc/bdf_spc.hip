@@ -1,7 +1,7 @@
 // Segment-per-cell instantiations of the BDF step kernels (blocks of 13 to
 // 64 species in segments of 16, 32 or 64 lanes; the Newton kernel also by
-// the row width each lane holds, and with FP64 LU also with stored factors
-// for the lazy Newton matrix).
+// the row width each lane holds, and with FP64 LU or the Gauss-Jordan
+// inverse also with stored factors for the lazy Newton matrix).
 #include "bdf_spc_dev.hpp"
 
 namespace bdfgpu {
@@ -31,15 +31,31 @@ constexpr int newton_waves() {
   return 0;
 }
 
+// Waves per SIMD asked of the lazy reuse kernel (0: as its registers allow):
+// the 64-column ones and the 32-column inverse sit a few registers above
+// three.
+template <int SEG, int LS, int NC>
+constexpr int reuse_waves() {
+  return ((SEG == 64 && NC == 64) || (SEG == 32 && NC == 32 && LS == 3)) ? 3 : 0;
+}
+
 template <int SEG, int LS, int NC>
 static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
   static size_t raised = 65536;
   constexpr int w = newton_waves<SEG, LS, NC>();
-  if constexpr (LS == 0) {
-    if (D.lazy) {   // stored factors (lazy Newton matrix)
-      static size_t raised_lz = 65536;
-      raise_lds(&k_spc_newton<SEG, 0, NC, true>, lds, raised_lz);
-      hipLaunchKernelGGL((k_spc_newton<SEG, 0, NC, true>), g, b, lds, s, D);
+  if constexpr (LS == 0 || LS == 3) {
+    if (D.lazy) {   // lazy Newton matrix: the setup kernel, then the reuse kernel
+      static size_t raised_s = 65536, raised_r = 65536;
+      raise_lds(&k_spc_newton<SEG, LS, NC, 1>, lds, raised_s);
+      hipLaunchKernelGGL((k_spc_newton<SEG, LS, NC, 1>), g, b, lds, s, D);
+      constexpr int rw = reuse_waves<SEG, LS, NC>();
+      if constexpr (rw > 0) {
+        raise_lds(&k_spc_newton_w<SEG, LS, NC, rw, 2>, lds, raised_r);
+        hipLaunchKernelGGL((k_spc_newton_w<SEG, LS, NC, rw, 2>), g, b, lds, s, D);
+      } else {
+        raise_lds(&k_spc_newton<SEG, LS, NC, 2>, lds, raised_r);
+        hipLaunchKernelGGL((k_spc_newton<SEG, LS, NC, 2>), g, b, lds, s, D);
+      }
       return;
     }
   }
@@ -83,6 +99,8 @@ static void spc_go(int ls, int which, const BdfDev& D, unsigned int grid, hipStr
         newton_nc<SEG, 1>(D, g, b, lds, s);
       else if (ls == 2)
         newton_nc<SEG, 2>(D, g, b, lds, s);
+      else if (ls == 3)
+        newton_nc<SEG, 3>(D, g, b, lds, s);
       else
         newton_nc<SEG, 0>(D, g, b, lds, s);
       break;

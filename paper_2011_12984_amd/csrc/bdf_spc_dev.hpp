@@ -205,8 +205,9 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_predict(BdfDev D) {
   spc_predict_body<SEG>(D, blockIdx.x, lds);
 }
 
-// Lazy Newton matrix on segment classes: the FP64 factors of cell c, lane i
-// holding row i of L\U in column order and its position in the permuted
+// Lazy Newton matrix on segment classes: per cell c, lane i's row as the
+// factorisation left it (row i of L\U for LU; for Gauss-Jordan the inverse
+// row that lane holds) in column order, and its position in the permuted
 // matrix, at K.lu[c NC^2 + j NC + i] (column j of the lane-held rows
 // contiguous, so each column is one coalesced access per segment) and
 // K.lpiv[c NC + i].  Only the lanes holding rows (i < NC) store or load.
@@ -218,6 +219,19 @@ __device__ __forceinline__ void spc_store_factors(const ClassDev& K, long c, int
 #pragma unroll
   for (int j = 0; j < NC; ++j) base[j * NC] = Mrow[j];
   K.lpiv[c * NC + i] = pos;
+}
+
+// Lazy Gauss-Jordan inverse: lane i's row from SpcGJ::invert (the inverse
+// row of unknown pos, columns in position order) stored as the plain
+// inverse, X[pos][wl[j]] at K.lu[c NC^2 + wl[j] NC + pos], so that the reuse
+// kernel loads row i of X in natural order like spc_load_factors.
+template <int SEG, int NC>
+__device__ __forceinline__ void spc_store_inverse(const ClassDev& K, long c, int i, bool act,
+                                                  const double (&S)[NC], int pos, const int* wl) {
+  if (!act || i >= NC) return;
+  double* base = K.lu + c * (long)(NC * NC) + pos;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) base[(long)wl[j] * NC] = S[j];
 }
 
 // Reload what spc_store_factors stored and rebuild the position -> lane map
@@ -236,6 +250,8 @@ __device__ __forceinline__ void spc_load_factors(const ClassDev& K, long c, int 
 }
 
 // Fused Newton iterations, segment per cell.  LS 0: FP64 LU factored once.
+// LS 3: explicit inverse by Gauss-Jordan elimination, applied as a
+// matrix-vector product (no serial substitution chain).
 // LS 1: FP32 LU factored once, each solve refined with FP64 residuals from
 // the FP64 rows; a cell whose refinement fails factors its FP64 rows in
 // place and uses them from then on.  LS 2: correction X r with the cell's
@@ -244,11 +260,15 @@ __device__ __forceinline__ void spc_load_factors(const ClassDev& K, long c, int 
 // is not finite, or from the second iteration on when its correction norm
 // does not fall below 0.9 times the previous one.
 // NC: columns held per lane (n rounded up to a multiple of 8, at most SEG).
-// LZ (LS 0 only): lazy Newton matrix, the factors stored at a setup attempt
-// and reloaded at the others, each correction then scaled by C->dscale.
-template <int SEG, int LS, int NC = SEG, bool LZ = false>
+// LZ (LS 0 and 3), the lazy Newton matrix in two kernels so that the reuse
+// kernel carries no factorisation (and needs far fewer registers): 1 forms,
+// factors (inverts) and stores M (a setup attempt), 2 reloads the stored
+// factors (inverse) and scales each correction by C->dscale; the caller
+// launches the one that C->setup asks for or both (the other returns at
+// once).
+template <int SEG, int LS, int NC = SEG, int LZ = 0>
 __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, double* lds) {
-  static_assert(!LZ || LS == 0, "stored factors: FP64 LU");
+  static_assert(LZ == 0 || LS == 0 || LS == 3, "stored factors: FP64 LU or the inverse");
   Ctrl* C = D.C;
   const ClassDev& K = D.k;
   const NetDev& nd = K.net;
@@ -271,8 +291,9 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   // summed over the wave at once and kept in LDS (the iteration number is
   // not a compile-time index, and per-lane accumulators for every iteration
   // cost registers those kernels need to run two or three waves per SIMD);
-  // the FP64 kernel, which gains no wave from that, keeps per-lane sums.
-  constexpr bool kLdsSums = LS != 0;
+  // so do the lazy kernels, whose reuse kernel gains a wave from it; the
+  // eager FP64 kernel, which gains none, keeps per-lane sums.
+  constexpr bool kLdsSums = LS != 0 || LZ != 0;
   double* wsum = sh.wsum + (threadIdx.x >> 6) * kRedNewton;
   if (kLdsSums && lane < kRedNewton) wsum[lane] = 0.0;
   double red[kRedNewton];
@@ -317,14 +338,26 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   int mode = 0;                           // 2 learned, 3 switching to LU, 4 LU
   bool factored = false;
   double dcprev = 0.0;
-  const bool reuse = LZ && !C->setup;   // uniform over the grid
+  constexpr bool reuse = LZ == 2;
   if constexpr (LS == 0) {
-    if (reuse) {
+    if constexpr (reuse) {
       spc_load_factors<SEG, NC>(K, c, i, act, Mrow, pos, sh.wl + sb);
     } else {
       assemble();
       info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
-      if constexpr (LZ) spc_store_factors<SEG, NC>(K, c, i, act, Mrow, pos);
+      if constexpr (LZ == 1) spc_store_factors<SEG, NC>(K, c, i, act, Mrow, pos);
+    }
+    factored = true;
+  } else if constexpr (LS == 3) {
+    if constexpr (reuse) {   // row i of the stored inverse, natural order
+      const bool has = act && i < NC;
+      const double* base = K.lu + (has ? c * (long)(NC * NC) + i : 0);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) Mrow[j] = has ? base[j * NC] : 0.0;
+    } else {
+      assemble();
+      info = SpcGJ<SEG, NC>::invert(Mrow, i, nn, pos, sh.prow + sb, sh.wl + sb);
+      if constexpr (LZ == 1) spc_store_inverse<SEG, NC>(K, c, i, act, Mrow, pos, sh.wl + sb);
     }
     factored = true;
   } else if constexpr (LS == 1) {
@@ -371,7 +404,12 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
     double lp_solves = 0.0, lp_fb = 0.0, lp_unconv = 0.0;
     if constexpr (LS == 0) {
       del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
-      if (reuse) del *= C->dscale;
+      if constexpr (reuse) del *= C->dscale;
+    } else if constexpr (LS == 3) {
+      if constexpr (reuse)
+        del = C->dscale * SpcGJ<SEG, NC>::apply_natural(Mrow, i, r, seg_base, sh.prow + sb);
+      else
+        del = SpcGJ<SEG, NC>::apply(Mrow, i, pos, r, sh.prow + sb);
     } else if constexpr (LS == 1) {
       bool ok = false;
       if (!fp64) {
@@ -485,10 +523,11 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   block_partials<kRedNewton>(D, (unsigned int)(K.blk0 + blk), red, sh.red);
 }
 
-template <int SEG, int LS, int NC = SEG, bool LZ = false>
+template <int SEG, int LS, int NC = SEG, int LZ = 0>
 __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
   extern __shared__ double lds[];
   if (D.C->phase != PH_PREDICT) return;
+  if (LZ != 0 && (D.C->setup != 0) != (LZ == 1)) return;   // the other lazy kernel's attempt
   spc_newton_body<SEG, LS, NC, LZ>(D, blockIdx.x, lds);
 }
 
@@ -496,12 +535,13 @@ __global__ void __launch_bounds__(kCellThreads) k_spc_newton(BdfDev D) {
 // instantiations that need only a few registers more than that, or whose
 // excess belongs to a rarely taken path (the FP64 fallback of the
 // FP32-refined solver), around which the compiler places the spills.
-template <int SEG, int LS, int NC, int W>
+template <int SEG, int LS, int NC, int W, int LZ = 0>
 __global__ void __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(W)))
 k_spc_newton_w(BdfDev D) {
   extern __shared__ double lds[];
   if (D.C->phase != PH_PREDICT) return;
-  spc_newton_body<SEG, LS, NC>(D, blockIdx.x, lds);
+  if (LZ != 0 && (D.C->setup != 0) != (LZ == 1)) return;
+  spc_newton_body<SEG, LS, NC, LZ>(D, blockIdx.x, lds);
 }
 
 __host__ __device__ inline size_t spc_accept_lds() {

@@ -276,4 +276,142 @@ struct SpcLU {
   }
 };
 
+// Segment-per-cell explicit inverse by Gauss-Jordan elimination, in place
+// and one row per lane as in SpcLU.  Step k takes the pivot as factor() does
+// (first maximal |a| among the rows not yet pivoted), divides the pivot row
+// by it and subtracts multiples of it from every other row, so that column k
+// becomes a unit vector; the freed column then holds the new column of the
+// inverse (the right half of Gauss-Jordan on [A | I], kept in the left
+// half's place).  The divisions of the pivot row are spread over the lanes,
+// one entry each.
+template <int SEG, int NC = SEG>
+struct SpcGJ {
+  static constexpr int CH = SEG < 8 ? SEG : 8;
+  static constexpr int NCH = NC / CH;
+  static_assert(NC % CH == 0 && NC <= SEG, "row width");
+
+  __device__ static __forceinline__ void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+
+  // Invert the lane-held rows in place (n <= NC real rows, identity rows
+  // past n).  prow: SEG doubles of LDS for this segment, wl: SEG ints of LDS
+  // (receives the lane holding each position).  On return lane r holds, in
+  // position order of its columns, the row of the inverse of the
+  // row-permuted block PA for unknown pos: x[pos] = sum_j row[j] (P b)_j with
+  // (P b)_j the right-hand side of the row at position j.  Returns info
+  // (1-based first exactly-zero pivot, 0 if none).
+  __device__ static __forceinline__ int invert(double (&row)[NC], int r, int n, int& pos,
+                                               double* prow, int* wl) {
+    pos = r;
+    bool done = r >= NC;
+    const bool held = r < NC;
+    int info = 0;
+    const int nch = (n + CH - 1) / CH;
+    for (int c = 0; c < NCH; ++c) {
+      if (c < nch) {
+#pragma unroll
+        for (int kk = 0; kk < CH; ++kk) {
+          const int k = c * CH + kk;
+          double v = done ? -1.0 : sabs(row[kk]);
+          if (!(v == v)) v = __builtin_inf();
+          int key = done ? 0x7fffffff : pos;
+          int bl = r;
+          seg_argmax<SEG>(v, key, bl);
+          if (r == bl) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j) prow[j] = row[j];
+            wl[k] = bl;
+          }
+          sync();
+          const double d = prow[kk];
+          // lane t divides entry t of the pivot row; the entry of column k
+          // becomes the new inverse column's 1 / d
+          double e = 0.0;
+          if (held) e = (r == kk ? 1.0 : prow[r]) / d;
+          sync();
+          if (held) prow[r] = e;
+          sync();
+          if (pos == k) pos = key;
+          if (r == bl) {
+            pos = k;
+            done = true;
+          }
+          if (d == 0.0) {
+            if (!info) info = k + 1;
+          } else if (held) {
+            if (r == bl) {
+#pragma unroll
+              for (int j = 0; j < NC; ++j) row[j] = prow[j];
+            } else {
+              const double f = row[kk];
+#pragma unroll
+              for (int j = 0; j < NC; ++j)
+                if (j != kk) row[j] = fma(-f, prow[j], row[j]);
+              row[kk] = -f * prow[kk];
+            }
+          }
+          sync();
+        }
+      }
+      if constexpr (NCH > 1) {   // rotate left by CH (see SpcLU)
+        double tmp[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) tmp[q] = row[q];
+#pragma unroll
+        for (int j = 0; j < NC - CH; ++j) row[j] = row[j + CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) row[NC - CH + q] = tmp[q];
+      }
+    }
+    return info;
+  }
+
+  // x_r = sum_m X[r][m] b_m with row r of the inverse in natural column order
+  // in this lane (b_m from lane m of the segment: v_readlane for a
+  // whole-wave segment, an LDS broadcast otherwise).  prow: SEG doubles of
+  // LDS for the segment.  Lanes past NC return 0.
+  __device__ static __forceinline__ double apply_natural(const double (&X)[NC], int r, double b,
+                                                         int seg_base, double* prow) {
+    double s = 0.0;
+    if constexpr (SEG == 64) {
+#pragma unroll
+      for (int m = 0; m < NC; ++m) s = fma(X[m], readlane_t(b, m), s);
+    } else {
+      __builtin_amdgcn_wave_barrier();
+      prow[r] = b;
+      sync();
+#pragma unroll
+      for (int m = 0; m < NC; ++m) s = fma(X[m], prow[m], s);
+      sync();
+    }
+    (void)seg_base;
+    return r < NC ? s : 0.0;
+  }
+
+  // x for this lane's unknown r from the rows invert() left (row, pos) and
+  // this lane's right-hand-side entry b: the right-hand sides are placed by
+  // position, each lane forms its inverse row's sum in position order, and
+  // the sums return to the lanes of their unknowns.  prow: SEG doubles of
+  // LDS for the segment.  Lanes past NC return 0.
+  __device__ static __forceinline__ double apply(const double (&row)[NC], int r, int pos, double b,
+                                                 double* prow) {
+    const bool held = r < NC;
+    __builtin_amdgcn_wave_barrier();
+    if (held) prow[pos] = b;
+    sync();
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) s = fma(row[j], prow[j], s);
+    sync();
+    if (held) prow[pos] = s;
+    sync();
+    const double x = held ? prow[r] : 0.0;
+    sync();
+    return x;
+  }
+};
+
 }  // namespace bdfgpu

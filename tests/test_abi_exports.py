@@ -70,17 +70,23 @@ def test_workspace_bytes_without_device_memory():
 
 def test_gauss_jordan_and_order3_option_checks():
     """Option checks of the dry run: the Gauss-Jordan block inverse is
-    accepted for blocks of <= 4 species on per-class launches (also with
-    per-cell stepping) and refused otherwise; a reaction of order three
-    (the demonstration reaction's 2u + v -> 3u) is refused by the FP32 LU
-    with refinement, whose matrix-free product covers order <= 2."""
+    accepted on per-class launches for blocks of any size (one lane per
+    cell up to 4 species, a segment beyond; per-cell stepping only in the
+    first case) and refused on one launch over all classes; a reaction of
+    order three (the demonstration reaction's 2u + v -> 3u) is refused by
+    the FP32 LU with refinement, whose matrix-free product covers order
+    <= 2."""
     import workloads as W
     from paper_2011_12984_amd import LS_GJ, LS_LU32REF, LAUNCH_FUSED, Bdf
     br = W.brusselator_batch(100)
     assert Bdf.workspace_bytes(br, linsol=LS_GJ) > 0
     assert Bdf.workspace_bytes(br, linsol=LS_GJ, per_cell=True) > 0
     assert Bdf.workspace_bytes(br, linsol=LS_GJ, launch=LAUNCH_FUSED) == 0
-    assert Bdf.workspace_bytes(W.random_network_batch(100, n=10, seed=1), linsol=LS_GJ) == 0
+    net = W.random_network_batch(100, n=10, seed=1)
+    assert Bdf.workspace_bytes(net, linsol=LS_GJ) > 0
+    assert Bdf.workspace_bytes(net, linsol=LS_GJ, per_cell=True) == 0
+    assert Bdf.workspace_bytes(W.uneven_batch(1 << 12, seed=9), linsol=LS_GJ) > 0
+    assert Bdf.workspace_bytes(net, linsol=LS_GJ, lazy=True) > Bdf.workspace_bytes(net, linsol=LS_GJ)
     assert Bdf.workspace_bytes(br, linsol=LS_LU32REF) == 0
 
 

@@ -131,6 +131,26 @@ def test_trajectory_uneven(orc, dev, G, launch, map_small, linsol):
                        map_small=map_small, linsol=linsol)
 
 
+@pytest.mark.parametrize("map_small", [0, 1])
+def test_trajectory_uneven_gauss_jordan(orc, dev, G, map_small):
+    """The Gauss-Jordan block inverse on blocks of 4..64 species: one lane
+    per cell for 4 species (or a 16-lane segment with map_small), one row
+    per lane of a segment beyond (in-place elimination over the lanes, the
+    inverse applied as a matrix-vector product), against the oracle's
+    Gauss-Jordan on the augmented block."""
+    compare_trajectory(orc, dev, G, W.uneven_batch(1 << 12, seed=9), map_small=map_small,
+                       linsol=G.LS_GJ)
+
+
+@pytest.mark.parametrize("classes,total", [((14, 42), 2800), ((20, 40, 60), 3000)])
+def test_trajectory_gauss_jordan_padded_rows(orc, dev, G, classes, total):
+    """Segment classes whose species count is not the row width (14, 20,
+    42 and 60 species in rows of 16, 24, 48 and 64 columns): the identity
+    rows and columns past n take part in the elimination."""
+    p = W.uneven_batch(total, seed=23, classes=classes, t_end=0.05)
+    compare_trajectory(orc, dev, G, p, linsol=G.LS_GJ)
+
+
 @pytest.mark.parametrize("launch", [0, 1])
 def test_trajectory_uneven_fp32_fallback_path(orc, dev, G, launch):
     """One refinement sweep allowed: a block that needs a second one to pass

@@ -144,3 +144,27 @@ def test_lazy_segment_padded_rows(orc, dev, G, classes, total):
     p = W.uneven_batch(total, seed=23, classes=classes, t_end=0.05)
     compare_trajectory(orc, dev, G, p, okw=kw, bar_per_step=END_BAR_PER_STEP_LAZY, **kw)
 
+
+@pytest.mark.parametrize("map_small", [False, True])
+def test_lazy_gauss_jordan_uneven(orc, dev, G, map_small):
+    """The lazy Newton matrix with the Gauss-Jordan inverse on blocks of
+    4..64 species: the setup kernel inverts in place and stores the plain
+    inverse, the reuse kernel reloads its rows and applies them (v_readlane
+    broadcasts in whole-wave segments, LDS in smaller ones); lockstep
+    against the oracle's lazy Gauss-Jordan run."""
+    kw = dict(lazy=True)
+    ob, gb = compare_trajectory(orc, dev, G, W.uneven_batch(1 << 12, seed=9), okw=kw,
+                                bar_per_step=END_BAR_PER_STEP_LAZY, map_small=map_small,
+                                linsol=G.LS_GJ, **kw)
+    s = gb.stats()
+    print({k: s[k] for k in ("nsteps", "nattempts", "nsetups", "nstale_retries")})
+    assert s["nsetups"] * 3 < s["nattempts"]
+
+
+@pytest.mark.parametrize("classes,total", [((14, 42), 2800), ((20, 40, 60), 3000)])
+def test_lazy_gauss_jordan_padded_rows(orc, dev, G, classes, total):
+    kw = dict(lazy=True)
+    p = W.uneven_batch(total, seed=23, classes=classes, t_end=0.05)
+    compare_trajectory(orc, dev, G, p, okw=kw, bar_per_step=END_BAR_PER_STEP_LAZY,
+                       linsol=G.LS_GJ, **kw)
+
