@@ -857,6 +857,15 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
       return arg_error("bdf_create: three-molecule reactions need one lane per cell (<= 12 "
                        "species) and FP64 LU or the Gauss-Jordan solve");
     }
+    // segment kernels read the tables in groups (reactions by 8, each
+    // column's entries by 4): padding reactions have no reactant, padding
+    // entries a zero multiplicity
+    const bool pad = ch.map == MAP_SPC;
+    if (pad) {
+      ra.resize((size_t)(R + 7) / 8 * 8, -1);
+      rb.resize((size_t)(R + 7) / 8 * 8, -1);
+      rc.resize((size_t)(R + 7) / 8 * 8, -1);
+    }
     std::vector<int> jst(np + 1, 0), jk, jp, jp2;
     std::vector<double> jm;
     for (int a = 0; a < np; ++a) {
@@ -866,6 +875,12 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
         jp.push_back(e.p);
         jp2.push_back(e.p2);
         jm.push_back(e.m);
+      }
+      while (pad && (jk.size() - (size_t)jst[a]) % 4 != 0) {
+        jk.push_back(0);
+        jp.push_back(-1);
+        jp2.push_back(-1);
+        jm.push_back(0.0);
       }
     }
     jst[np] = (int)jk.size();

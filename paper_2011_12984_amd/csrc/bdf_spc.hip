@@ -32,11 +32,11 @@ constexpr int newton_waves() {
 }
 
 // Waves per SIMD asked of the lazy reuse kernel (0: as its registers allow):
-// the 64-column ones and the 32-column inverse sit a few registers above
-// three.
+// the 48- and 64-column ones and the 32-column inverse sit a few registers
+// above three.
 template <int SEG, int LS, int NC>
 constexpr int reuse_waves() {
-  return ((SEG == 64 && NC == 64) || (SEG == 32 && NC == 32 && LS == 3)) ? 3 : 0;
+  return ((SEG == 64 && (NC == 64 || NC == 48)) || (SEG == 32 && NC == 32 && LS == 3)) ? 3 : 0;
 }
 
 template <int SEG, int LS, int NC>

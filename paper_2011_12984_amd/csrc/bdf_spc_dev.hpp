@@ -11,42 +11,85 @@ namespace bdfgpu {
 // ===========================================================================
 // Segment per cell
 // ===========================================================================
+// The network tables through the constant address space: they are not
+// written while a kernel runs, and every lane of a wave reads the same entry,
+// so the loads go through the scalar cache (read only) instead of one vector
+// load per entry with its full memory latency in the reaction loops.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* ro(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
+
 template <int SEG>
 struct Spc {
   static constexpr int CPB = kCellThreads / SEG;   // cells per block
 
   // lane i: f_i at the segment's state in ys (LDS, SEG values); kap: the
   // cell's rates, St: the stoichiometry staged in LDS as St[k * SEG + i]
-  // (FP32 holds the small integer entries exactly)
+  // (FP32 holds the small integer entries exactly), both zero-padded to R
+  // rounded up to 8 (spc_stage), with the reactant tables padded alike
+  // (index -1).  Reactions go in groups of 8 whose reactant indices are
+  // loaded together (scalar loads, then one wait); an absent reactant is
+  // selected out, not branched over.
   __device__ static __forceinline__ void rhs_row(const NetDev& nd, const double* kap,
                                                  const float* St, const double* ys, int i,
                                                  double& f) {
-    f = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < nd.R; ++k) {
-      const int a = nd.ra[k], b = nd.rb[k];
-      double r = kap[k];
-      if (a >= 0) r *= ys[a];
-      if (b >= 0) r *= ys[b];
-      f = fma((double)St[k * SEG + i], r, f);
+    const auto* ra = ro(nd.ra);
+    const auto* rb = ro(nd.rb);
+    const int R = nd.R;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < R; k0 += 8) {
+      int a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a[u] = ra[k0 + u];
+        b[u] = rb[k0 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double ya = ys[a[u] < 0 ? 0 : a[u]];
+        const double yb = ys[b[u] < 0 ? 0 : b[u]];
+        double r = kap[k0 + u];
+        r = a[u] < 0 ? r : r * ya;
+        r = b[u] < 0 ? r : r * yb;
+        acc = fma((double)St[(k0 + u) * SEG + i], r, acc);
+      }
     }
+    f = acc;
   }
 
+  // Row i of J: column a sums its table entries in groups of 4 (each
+  // column's list is padded to a multiple of 4 with zero-multiplicity
+  // entries), loaded together as rhs_row does for the reactions.
   template <int NC>
   __device__ static __forceinline__ void jac_row(const NetDev& nd, const double* kap,
                                                  const float* St, const double* ys, int i,
                                                  double (&J)[NC]) {
+    const auto* jst = ro(nd.jst);
+    const auto* jk = ro(nd.jk);
+    const auto* jp = ro(nd.jp);
+    const auto* jm = ro(nd.jm);
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       double acc = 0.0;
       if (a < nd.n) {
-        const int e0 = nd.jst[a], e1 = nd.jst[a + 1];
-#pragma unroll 2
-        for (int e = e0; e < e1; ++e) {
-          const int k = nd.jk[e], p = nd.jp[e];
-          double g = kap[k] * nd.jm[e];
-          if (p >= 0) g *= ys[p];
-          acc = fma((double)St[k * SEG + i], g, acc);
+        const int e0 = jst[a], e1 = jst[a + 1];
+        for (int e = e0; e < e1; e += 4) {
+          int k[4], p[4];
+          double m[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            k[u] = jk[e + u];
+            p[u] = jp[e + u];
+            m[u] = jm[e + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double yp = ys[p[u] < 0 ? 0 : p[u]];
+            double g = kap[k[u]] * m[u];
+            g = p[u] < 0 ? g : g * yp;
+            acc = fma((double)St[k[u] * SEG + i], g, acc);
+          }
         }
       }
       J[a] = acc;
@@ -76,11 +119,15 @@ __device__ __forceinline__ void wave_add(double v, double* s) {
   if ((threadIdx.x & 63) == 0) *s += v;
 }
 
+// Reactions of a segment class rounded up to the group of rhs_row.
+__host__ __device__ inline int spc_rpad(int R) { return R > 0 ? (R + 7) / 8 * 8 : 8; }
+
 // Dynamic LDS of the SPC kernels: the shared scratch, then the rates of the
-// block's cells (CPB x R, FP64), then the stoichiometry (R x SEG; its entries
-// are small integers, exact in FP32).
+// block's cells (CPB x Rp, FP64), then the stoichiometry (Rp x SEG; its
+// entries are small integers, exact in FP32), Rp = R rounded up to 8 with
+// zero rates and stoichiometry past R.
 __host__ __device__ inline size_t spc_lds_bytes(int seg, int R) {
-  const size_t r = (size_t)(R > 0 ? R : 1);
+  const size_t r = (size_t)spc_rpad(R);
   return sizeof(SpcShared) + sizeof(double) * (size_t)(kCellThreads / seg) * r +
          sizeof(float) * r * seg;
 }
@@ -91,22 +138,25 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Carve the dynamic LDS and stage the rates of the block's cells
-// (cell-major, contiguous) and the class stoichiometry.
+// Carve the dynamic LDS and stage the rates of the block's cells (cell c at
+// lk + c Rp, zero past R) and the class stoichiometry (zero rows past R).
 template <int SEG>
 __device__ __forceinline__ void spc_stage(const ClassDev& K, long blk, double* lds,
                                           SpcShared*& sh, double*& lk, float*& St) {
   sh = reinterpret_cast<SpcShared*>(lds);
   lk = lds + sizeof(SpcShared) / sizeof(double);
-  const int R = K.R;
-  St = reinterpret_cast<float*>(lk + (size_t)Spc<SEG>::CPB * (R > 0 ? R : 1));
+  const int R = K.R, Rp = spc_rpad(R);
+  St = reinterpret_cast<float*>(lk + (size_t)Spc<SEG>::CPB * Rp);
   const long c0 = blk * Spc<SEG>::CPB;
-  const long cnt = (K.ncells - c0 < Spc<SEG>::CPB ? K.ncells - c0 : Spc<SEG>::CPB) * (long)R;
-  for (long t = threadIdx.x; t < cnt; t += blockDim.x) lk[t] = K.rates[c0 * R + t];
+  const long nc = K.ncells - c0 < Spc<SEG>::CPB ? K.ncells - c0 : Spc<SEG>::CPB;
+  for (int t = threadIdx.x; t < Spc<SEG>::CPB * Rp; t += blockDim.x) {
+    const int cl = t / Rp, k = t - cl * Rp;
+    lk[t] = (cl < nc && k < R) ? K.rates[(c0 + cl) * R + k] : 0.0;
+  }
   const int np = K.net.np;
-  for (int t = threadIdx.x; t < R * SEG; t += blockDim.x) {
+  for (int t = threadIdx.x; t < Rp * SEG; t += blockDim.x) {
     const int k = t / SEG, i = t - k * SEG;
-    St[t] = i < np ? (float)K.net.S[(long)k * np + i] : 0.0f;
+    St[t] = (k < R && i < np) ? (float)K.net.S[(long)k * np + i] : 0.0f;
   }
   __syncthreads();
 }
@@ -187,7 +237,7 @@ __device__ __forceinline__ void spc_predict_body(const BdfDev& D, long blk, doub
   double* lk;
   float* St;
   spc_stage<SEG>(K, blk, lds, shp, lk, St);
-  const double* kap = lk + cb * K.R;
+  const double* kap = lk + cb * spc_rpad(K.R);
   double zp0, cv, w;
   spc_predict_row<SEG>(D, C, *shp, sb, i, act, row, id, kap, St, zp0, cv, w);
   if (row) {
@@ -299,7 +349,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   double red[kRedNewton];
 #pragma unroll
   for (int k = 0; k < kRedNewton; ++k) red[k] = 0.0;
-  const double* kap = lk + cb * K.R;
+  const double* kap = lk + cb * spc_rpad(K.R);
   const double gamma = C->gamma;
   const int maxcor = C->maxcor;
   double zp0 = 0.0, cv = 0.0, w = 0.0;
@@ -624,7 +674,7 @@ __device__ __forceinline__ void spc_init_body(const BdfDev& D, long blk, double*
   float* St;
   spc_stage<SEG>(K, blk, lds, shp, lk, St);
   SpcShared& sh = *shp;
-  const double* kap = lk + cb * K.R;
+  const double* kap = lk + cb * spc_rpad(K.R);
   const double y0 = row ? K.z[0][id] : 0.0;
   const double f0 = (PART == 2 && row) ? K.z[1][id] : 0.0;
   sh.ys[threadIdx.x] = PART == 1 ? y0 : y0 + C->hnw_h0 * f0;
