@@ -20,7 +20,8 @@ static void raise_lds(KF* kern, size_t lds, size_t& raised) {
 // at 48 and 64 columns need more registers than two waves allow, mostly for
 // paths that rarely run (the FP64 fallback); the hint makes them fit, with
 // spills around those paths.  The FP32-refined 16-, 24- and 32-column
-// kernels sit a few registers above four, three and three waves.
+// kernels sit a few registers above four, three and three waves, the FP64 LU
+// and Gauss-Jordan 64-column kernels a few above two.
 template <int SEG, int LS, int NC>
 constexpr int newton_waves() {
   if (SEG == 32 && LS == 2 && NC == 24) return 2;
@@ -28,6 +29,7 @@ constexpr int newton_waves() {
   if (SEG == 32 && LS == 1 && NC == 24) return 3;
   if (SEG == 32 && LS == 1 && NC == 32) return 3;
   if (SEG == 16 && LS == 1 && NC == 16) return 4;
+  if (SEG == 64 && (LS == 0 || LS == 3) && NC == 64) return 2;   // FP64 LU, inverse: ~280
   return 0;
 }
 
@@ -39,6 +41,13 @@ constexpr int reuse_waves() {
   return ((SEG == 64 && (NC == 64 || NC == 48)) || (SEG == 32 && NC == 32 && LS == 3)) ? 3 : 0;
 }
 
+// ... and of the lazy setup kernel: the 64-column one sits a few registers
+// above two.
+template <int SEG, int LS, int NC>
+constexpr int setup_waves() {
+  return (SEG == 64 && NC == 64) ? 2 : 0;
+}
+
 template <int SEG, int LS, int NC>
 static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s) {
   static size_t raised = 65536;
@@ -46,8 +55,14 @@ static void go_newton(const BdfDev& D, dim3 g, dim3 b, size_t lds, hipStream_t s
   if constexpr (LS == 0 || LS == 3) {
     if (D.lazy) {   // lazy Newton matrix: the setup kernel, then the reuse kernel
       static size_t raised_s = 65536, raised_r = 65536;
-      raise_lds(&k_spc_newton<SEG, LS, NC, 1>, lds, raised_s);
-      hipLaunchKernelGGL((k_spc_newton<SEG, LS, NC, 1>), g, b, lds, s, D);
+      constexpr int sw = setup_waves<SEG, LS, NC>();
+      if constexpr (sw > 0) {
+        raise_lds(&k_spc_newton_w<SEG, LS, NC, sw, 1>, lds, raised_s);
+        hipLaunchKernelGGL((k_spc_newton_w<SEG, LS, NC, sw, 1>), g, b, lds, s, D);
+      } else {
+        raise_lds(&k_spc_newton<SEG, LS, NC, 1>, lds, raised_s);
+        hipLaunchKernelGGL((k_spc_newton<SEG, LS, NC, 1>), g, b, lds, s, D);
+      }
       constexpr int rw = reuse_waves<SEG, LS, NC>();
       if constexpr (rw > 0) {
         raise_lds(&k_spc_newton_w<SEG, LS, NC, rw, 2>, lds, raised_r);

@@ -342,15 +342,19 @@ struct SpcGJ {
           if (d == 0.0) {
             if (!info) info = k + 1;
           } else if (held) {
-            if (r == bl) {
+            // the pivot row is read 16 columns at a time (the empty asm keeps
+            // the next group's LDS reads after this group's update, so they
+            // do not all wait in registers at once)
+            const double f = row[kk];
+            const bool piv_row = r == bl;
 #pragma unroll
-              for (int j = 0; j < NC; ++j) row[j] = prow[j];
-            } else {
-              const double f = row[kk];
+            for (int j0 = 0; j0 < NC; j0 += 16) {
 #pragma unroll
-              for (int j = 0; j < NC; ++j)
-                if (j != kk) row[j] = fma(-f, prow[j], row[j]);
-              row[kk] = -f * prow[kk];
+              for (int j = j0; j < j0 + 16 && j < NC; ++j) {
+                const double pj = prow[j];
+                row[j] = piv_row ? pj : (j == kk ? -f * pj : fma(-f, pj, row[j]));
+              }
+              asm volatile("" ::: "memory");
             }
           }
           sync();
