@@ -77,10 +77,10 @@ def time_advance(b, t_end, steps, torch):
 
 
 def bdf_leg(G, W, torch, prob, dev, warmup, steps, linsol, precond=None, jit=True, graph=False,
-            defer=True):
+            defer=True, lazy=False):
     b = G.Bdf.from_problem(prob, device=dev, mode=G.MODE_GRAPH if graph else G.MODE_STREAM,
                            attempts_per_sync=16, linsol=linsol, maxcor=MAXCOR, precond=precond,
-                           jit=jit, defer=defer)
+                           jit=jit, defer=defer, lazy=lazy)
     b.advance(prob.t_end, warmup)
     s0 = b.stats()
     dt, taken, t = time_advance(b, prob.t_end, steps, torch)
@@ -279,9 +279,11 @@ def learned_leg(G, W, torch, dev, cells, warmup, steps, epochs, nblocks):
     out = {"cells": cells, "species": n, "training_blocks": int(nblocks), "epochs": epochs,
            "capture_s": round(t_cap, 2), "train_s": round(t_train, 2),
            "val_loss": [round(hist["val0"], 6), round(hist["val"][-1], 6)]}
-    for name, kw in (("plain_lu", {}), ("learned", {"linsol": G.LS_LEARNED, "precond": pc})):
+    for name, kw in (("plain_lu", {}), ("learned", {"linsol": G.LS_LEARNED, "precond": pc}),
+                     ("gauss_jordan_lazy", {"linsol": G.LS_GJ, "lazy": True})):
         b, dt, taken, s0, s1 = bdf_leg(G, W, torch, prob, dev, warmup, steps,
-                                       kw.get("linsol", G.LS_LU64), precond=kw.get("precond"))
+                                       kw.get("linsol", G.LS_LU64), precond=kw.get("precond"),
+                                       lazy=kw.get("lazy", False))
         d = {k: s1[k] - s0[k] for k in ("nsteps", "nattempts", "nniters", "lp_cell_solves",
                                         "lp_fallback_cells", "lp_step_fallbacks")}
         out[name] = {"value": round(cells * taken / dt, 1), "unit": "cell-steps/s",
