@@ -168,3 +168,21 @@ def test_lazy_gauss_jordan_padded_rows(orc, dev, G, classes, total):
     compare_trajectory(orc, dev, G, p, okw=kw, bar_per_step=END_BAR_PER_STEP_LAZY,
                        linsol=G.LS_GJ, **kw)
 
+
+@pytest.mark.parametrize("solve", ["lu", "gauss_jordan"])
+def test_lazy_uneven_2p16_unknowns_bench_configuration(orc, dev, G, solve):
+    """The lazy forms of the bench's uneven legs at 2^16 unknowns (about
+    2,300 cells of 4..64 species, several blocks per class and reduction
+    group) in the bench's launch configuration (graph mode, autotuned
+    launch, generated kernels for the small classes): 80 steps in lockstep
+    with the oracle's lazy run, setups and retries compared step by step."""
+    p = W.uneven_batch(1 << 16, seed=W.BASE_SEED + 4)
+    kw = dict(lazy=True)
+    ob, gb = compare_trajectory(orc, dev, G, p, max_steps=80, okw=kw,
+                                bar_per_step=END_BAR_PER_STEP_LAZY,
+                                linsol=G.LS_GJ if solve == "gauss_jordan" else G.LS_LU64,
+                                launch=G.LAUNCH_AUTO, mode=G.MODE_GRAPH, jit=True, **kw)
+    s = gb.stats()
+    print({k: s[k] for k in ("nsteps", "nattempts", "nsetups", "nstale_retries")})
+    assert s["nsetups"] < s["nattempts"]
+
