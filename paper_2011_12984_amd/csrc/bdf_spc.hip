@@ -25,7 +25,7 @@ static void raise_lds(KF* kern, size_t lds, size_t& raised) {
 template <int SEG, int LS, int NC>
 constexpr int newton_waves() {
   if (SEG == 32 && LS == 2 && NC == 24) return 2;
-  if (SEG == 64 && LS == 1 && (NC == 48 || NC == 64)) return 2;
+  if (SEG == 64 && LS == 1 && (NC == 48 || NC == 64)) return 3;
   if (SEG == 32 && LS == 1 && NC == 24) return 3;
   if (SEG == 32 && LS == 1 && NC == 32) return 3;
   if (SEG == 16 && LS == 1 && NC == 16) return 4;

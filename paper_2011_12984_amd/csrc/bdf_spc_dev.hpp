@@ -20,6 +20,9 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T* ro(const T
   return (const __attribute__((address_space(4))) T*)p;
 }
 
+// Reactions of a segment class rounded up to the group of rhs_row.
+__host__ __device__ inline int spc_rpad(int R) { return R > 0 ? (R + 7) / 8 * 8 : 8; }
+
 template <int SEG>
 struct Spc {
   static constexpr int CPB = kCellThreads / SEG;   // cells per block
@@ -65,6 +68,16 @@ struct Spc {
   __device__ static __forceinline__ void jac_row(const NetDev& nd, const double* kap,
                                                  const float* St, const double* ys, int i,
                                                  double (&J)[NC]) {
+    jac_cols<NC>(nd, kap, St, ys, i, [&](int a, double v) { J[a] = v; });
+  }
+
+  // The same, handing each entry J_ia to put(a, J_ia) as it is formed (a
+  // compile-time index once the column loop is unrolled), so that a caller
+  // can convert the row without holding it in FP64.
+  template <int NC, typename F>
+  __device__ static __forceinline__ void jac_cols(const NetDev& nd, const double* kap,
+                                                  const float* St, const double* ys, int i,
+                                                  F&& put) {
     const auto* jst = ro(nd.jst);
     const auto* jk = ro(nd.jk);
     const auto* jp = ro(nd.jp);
@@ -92,8 +105,40 @@ struct Spc {
           }
         }
       }
-      J[a] = acc;
+      put(a, acc);
     }
+  }
+
+  // Lane i: (J x)_i without the matrix, J at the state whose values ys holds
+  // and x in xs (LDS, SEG values each).  Each reaction's derivative along x,
+  // kappa (x_a y_b + y_a x_b) (an absent reactant contributes a factor 1 and
+  // no derivative), is formed once, the segment's lanes taking reactions i,
+  // i + SEG, ..., and kept in g (LDS, R rounded up to 8 values for this
+  // segment); then every row sums its stoichiometry against them in reaction
+  // order, as rhs_row does against the rates.
+  __device__ static __forceinline__ double jx_row(const NetDev& nd, const double* kap,
+                                                  const float* St, const double* ys,
+                                                  const double* xs, double* g, int i) {
+    const auto* ra = ro(nd.ra);
+    const auto* rb = ro(nd.rb);
+    const int R = nd.R, Rp = spc_rpad(R);
+    __builtin_amdgcn_wave_barrier();
+    for (int k = i; k < Rp; k += SEG) {
+      const int a = k < R ? ra[k] : -1;
+      const int b = k < R ? rb[k] : -1;
+      const double xa = a < 0 ? 0.0 : xs[a], ya = a < 0 ? 1.0 : ys[a];
+      const double xb = b < 0 ? 0.0 : xs[b], yb = b < 0 ? 1.0 : ys[b];
+      g[k] = kap[k] * fma(xa, yb, ya * xb);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double acc = 0.0;
+    for (int k0 = 0; k0 < R; k0 += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = fma((double)St[(k0 + u) * SEG + i], g[k0 + u], acc);
+    }
+    return acc;
   }
 };
 
@@ -119,17 +164,22 @@ __device__ __forceinline__ void wave_add(double v, double* s) {
   if ((threadIdx.x & 63) == 0) *s += v;
 }
 
-// Reactions of a segment class rounded up to the group of rhs_row.
-__host__ __device__ inline int spc_rpad(int R) { return R > 0 ? (R + 7) / 8 * 8 : 8; }
-
 // Dynamic LDS of the SPC kernels: the shared scratch, then the rates of the
 // block's cells (CPB x Rp, FP64), then the stoichiometry (Rp x SEG; its
 // entries are small integers, exact in FP32), Rp = R rounded up to 8 with
-// zero rates and stoichiometry past R.
+// zero rates and stoichiometry past R, then the reaction derivatives of the
+// matrix-free Jacobian products (CPB x Rp, FP64).
 __host__ __device__ inline size_t spc_lds_bytes(int seg, int R) {
   const size_t r = (size_t)spc_rpad(R);
-  return sizeof(SpcShared) + sizeof(double) * (size_t)(kCellThreads / seg) * r +
+  return sizeof(SpcShared) + 2 * sizeof(double) * (size_t)(kCellThreads / seg) * r +
          sizeof(float) * r * seg;
+}
+
+// This segment's Rp values of the derivative area (after the stoichiometry).
+template <int SEG>
+__device__ __forceinline__ double* spc_gk(const float* St, int R, int cb) {
+  const int Rp = spc_rpad(R);
+  return reinterpret_cast<double*>(const_cast<float*>(St) + (size_t)Rp * SEG) + (size_t)cb * Rp;
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -302,9 +352,12 @@ __device__ __forceinline__ void spc_load_factors(const ClassDev& K, long c, int 
 // Fused Newton iterations, segment per cell.  LS 0: FP64 LU factored once.
 // LS 3: explicit inverse by Gauss-Jordan elimination, applied as a
 // matrix-vector product (no serial substitution chain).
-// LS 1: FP32 LU factored once, each solve refined with FP64 residuals from
-// the FP64 rows; a cell whose refinement fails factors its FP64 rows in
-// place and uses them from then on.  LS 2: correction X r with the cell's
+// LS 1: FP32 LU factored once, each solve refined with FP64 residuals
+// r - M x = r - x + gamma J x, the product with J formed without the matrix
+// (Spc::jx_row), so that no FP64 row stays in registers; a cell whose FP32
+// factor is singular, or whose refinement fails, is solved with FP64 LU from
+// then on, its M formed and factored again at each iteration that needs it
+// (a rare path, kept off the registers of the refined one).  LS 2: correction X r with the cell's
 // learned approximate inverse (X from the MLP, computed after the predictor
 // kernel); a cell switches to FP64 LU for the rest of the attempt when X r
 // is not finite, or from the second iteration on when its correction norm
@@ -411,19 +464,30 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
     }
     factored = true;
   } else if constexpr (LS == 1) {
-    assemble();
+    // M as assemble() forms it, converted to FP32 entry by entry
+    double rs = 0.0;
+    auto put = [&](int a, double v) {
+      const double e = i == a ? 1.0 : 0.0;
+      const double mv = row ? e - gamma * v : e;
+      rs += fabs(mv);
+      L[a] = (float)mv;
+    };
+    __builtin_amdgcn_wave_barrier();
+    sh.ys[threadIdx.x] = zp0;
+    wave_sync_lds();
+    if (act)
+      Spc<SEG>::template jac_cols<NC>(nd, kap, St, sh.ys + sb, i, put);
+    else
 #pragma unroll
-    for (int j = 0; j < NC; ++j) L[j] = (float)Mrow[j];
+      for (int j = 0; j < NC; ++j) put(j, 0.0);
+    mnorm = seg_max<SEG>(rs);
     const int inf32 =
         SpcLU<SEG, float, NC>::factor(L, i, nn, pos32, piv32, sh.prow32 + sb, sh.wl32 + sb);
-    double rs = 0.0;
-#pragma unroll
-    for (int j = 0; j < NC; ++j) rs += fabs(Mrow[j]);
-    mnorm = seg_max<SEG>(rs);
-    if (inf32) {
-      fp64 = true;
-      info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
-    }
+    fp64 = inf32 != 0;
+    // J's evaluation point for the matrix-free residuals (this segment's
+    // part of prow, which only an FP64 factorisation, after which the
+    // segment no longer refines, writes)
+    sh.prow[threadIdx.x] = zp0;
   } else {
     mode = (act && !C->force_lu) ? 2 : 4;
     if (mode == 4) {
@@ -442,7 +506,14 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   }
   if (LS == 1 && fp64 && act && i == 0) wsum[4] = 1.0;   // FP32 factor singular at setup
   double y = zp0;
-  for (int m = 0; m < maxcor; ++m) {
+  // LS 1 with whole-wave segments (one cell per wave): the FP32-refined
+  // iterations run on their own path (P 1), and a cell that needs FP64 LU
+  // leaves it for a path that holds the FP64 factors and no FP32 ones (P 2),
+  // redoing the iteration whose refinement failed; its sweeps and the
+  // fallback are counted at that iteration.
+  int sweeps_p = 0, fb_p = 0;
+  auto iterate = [&](int m, auto path) -> bool {
+    constexpr int P = decltype(path)::value;
     __builtin_amdgcn_wave_barrier();
     sh.ys[threadIdx.x] = y;
     wave_sync_lds();
@@ -450,7 +521,9 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
     if (act) Spc<SEG>::rhs_row(nd, kap, St, sh.ys + sb, i, f);
     const double r = row ? fma(gamma, f, cv - y) : 0.0;
     double del = 0.0;
-    int sweeps = 0, fb = 0;
+    int sweeps = sweeps_p, fb = fb_p;
+    sweeps_p = 0;
+    fb_p = 0;
     double lp_solves = 0.0, lp_fb = 0.0, lp_unconv = 0.0;
     if constexpr (LS == 0) {
       del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
@@ -460,6 +533,8 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
         del = C->dscale * SpcGJ<SEG, NC>::apply_natural(Mrow, i, r, seg_base, sh.prow + sb);
       else
         del = SpcGJ<SEG, NC>::apply(Mrow, i, pos, r, sh.prow + sb);
+    } else if constexpr (LS == 1 && P == 2) {
+      del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
     } else if constexpr (LS == 1) {
       bool ok = false;
       if (!fp64) {
@@ -467,10 +542,13 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
                                                     (float)r);
         const double eps64 = 2.220446049250313e-16;
         double dprv = 0.0;
+        double* gk = spc_gk<SEG>(St, K.R, cb);
         for (int it = 0; it <= K.refine_max_it; ++it) {
-          double res = r;
-#pragma unroll
-          for (int j = 0; j < NC; ++j) res = fma(-Mrow[j], __shfl(x, seg_base + j, 64), res);
+          __builtin_amdgcn_wave_barrier();
+          sh.ys[threadIdx.x] = x;
+          wave_sync_lds();
+          const double jx = Spc<SEG>::jx_row(nd, kap, St, sh.prow + sb, sh.ys + sb, gk, i);
+          const double res = row ? fma(gamma, jx, r - x) : r - x;
           const double rn = seg_max<SEG>(fabs(res));
           const double xn = seg_max<SEG>(fabs(x));
           if (!(rn == rn) || !(xn == xn)) break;
@@ -491,10 +569,18 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
         if (!ok) {
           fb = 1;
           fp64 = true;
-          info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+          if constexpr (P == 1) {
+            sweeps_p = sweeps;
+            fb_p = 1;
+            return false;
+          }
         }
       }
-      if (!ok) del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
+      if (P == 0 && !ok) {   // FP64 M formed and factored again at each such iteration
+        assemble();
+        info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+        del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
+      }
     } else {
       if (mode == 2) {
         // correction = X r with row i of the cell's approximate inverse
@@ -562,6 +648,20 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
         red[kRedPerIter * mm + 2] += hit ? neg : 0.0;
       }
     }
+    return true;
+  };
+  if constexpr (LS == 1 && SEG == 64) {
+    int m = 0;
+    if (!fp64)
+      for (; m < maxcor; ++m)
+        if (!iterate(m, std::integral_constant<int, 1>{})) break;
+    if (m < maxcor) {   // uniform over the wave
+      assemble();
+      info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
+      for (; m < maxcor; ++m) iterate(m, std::integral_constant<int, 2>{});
+    }
+  } else {
+    for (int m = 0; m < maxcor; ++m) iterate(m, std::integral_constant<int, 0>{});
   }
   if constexpr (kLdsSums) {
 #pragma unroll

@@ -189,10 +189,18 @@ struct SpcLU {
           int bl = r;
           seg_argmax<SEG>(v, key, bl);
           if (r == k) piv = key;
+          // Columns at or past lim hold multipliers of earlier chunks: the
+          // pivot row is published, and the other rows updated, only over
+          // the groups of CH columns before lim (a uniform branch per group).
           if (r == bl) {
             prow[kk] = row[kk];
 #pragma unroll
-            for (int j = kk + 1; j < NC; ++j) prow[j] = j < lim ? row[j] : T(0);
+            for (int j = kk + 1; j < CH; ++j) prow[j] = row[j];
+#pragma unroll
+            for (int g = 1; g < NCH; ++g)
+              if (g * CH < lim)
+#pragma unroll
+                for (int j = g * CH; j < (g + 1) * CH; ++j) prow[j] = row[j];
             wl[k] = bl;
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -210,7 +218,12 @@ struct SpcLU {
             const T l = row[kk] / d;
             row[kk] = l;
 #pragma unroll
-            for (int j = kk + 1; j < NC; ++j) row[j] = fma(-l, prow[j], row[j]);
+            for (int j = kk + 1; j < CH; ++j) row[j] = fma(-l, prow[j], row[j]);
+#pragma unroll
+            for (int g = 1; g < NCH; ++g)
+              if (g * CH < lim)
+#pragma unroll
+                for (int j = g * CH; j < (g + 1) * CH; ++j) row[j] = fma(-l, prow[j], row[j]);
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
