@@ -220,9 +220,13 @@ int batched_lu_solve_refine(int nb, int n, const double* M, const float* LU32,
 #define BDFGPU_MODE_GRAPH 1  /* one attempt captured in a hipGraph */
 
 #define BDFGPU_LAUNCH_PER_CLASS 0 /* one launch per class of cells and phase */
-#define BDFGPU_LAUNCH_FUSED 1     /* one launch over every class per phase (blocks
-                                     of uneven sizes together; <= 8 classes, not
-                                     with the learned preconditioner) */
+#define BDFGPU_LAUNCH_FUSED 1     /* one persistent launch over every class per
+                                     phase (blocks of uneven sizes together): the
+                                     workgroups the device holds at once take the
+                                     classes' blocks from a work queue in the
+                                     handle's device memory, costliest blocks
+                                     first; <= 8 classes, not with the learned
+                                     preconditioner */
 #define BDFGPU_LAUNCH_AUTO 2      /* bdf_create times the candidate launch modes and
                                      small-block mappings and keeps the fastest */
 

@@ -178,7 +178,11 @@ struct bdf_handle {
   double* partials = nullptr;
   double* gpartials = nullptr;
   unsigned int nblocks_total = 0;  // per-class launches
-  unsigned int nblocks_multi = 0;  // single launch over all classes
+  unsigned int nblocks_multi = 0;  // single launch over all classes: work items
+  unsigned int* d_queue = nullptr;  // its work-queue counter
+  unsigned int multi_grid[4] = {0, 0, 0, 0};   // its persistent grid per phase
+  int qcls[kMaxClasses] = {0};      // classes in queue order, costliest blocks first
+  long qend[kMaxClasses] = {0};
   bool fused = false;              // launch mode in use
   bool defer = false;              // deferred history update (Ctrl::fuse)
   bool fusable = false;
@@ -325,9 +329,13 @@ static void launch_phase_kernels(bdf_handle* h, int which, hipStream_t s) {
       M.k[k] = c.dev;
       M.kind[k] = c.kind;
       M.bend[k] = c.mblk0 + c.mblocks;
+      M.qcls[k] = h->qcls[k];
+      M.qend[k] = h->qend[k];
     }
+    M.queue = h->d_queue;
+    M.total = h->nblocks_multi;
     M.base = make_dev(h, h->cls[0]);
-    launch_multi(h->o.linsol, which, M, h->nblocks_multi, h->multi_lds[which], s);
+    launch_multi(h->o.linsol, which, M, h->multi_grid[which], h->multi_lds[which], s);
     return;
   }
   for (const ClassHost& c : h->cls) {
@@ -1007,6 +1015,16 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     h->multi_lds[w] = mx;
     if (mx > (size_t)lds_max) h->fusable = false;
   }
+  if (h->fusable) {   // queue order: classes by the work of one block, costliest first
+    const int nc = (int)h->cls.size();
+    for (int k = 0; k < nc; ++k) h->qcls[k] = k;
+    std::stable_sort(h->qcls, h->qcls + nc, [&](int a, int b) {
+      return multi_block_cost(h->cls[a].kind, h->cls[a].np) >
+             multi_block_cost(h->cls[b].kind, h->cls[b].np);
+    });
+    long e = 0;
+    for (int k = 0; k < nc; ++k) h->qend[k] = (e += h->cls[h->qcls[k]].mblocks);
+  }
   if (o->launch == BDFGPU_LAUNCH_FUSED && !h->fusable) {
     bdf_destroy(h);
     return arg_error("bdf_create: one launch over all classes needs <= 8 classes, no learned "
@@ -1051,10 +1069,19 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
     bdf_destroy(h);
     return st;
   }
+  if (h->fusable && (st = dalloc(h, (void**)&h->d_queue, sizeof(unsigned int)))) {
+    bdf_destroy(h);
+    return st;
+  }
   if (dry) {   // sizes counted: nothing was allocated or launched
     *out = h;
     return 0;
   }
+  if (h->fusable)
+    for (int w = 0; w < 4; ++w) {
+      const unsigned int r = multi_grid(o->linsol, w, h->multi_lds[w]);
+      h->multi_grid[w] = r == 0 ? h->nblocks_multi : std::min(r, h->nblocks_multi);
+    }
   if (o->per_cell)
     BDF_HIP_TRY(hipHostMalloc((void**)&h->h_active, sizeof(unsigned int), hipHostMallocDefault));
   if (h->krylov)
