@@ -434,7 +434,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   int pos = i, piv = i, info = 0;
   // LS 1 state
   float L[LS == 1 ? NC : 1];
-  int pos32 = i, piv32 = i;
+  int pos32 = i, piv32 = i, src32 = i;
   bool fp64 = LS == 0;
   double mnorm = 0.0;
   // LS 2 state
@@ -484,6 +484,9 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
     const int inf32 =
         SpcLU<SEG, float, NC>::factor(L, i, nn, pos32, piv32, sh.prow32 + sb, sh.wl32 + sb);
     fp64 = inf32 != 0;
+    // rows to position order: each right-hand side is read from lane src32
+    src32 = SpcLU<SEG, float, NC>::position_source(i, nn, sh.wl32 + sb);
+    SpcLU<SEG, float, NC>::to_position_order(L, seg_base, src32);
     // J's evaluation point for the matrix-free residuals (this segment's
     // part of prow, which only an FP64 factorisation, after which the
     // segment no longer refines, writes)
@@ -538,8 +541,8 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
     } else if constexpr (LS == 1) {
       bool ok = false;
       if (!fp64) {
-        double x = (double)SpcLU<SEG, float, NC>::solve(L, i, seg_base, nn, pos32, sh.wl32 + sb,
-                                                    (float)r);
+        double x = (double)SpcLU<SEG, float, NC>::solve_ordered(
+            L, i, seg_base, nn, (float)__shfl(r, seg_base + src32, 64));
         const double eps64 = 2.220446049250313e-16;
         double dprv = 0.0;
         double* gk = spc_gk<SEG>(St, K.R, cb);
@@ -557,8 +560,8 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
             break;
           }
           if (it == K.refine_max_it) break;
-          const double d = (double)SpcLU<SEG, float, NC>::solve(L, i, seg_base, nn, pos32,
-                                                            sh.wl32 + sb, (float)res);
+          const double d = (double)SpcLU<SEG, float, NC>::solve_ordered(
+              L, i, seg_base, nn, (float)__shfl(res, seg_base + src32, 64));
           x += d;
           const double dn = seg_max<SEG>(fabs(d));
           sweeps = it + 1;

@@ -272,6 +272,59 @@ struct SpcLU {
     return x;
   }
 
+  // solve() for factors in position order (lane r holds position r, val
+  // already permuted), its substitutions unrolled over all NC columns:
+  // static register indices without the rotations, and a fixed source lane
+  // at every step; one uniform branch per chunk of CH columns skips the
+  // chunks past n.  Same operations in the same order as solve().
+  __device__ static __forceinline__ T solve_ordered(T (&row)[NC], int r, int seg_base, int n,
+                                                    T val) {
+    const int nch = (n + CH - 1) / CH;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      if (c < nch) {
+#pragma unroll
+        for (int kk = 0; kk < CH; ++kk) {
+          const int k = c * CH + kk;
+          const T yk = seg_bcast<SEG>(val, seg_base, k);
+          if (r > k) val = fma(-row[k], yk, val);
+        }
+      }
+    }
+    T x = T(0);
+#pragma unroll
+    for (int c = NCH - 1; c >= 0; --c) {
+      if (c < nch) {
+#pragma unroll
+        for (int kk = CH - 1; kk >= 0; --kk) {
+          const int k = c * CH + kk;
+          if (r == k) val = val / row[k];
+          const T xk = seg_bcast<SEG>(val, seg_base, k);
+          if (r < k) val = fma(-row[k], xk, val);
+          if (r == k) x = xk;
+        }
+      }
+    }
+    return x;
+  }
+
+  // Lane (within the segment) that holds position r after factor(): the
+  // pivot lane of step r for the factored chunks, r itself past them
+  // (identity rows of padding lanes, never exchanged).
+  __device__ static __forceinline__ int position_source(int r, int n, const int* wl) {
+    const int nk = (n + CH - 1) / CH * CH;
+    return r < nk ? wl[r] : r;
+  }
+
+  // Move the rows of factor() into position order (lane r then holds the row
+  // of position r, for solve_ordered with the right-hand side read from lane
+  // src first), so that every substitution step reads a fixed lane.  src:
+  // position_source(r, ...).
+  __device__ static __forceinline__ void to_position_order(T (&row)[NC], int seg_base, int src) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) row[j] = __shfl(row[j], seg_base + src, 64);
+  }
+
   // Solve with factors stored in LAPACK layout (lane r holds the row at
   // position r) and LAPACK pivots piv[0..n-1] in global memory.
   __device__ static __forceinline__ T solve_stored(T (&row)[NC], int r, int seg_base, const int* piv, int n,
