@@ -435,6 +435,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   // LS 1 state
   float L[LS == 1 ? NC : 1];
   int pos32 = i, piv32 = i, src32 = i;
+  float dinv32 = 1.0f;
   bool fp64 = LS == 0;
   double mnorm = 0.0;
   // LS 2 state
@@ -487,6 +488,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
     // rows to position order: each right-hand side is read from lane src32
     src32 = SpcLU<SEG, float, NC>::position_source(i, nn, sh.wl32 + sb);
     SpcLU<SEG, float, NC>::to_position_order(L, seg_base, src32);
+    dinv32 = SpcLU<SEG, float, NC>::pivot_reciprocal(L, i);
     // J's evaluation point for the matrix-free residuals (this segment's
     // part of prow, which only an FP64 factorisation, after which the
     // segment no longer refines, writes)
@@ -542,7 +544,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
       bool ok = false;
       if (!fp64) {
         double x = (double)SpcLU<SEG, float, NC>::solve_ordered(
-            L, i, seg_base, nn, (float)__shfl(r, seg_base + src32, 64));
+            L, i, seg_base, nn, dinv32, (float)__shfl(r, seg_base + src32, 64));
         const double eps64 = 2.220446049250313e-16;
         double dprv = 0.0;
         double* gk = spc_gk<SEG>(St, K.R, cb);
@@ -561,7 +563,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
           }
           if (it == K.refine_max_it) break;
           const double d = (double)SpcLU<SEG, float, NC>::solve_ordered(
-              L, i, seg_base, nn, (float)__shfl(res, seg_base + src32, 64));
+              L, i, seg_base, nn, dinv32, (float)__shfl(res, seg_base + src32, 64));
           x += d;
           const double dn = seg_max<SEG>(fabs(d));
           sweeps = it + 1;

@@ -273,12 +273,15 @@ struct SpcLU {
   }
 
   // solve() for factors in position order (lane r holds position r, val
-  // already permuted), its substitutions unrolled over all NC columns:
-  // static register indices without the rotations, and a fixed source lane
-  // at every step; one uniform branch per chunk of CH columns skips the
-  // chunks past n.  Same operations in the same order as solve().
+  // already permuted), for the FP32 solves that iterative refinement
+  // corrects: the substitutions are unrolled over all NC columns (static
+  // register indices without the rotations, a fixed source lane at every
+  // step, one uniform branch per chunk of CH columns skipping the chunks past
+  // n), each step is branch-free (selects), and the back substitution
+  // multiplies by the reciprocal of the pivot, dinv = 1 / U_rr of this lane
+  // (pivot_reciprocal), in place of the division.
   __device__ static __forceinline__ T solve_ordered(T (&row)[NC], int r, int seg_base, int n,
-                                                    T val) {
+                                                    T dinv, T val) {
     const int nch = (n + CH - 1) / CH;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -287,7 +290,8 @@ struct SpcLU {
         for (int kk = 0; kk < CH; ++kk) {
           const int k = c * CH + kk;
           const T yk = seg_bcast<SEG>(val, seg_base, k);
-          if (r > k) val = fma(-row[k], yk, val);
+          const T u = fma(-row[k], yk, val);
+          val = r > k ? u : val;
         }
       }
     }
@@ -298,14 +302,24 @@ struct SpcLU {
 #pragma unroll
         for (int kk = CH - 1; kk >= 0; --kk) {
           const int k = c * CH + kk;
-          if (r == k) val = val / row[k];
-          const T xk = seg_bcast<SEG>(val, seg_base, k);
-          if (r < k) val = fma(-row[k], xk, val);
-          if (r == k) x = xk;
+          const T xk = seg_bcast<SEG>(val, seg_base, k) * seg_bcast<SEG>(dinv, seg_base, k);
+          const T u = fma(-row[k], xk, val);
+          val = r < k ? u : val;
+          x = r == k ? xk : x;
         }
       }
     }
     return x;
+  }
+
+  // 1 / U_rr of this lane's row in position order (1 on rows past n and on
+  // lanes without a row; an exactly zero pivot gives an infinity, as the
+  // division would).
+  __device__ static __forceinline__ T pivot_reciprocal(const T (&row)[NC], int r) {
+    T d = T(1);
+#pragma unroll
+    for (int j = 0; j < NC; ++j) d = r == j ? row[j] : d;
+    return T(1) / d;
   }
 
   // Lane (within the segment) that holds position r after factor(): the
