@@ -98,9 +98,12 @@ def fused_ops(G, W, torch, dev, n=1 << 26, warm=10, reps=50):
     out8 = torch.empty(8, dtype=torch.float64, device=dev)
     out1 = torch.empty(1, dtype=torch.float64, device=dev)
     ops = {
-        # device-to-device copy by the runtime: the streaming bandwidth this
-        # GPU reaches in practice, for context beside the 8 TB/s peak
-        "copy_reference": (lambda: z.copy_(X[0]), 2 * 8 * n),
+        # a plain copy (nvec_scale by 1: one 16-byte unit per thread,
+        # non-temporal): the streaming bandwidth this GPU reaches in practice,
+        # for context beside the 8 TB/s peak; the runtime's own device copy
+        # beside it
+        "copy_reference": (lambda: G.nvec_scale(1.0, X[0], z), 2 * 8 * n),
+        "runtime_copy": (lambda: z.copy_(X[0]), 2 * 8 * n),
         "linear_combination_16": (lambda: G.nvec_linear_combination(c, X, z), 17 * 8 * n),
         "dot_prod_multi_1x8": (lambda: G.nvec_dot_prod_multi(X[0], X[1:9], out=out8), 9 * 8 * n),
         "wrms_norm": (lambda: G.nvec_wrms_norm(X[2], w, out=out1), 2 * 8 * n),
@@ -530,7 +533,7 @@ def main():
         for _ in range(5):
             G.nvec_scale(1.0, x, z)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration": {"kernel": "k_scale", "bytes_read": 8 << 26,
+        print(json.dumps({"copy_calibration": {"kernel": "k_scale2", "bytes_read": 8 << 26,
                                                "bytes_written": 8 << 26, "launches": 5}}))
         return
     if args.profile_uneven > 0:

@@ -67,6 +67,26 @@ def test_linear_sum_scale_const_ewt(orc, dev, G, n):
     assert np.allclose(z.cpu().numpy(), orc.ewt(x, 1e-6, 1e-10), rtol=1e-15, atol=0)
 
 
+@pytest.mark.parametrize("n", [1, 2, 4099, 1 << 18 | 3])
+def test_scale_const_ewt_misaligned_and_in_place(orc, dev, G, n):
+    """8-byte offset views (element-by-element kernels), then the aligned
+    16-byte-unit kernels in place (z aliases x) with an odd tail."""
+    rng = W.rng_for(90 + n)
+    x = rng.uniform(-1, 1, n + 1)
+    base = T(x, dev)
+    xd = base[1:]
+    z = torch.empty(n + 1, dtype=torch.float64, device=dev)[1:]
+    G.nvec_scale(-0.75, xd, z)
+    assert np.array_equal(z.cpu().numpy(), orc.scale(-0.75, x[1:]))
+    G.nvec_ewt(xd, 1e-6, 1e-10, z)
+    assert np.allclose(z.cpu().numpy(), orc.ewt(x[1:], 1e-6, 1e-10), rtol=1e-15, atol=0)
+    G.nvec_const(7.5, z)
+    assert np.array_equal(z.cpu().numpy(), orc.const(7.5, n))
+    y = T(x[1:], dev)
+    G.nvec_scale(3.0, y, y)
+    assert np.array_equal(y.cpu().numpy(), orc.scale(3.0, x[1:]))
+
+
 @pytest.mark.parametrize("n", SIZES)
 @pytest.mark.parametrize("nv", [1, 3, 6])
 def test_scale_add_multi(orc, dev, G, n, nv):
