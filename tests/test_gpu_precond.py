@@ -9,8 +9,9 @@ a hidden activation whose value sits next to a BF16 rounding boundary can
 round one BF16 ulp (2^-8) the other way; a few such flips move an output by
 about 1e-3 of the output scale.  Outputs: max error <= 1e-2 of the largest
 output magnitude and mean error <= 1e-3 of it.  Loss: 1e-4 relative.
-Gradients (FP32 sums over a batch): relative 2-norm error <= 1e-2 per
-tensor.  Adam on identical gradients: FP32 rounding of the update, 1e-6
+Gradients (FP32 products over the same BF16 rounding points as the oracle,
+sums over a batch): relative 2-norm error <= 1e-3 per tensor (measured
+~2e-7).  Adam on identical gradients: FP32 rounding of the update, 1e-6
 relative.
 """
 import numpy as np
@@ -102,7 +103,7 @@ def test_loss_and_gradients_match_oracle(orc, dev, G, net):
     for name, a, b in zip(("W1", "b1", "W2", "b2", "W3", "b3"), gparts, g_ref):
         rel = np.linalg.norm(a.astype(np.float64) - b) / max(np.linalg.norm(b), 1e-300)
         print(f"  grad {name}: rel err {rel:.2e}")
-        assert rel <= 1e-2
+        assert rel <= 1e-3
 
 
 def test_adam_step_matches_oracle(orc, dev, G, net):
