@@ -608,8 +608,12 @@ def main():
     pb.close()
     p_ms, p_cnt = kt["newton"]
     p_att = ps1["nattempts"] - ps0["nattempts"]
-    if p_cnt != p_att:
-        raise RuntimeError(f"timed {p_cnt} Newton launches for {p_att} attempts")
+    # a launch runs two Newton iterations; an attempt the replay of those
+    # leaves undecided takes a continuation launch
+    p_cont = ps1["ncont"] - ps0["ncont"]
+    if p_cnt != p_att + p_cont:
+        raise RuntimeError(f"timed {p_cnt} Newton launches for {p_att} attempts and "
+                           f"{p_cont} continuations")
     q1 = (ps1["hist_reads"] - ps0["hist_reads"]) / max(p_att, 1)   # mean q + 1
     # The step's algorithmic bytes per cell are 8 (2 (q+1) n + R): the
     # history read and written once and the rates read once.  With the
@@ -620,13 +624,13 @@ def main():
     # 8 ((q+1) n + R), and the update's the write half.
     deferred = kt["accept"][1] == 0
     if deferred:
-        bytes_per_launch = 8.0 * args.cells * (2 * q1 * n + R) * ptaken / max(p_att, 1)
+        bytes_per_launch = 8.0 * args.cells * (2 * q1 * n + R) * ptaken / max(p_cnt, 1)
         alg = "8 * cells * (2 (q+1) n + R) per accepted step (history read and written, rates " \
               "read), times accepted steps per launch"
     else:
         bytes_per_launch = 8.0 * args.cells * (q1 * n + R)
         alg = "8 * cells * ((q+1) * n + R): history read + rates"
-    avg_ms = p_ms / max(p_att, 1)
+    avg_ms = p_ms / max(p_cnt, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     sha = sources_hash(NEWTON_SOURCES)
     traffic = (MEASURED_TRAFFIC["bytes"]
@@ -645,6 +649,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "newton_sources_sha256_16": sha,
                 "avg_launch_ms": round(avg_ms, 4), "launches": p_cnt, "attempts": p_att,
+                "continuations": p_cont,
                 "algorithmic_bytes_per_launch": int(bytes_per_launch),
                 "algorithmic_bytes": alg, "deferred_history_update": deferred,
                 "mean_q_plus_1": round(q1, 3),

@@ -339,6 +339,8 @@ typedef struct {
   int q, qu, qwait, status;
   long nstale_retries;    /* lazy: attempts redone with fresh factors */
   long nliters;           /* GMRES iterations */
+  long ncont;             /* Newton kernel launches that continued an attempt's
+                             iterations (two iterations per launch) */
 } bdf_stats;
 
 typedef struct bdf_handle bdf_handle;

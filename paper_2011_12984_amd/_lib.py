@@ -44,7 +44,7 @@ class BdfStats(C.Structure):
         ("order_hist", C.c_long * 6), ("t", C.c_double), ("h", C.c_double),
         ("hu", C.c_double), ("err_last", C.c_double), ("q", C.c_int), ("qu", C.c_int),
         ("qwait", C.c_int), ("status", C.c_int), ("nstale_retries", C.c_long),
-        ("nliters", C.c_long)]
+        ("nliters", C.c_long), ("ncont", C.c_long)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "order_hist"}

@@ -549,7 +549,7 @@ static int drive_krylov(bdf_handle* h, double* tret) {
       return h->hC->status;
     }
     if (ph == PH_DONE || ph == PH_PAUSE) break;
-    const long progress = h->hC->nattempts + h->hC->nsteps;
+    const long progress = h->hC->nattempts + h->hC->nsteps + h->hC->ncont;
     if (progress == last_progress) {
       set_last_error("integrator made no progress (phase stuck)", __FILE__, __LINE__);
       return BDFGPU_ERR_HIP;
@@ -603,7 +603,7 @@ static int drive(bdf_handle* h, double tend, long inc, double* tret) {
       BDF_HIP_TRY(hipStreamSynchronize(h->s));
       break;
     }
-    const long progress = h->hC->nattempts + h->hC->nsteps;
+    const long progress = h->hC->nattempts + h->hC->nsteps + h->hC->ncont;
     if (progress == last_progress) {
       set_last_error("integrator made no progress (phase stuck)", __FILE__, __LINE__);
       return BDFGPU_ERR_HIP;
@@ -1105,6 +1105,11 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   C.vc = o->vc ? 1 : 0;
   C.lazy = o->lazy ? 1 : 0;
   C.krylov = h->krylov ? 1 : 0;
+  // two Newton iterations per fused launch (a third, when the replay of the
+  // first two leaves the attempt undecided, in a continuation launch); the
+  // learned mode keeps per-cell state across its iterations and the GMRES
+  // path drives its iterations from the host, so they run all in one
+  C.kiters = (C.learned || C.krylov || o->maxcor < 2) ? o->maxcor : 2;
   C.kap = 1.0;
   C.dscale = 1.0;
   C.setup = 1;
@@ -1410,6 +1415,7 @@ int bdf_get_stats(bdf_handle* h, bdf_stats* s) {
   s->lp_cell_solves = C.lp_cell_solves;
   s->lp_fallback_cells = C.lp_fallback_cells;
   s->lp_step_fallbacks = C.lp_step_fallbacks;
+  s->ncont = C.ncont;
   for (int j = 0; j < 6; ++j) s->order_hist[j] = C.order_hist[j];
   s->t = C.t;
   s->h = C.h;

@@ -106,6 +106,12 @@ struct Ctrl {
   double gamma_s, dscale, crate_keep;
   long nst_s, nstale_retries;
   int krylov, pad4;          // Newton-Krylov: GMRES solves the current M (no scaling)
+  // Newton iterations per launch of the fused kernel (kiters <= maxcor):
+  // a launch runs iterations m0 .. m0 + kiters - 1; when the replay of
+  // their sums leaves the attempt undecided, m0 moves on and the next
+  // launch continues from the stored iterate (the phase stays PH_PREDICT)
+  int kiters, m0;
+  long ncont;                // continuation launches
   long nliters;              // GMRES iterations
   long step_limit;
   long nsteps, nattempts, nfevals, nsetups, nniters, nncfails, netfails;
@@ -190,6 +196,7 @@ __device__ inline void prepare_attempt(Ctrl* C) {
   set_coeffs(C);
   C->gamma = C->h * C->l[0];
   C->m = 0;
+  C->m0 = 0;
   C->crate = 1.0;
   C->dold = 0.0;
   C->phase = PH_PREDICT;
@@ -289,7 +296,10 @@ __device__ inline void after_newton_all(Ctrl* C, const double* s) {
     C->restart = 0;
   }
   C->upd = 0;         // the Newton kernel applied any pending history update
-  for (int m = 0; m < C->maxcor; ++m) {
+  const int m0 = C->m0;
+  const int m1 = m0 + C->kiters < C->maxcor ? m0 + C->kiters : C->maxcor;
+  C->m0 = 0;
+  for (int m = m0; m < m1; ++m) {
     const double* t = s + kRedPerIter * m;
     C->nfevals++;
     C->nniters++;
@@ -343,6 +353,11 @@ __device__ inline void after_newton_all(Ctrl* C, const double* s) {
     if (m + 1 == C->maxcor) return newton_failed(C);
     if (m >= 1 && d > kRdiv * C->dold) return newton_failed(C);
     C->dold = d;
+  }
+  if (m1 < C->maxcor) {   // undecided: the next launch continues at m1
+    C->m0 = m1;
+    C->ncont++;
+    return;
   }
   newton_failed(C);
 }

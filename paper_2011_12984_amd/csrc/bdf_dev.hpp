@@ -803,6 +803,10 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
     const double l0 = C->l[0];
     const int q = C->q;
     const int maxcor = C->maxcor;
+    // this launch's iterations (a continuation starts at m0 > 0 from the
+    // stored iterate of iteration m0 - 1)
+    const int m0 = C->m0;
+    const int m1 = m0 + C->kiters < maxcor ? m0 + C->kiters : maxcor;
     // deferred update: if accepted, this step selects the order (qwait == 1),
     // so each iteration also sums the selection's norms
     const bool sel = C->fuse && C->qwait == 1;
@@ -899,12 +903,18 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
     const double dscale = C->dscale;
     bool fp64 = (LS == 1) && info != 0;   // LS 1: FP32 factor singular -> FP64 LU
     bool sing = (LS == 0 || LS == 3) && info != 0;
-    red[4] = fp64 ? 1.0 : 0.0;            // counted with the first iteration
+    red[4] = fp64 && m0 == 0 ? 1.0 : 0.0;   // counted with the first iteration
     double y[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) y[i] = zp0[i];
+    if (m0 > 0) {
+      const double* yp = K.ys[m0 - 1];
+#pragma unroll
+      for (int i = 0; i < NP; ++i)
+        if (i < n) y[i] = yp[TP::idx(c, i, n)];
+    }
     double* yev = LS == 1 ? xcol : ycol;   // LS 1 keeps z(0)[0] in ycol for J
-    for (int m = 0; m < maxcor; ++m) {
+    for (int m = m0; m < m1; ++m) {
       TP::store_col(yev, y);
       double r[NP];
       Net::template rhs<NP, TB>(nd, kcol, TB, yev, r);

@@ -405,6 +405,10 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   const double* kap = lk + cb * spc_rpad(K.R);
   const double gamma = C->gamma;
   const int maxcor = C->maxcor;
+  // this launch's iterations (a continuation starts at m0 > 0 from the
+  // stored iterate of iteration m0 - 1)
+  const int m0 = C->m0;
+  const int m1 = m0 + C->kiters < maxcor ? m0 + C->kiters : maxcor;
   double zp0 = 0.0, cv = 0.0, w = 0.0;
   if (LS != 2) {
     spc_predict_row<SEG>(D, C, sh, sb, i, act, row, id, kap, St, zp0, cv, w);
@@ -511,6 +515,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   }
   if (LS == 1 && fp64 && act && i == 0) wsum[4] = 1.0;   // FP32 factor singular at setup
   double y = zp0;
+  if (m0 > 0 && row) y = K.ys[m0 - 1][id];
   // LS 1 with whole-wave segments (one cell per wave): the FP32-refined
   // iterations run on their own path (P 1), and a cell that needs FP64 LU
   // leaves it for a path that holds the FP64 factors and no FP32 ones (P 2),
@@ -635,7 +640,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
       wave_add(sd, ws + 0);
       wave_add(sa, ws + 1);
       wave_add(neg, ws + 2);
-      if constexpr (LS == 1) {
+      if constexpr (LS == 1 && SEG == 64) {
         wave_add(lead ? (double)sweeps : 0.0, ws + 3);
         wave_add(lead ? (double)fb : 0.0, ws + 4);
       }
@@ -655,18 +660,18 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
     }
     return true;
   };
-  if constexpr (LS == 1 && SEG == 64) {
-    int m = 0;
+  if constexpr (LS == 1) {
+    int m = m0;
     if (!fp64)
-      for (; m < maxcor; ++m)
+      for (; m < m1; ++m)
         if (!iterate(m, std::integral_constant<int, 1>{})) break;
-    if (m < maxcor) {   // uniform over the wave
+    if (m < m1) {   // uniform over the wave
       assemble();
       info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
-      for (; m < maxcor; ++m) iterate(m, std::integral_constant<int, 2>{});
+      for (; m < m1; ++m) iterate(m, std::integral_constant<int, 2>{});
     }
   } else {
-    for (int m = 0; m < maxcor; ++m) iterate(m, std::integral_constant<int, 0>{});
+    for (int m = m0; m < m1; ++m) iterate(m, std::integral_constant<int, 0>{});
   }
   if constexpr (kLdsSums) {
 #pragma unroll
