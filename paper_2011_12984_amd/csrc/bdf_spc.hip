@@ -16,19 +16,18 @@ static void raise_lds(KF* kern, size_t lds, size_t& raised) {
 }
 
 // Waves per SIMD asked of the segment Newton kernel (0: as many as its
-// registers allow).  Learned mode at 24 columns and the FP32-refined solver
-// at 48 and 64 columns need more registers than two waves allow, mostly for
-// paths that rarely run (the FP64 fallback); the hint makes them fit, with
-// spills around those paths.  The FP32-refined 16-, 24- and 32-column
-// kernels sit a few registers above four, three and three waves, the FP64 LU
-// and Gauss-Jordan 64-column kernels a few above two.
+// registers allow).  Learned mode at 24 columns needs more registers than
+// two waves allow, mostly for a path that rarely runs (the LU fallback); the
+// FP32-refined 48- and 64-column kernels fit three waves with their spills
+// on the FP64 path; the FP32-refined 24- and 32-column kernels sit a few
+// registers above four and three waves, the FP64 LU and Gauss-Jordan
+// 64-column kernels a few above two.
 template <int SEG, int LS, int NC>
 constexpr int newton_waves() {
   if (SEG == 32 && LS == 2 && NC == 24) return 2;
   if (SEG == 64 && LS == 1 && (NC == 48 || NC == 64)) return 3;
-  if (SEG == 32 && LS == 1 && NC == 24) return 3;
+  if (SEG == 32 && LS == 1 && NC == 24) return 4;
   if (SEG == 32 && LS == 1 && NC == 32) return 3;
-  if (SEG == 16 && LS == 1 && NC == 16) return 4;
   if (SEG == 64 && (LS == 0 || LS == 3) && NC == 64) return 2;   // FP64 LU, inverse: ~280
   return 0;
 }

@@ -440,7 +440,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
   float L[LS == 1 ? NC : 1];
   int pos32 = i, piv32 = i, src32 = i;
   float dinv32 = 1.0f;
-  bool fp64 = LS == 0;
+  bool fp64 = LS == 0, sing32 = false;
   double mnorm = 0.0;
   // LS 2 state
   int mode = 0;                           // 2 learned, 3 switching to LU, 4 LU
@@ -488,7 +488,9 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
     mnorm = seg_max<SEG>(rs);
     const int inf32 =
         SpcLU<SEG, float, NC>::factor(L, i, nn, pos32, piv32, sh.prow32 + sb, sh.wl32 + sb);
-    fp64 = inf32 != 0;
+    // a singular FP32 factor sends the segment's wave to FP64 LU (below)
+    sing32 = inf32 != 0;
+    fp64 = __any(sing32) != 0;
     // rows to position order: each right-hand side is read from lane src32
     src32 = SpcLU<SEG, float, NC>::position_source(i, nn, sh.wl32 + sb);
     SpcLU<SEG, float, NC>::to_position_order(L, seg_base, src32);
@@ -513,14 +515,15 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
 #pragma unroll
     for (int j = 0; j < NC; ++j) Xrow[j] = (mode == 2 && row && j < n) ? Xrow[j] : 0.0f;
   }
-  if (LS == 1 && fp64 && act && i == 0) wsum[4] = 1.0;   // FP32 factor singular at setup
+  if (LS == 1 && sing32 && act && i == 0) wsum[4] = 1.0;   // FP32 factor singular at setup
   double y = zp0;
   if (m0 > 0 && row) y = K.ys[m0 - 1][id];
-  // LS 1 with whole-wave segments (one cell per wave): the FP32-refined
-  // iterations run on their own path (P 1), and a cell that needs FP64 LU
-  // leaves it for a path that holds the FP64 factors and no FP32 ones (P 2),
-  // redoing the iteration whose refinement failed; its sweeps and the
-  // fallback are counted at that iteration.
+  // LS 1: the FP32-refined iterations run on their own path (P 1).  When a
+  // cell of the wave needs FP64 LU (a singular FP32 factor, or a refinement
+  // that fails), the whole wave leaves it for a path that holds the FP64
+  // factors and no FP32 ones (P 2), redoing the iteration whose refinement
+  // failed; the cells that needed it count as fallbacks (with their sweeps)
+  // at that iteration, the others of the wave are solved by FP64 LU too.
   int sweeps_p = 0, fb_p = 0;
   auto iterate = [&](int m, auto path) -> bool {
     constexpr int P = decltype(path)::value;
@@ -576,20 +579,11 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
           dprv = dn;
         }
         del = x;
-        if (!ok) {
-          fb = 1;
-          fp64 = true;
-          if constexpr (P == 1) {
-            sweeps_p = sweeps;
-            fb_p = 1;
-            return false;
-          }
+        if (__any(!ok)) {   // uniform over the wave
+          sweeps_p = sweeps;
+          fb_p = ok ? 0 : 1;
+          return false;
         }
-      }
-      if (P == 0 && !ok) {   // FP64 M formed and factored again at each such iteration
-        assemble();
-        info = SpcLU<SEG, double, NC>::factor(Mrow, i, nn, pos, piv, sh.prow + sb, sh.wl + sb);
-        del = SpcLU<SEG, double, NC>::solve(Mrow, i, seg_base, nn, pos, sh.wl + sb, r);
       }
     } else {
       if (mode == 2) {
@@ -640,7 +634,7 @@ __device__ __forceinline__ void spc_newton_body(const BdfDev& D, long blk, doubl
       wave_add(sd, ws + 0);
       wave_add(sa, ws + 1);
       wave_add(neg, ws + 2);
-      if constexpr (LS == 1 && SEG == 64) {
+      if constexpr (LS == 1) {
         wave_add(lead ? (double)sweeps : 0.0, ws + 3);
         wave_add(lead ? (double)fb : 0.0, ws + 4);
       }
