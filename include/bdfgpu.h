@@ -325,6 +325,13 @@ typedef struct {
                              size; needs FP64 LU, Gauss-Jordan or GMRES,
                              per-class launches (not BDFGPU_LAUNCH_FUSED) and
                              not per_cell. */
+  int newton_per_launch;  /* Newton iterations per launch of the fused Newton
+                             kernel, 1..maxcor (0: 2).  When the replay of a
+                             launch's iterations leaves the attempt undecided,
+                             the next launch continues from the stored iterate;
+                             decisions and results do not depend on it.  The
+                             learned preconditioner and GMRES run all maxcor
+                             iterations in one launch. */
 } bdf_options;
 
 typedef struct {

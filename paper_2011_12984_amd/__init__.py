@@ -284,13 +284,15 @@ class Bdf:
     (concatenated per cell).  jit: compile network-specialised Newton
     kernels for the one-lane-per-cell classes (bitwise the same results).
     defer: apply each accepted step's history update in the next attempt's
-    Newton kernel (where the classes allow it) instead of a separate pass."""
+    Newton kernel (where the classes allow it) instead of a separate pass.
+    newton_per_launch: Newton iterations per launch of the fused kernel
+    (0: 2); the results do not depend on it."""
 
     def __init__(self, topologies, cell_topo, rates, y0, t0=0.0, rtol=1e-6, atol=1e-10,
                  qmax=5, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64, refine_max_it=5,
                  max_steps=0, mode=MODE_STREAM, attempts_per_sync=8, nonneg=False,
                  precond=None, launch=LAUNCH_PER_CLASS, map_small=0, jit=False, defer=True,
-                 workspace=None, per_cell=False, vc=False, lazy=False):
+                 workspace=None, per_cell=False, vc=False, lazy=False, newton_per_launch=0):
         torch = _torch()
         _dev(rates, torch.float64)
         _dev(y0, torch.float64)
@@ -310,7 +312,7 @@ class Bdf:
                           mode, attempts_per_sync, launch,
                           precond.h if precond is not None else None, int(bool(nonneg)),
                           int(map_small), int(bool(jit)), int(not defer), int(bool(per_cell)),
-                          int(bool(vc)), int(bool(lazy)))
+                          int(bool(vc)), int(bool(lazy)), int(newton_per_launch))
         h = vp()
         if workspace is None:
             check("bdf_create", lib().bdf_create(C.byref(prob), C.byref(opts), _stream(),
@@ -338,7 +340,7 @@ class Bdf:
     def _sizing(prob, rtol=None, atol=None, qmax=None, maxcor=3, h0=0.0, hmin=0.0, linsol=LS_LU64,
                 refine_max_it=5, max_steps=0, mode=MODE_STREAM, attempts_per_sync=8,
                 nonneg=None, launch=LAUNCH_PER_CLASS, map_small=0, jit=False, defer=True,
-                precond=None, per_cell=False, vc=False, lazy=False):
+                precond=None, per_cell=False, vc=False, lazy=False, newton_per_launch=0):
         topologies = prob["topologies"]
         topo_n = np.array([nu.shape[1] for nu, _ in topologies], np.int32)
         topo_R = np.array([nu.shape[0] for nu, _ in topologies], np.int32)
@@ -355,7 +357,7 @@ class Bdf:
                           precond.h if precond is not None else None,
                           int(bool(prob.get("nonneg", False) if nonneg is None else nonneg)),
                           int(map_small), int(bool(jit)), int(not defer), int(bool(per_cell)),
-                          int(bool(vc)), int(bool(lazy)))
+                          int(bool(vc)), int(bool(lazy)), int(newton_per_launch))
         return int(lib().bdf_workspace_bytes(C.byref(pr), C.byref(opts)))
 
     @classmethod

@@ -33,7 +33,7 @@ class BdfOptions(C.Structure):
                 ("mode", C.c_int), ("attempts_per_sync", C.c_int), ("launch", C.c_int),
                 ("precond", vp), ("nonneg", C.c_int), ("map_small", C.c_int),
                 ("jit", C.c_int), ("no_defer", C.c_int), ("per_cell", C.c_int),
-                ("vc", C.c_int), ("lazy", C.c_int)]
+                ("vc", C.c_int), ("lazy", C.c_int), ("newton_per_launch", C.c_int)]
 
 
 class BdfStats(C.Structure):

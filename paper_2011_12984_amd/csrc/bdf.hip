@@ -681,7 +681,7 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
       (p->ncells > 0 && (!p->cell_topo || (!dry && (!p->rates || !p->y0)))))
     return arg_error("bdf_create: bad problem description");
   if (o->qmax < 1 || o->qmax > kQmaxAll || o->maxcor < 1 || o->maxcor > kMaxCor ||
-      !(o->rtol >= 0.0) || !(o->atol > 0.0) ||
+      o->newton_per_launch < 0 || !(o->rtol >= 0.0) || !(o->atol > 0.0) ||
       (o->linsol != BDFGPU_LS_LU64 && o->linsol != BDFGPU_LS_LU32REF &&
        o->linsol != BDFGPU_LS_LEARNED && o->linsol != BDFGPU_LS_GJ &&
        o->linsol != BDFGPU_LS_GMRES) ||
@@ -1105,11 +1105,14 @@ static int create_impl(const bdf_problem* p, const bdf_options* o, void* stream,
   C.vc = o->vc ? 1 : 0;
   C.lazy = o->lazy ? 1 : 0;
   C.krylov = h->krylov ? 1 : 0;
-  // two Newton iterations per fused launch (a third, when the replay of the
-  // first two leaves the attempt undecided, in a continuation launch); the
+  // two Newton iterations per fused launch unless asked otherwise (a third,
+  // when the replay of the first two leaves the attempt undecided, in a
+  // continuation launch); the
   // learned mode keeps per-cell state across its iterations and the GMRES
   // path drives its iterations from the host, so they run all in one
-  C.kiters = (C.learned || C.krylov || o->maxcor < 2) ? o->maxcor : 2;
+  C.kiters = (C.learned || C.krylov) ? o->maxcor
+             : o->newton_per_launch > 0 ? std::min(o->newton_per_launch, o->maxcor)
+                                        : std::min(2, o->maxcor);
   C.kap = 1.0;
   C.dscale = 1.0;
   C.setup = 1;

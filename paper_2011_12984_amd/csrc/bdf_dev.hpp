@@ -817,6 +817,13 @@ __device__ __forceinline__ void tpc_newton_body(const BdfDev& D, long blk, doubl
       double acp[NP];
       if (C->fuse && C->upd) {
         tpc_apply_update<NP, VC>(D, c, n, zs, acp);
+        // a continuation launch of this attempt reads acor_prev back for
+        // the order selection's sums
+        if (selp1) {
+#pragma unroll
+          for (int i = 0; i < NP; ++i)
+            if (i < n) K.dprev[TP::idx(c, i, n)] = acp[i];
+        }
 #pragma unroll
         for (int j = 0; j <= kQmaxAll; ++j) {
           const double hsj = C->hs[j];

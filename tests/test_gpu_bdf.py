@@ -325,6 +325,37 @@ def test_deferred_update_matches_separate_update(dev, G, linsol, jit):
     assert sa["order_hist"][3] > 0          # the order selection ran (and raised)
 
 
+@pytest.mark.parametrize("prob,kw", [
+    ("net10", dict(jit=True)),                 # one lane per cell, deferred history update
+    ("uneven", dict(linsol=1)),                # segment classes, FP32-refined LU
+    ("uneven", dict(linsol=0, lazy=True)),     # lazy Newton matrix: setup and reuse kernels
+])
+def test_newton_continuation_launches_bitwise(dev, G, prob, kw):
+    """An attempt's Newton iterations split over launches (1, 2 or all 3 per
+    launch; a later launch continues from the stored iterate and forms the
+    predictor, J and the factors again) give the same trajectory bit for
+    bit: the same counters, t, h and states after 300 steps.  The
+    one-iteration-per-launch run takes continuation launches, the
+    all-in-one run none."""
+    p = (W.random_network_batch(1000, n=10, seed=41) if prob == "net10"
+         else W.uneven_batch(1 << 12, seed=9))
+    runs = []
+    for npl in (1, 2, 3):
+        b = gpu_bdf(G, p, dev, newton_per_launch=npl, **kw)
+        _, taken = b.advance(p.t_end, 300)
+        assert taken == 300
+        runs.append((b.stats(), b.y().cpu()))
+        b.close()
+    print({npl: (s["nattempts"], s["nniters"], s["ncont"]) for npl, (s, _) in zip((1, 2, 3), runs)})
+    s1, y1 = runs[0]
+    assert s1["ncont"] > 0 and runs[2][0]["ncont"] == 0
+    for s, y in runs[1:]:
+        for k in ("nsteps", "nattempts", "nniters", "netfails", "nncfails", "order_hist"):
+            assert s[k] == s1[k], k
+        assert s["t"] == s1["t"] and s["h"] == s1["h"]
+        assert torch.equal(y, y1)
+
+
 @pytest.mark.parametrize("kw", [dict(jit=True), dict(linsol=1, launch=2, mode=1)])
 def test_caller_workspace(dev, G, kw):
     """A handle whose device state lives in caller memory sized by
