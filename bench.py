@@ -34,7 +34,7 @@ NEWTON_SOURCES = ("paper_2011_12984_amd/csrc/bdf_dev.hpp", "paper_2011_12984_amd
 # FETCH_SIZE / WRITE_SIZE counter runs scaled by a plain copy kernel (the
 # traffic summary under profiles/), with the hash of NEWTON_SOURCES they
 # were taken at: reported only while the sources still hash to it.
-MEASURED_TRAFFIC = {"sha256_16": "d38a948aa287cc6a", "bytes": 1430300562}
+MEASURED_TRAFFIC = {"sha256_16": "f350373e5de32fdd", "bytes": 1430296658}
 
 
 def log(*a):
