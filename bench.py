@@ -236,7 +236,30 @@ def uneven_leg(G, W, torch, dev, warmup, steps, jit=True, linsol=None, lazy=Fals
     b.close()
     names = {(0, 0): "per_class_tpc", (0, 1): "per_class_spc16", (1, 0): "one_launch_tpc",
              (1, 1): "one_launch_spc16"}
+    # The step's bound: max(algorithmic bytes at 8 TB/s, LU flops at the
+    # vector peak of the factorisation's type).  Bytes per cell-step
+    # 8 (2 (q+1) n + R) (history read and written once, rates read once, the
+    # run's mean q + 1); flops per factorisation n(n-1)/2 + (n-1)n(2n-1)/3,
+    # times factorisations (set-ups) per step.
+    import numpy as np
+    ct = np.asarray(prob.cell_topo)
+    n_c = np.array([nu.shape[1] for nu, _ in prob.topologies], np.float64)[ct]
+    r_c = np.array([nu.shape[0] for nu, _ in prob.topologies], np.float64)[ct]
+    att = max(s1["nattempts"] - s0["nattempts"], 1)
+    q1 = (s1["hist_reads"] - s0["hist_reads"]) / att
+    step_bytes = 8.0 * float(np.sum(2.0 * q1 * n_c + r_c))
+    setups = (s1["nsetups"] - s0["nsetups"]) / max(taken, 1)
+    lu_flops = float(np.sum(n_c * (n_c - 1) / 2 + (n_c - 1) * n_c * (2 * n_c - 1) / 3)) * setups
+    fp32 = (G.LS_LU32REF if linsol is None else linsol) == G.LS_LU32REF
+    t_hbm = step_bytes / (HBM_PEAK_GBS * 1e9) * 1e3
+    t_alu = lu_flops / ((157.3e12 if fp32 else 78.6e12)) * 1e3
+    ms_step = 1e3 * dt / max(taken, 1)
+    roof = {"bound": "hbm" if t_hbm >= t_alu else "alu", "bound_ms_per_step": round(max(t_hbm, t_alu), 4),
+            "algorithmic_bytes_per_step": int(step_bytes), "lu_flops_per_step": int(lu_flops),
+            "mean_q_plus_1": round(q1, 3), "frac": round(max(t_hbm, t_alu) / ms_step, 4),
+            "peaks": "8 TB/s; FP32 157.3 / FP64 78.6 TFLOP/s vector"}
     return {"cells": prob.ncells, "unknowns": prob.N, "value": round(prob.ncells * taken / dt, 1),
+            "roofline": roof,
             "unit": "cell-steps/s", "ms_per_step": round(1e3 * dt / max(taken, 1), 4),
             "chosen": names[(tu["launch"], tu["map_small"])],
             "candidates_ms_per_step": {names[k]: round(v, 4) for k, v in tu["ms_per_step"].items()},
