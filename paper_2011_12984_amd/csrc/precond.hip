@@ -377,85 +377,112 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_mfma(long B, int n, const doubl
   }
   __syncthreads();
   const int row = l & 31, kh = l >> 5;
-  // ---- layer 1 (K = 32) and layer 2 (K = 256): all 8 output tiles in registers
+  // The two waves of a pair (waves 2p and 2p + 1) split each layer's
+  // output tiles and compute them for the pair's 64 samples (both waves'
+  // activations are in LDS), so every weight fragment loaded from L2 feeds
+  // two MFMAs.  Each output's MFMA sequence over k is the one a single wave
+  // would run.
+  unsigned short* Ap[2] = {act[wave & ~1], act[wave | 1]};
+  const long sp[2] = {((long)blockIdx.x * 4 + (wave & ~1)) * 32,
+                      ((long)blockIdx.x * 4 + (wave | 1)) * 32};
+  const int half = wave & 1;
+  // ---- layer 1 (K = 32) and layer 2 (K = 256): 8 output tiles, 4 per wave
   for (int layer = 0; layer < 2; ++layer) {
     const int K = layer == 0 ? 32 : kMlpHid;
     const unsigned short* W = layer == 0 ? w1b : w2b;
     const float* bias = layer == 0 ? b1 : b2;
-    f32x16 acc[8];
+    f32x16 acc[4][2];
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[t][g][v] = 0.f;
     // weight fragments of the next k step are loaded while this step's
-    // MFMAs run (each wave streams the weights from L2; without the overlap
-    // every MFMA waited for its own load)
-    const unsigned short* Wl = W + (long)row * K + 8 * kh;
-    bf16x8 bcur[8], bnext[8];
+    // MFMAs run (without the overlap every MFMA waited for its own load)
+    const unsigned short* Wl = W + (long)(half * 4 * 32 + row) * K + 8 * kh;
+    bf16x8 bcur[4], bnext[4];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) bcur[t] = *reinterpret_cast<const bf16x8*>(&Wl[(long)t * 32 * K]);
+    for (int t = 0; t < 4; ++t) bcur[t] = *reinterpret_cast<const bf16x8*>(&Wl[(long)t * 32 * K]);
     for (int k0 = 0; k0 < K; k0 += 16) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&A[row * kMlpRowPad + k0 + 8 * kh]);
+      const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&Ap[0][row * kMlpRowPad + k0 + 8 * kh]);
+      const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&Ap[1][row * kMlpRowPad + k0 + 8 * kh]);
       const int kn = k0 + 16 < K ? k0 + 16 : k0;   // (the last step reloads its own)
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
+      for (int t = 0; t < 4; ++t)
         bnext[t] = *reinterpret_cast<const bf16x8*>(&Wl[(long)t * 32 * K + kn]);
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bcur[t], acc[t], 0, 0, 0);
+      for (int t = 0; t < 4; ++t) {
+        acc[t][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bcur[t], acc[t][0], 0, 0, 0);
+        acc[t][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bcur[t], acc[t][1], 0, 0, 0);
+      }
 #pragma unroll
-      for (int t = 0; t < 8; ++t) bcur[t] = bnext[t];
+      for (int t = 0; t < 4; ++t) bcur[t] = bnext[t];
     }
     __syncthreads();   // every lane finished reading this layer's input
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int col = t * 32 + row;
+    for (int t = 0; t < 4; ++t) {
+      const int col = (half * 4 + t) * 32 + row;
       const float bb = bias[col];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int r = 8 * (v >> 2) + 4 * kh + (v & 3);
-        const float x = acc[t][v] + bb;
-        A[r * kMlpRowPad + col] = f2bf(x > 0.f ? x : 0.f);
-      }
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int r = 8 * (v >> 2) + 4 * kh + (v & 3);
+          const float x = acc[t][g][v] + bb;
+          Ap[g][r * kMlpRowPad + col] = f2bf(x > 0.f ? x : 0.f);
+        }
     }
     __syncthreads();
   }
-  // ---- layer 3 (K = 256, nout_pad / 32 tiles, two at a time; the next
-  // k step's weight fragments load during this step's MFMAs)
-  for (int t0 = 0; t0 < nout_pad / 32; t0 += 2) {
-    f32x16 acc[2];
+  // ---- layer 3 (K = 256, nout_pad / 32 output tiles, split between the
+  // pair as above; tiles two at a time, the next k step's weight fragments
+  // loading during the current MFMAs)
+  const int ntile = nout_pad / 32;
+  const int tb = half ? (ntile + 1) / 2 : 0, te = half ? ntile : (ntile + 1) / 2;
+  for (int t0 = tb; t0 < te; t0 += 2) {
+    f32x16 acc[2][2];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[u][v] = 0.f;
-    // a second tile past nout_pad reads the first tile's rows (in bounds);
-    // its MFMAs are skipped
-    const bool two = (t0 + 1) * 32 < nout_pad;
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[u][g][v] = 0.f;
+    // a second tile past this wave's range reads the first tile's rows (in
+    // bounds); its MFMAs are skipped
+    const bool two = t0 + 1 < te;
     const unsigned short* W0 = w3b + (long)(t0 * 32 + row) * kMlpHid + 8 * kh;
     const unsigned short* W1 = two ? W0 + 32L * kMlpHid : W0;
     bf16x8 c0 = *reinterpret_cast<const bf16x8*>(W0);
     bf16x8 c1 = *reinterpret_cast<const bf16x8*>(W1);
     for (int k0 = 0; k0 < kMlpHid; k0 += 16) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&A[row * kMlpRowPad + k0 + 8 * kh]);
+      const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&Ap[0][row * kMlpRowPad + k0 + 8 * kh]);
+      const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&Ap[1][row * kMlpRowPad + k0 + 8 * kh]);
       const int kn = k0 + 16 < kMlpHid ? k0 + 16 : k0;
       const bf16x8 n0 = *reinterpret_cast<const bf16x8*>(W0 + kn);
       const bf16x8 n1 = *reinterpret_cast<const bf16x8*>(W1 + kn);
-      acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, c0, acc[0], 0, 0, 0);
-      if (two) acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, c1, acc[1], 0, 0, 0);
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, c0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, c0, acc[0][1], 0, 0, 0);
+      if (two) {
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, c1, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, c1, acc[1][1], 0, 0, 0);
+      }
       c0 = n0;
       c1 = n1;
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int col = (t0 + u) * 32 + row;
-      if (col >= nout) continue;
+      if (col >= nout || (u == 1 && !two)) continue;
       const float bb = b3[col];
       const bool diag = (col / n) == (col % n);
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const long s = s0 + 8 * (v >> 2) + 4 * kh + (v & 3);
-        if (s < B) out[s * nout + col] = acc[u][v] + bb + (diag ? 1.0f : 0.0f);
-      }
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const long s = sp[g] + 8 * (v >> 2) + 4 * kh + (v & 3);
+          if (s < B) out[s * nout + col] = acc[u][g][v] + bb + (diag ? 1.0f : 0.0f);
+        }
     }
   }
 }
