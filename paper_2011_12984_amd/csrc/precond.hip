@@ -377,55 +377,53 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_mfma(long B, int n, const doubl
   }
   __syncthreads();
   const int row = l & 31, kh = l >> 5;
-  // The two waves of a pair (waves 2p and 2p + 1) split each layer's
-  // output tiles and compute them for the pair's 64 samples (both waves'
-  // activations are in LDS), so every weight fragment loaded from L2 feeds
-  // two MFMAs.  Each output's MFMA sequence over k is the one a single wave
-  // would run.
-  unsigned short* Ap[2] = {act[wave & ~1], act[wave | 1]};
-  const long sp[2] = {((long)blockIdx.x * 4 + (wave & ~1)) * 32,
-                      ((long)blockIdx.x * 4 + (wave | 1)) * 32};
-  const int half = wave & 1;
-  // ---- layer 1 (K = 32) and layer 2 (K = 256): 8 output tiles, 4 per wave
+  // The block's four waves split each layer's output tiles and compute
+  // them for all 128 samples of the block (every wave's activations are in
+  // LDS), so every weight fragment loaded from L2 feeds four MFMAs.  Each
+  // output's MFMA sequence over k is the one a single wave would run.
+  unsigned short* Ap[4] = {act[0], act[1], act[2], act[3]};
+  // ---- layer 1 (K = 32) and layer 2 (K = 256): 8 output tiles, 2 per wave
   for (int layer = 0; layer < 2; ++layer) {
     const int K = layer == 0 ? 32 : kMlpHid;
     const unsigned short* W = layer == 0 ? w1b : w2b;
     const float* bias = layer == 0 ? b1 : b2;
-    f32x16 acc[4][2];
+    f32x16 acc[2][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int g = 0; g < 2; ++g)
+      for (int g = 0; g < 4; ++g)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[t][g][v] = 0.f;
     // weight fragments of the next k step are loaded while this step's
     // MFMAs run (without the overlap every MFMA waited for its own load)
-    const unsigned short* Wl = W + (long)(half * 4 * 32 + row) * K + 8 * kh;
-    bf16x8 bcur[4], bnext[4];
+    const unsigned short* Wl = W + (long)(wave * 2 * 32 + row) * K + 8 * kh;
+    bf16x8 bcur[2], bnext[2];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) bcur[t] = *reinterpret_cast<const bf16x8*>(&Wl[(long)t * 32 * K]);
+    for (int t = 0; t < 2; ++t) bcur[t] = *reinterpret_cast<const bf16x8*>(&Wl[(long)t * 32 * K]);
     for (int k0 = 0; k0 < K; k0 += 16) {
-      const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&Ap[0][row * kMlpRowPad + k0 + 8 * kh]);
-      const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&Ap[1][row * kMlpRowPad + k0 + 8 * kh]);
+      bf16x8 a[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        a[g] = *reinterpret_cast<const bf16x8*>(&Ap[g][row * kMlpRowPad + k0 + 8 * kh]);
       const int kn = k0 + 16 < K ? k0 + 16 : k0;   // (the last step reloads its own)
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < 2; ++t)
         bnext[t] = *reinterpret_cast<const bf16x8*>(&Wl[(long)t * 32 * K + kn]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        acc[t][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bcur[t], acc[t][0], 0, 0, 0);
-        acc[t][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bcur[t], acc[t][1], 0, 0, 0);
-      }
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) bcur[t] = bnext[t];
+        for (int g = 0; g < 4; ++g)
+          acc[t][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[g], bcur[t], acc[t][g], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) bcur[t] = bnext[t];
     }
     __syncthreads();   // every lane finished reading this layer's input
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int col = (half * 4 + t) * 32 + row;
+    for (int t = 0; t < 2; ++t) {
+      const int col = (wave * 2 + t) * 32 + row;
       const float bb = bias[col];
 #pragma unroll
-      for (int g = 0; g < 2; ++g)
+      for (int g = 0; g < 4; ++g)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int r = 8 * (v >> 2) + 4 * kh + (v & 3);
@@ -435,17 +433,17 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_mfma(long B, int n, const doubl
     }
     __syncthreads();
   }
-  // ---- layer 3 (K = 256, nout_pad / 32 output tiles, split between the
-  // pair as above; tiles two at a time, the next k step's weight fragments
-  // loading during the current MFMAs)
+  // ---- layer 3 (K = 256, nout_pad / 32 output tiles, split in four
+  // contiguous ranges; tiles two at a time, the next k step's weight
+  // fragments loading during the current MFMAs)
   const int ntile = nout_pad / 32;
-  const int tb = half ? (ntile + 1) / 2 : 0, te = half ? ntile : (ntile + 1) / 2;
+  const int tb = ntile * wave / 4, te = ntile * (wave + 1) / 4;
   for (int t0 = tb; t0 < te; t0 += 2) {
-    f32x16 acc[2][2];
+    f32x16 acc[2][4];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int g = 0; g < 2; ++g)
+      for (int g = 0; g < 4; ++g)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[u][g][v] = 0.f;
     // a second tile past this wave's range reads the first tile's rows (in
@@ -456,16 +454,20 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_mfma(long B, int n, const doubl
     bf16x8 c0 = *reinterpret_cast<const bf16x8*>(W0);
     bf16x8 c1 = *reinterpret_cast<const bf16x8*>(W1);
     for (int k0 = 0; k0 < kMlpHid; k0 += 16) {
-      const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&Ap[0][row * kMlpRowPad + k0 + 8 * kh]);
-      const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&Ap[1][row * kMlpRowPad + k0 + 8 * kh]);
+      bf16x8 a[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        a[g] = *reinterpret_cast<const bf16x8*>(&Ap[g][row * kMlpRowPad + k0 + 8 * kh]);
       const int kn = k0 + 16 < kMlpHid ? k0 + 16 : k0;
       const bf16x8 n0 = *reinterpret_cast<const bf16x8*>(W0 + kn);
       const bf16x8 n1 = *reinterpret_cast<const bf16x8*>(W1 + kn);
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, c0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, c0, acc[0][1], 0, 0, 0);
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        acc[0][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[g], c0, acc[0][g], 0, 0, 0);
       if (two) {
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, c1, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, c1, acc[1][1], 0, 0, 0);
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          acc[1][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[g], c1, acc[1][g], 0, 0, 0);
       }
       c0 = n0;
       c1 = n1;
@@ -477,12 +479,14 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_mfma(long B, int n, const doubl
       const float bb = b3[col];
       const bool diag = (col / n) == (col % n);
 #pragma unroll
-      for (int g = 0; g < 2; ++g)
+      for (int g = 0; g < 4; ++g) {
+        const long sg = ((long)blockIdx.x * 4 + g) * 32;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const long s = sp[g] + 8 * (v >> 2) + 4 * kh + (v & 3);
+          const long s = sg + 8 * (v >> 2) + 4 * kh + (v & 3);
           if (s < B) out[s * nout + col] = acc[u][g][v] + bb + (diag ? 1.0f : 0.0f);
         }
+      }
     }
   }
 }
