@@ -37,6 +37,26 @@ def test_linear_combination(orc, dev, G, n, nv):
     assert np.all(np.abs(z.cpu().numpy() - ref) <= bound)
 
 
+# From 12 vectors, whole chunks of 8192 16-byte units (16384 doubles) take the long-run kernel and
+# the rest the tile kernel on advanced pointers: one unit short of a chunk, exactly one chunk, and
+# three chunks plus 2048 units plus an odd element.
+CHUNK = 16384
+
+
+@pytest.mark.parametrize("n", [CHUNK - 2, CHUNK, 3 * CHUNK + 4096 + 1])
+@pytest.mark.parametrize("nv", [12, 13, 16])
+@pytest.mark.parametrize("alias", [False, True])
+def test_linear_combination_long_runs(orc, dev, G, n, nv, alias):
+    X = W.uniform_vectors(nv, n, seed=31 + n + nv)
+    c = W.uniform_coefficients(nv, seed=7 + nv)
+    Xd = [T(x, dev) for x in X]
+    z = Xd[0] if alias else torch.empty(n, dtype=torch.float64, device=dev)
+    G.nvec_linear_combination(c, Xd, z)
+    ref = orc.linear_combination(c, list(X))
+    bound = 1e-12 * (np.abs(c[:, None] * X).sum(0))
+    assert np.all(np.abs(z.cpu().numpy() - ref) <= bound)
+
+
 def test_linear_combination_misaligned_and_aliased(orc, dev, G):
     n = 10001
     X = W.uniform_vectors(3, n + 1, seed=5)
